@@ -1,0 +1,201 @@
+/*
+ * mnufft: 2D/3D nonuniform FFTs of type 1 and type 2 on AMD Instinct MI355X
+ * (gfx950), following the three-step method of cuFINUFFT (arXiv 2102.08463):
+ * exponential-of-semicircle spreading / interpolation on an upsampled grid,
+ * a fine-grid FFT, and deconvolution by the kernel's Fourier transform.
+ *
+ * C ABI.  Every entry point returns an int status (MNUFFT_OK = 0, a positive
+ * value is a warning, a negative value an error) and never throws.  Pointers
+ * to array data are device pointers unless a comment says otherwise.  Complex
+ * data are interleaved (re, im) of the plan precision: float2 for
+ * MNUFFT_F32, double2 for MNUFFT_F64.  A plan is not re-entrant: calls on
+ * one plan must not overlap.
+ *
+ * Problem statement (Sec. I, eqs. 2d1 / 2d2 and their 3D analogue):
+ *   type 1:  f_k = sum_{j<M} c_j exp(iflag * i * k.x_j),   k in I_N1 x I_N2 (x I_N3)
+ *   type 2:  c_j = sum_k f_k exp(iflag * i * k.x_j),       j < M
+ * with I_N = {k integer : -N/2 <= k < N/2} (eq. I) and points x_j in
+ * [-pi, pi)^d.  The paper uses iflag = -1 for type 1 and +1 for type 2;
+ * either sign is accepted here.  No normalisation is applied.
+ *
+ * Mode arrays f are stored with k1 fastest, each k_i ascending from
+ * -floor(N_i/2); point arrays c are in the caller's point order.  With
+ * ntransf > 1 the transforms are stacked: c is ntransf x M, f is
+ * ntransf x (N1 N2 N3), all sharing the same points.
+ */
+#ifndef MNUFFT_H
+#define MNUFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define MNUFFT_OK                 0
+#define MNUFFT_WARN_EPS_CLAMPED   1   /* eps below the precision floor; plan valid, width capped */
+#define MNUFFT_ERR_ARG          (-1)  /* invalid argument; nothing was done */
+#define MNUFFT_ERR_ALLOC        (-2)  /* device or host allocation failed */
+#define MNUFFT_ERR_HIP          (-3)  /* a HIP runtime call failed */
+#define MNUFFT_ERR_FFT          (-4)  /* rocFFT plan creation or execution failed */
+#define MNUFFT_ERR_STATE        (-5)  /* call out of order (e.g. execute before setpts) */
+#define MNUFFT_ERR_PTS          (-6)  /* a point is non-finite or outside [-3pi, 3pi) (validate_pts) */
+#define MNUFFT_ERR_UNSUPPORTED  (-7)  /* valid request this build does not provide */
+
+/* ---- precisions and methods ------------------------------------------ */
+#define MNUFFT_F32 0
+#define MNUFFT_F64 1
+
+/* Spreading / interpolation methods (Sec. III-A, III-B).
+ *   GM      one thread per point in user order, global-memory atomics
+ *   GMSORT  one thread per point in bin-sorted order, global-memory atomics
+ *   SM      bin-sorted subproblems of at most msub points, each accumulated
+ *           in an LDS copy of its padded bin and added back to the grid
+ *           (type 1); for type 2 the padded bin is staged through LDS and
+ *           the points read it there
+ *   AUTO    SM (the library's default) */
+#define MNUFFT_METHOD_AUTO   0
+#define MNUFFT_METHOD_GM     1
+#define MNUFFT_METHOD_GMSORT 2
+#define MNUFFT_METHOD_SM     3
+
+typedef struct mnufft_opts {
+    int   method;       /* MNUFFT_METHOD_*; default AUTO */
+    int   binsize[3];   /* bin extents m_i in fine-grid cells; 0 selects the default
+                           (32 x 32 in 2D, 16 x 16 x 2 in 3D: Sec. III-A, first remark) */
+    int   msub;         /* max points per subproblem, > 0; 0 selects 1024 (same remark) */
+    int   validate_pts; /* nonzero: setpts checks that every coordinate is finite and
+                           in [-3pi, 3pi) and returns MNUFFT_ERR_PTS otherwise (this
+                           synchronises the stream) */
+    int   device;       /* HIP device ordinal, -1 = the current device */
+    void *stream;       /* hipStream_t all work is ordered on; NULL = the null stream */
+    int   reserved[8];  /* must be zero */
+} mnufft_opts;
+
+typedef struct mnufft_plan_s *mnufft_plan;
+
+/* Read-only description of a plan (host memory). */
+typedef struct mnufft_info {
+    int     type, dim, prec, iflag;
+    int64_t nmodes[3];     /* N_i (1 for unused dimensions) */
+    int64_t nfine[3];      /* fine grid n_i: smallest 2^a 3^b 5^c >= max(2 N_i, 2w) (Sec. II) */
+    int64_t ntransf;
+    int64_t M;             /* points set by the last setpts, -1 before */
+    int     w;             /* kernel width ceil(log10(1/eps)) + 1 (Sec. II), after clamping */
+    double  beta;          /* 2.30 w (Sec. II) */
+    int     method;        /* resolved method (never AUTO) */
+    int     binsize[3];
+    int     msub;
+    int64_t nbins;         /* prod ceil(n_i / m_i) */
+    int64_t nsub_max;      /* capacity of the subproblem list: nbins + ceil(M / msub) */
+    int64_t device_bytes;  /* device memory owned by the plan */
+} mnufft_info;
+
+/* Fill *o with the defaults listed in mnufft_opts.  Errors: ERR_ARG if o is NULL. */
+int mnufft_default_opts(mnufft_opts *o);
+
+/* Create a plan (Sec. I-A: plan, set up, execute, destroy).
+ *   type     1 or 2
+ *   dim      2 or 3
+ *   nmodes   host array of dim entries N_i >= 1 (the rest ignored)
+ *   iflag    +1 or -1, the sign in the exponent
+ *   ntransf  >= 1 transforms sharing one set of points
+ *   eps      requested relative l2 tolerance in (0, 1); sets w and beta (Sec. II)
+ *   prec     MNUFFT_F32 or MNUFFT_F64
+ *   opts     NULL for defaults
+ *   out      receives the plan handle, owned by the caller until mnufft_destroy
+ * Picks w, beta and the fine grid, computes the correction factors
+ * p_k = (2/w) / phi_hat(alpha k) (Sec. II-A step 3) once, creates the rocFFT
+ * plan and allocates the fine grid.  All arguments are validated before any
+ * device call.  Returns MNUFFT_WARN_EPS_CLAMPED if eps needs w > 8 in F32 or
+ * w > 16 in F64 (the plan then runs at the capped width).  Errors: ERR_ARG,
+ * ERR_ALLOC, ERR_HIP, ERR_FFT; *out is NULL on error. */
+int mnufft_makeplan(int type, int dim, const int64_t *nmodes, int iflag,
+                    int64_t ntransf, double eps, int prec,
+                    const mnufft_opts *opts, mnufft_plan *out);
+
+/* Set the M nonuniform points (Sec. III-A bin-sort; the paper's setup stage).
+ *   x, y, z  device arrays of M reals of the plan precision (z = NULL in 2D);
+ *            coordinates in [-pi, pi); values in [-3pi, 3pi) are folded by
+ *            whole periods, exactly.
+ * Bins the points on the fine grid, builds the stable bin-sort permutation
+ * (within a bin, points keep their input order) and the subproblem list, and
+ * keeps its own sorted copy of the coordinates, so the caller may reuse x/y/z
+ * once the stream has passed this call.  Stream-ordered, no host
+ * synchronisation unless validate_pts is set.  M = 0 is allowed.
+ * Errors: ERR_ARG (M < 0, M > 2^31 - 1, NULL x or y, z given in 2D or
+ * missing in 3D), ERR_PTS, ERR_ALLOC, ERR_HIP. */
+int mnufft_setpts(mnufft_plan p, int64_t M, const void *x, const void *y,
+                  const void *z);
+
+/* Run the transform (Sec. II-A for type 1, Sec. II-B for type 2).
+ *   type 1: c is input (ntransf x M complex), f is output (ntransf x N1 N2 N3)
+ *   type 2: f is input, c is output
+ * The output is overwritten.  Asynchronous on the plan's stream.
+ * Errors: ERR_STATE (no setpts), ERR_ARG (NULL pointer with M > 0), ERR_HIP, ERR_FFT. */
+int mnufft_execute(mnufft_plan p, void *c, void *f);
+
+/* Apply the adjoint of the plan's operator on the same sorted points: the
+ * other type with the opposite sign (type 2 is the adjoint of type 1, Sec. I).
+ * Same array roles as mnufft_execute with the directions swapped: for a
+ * type 1 plan, f is input and c is output; for a type 2 plan, c is input and
+ * f is output.  Errors as mnufft_execute. */
+int mnufft_execute_adjoint(mnufft_plan p, void *c, void *f);
+
+/* Step 1 of type 1 alone (Sec. II-A): grid = sum_j c_j psi_per(l h - pi - x_j)
+ * for the first transform, with the plan's method.  grid is caller-owned,
+ * n1 n2 (n3) complex, first coordinate fastest, overwritten.  Grid point l
+ * sits at l h - pi (the lattice that bins points in Sec. III-A).
+ * Errors: ERR_STATE, ERR_ARG, ERR_HIP. */
+int mnufft_spread(mnufft_plan p, const void *c, void *grid);
+
+/* Step 3 of type 2 alone (Sec. II-B): c_j = sum_l grid_l psi_per(l h - pi - x_j)
+ * for one vector, with the plan's method.  Same grid layout as mnufft_spread;
+ * c (M complex) is overwritten.  Errors as mnufft_spread. */
+int mnufft_interp(mnufft_plan p, const void *grid, void *c);
+
+/* Copy the bin-sort result into caller-owned device buffers (stream-ordered):
+ *   perm      M int32: perm[i] = input index of the point at sorted position i
+ *   binstart  nbins + 1 int32: first sorted position of each bin, binstart[nbins] = M
+ * Either pointer may be NULL.  Errors: ERR_STATE, ERR_HIP. */
+int mnufft_get_sort(mnufft_plan p, int32_t *perm, int32_t *binstart);
+
+/* Copy the subproblem list (Sec. III-A, SM step 1) into caller-owned device
+ * buffers: sub holds nsub_max records of 4 int32 (bin, first sorted position,
+ * number of points, 0) in bin order, and *nsub (device int32) the number of
+ * records in use.  Errors: ERR_STATE, ERR_HIP. */
+int mnufft_get_subproblems(mnufft_plan p, int32_t *sub, int32_t *nsub);
+
+/* Describe the plan (host memory).  Errors: ERR_ARG. */
+int mnufft_get_info(mnufft_plan p, mnufft_info *info);
+
+/* Synchronise the plan's stream, free everything the plan owns and the plan
+ * itself.  NULL is accepted and ignored.  Errors: ERR_HIP. */
+int mnufft_destroy(mnufft_plan p);
+
+/* Host-only helpers (no device call; usable without a GPU). */
+
+/* Parameters of Sec. II for one dimension: kernel width w = ceil(log10(1/eps)) + 1
+ * (at least 2; capped at 8 in F32 and 16 in F64), beta = 2.30 w, and the fine
+ * grid n = smallest 2^a 3^b 5^c >= max(2N, 2w).  Outputs are host pointers.
+ * Returns MNUFFT_WARN_EPS_CLAMPED when the cap applied.  Errors: ERR_ARG. */
+int mnufft_choose_params(double eps, int prec, int64_t N, int *w, double *beta, int64_t *n);
+
+/* The N per-dimension correction factors of Sec. II-A step 3, as the library
+ * computes them at plan time (host array out, double):
+ *   out[i] = (2/w) / phi_hat(alpha k) * (-1)^k,  k = i - floor(N/2),  alpha = w pi / n,
+ * with phi_hat(xi) = int_{-1}^{1} exp(beta (sqrt(1-z^2) - 1)) exp(-i xi z) dz
+ * evaluated by tanh-sinh quadrature.  The factor (-1)^k comes from placing
+ * grid point l at l h - pi.  Errors: ERR_ARG (N < 1, n < 2N, w outside 2..16,
+ * beta <= 0, out NULL). */
+int mnufft_correction_factors(int64_t N, int64_t n, int w, double beta, double *out);
+
+/* Human-readable name of a status code (static storage, never NULL). */
+const char *mnufft_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MNUFFT_H */

@@ -1,0 +1,11 @@
+"""MI355X-native 2D/3D nonuniform FFTs (type 1 and type 2) after cuFINUFFT.
+
+The transforms run in libmnufft.so (hand-written HIP kernels for gfx950 plus
+rocFFT for the fine-grid FFT) behind the C ABI in include/mnufft.h; this
+package is its thin Python binding.  PyTorch provides device memory and
+streams only.
+"""
+from .plan import Plan, nufft_type1, nufft_type2  # noqa: F401
+from . import lib  # noqa: F401
+
+__all__ = ["Plan", "nufft_type1", "nufft_type2", "lib"]

@@ -1,0 +1,444 @@
+// Bin-sort of the nonuniform points (Sec. III-A, GM-sort and SM step 1).
+//
+// A point lies in the bin that holds its integer fine-grid coordinates
+// l_i = floor((x_i + pi) / h_i).  The permutation t lists bin 0's points
+// first, then bin 1's, ...; inside a bin the input order is kept, which makes
+// t unique and reproducible.  It is built as a stable LSD radix sort of
+// (bin key, input index) pairs with 8-bit digits: per pass a digit histogram
+// per 4096-key tile, one exclusive scan over the (digit, tile) counts, and a
+// scatter whose in-tile ranks come from wavefront ballots (all lanes holding
+// the same digit are found with eight 64-bit ballots, so no lane order has to
+// be assumed of LDS atomics).
+//
+// The grid coordinate is evaluated with a fixed sequence of correctly rounded
+// double operations and no contraction: g = (x + pi) * S with S = n / (2 pi)
+// rounded once on the host; then one whole-period correction.  That makes
+// the keys, and hence t, reproducible bit for bit on any IEEE machine.
+#include "internal.h"
+
+#include <algorithm>
+
+namespace mn {
+namespace {
+
+constexpr double kPi = 3.141592653589793;
+constexpr int kThreads = 256;
+constexpr int kItems = 16;
+constexpr int kTile = kThreads * kItems;  // keys per radix block
+
+// Folded grid coordinate in [0, n).  `bad` is set when one period shift does
+// not bring the value into range (non-finite or beyond about [-3pi, 3pi)).
+__device__ __forceinline__ double grid_coord(double x, double S, int n, int &bad)
+{
+    const double nd = (double)n;
+    double g = __dmul_rn(__dadd_rn(x, kPi), S);
+    if (g < 0.0) g = __dadd_rn(g, nd);
+    if (g >= nd) g = __dsub_rn(g, nd);
+    if (!(g >= 0.0 && g < nd)) {
+        bad = 1;
+        const double q = floor(__ddiv_rn(g, nd));
+        g = __dsub_rn(g, __dmul_rn(q, nd));
+        if (g >= nd) g = __dsub_rn(g, nd);
+        if (!(g >= 0.0 && g < nd)) g = 0.0;
+    }
+    return g;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_binkey(Geom g, int M, const T *__restrict__ x, const T *__restrict__ y,
+         const T *__restrict__ z, uint32_t *__restrict__ key, T *__restrict__ u0,
+         T *__restrict__ u1, T *__restrict__ u2, int *__restrict__ flag)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= M) return;
+    int bad = 0;
+    const T *xs[3] = {x, y, z};
+    T *us[3] = {u0, u1, u2};
+    uint32_t k = 0, stride = 1;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (d >= g.dim) break;
+        const double gc = grid_coord((double)xs[d][j], g.S[d], g.n[d], bad);
+        const int l = (int)gc;  // gc >= 0, so truncation is floor; l <= n - 1
+        const int b = l / g.m[d];
+        k += (uint32_t)b * stride;
+        stride *= (uint32_t)g.B[d];
+        if (us[d]) us[d][j] = (T)(gc - (double)b * (double)g.m[d]);
+    }
+    key[j] = k;
+    if (bad) atomicOr(flag, 1);
+}
+
+// Per-tile digit histogram, stored digit-major: hist[d * nblk + blk].
+__global__ void __launch_bounds__(kThreads)
+k_radix_hist(const uint32_t *__restrict__ keys, int M, int shift, int nblk,
+             uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t h[256];
+    const int tid = threadIdx.x;
+    h[tid] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    for (int r = 0; r < kItems; ++r) {
+        const int64_t idx = base + (int64_t)r * kThreads + tid;
+        const bool valid = idx < M;
+        const uint32_t d = valid ? (keys[idx] >> shift) & 255u : 0u;
+        // Lanes are contiguous in idx, so lane 0 is valid whenever any lane is.
+        const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)d);
+        const bool same = !valid || d == d0;
+        if (__all(same)) {
+            const uint64_t vm = __ballot(valid);
+            if ((threadIdx.x & 63) == 0 && vm) atomicAdd(&h[d0], (uint32_t)__popcll(vm));
+        } else if (valid) {
+            atomicAdd(&h[d], 1u);
+        }
+    }
+    __syncthreads();
+    hist[(int64_t)tid * nblk + blockIdx.x] = h[tid];
+}
+
+// Stable scatter of one radix pass.  Wave w of a block owns keys
+// [blk*kTile + w*1024, +1024) and walks them in 16 rounds of 64 consecutive
+// keys, so ranks grow with the input index.
+__global__ void __launch_bounds__(kThreads)
+k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, int M,
+                int shift, int nblk, const uint32_t *__restrict__ offs,
+                uint32_t *__restrict__ kout, uint32_t *__restrict__ vout)
+{
+    constexpr int kWaves = kThreads / 64;
+    __shared__ uint32_t cnt[kWaves][256];
+    __shared__ uint32_t wbase[kWaves][256];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    for (int w = 0; w < kWaves; ++w) cnt[w][tid] = 0;
+    __syncthreads();
+
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)wave * (64 * kItems);
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t kk[kItems], vv[kItems], rk[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const int64_t idx = base + r * 64 + lane;
+        const bool valid = idx < M;
+        const uint32_t key = valid ? kin[idx] : 0u;
+        const uint32_t val = valid ? (vin ? vin[idx] : (uint32_t)idx) : 0u;
+        const uint32_t d = (key >> shift) & 255u;
+        uint64_t mask = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            mask &= bit ? bb : ~bb;
+        }
+        const uint32_t rank = (uint32_t)__popcll(mask & lt);
+        uint32_t old = 0;
+        if (valid) {
+            old = cnt[wave][d];
+            if (rank == 0) cnt[wave][d] = old + (uint32_t)__popcll(mask);
+        }
+        kk[r] = key;
+        vv[r] = val;
+        rk[r] = old + rank;
+    }
+    __syncthreads();
+    {
+        const int d = tid;  // 256 threads, one digit each
+        uint32_t run = offs[(int64_t)d * nblk + blockIdx.x];
+        for (int w = 0; w < kWaves; ++w) {
+            wbase[w][d] = run;
+            run += cnt[w][d];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const int64_t idx = base + r * 64 + lane;
+        if (idx < M) {
+            const uint32_t d = (kk[r] >> shift) & 255u;
+            const uint32_t pos = wbase[wave][d] + rk[r];
+            kout[pos] = kk[r];
+            vout[pos] = vv[r];
+        }
+    }
+}
+
+// ---- generic exclusive scan (reduce, scan partials, down-sweep) ----------
+constexpr int kScanChunk = kThreads * kItems;
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan of one value per thread over the block; returns the block total.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t &excl)
+{
+    __shared__ uint32_t wsum[kThreads / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t inc = wave_incl_scan(v, lane);
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (int w = 0; w < kThreads / 64; ++w) {
+        if (w < wave) before += wsum[w];
+        total += wsum[w];
+    }
+    __syncthreads();
+    excl = before + inc - v;
+    return total;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_scan_reduce(const uint32_t *__restrict__ in, size_t n, uint32_t *__restrict__ partials)
+{
+    const size_t base = (size_t)blockIdx.x * kScanChunk;
+    uint32_t s = 0;
+    for (int r = 0; r < kItems; ++r) {
+        const size_t i = base + (size_t)r * kThreads + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    uint32_t ex;
+    const uint32_t tot = block_excl_scan(s, ex);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_partials(uint32_t *__restrict__ partials, int np)
+{
+    // One block: thread t scans a contiguous run of the partials serially.
+    __shared__ uint32_t sums[1024];
+    const int t = threadIdx.x;
+    const int per = (np + 1023) / 1024;
+    const int lo = std::min(np, t * per), hi = std::min(np, lo + per);
+    uint32_t s = 0;
+    for (int i = lo; i < hi; ++i) s += partials[i];
+    sums[t] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const uint32_t v = (t >= o) ? sums[t - o] : 0u;
+        __syncthreads();
+        sums[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = sums[t] - s;
+    for (int i = lo; i < hi; ++i) {
+        const uint32_t v = partials[i];
+        partials[i] = run;
+        run += v;
+    }
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_scan_down(const uint32_t *__restrict__ in, uint32_t *__restrict__ out, size_t n,
+            const uint32_t *__restrict__ partials)
+{
+    __shared__ uint32_t buf[kScanChunk + kScanChunk / 32];
+    const size_t base = (size_t)blockIdx.x * kScanChunk;
+    auto sk = [](int e) { return e + (e >> 5); };  // skew against bank conflicts
+    for (int r = 0; r < kItems; ++r) {
+        const int e = r * kThreads + threadIdx.x;
+        const size_t i = base + e;
+        buf[sk(e)] = (i < n) ? in[i] : 0u;
+    }
+    __syncthreads();
+    uint32_t s = 0;
+    for (int q = 0; q < kItems; ++q) s += buf[sk(threadIdx.x * kItems + q)];
+    uint32_t ex;
+    block_excl_scan(s, ex);
+    uint32_t run = ex + partials[blockIdx.x];
+    for (int q = 0; q < kItems; ++q) {
+        const int e = threadIdx.x * kItems + q;
+        const uint32_t v = buf[sk(e)];
+        buf[sk(e)] = run;
+        run += v;
+    }
+    __syncthreads();
+    for (int r = 0; r < kItems; ++r) {
+        const int e = r * kThreads + threadIdx.x;
+        const size_t i = base + e;
+        if (i < n) out[i] = buf[sk(e)];
+    }
+}
+
+__global__ void k_binstart(int M, int nbins, const uint32_t *__restrict__ skey,
+                           int32_t *__restrict__ binstart)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > nbins) return;
+    int lo = 0, hi = M;  // first position with skey >= b
+    while (lo < hi) {
+        const int mid = lo + ((hi - lo) >> 1);
+        if (skey[mid] < (uint32_t)b) lo = mid + 1; else hi = mid;
+    }
+    binstart[b] = lo;
+}
+
+__global__ void k_subcount(int nbins, int msub, const int32_t *__restrict__ binstart,
+                           uint32_t *__restrict__ cnt)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > nbins) return;
+    if (b == nbins) { cnt[b] = 0; return; }
+    const int c = binstart[b + 1] - binstart[b];
+    cnt[b] = (uint32_t)((c + msub - 1) / msub);
+}
+
+__global__ void k_subfill(int nbins, int msub, int nsub_max, const int32_t *__restrict__ binstart,
+                          const uint32_t *__restrict__ off, int32_t *__restrict__ sub,
+                          int32_t *__restrict__ nsub)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    // the count is clamped to the list's capacity so that no consumer can
+    // read past it, whatever the counts held
+    const int total = std::min((int)off[nbins], nsub_max);
+    if (q == 0) *nsub = total;
+    if (q >= total || q >= nsub_max) return;
+    int lo = 0, hi = nbins - 1;  // last bin b with off[b] <= q
+    while (lo < hi) {
+        const int mid = lo + ((hi - lo + 1) >> 1);
+        if (off[mid] <= (uint32_t)q) lo = mid; else hi = mid - 1;
+    }
+    const int b = lo;
+    const int s = q - (int)off[b];
+    const int start = binstart[b] + s * msub;
+    const int len = std::min(msub, binstart[b + 1] - start);
+    int4 rec;
+    rec.x = b; rec.y = start; rec.z = len; rec.w = 0;
+    reinterpret_cast<int4 *>(sub)[q] = rec;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_gather_coords(Geom g, int M, const T *__restrict__ x, const T *__restrict__ y,
+                const T *__restrict__ z, const int32_t *__restrict__ perm,
+                const uint32_t *__restrict__ skey, T *__restrict__ u0, T *__restrict__ u1,
+                T *__restrict__ u2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const int j = perm[i];
+    uint32_t k = skey[i];
+    int bad = 0;
+    const T *xs[3] = {x, y, z};
+    T *us[3] = {u0, u1, u2};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (d >= g.dim) break;
+        const int b = (int)(k % (uint32_t)g.B[d]);
+        k /= (uint32_t)g.B[d];
+        const double gc = grid_coord((double)xs[d][j], g.S[d], g.n[d], bad);
+        us[d][i] = (T)(gc - (double)b * (double)g.m[d]);
+    }
+}
+
+inline int nblocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
+
+}  // namespace
+
+size_t radix_hist_elems(int M) { return (size_t)256 * std::max(1, nblocks(M, kTile)); }
+
+size_t scan_partial_elems(size_t n) { return (n + kScanChunk - 1) / kScanChunk + 1; }
+
+hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, size_t n, uint32_t *partials,
+                          hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const int np = (int)((n + kScanChunk - 1) / kScanChunk);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(np), dim3(kThreads), 0, s, in, n, partials);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, np);
+    hipLaunchKernelGGL(k_scan_down, dim3(np), dim3(kThreads), 0, s, in, out, n,
+                       (const uint32_t *)partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_binkey(const Geom &g, int prec, int M, const void *x, const void *y,
+                         const void *z, uint32_t *key, void *const u_in[3], int *flag,
+                         hipStream_t s)
+{
+    if (M == 0) return hipSuccess;
+    const dim3 grid(nblocks(M, kThreads)), blk(kThreads);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_binkey<float>, grid, blk, 0, s, g, M, (const float *)x,
+                           (const float *)y, (const float *)z, key, (float *)u_in[0],
+                           (float *)u_in[1], (float *)u_in[2], flag);
+    else
+        hipLaunchKernelGGL(k_binkey<double>, grid, blk, 0, s, g, M, (const double *)x,
+                           (const double *)y, (const double *)z, key, (double *)u_in[0],
+                           (double *)u_in[1], (double *)u_in[2], flag);
+    return hipGetLastError();
+}
+
+hipError_t radix_sort(int M, int bits, uint32_t *keysA, uint32_t *valsA, uint32_t *keysB,
+                      uint32_t *valsB, uint32_t *hist, uint32_t *partials,
+                      uint32_t **keys_out, uint32_t **vals_out, hipStream_t s)
+{
+    // Keys start in keysA with implicit values 0..M-1; each pass moves the
+    // pairs to the other buffer.
+    const int passes = std::max(1, (bits + 7) / 8);
+    const int nblk = std::max(1, nblocks(M, kTile));
+    uint32_t *kb[2] = {keysA, keysB}, *vb[2] = {valsA, valsB};
+    int cur = 0;
+    for (int p = 0; p < passes; ++p) {
+        if (M > 0) {
+            const int shift = 8 * p;
+            hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kThreads), 0, s,
+                               (const uint32_t *)kb[cur], M, shift, nblk, hist);
+            hipError_t e = scan_exclusive(hist, hist, (size_t)256 * nblk, partials, s);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kThreads), 0, s,
+                               (const uint32_t *)kb[cur], p == 0 ? nullptr : (const uint32_t *)vb[cur],
+                               M, shift, nblk, (const uint32_t *)hist, kb[1 - cur], vb[1 - cur]);
+        }
+        cur = 1 - cur;
+    }
+    *keys_out = kb[cur];
+    *vals_out = vb[cur];
+    return hipGetLastError();
+}
+
+hipError_t launch_binstart(int M, int nbins, const uint32_t *skey, int32_t *binstart,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_binstart, dim3(nblocks(nbins + 1, 256)), dim3(256), 0, s, M, nbins,
+                       skey, binstart);
+    return hipGetLastError();
+}
+
+hipError_t launch_subproblems(int nbins, int msub, int nsub_max, const int32_t *binstart,
+                              int32_t *subcount, uint32_t *partials, int32_t *sub,
+                              int32_t *nsub, hipStream_t s)
+{
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(subcount);
+    hipLaunchKernelGGL(k_subcount, dim3(nblocks(nbins + 1, 256)), dim3(256), 0, s, nbins, msub,
+                       binstart, cnt);
+    hipError_t e = scan_exclusive(cnt, cnt, (size_t)nbins + 1, partials, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_subfill, dim3(nblocks(std::max(nsub_max, 1), 256)), dim3(256), 0, s,
+                       nbins, msub, nsub_max, binstart, (const uint32_t *)cnt, sub, nsub);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_coords(const Geom &g, int prec, int M, const void *x, const void *y,
+                                const void *z, const int32_t *perm, const uint32_t *skey,
+                                void *const u[3], hipStream_t s)
+{
+    if (M == 0) return hipSuccess;
+    const dim3 grid(nblocks(M, kThreads)), blk(kThreads);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_gather_coords<float>, grid, blk, 0, s, g, M, (const float *)x,
+                           (const float *)y, (const float *)z, perm, skey, (float *)u[0],
+                           (float *)u[1], (float *)u[2]);
+    else
+        hipLaunchKernelGGL(k_gather_coords<double>, grid, blk, 0, s, g, M, (const double *)x,
+                           (const double *)y, (const double *)z, perm, skey, (double *)u[0],
+                           (double *)u[1], (double *)u[2]);
+    return hipGetLastError();
+}
+
+}  // namespace mn

@@ -1,0 +1,655 @@
+// Host side of libmnufft: plan construction, parameter choice, correction
+// factors, the rocFFT fine-grid transform and the C ABI declared in
+// include/mnufft.h.  The stages follow the paper's plan / setup / execute /
+// destroy interface (Sec. I-A) and three-step algorithm (Sec. II); every
+// step on the device runs in the kernels of kernels_*.hip except the FFT.
+#include "../../include/mnufft.h"
+#include "internal.h"
+
+#include <rocfft/rocfft.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+namespace {
+
+constexpr double kPi = 3.141592653589793;
+constexpr size_t kLdsMax = 160 * 1024;  // LDS per workgroup on gfx950
+
+// ---- parameter choice (Sec. II) -----------------------------------------
+
+// w = ceil(log10(1/eps)) + 1; a guard of 1e-9 keeps decade tolerances (whose
+// logarithm is not exactly an integer in floating point) on the intended side.
+int width_for_eps(double eps) { return (int)std::ceil(std::log10(1.0 / eps) - 1e-9) + 1; }
+
+bool smooth235(int64_t n)
+{
+    for (int64_t p : {2, 3, 5})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+// Smallest 2^a 3^b 5^c >= max(2N, 2w).
+int64_t fine_size(int64_t N, int w)
+{
+    int64_t n = std::max<int64_t>(2 * N, 2 * (int64_t)w);
+    while (!smooth235(n)) ++n;
+    return n;
+}
+
+// phi_hat(xi) = int_{-1}^{1} phi_beta(z) exp(-i xi z) dz = 2 int_0^1 phi(z) cos(xi z) dz
+// by the tanh-sinh rule z = (1 + tanh u)/2, u = (pi/2) sinh t, which is
+// insensitive to the square-root behaviour of phi at z = 1.
+void es_fourier(double beta, const std::vector<double> &xi, std::vector<double> &out)
+{
+    const double h = 1.0 / 64.0;
+    const int K = 4 * 64;  // t in [-4, 4]: the weights beyond are below 1e-20
+    std::vector<double> zz, ww;
+    zz.reserve(2 * K + 1);
+    ww.reserve(2 * K + 1);
+    for (int k = -K; k <= K; ++k) {
+        const double t = k * h;
+        const double u = 0.5 * kPi * std::sinh(t);
+        const double one_minus_z = 1.0 / (1.0 + std::exp(2.0 * u));
+        const double z = 1.0 - one_minus_z;
+        const double ch = std::cosh(u);
+        const double dz = 0.25 * kPi * std::cosh(t) / (ch * ch);
+        const double s = one_minus_z * (1.0 + z);  // 1 - z^2 without cancellation
+        const double phi = std::exp(beta * (std::sqrt(std::max(s, 0.0)) - 1.0));
+        zz.push_back(z);
+        ww.push_back(h * dz * phi);
+    }
+    out.assign(xi.size(), 0.0);
+    for (size_t i = 0; i < xi.size(); ++i) {
+        double acc = 0.0;
+        for (size_t q = 0; q < zz.size(); ++q) acc += ww[q] * std::cos(xi[i] * zz[q]);
+        out[i] = 2.0 * acc;
+    }
+}
+
+// p_k = (2/w) / phi_hat(alpha k) * (-1)^k for k in I_N, alpha = w pi / n.
+void correction(int64_t N, int64_t n, int w, double beta, std::vector<double> &p)
+{
+    std::vector<double> xi(N), ph;
+    const double alpha = w * kPi / (double)n;
+    for (int64_t i = 0; i < N; ++i) xi[i] = alpha * (double)(i - N / 2);
+    es_fourier(beta, xi, ph);
+    p.resize(N);
+    for (int64_t i = 0; i < N; ++i) {
+        const int64_t k = i - N / 2;
+        p[i] = (2.0 / w) / ph[i] * ((k % 2 == 0) ? 1.0 : -1.0);
+    }
+}
+
+int bits_for(int64_t nbins)
+{
+    int b = 0;
+    while (((int64_t)1 << b) < nbins) ++b;
+    return b;
+}
+
+std::once_flag g_fft_once;
+rocfft_status g_fft_setup = rocfft_status_success;
+
+}  // namespace
+
+struct mnufft_plan_s {
+    int type = 1, dim = 2, prec = 0, iflag = -1;
+    int64_t N[3] = {1, 1, 1};
+    int64_t ntransf = 1;
+    double eps = 1e-6;
+    mn::Geom g{};
+    int method = MNUFFT_METHOD_SM;
+    int msub = 1024;
+    int device = -1;
+    int validate = 0;
+    hipStream_t stream = nullptr;
+    size_t rsz = 4;             // bytes per real of the plan precision
+    size_t grid_elems = 0;      // complex cells per transform
+    void *grid = nullptr;       // ntransf fine grids
+    void *pfac[3] = {nullptr, nullptr, nullptr};
+    // points
+    int64_t M = -1;
+    int64_t Mcap = -1;
+    void *su[3] = {nullptr, nullptr, nullptr};
+    void *su_in[3] = {nullptr, nullptr, nullptr};
+    uint32_t *keyA = nullptr, *valA = nullptr, *keyB = nullptr, *valB = nullptr;
+    uint32_t *key_in = nullptr;
+    uint32_t *skey = nullptr;   // alias of keyA/keyB after the sort
+    int32_t *perm = nullptr;    // alias of valA/valB after the sort
+    int32_t *binstart = nullptr, *subcount = nullptr, *sub = nullptr, *nsub = nullptr;
+    int nsub_max = 0, nsub_cap = 0;
+    uint32_t *hist = nullptr, *partials = nullptr;
+    size_t hist_cap = 0, partials_cap = 0;
+    int *flag = nullptr;
+    // FFT
+    rocfft_plan fft[2] = {nullptr, nullptr};  // [0]: exponent sign -1, [1]: +1
+    rocfft_execution_info fftinfo = nullptr;
+    void *fftwork = nullptr;
+    size_t fftwork_bytes = 0;
+    int64_t devbytes = 0;
+};
+
+namespace {
+
+#define MN_HIP(call)                                                  \
+    do {                                                              \
+        hipError_t e_ = (call);                                       \
+        if (e_ != hipSuccess) return e_ == hipErrorOutOfMemory ? MNUFFT_ERR_ALLOC : MNUFFT_ERR_HIP; \
+    } while (0)
+
+int dalloc(mnufft_plan p, void **ptr, size_t bytes)
+{
+    *ptr = nullptr;
+    if (bytes == 0) return MNUFFT_OK;
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        (void)hipGetLastError();
+        return e == hipErrorOutOfMemory ? MNUFFT_ERR_ALLOC : MNUFFT_ERR_HIP;
+    }
+    p->devbytes += (int64_t)bytes;
+    return MNUFFT_OK;
+}
+
+void dfree(mnufft_plan p, void **ptr, size_t bytes)
+{
+    if (*ptr) {
+        (void)hipFree(*ptr);
+        p->devbytes -= (int64_t)bytes;
+    }
+    *ptr = nullptr;
+}
+
+int use_device(mnufft_plan p)
+{
+    if (p->device >= 0) MN_HIP(hipSetDevice(p->device));
+    return MNUFFT_OK;
+}
+
+void free_points(mnufft_plan p)
+{
+    if (p->Mcap < 0) return;
+    const size_t M = (size_t)std::max<int64_t>(p->Mcap, 1);
+    for (int d = 0; d < 3; ++d) {
+        dfree(p, &p->su[d], M * p->rsz);
+        dfree(p, &p->su_in[d], M * p->rsz);
+    }
+    dfree(p, (void **)&p->keyA, M * 4);
+    dfree(p, (void **)&p->valA, M * 4);
+    dfree(p, (void **)&p->keyB, M * 4);
+    dfree(p, (void **)&p->valB, M * 4);
+    dfree(p, (void **)&p->key_in, M * 4);
+    dfree(p, (void **)&p->sub, (size_t)p->nsub_cap * 16);
+    dfree(p, (void **)&p->hist, p->hist_cap * 4);
+    dfree(p, (void **)&p->partials, p->partials_cap * 4);
+    p->Mcap = -1;
+    p->nsub_cap = 0;
+    p->hist_cap = 0;
+    p->partials_cap = 0;
+}
+
+int alloc_points(mnufft_plan p, int64_t M)
+{
+    free_points(p);
+    const size_t Ma = (size_t)std::max<int64_t>(M, 1);
+    int rc;
+    for (int d = 0; d < p->dim; ++d) {
+        if ((rc = dalloc(p, &p->su[d], Ma * p->rsz))) return rc;
+        if (p->method == MNUFFT_METHOD_GM && (rc = dalloc(p, &p->su_in[d], Ma * p->rsz))) return rc;
+    }
+    if ((rc = dalloc(p, (void **)&p->keyA, Ma * 4))) return rc;
+    if ((rc = dalloc(p, (void **)&p->valA, Ma * 4))) return rc;
+    if ((rc = dalloc(p, (void **)&p->keyB, Ma * 4))) return rc;
+    if ((rc = dalloc(p, (void **)&p->valB, Ma * 4))) return rc;
+    if (p->method == MNUFFT_METHOD_GM && (rc = dalloc(p, (void **)&p->key_in, Ma * 4))) return rc;
+    p->nsub_cap = (int)(p->g.nbins + (M + p->msub - 1) / p->msub);
+    if ((rc = dalloc(p, (void **)&p->sub, (size_t)std::max(p->nsub_cap, 1) * 16))) return rc;
+    p->hist_cap = mn::radix_hist_elems((int)M);
+    if ((rc = dalloc(p, (void **)&p->hist, p->hist_cap * 4))) return rc;
+    p->partials_cap = std::max(mn::scan_partial_elems(p->hist_cap),
+                               mn::scan_partial_elems((size_t)p->g.nbins + 1));
+    if ((rc = dalloc(p, (void **)&p->partials, p->partials_cap * 4))) return rc;
+    p->Mcap = M;
+    return MNUFFT_OK;
+}
+
+int make_fft(mnufft_plan p, int which)
+{
+    if (p->fft[which]) return MNUFFT_OK;
+    size_t len[3];
+    for (int d = 0; d < p->dim; ++d) len[d] = (size_t)p->g.n[d];  // first dimension fastest
+    rocfft_status st = rocfft_plan_create(
+        &p->fft[which], rocfft_placement_inplace,
+        which == 0 ? rocfft_transform_type_complex_forward : rocfft_transform_type_complex_inverse,
+        p->prec == MNUFFT_F32 ? rocfft_precision_single : rocfft_precision_double,
+        (size_t)p->dim, len, (size_t)p->ntransf, nullptr);
+    if (st != rocfft_status_success) {
+        p->fft[which] = nullptr;
+        return MNUFFT_ERR_FFT;
+    }
+    size_t wb = 0;
+    if (rocfft_plan_get_work_buffer_size(p->fft[which], &wb) != rocfft_status_success)
+        return MNUFFT_ERR_FFT;
+    if (wb > p->fftwork_bytes) {
+        dfree(p, &p->fftwork, p->fftwork_bytes);
+        p->fftwork_bytes = 0;
+        int rc = dalloc(p, &p->fftwork, wb);
+        if (rc) return rc;
+        p->fftwork_bytes = wb;
+    }
+    return MNUFFT_OK;
+}
+
+// In-place unnormalised FFT of all ntransf grids with exponent sign `sign`.
+int run_fft(mnufft_plan p, int sign)
+{
+    const int which = sign < 0 ? 0 : 1;
+    int rc = make_fft(p, which);
+    if (rc) return rc;
+    if (rocfft_execution_info_set_stream(p->fftinfo, p->stream) != rocfft_status_success)
+        return MNUFFT_ERR_FFT;
+    if (p->fftwork_bytes &&
+        rocfft_execution_info_set_work_buffer(p->fftinfo, p->fftwork, p->fftwork_bytes) !=
+            rocfft_status_success)
+        return MNUFFT_ERR_FFT;
+    void *buf[1] = {p->grid};
+    if (rocfft_execute(p->fft[which], buf, nullptr, p->fftinfo) != rocfft_status_success)
+        return MNUFFT_ERR_FFT;
+    return MNUFFT_OK;
+}
+
+mn::Pts points_of(mnufft_plan p)
+{
+    mn::Pts P{};
+    P.M = (int)p->M;
+    for (int d = 0; d < 3; ++d) {
+        P.u[d] = p->su[d];
+        P.u_in[d] = p->su_in[d];
+    }
+    P.key = p->skey;
+    P.perm = p->perm;
+    P.binstart = p->binstart;
+    P.sub = p->sub;
+    P.nsub = p->nsub;
+    P.nsub_max = p->nsub_max;
+    P.key_in = p->key_in;
+    return P;
+}
+
+size_t grid_bytes(mnufft_plan p) { return p->grid_elems * 2 * p->rsz; }
+
+// Type 1 with exponent sign `sign`: c (ntransf x M) -> f (ntransf x N).
+int exec_type1(mnufft_plan p, int sign, const void *c, void *f)
+{
+    const mn::Pts P = points_of(p);
+    MN_HIP(mn::launch_zero(p->grid, grid_bytes(p) * p->ntransf, p->stream));
+    for (int64_t t = 0; t < p->ntransf; ++t) {
+        const char *ct = (const char *)c + (size_t)t * p->M * 2 * p->rsz;
+        char *gt = (char *)p->grid + (size_t)t * grid_bytes(p);
+        MN_HIP(mn::launch_spread(p->g, p->prec, p->method, P, ct, gt, p->stream));
+    }
+    int rc = run_fft(p, sign);
+    if (rc) return rc;
+    MN_HIP(mn::launch_deconv(p->dim, p->N, p->g.n, p->prec, (int)p->ntransf, p->grid,
+                             p->pfac, f, p->stream));
+    return MNUFFT_OK;
+}
+
+// Type 2 with exponent sign `sign`: f (ntransf x N) -> c (ntransf x M).
+int exec_type2(mnufft_plan p, int sign, const void *f, void *c)
+{
+    const mn::Pts P = points_of(p);
+    MN_HIP(mn::launch_precorrect(p->dim, p->N, p->g.n, p->prec, (int)p->ntransf, f, p->pfac,
+                                 p->grid, p->stream));
+    int rc = run_fft(p, sign);
+    if (rc) return rc;
+    for (int64_t t = 0; t < p->ntransf; ++t) {
+        char *ct = (char *)c + (size_t)t * p->M * 2 * p->rsz;
+        const char *gt = (const char *)p->grid + (size_t)t * grid_bytes(p);
+        MN_HIP(mn::launch_interp(p->g, p->prec, p->method, P, gt, ct, p->stream));
+    }
+    return MNUFFT_OK;
+}
+
+int check_ready(mnufft_plan p)
+{
+    if (!p) return MNUFFT_ERR_ARG;
+    if (p->M < 0) return MNUFFT_ERR_STATE;
+    return MNUFFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mnufft_strerror(int s)
+{
+    switch (s) {
+    case MNUFFT_OK: return "ok";
+    case MNUFFT_WARN_EPS_CLAMPED: return "eps below the precision floor; kernel width capped";
+    case MNUFFT_ERR_ARG: return "invalid argument";
+    case MNUFFT_ERR_ALLOC: return "allocation failed";
+    case MNUFFT_ERR_HIP: return "HIP runtime error";
+    case MNUFFT_ERR_FFT: return "rocFFT error";
+    case MNUFFT_ERR_STATE: return "call out of order (points not set)";
+    case MNUFFT_ERR_PTS: return "point coordinate non-finite or outside [-3pi, 3pi)";
+    case MNUFFT_ERR_UNSUPPORTED: return "unsupported request";
+    }
+    return "unknown status";
+}
+
+int mnufft_default_opts(mnufft_opts *o)
+{
+    if (!o) return MNUFFT_ERR_ARG;
+    std::memset(o, 0, sizeof(*o));
+    o->method = MNUFFT_METHOD_AUTO;
+    o->device = -1;
+    return MNUFFT_OK;
+}
+
+int mnufft_choose_params(double eps, int prec, int64_t N, int *w, double *beta, int64_t *n)
+{
+    if (!(eps > 0.0 && eps < 1.0) || (prec != MNUFFT_F32 && prec != MNUFFT_F64) || N < 1 ||
+        !w || !beta || !n)
+        return MNUFFT_ERR_ARG;
+    int rc = MNUFFT_OK;
+    int ww = std::max(2, width_for_eps(eps));
+    const int wmax = prec == MNUFFT_F32 ? 8 : 16;
+    if (ww > wmax) {
+        ww = wmax;
+        rc = MNUFFT_WARN_EPS_CLAMPED;
+    }
+    *w = ww;
+    *beta = 2.30 * ww;
+    *n = fine_size(N, ww);
+    return rc;
+}
+
+int mnufft_correction_factors(int64_t N, int64_t n, int w, double beta, double *out)
+{
+    if (N < 1 || n < 2 * N || w < 2 || w > 16 || !(beta > 0.0) || !out) return MNUFFT_ERR_ARG;
+    std::vector<double> p;
+    correction(N, n, w, beta, p);
+    std::copy(p.begin(), p.end(), out);
+    return MNUFFT_OK;
+}
+
+int mnufft_makeplan(int type, int dim, const int64_t *nmodes, int iflag, int64_t ntransf,
+                    double eps, int prec, const mnufft_opts *opts, mnufft_plan *out)
+{
+    if (!out) return MNUFFT_ERR_ARG;
+    *out = nullptr;
+    // ---- validate everything before touching the device ----
+    if ((type != 1 && type != 2) || (dim != 2 && dim != 3) || !nmodes ||
+        (iflag != 1 && iflag != -1) || ntransf < 1 || !(eps > 0.0 && eps < 1.0) ||
+        (prec != MNUFFT_F32 && prec != MNUFFT_F64))
+        return MNUFFT_ERR_ARG;
+    mnufft_opts o;
+    mnufft_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.method < MNUFFT_METHOD_AUTO || o.method > MNUFFT_METHOD_SM || o.msub < 0 ||
+        o.device < -1)
+        return MNUFFT_ERR_ARG;
+    for (int i = 0; i < 8; ++i)
+        if (o.reserved[i]) return MNUFFT_ERR_ARG;
+    for (int d = 0; d < dim; ++d)
+        if (nmodes[d] < 1 || nmodes[d] > (1 << 24) || o.binsize[d] < 0) return MNUFFT_ERR_ARG;
+
+    int w = 0;
+    double beta = 0;
+    int64_t nf[3] = {1, 1, 1};
+    int warn = MNUFFT_OK;
+    for (int d = 0; d < dim; ++d) {
+        int rc = mnufft_choose_params(eps, prec, nmodes[d], &w, &beta, &nf[d]);
+        if (rc < 0) return rc;
+        if (rc > 0) warn = rc;
+    }
+    int64_t cells = 1;
+    for (int d = 0; d < dim; ++d) {
+        if (nf[d] > (int64_t)1 << 30) return MNUFFT_ERR_ARG;
+        cells *= nf[d];
+    }
+    if (cells > ((int64_t)1 << 40) / ntransf) return MNUFFT_ERR_ARG;
+
+    mnufft_plan p = new (std::nothrow) mnufft_plan_s();
+    if (!p) return MNUFFT_ERR_ALLOC;
+    p->type = type;
+    p->dim = dim;
+    p->prec = prec;
+    p->iflag = iflag;
+    p->ntransf = ntransf;
+    p->eps = eps;
+    p->rsz = prec == MNUFFT_F32 ? 4 : 8;
+    p->device = o.device;
+    p->validate = o.validate_pts;
+    p->stream = (hipStream_t)o.stream;
+    p->msub = o.msub > 0 ? o.msub : 1024;
+    mn::Geom &g = p->g;
+    g.dim = dim;
+    g.w = w;
+    g.beta = beta;
+    g.pad = (w + 1) / 2;
+    const int defm[2][3] = {{32, 32, 1}, {16, 16, 2}};
+    int64_t nbins = 1;
+    for (int d = 0; d < 3; ++d) {
+        p->N[d] = d < dim ? nmodes[d] : 1;
+        g.n[d] = d < dim ? (int)nf[d] : 1;
+        int m = d < dim ? (o.binsize[d] > 0 ? o.binsize[d] : defm[dim - 2][d]) : 1;
+        m = std::min(m, g.n[d]);
+        g.m[d] = m;
+        g.B[d] = (g.n[d] + m - 1) / m;
+        g.S[d] = (double)g.n[d] / (2.0 * kPi);
+        nbins *= g.B[d];
+    }
+    if (nbins > ((int64_t)1 << 30)) {
+        delete p;
+        return MNUFFT_ERR_ARG;
+    }
+    g.nbins = (int)nbins;
+    p->grid_elems = (size_t)cells;
+    const size_t lds = mn::sm_lds_bytes(g, prec, type == 2);
+    if (o.method == MNUFFT_METHOD_AUTO)
+        p->method = lds <= kLdsMax ? MNUFFT_METHOD_SM : MNUFFT_METHOD_GMSORT;
+    else
+        p->method = o.method;
+    if (p->method == MNUFFT_METHOD_SM && lds > kLdsMax) {
+        delete p;
+        return MNUFFT_ERR_ARG;
+    }
+
+    // ---- device state ----
+    std::call_once(g_fft_once, [] { g_fft_setup = rocfft_setup(); });
+    int rc = MNUFFT_OK;
+    if (g_fft_setup != rocfft_status_success) rc = MNUFFT_ERR_FFT;
+    if (!rc) rc = use_device(p);
+    if (!rc) rc = dalloc(p, &p->grid, (size_t)cells * 2 * p->rsz * ntransf);
+    for (int d = 0; d < 3 && !rc; ++d) {
+        std::vector<double> fac;
+        if (d < dim) correction(p->N[d], nf[d], w, beta, fac);
+        else fac.assign(1, 1.0);
+        rc = dalloc(p, &p->pfac[d], fac.size() * p->rsz);
+        if (rc) break;
+        if (prec == MNUFFT_F32) {
+            std::vector<float> ff(fac.begin(), fac.end());
+            if (hipMemcpy(p->pfac[d], ff.data(), ff.size() * 4, hipMemcpyHostToDevice))
+                rc = MNUFFT_ERR_HIP;
+        } else if (hipMemcpy(p->pfac[d], fac.data(), fac.size() * 8, hipMemcpyHostToDevice)) {
+            rc = MNUFFT_ERR_HIP;
+        }
+    }
+    if (!rc) rc = dalloc(p, (void **)&p->binstart, ((size_t)nbins + 1) * 4);
+    if (!rc) rc = dalloc(p, (void **)&p->subcount, ((size_t)nbins + 1) * 4);
+    if (!rc) rc = dalloc(p, (void **)&p->nsub, 16);
+    if (!rc) rc = dalloc(p, (void **)&p->flag, 16);
+    if (!rc && rocfft_execution_info_create(&p->fftinfo) != rocfft_status_success)
+        rc = MNUFFT_ERR_FFT;
+    if (!rc) rc = make_fft(p, iflag < 0 ? 0 : 1);
+    if (rc) {
+        mnufft_destroy(p);
+        return rc;
+    }
+    *out = p;
+    return warn;
+}
+
+int mnufft_setpts(mnufft_plan p, int64_t M, const void *x, const void *y, const void *z)
+{
+    if (!p || M < 0 || M > 2147483647LL) return MNUFFT_ERR_ARG;
+    if (M > 0 && (!x || !y)) return MNUFFT_ERR_ARG;
+    if (M > 0 && ((p->dim == 3) != (z != nullptr))) return MNUFFT_ERR_ARG;
+    int rc = use_device(p);
+    if (rc) return rc;
+    if (M > p->Mcap && (rc = alloc_points(p, M))) {
+        free_points(p);
+        p->M = -1;
+        return rc;
+    }
+    const mn::Geom &g = p->g;
+    hipStream_t s = p->stream;
+    p->M = -1;  // invalid until the whole setup has been enqueued
+    p->nsub_max = (int)(g.nbins + (M + p->msub - 1) / p->msub);
+    if (p->validate) MN_HIP(mn::launch_zero(p->flag, 16, s));
+    void *u_in[3] = {nullptr, nullptr, nullptr};
+    if (p->method == MNUFFT_METHOD_GM)
+        for (int d = 0; d < 3; ++d) u_in[d] = p->su_in[d];
+    MN_HIP(mn::launch_binkey(g, p->prec, (int)M, x, y, z, p->keyA, u_in, p->flag, s));
+    if (p->method == MNUFFT_METHOD_GM && M > 0)
+        MN_HIP(hipMemcpyAsync(p->key_in, p->keyA, (size_t)M * 4, hipMemcpyDeviceToDevice, s));
+    uint32_t *sk = nullptr, *sv = nullptr;
+    MN_HIP(mn::radix_sort((int)M, bits_for(g.nbins), p->keyA, p->valA, p->keyB, p->valB,
+                          p->hist, p->partials, &sk, &sv, s));
+    p->skey = sk;
+    p->perm = reinterpret_cast<int32_t *>(sv);
+    MN_HIP(mn::launch_binstart((int)M, g.nbins, p->skey, p->binstart, s));
+    MN_HIP(mn::launch_subproblems(g.nbins, p->msub, p->nsub_max, p->binstart, p->subcount,
+                                  p->partials, p->sub, p->nsub, s));
+    void *u[3] = {p->su[0], p->su[1], p->su[2]};
+    MN_HIP(mn::launch_gather_coords(g, p->prec, (int)M, x, y, z, p->perm, p->skey, u, s));
+    if (p->validate) {
+        int h = 0;
+        MN_HIP(hipMemcpyAsync(&h, p->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        MN_HIP(hipStreamSynchronize(s));
+        if (h) return MNUFFT_ERR_PTS;
+    }
+    p->M = M;
+    return MNUFFT_OK;
+}
+
+int mnufft_execute(mnufft_plan p, void *c, void *f)
+{
+    int rc = check_ready(p);
+    if (rc) return rc;
+    if (!f || (p->M > 0 && !c)) return MNUFFT_ERR_ARG;
+    if ((rc = use_device(p))) return rc;
+    return p->type == 1 ? exec_type1(p, p->iflag, c, f) : exec_type2(p, p->iflag, f, c);
+}
+
+int mnufft_execute_adjoint(mnufft_plan p, void *c, void *f)
+{
+    int rc = check_ready(p);
+    if (rc) return rc;
+    if (!f || (p->M > 0 && !c)) return MNUFFT_ERR_ARG;
+    if ((rc = use_device(p))) return rc;
+    return p->type == 1 ? exec_type2(p, -p->iflag, f, c) : exec_type1(p, -p->iflag, c, f);
+}
+
+int mnufft_spread(mnufft_plan p, const void *c, void *grid)
+{
+    int rc = check_ready(p);
+    if (rc) return rc;
+    if (!grid || (p->M > 0 && !c)) return MNUFFT_ERR_ARG;
+    if ((rc = use_device(p))) return rc;
+    MN_HIP(mn::launch_zero(grid, grid_bytes(p), p->stream));
+    MN_HIP(mn::launch_spread(p->g, p->prec, p->method, points_of(p), c, grid, p->stream));
+    return MNUFFT_OK;
+}
+
+int mnufft_interp(mnufft_plan p, const void *grid, void *c)
+{
+    int rc = check_ready(p);
+    if (rc) return rc;
+    if (!grid || (p->M > 0 && !c)) return MNUFFT_ERR_ARG;
+    if ((rc = use_device(p))) return rc;
+    MN_HIP(mn::launch_interp(p->g, p->prec, p->method, points_of(p), grid, c, p->stream));
+    return MNUFFT_OK;
+}
+
+int mnufft_get_sort(mnufft_plan p, int32_t *perm, int32_t *binstart)
+{
+    int rc = check_ready(p);
+    if (rc) return rc;
+    if ((rc = use_device(p))) return rc;
+    if (perm && p->M > 0)
+        MN_HIP(hipMemcpyAsync(perm, p->perm, (size_t)p->M * 4, hipMemcpyDeviceToDevice, p->stream));
+    if (binstart)
+        MN_HIP(hipMemcpyAsync(binstart, p->binstart, ((size_t)p->g.nbins + 1) * 4,
+                              hipMemcpyDeviceToDevice, p->stream));
+    return MNUFFT_OK;
+}
+
+int mnufft_get_subproblems(mnufft_plan p, int32_t *sub, int32_t *nsub)
+{
+    int rc = check_ready(p);
+    if (rc) return rc;
+    if ((rc = use_device(p))) return rc;
+    if (sub && p->nsub_max > 0)
+        MN_HIP(hipMemcpyAsync(sub, p->sub, (size_t)p->nsub_max * 16, hipMemcpyDeviceToDevice,
+                              p->stream));
+    if (nsub)
+        MN_HIP(hipMemcpyAsync(nsub, p->nsub, 4, hipMemcpyDeviceToDevice, p->stream));
+    return MNUFFT_OK;
+}
+
+int mnufft_get_info(mnufft_plan p, mnufft_info *info)
+{
+    if (!p || !info) return MNUFFT_ERR_ARG;
+    std::memset(info, 0, sizeof(*info));
+    info->type = p->type;
+    info->dim = p->dim;
+    info->prec = p->prec;
+    info->iflag = p->iflag;
+    for (int d = 0; d < 3; ++d) {
+        info->nmodes[d] = p->N[d];
+        info->nfine[d] = p->g.n[d];
+        info->binsize[d] = p->g.m[d];
+    }
+    info->ntransf = p->ntransf;
+    info->M = p->M;
+    info->w = p->g.w;
+    info->beta = p->g.beta;
+    info->method = p->method;
+    info->msub = p->msub;
+    info->nbins = p->g.nbins;
+    info->nsub_max = p->M >= 0 ? p->nsub_max : 0;
+    info->device_bytes = p->devbytes;
+    return MNUFFT_OK;
+}
+
+int mnufft_destroy(mnufft_plan p)
+{
+    if (!p) return MNUFFT_OK;
+    int rc = MNUFFT_OK;
+    if (p->device >= 0 && hipSetDevice(p->device) != hipSuccess) rc = MNUFFT_ERR_HIP;
+    if (hipStreamSynchronize(p->stream) != hipSuccess) rc = MNUFFT_ERR_HIP;
+    for (int k = 0; k < 2; ++k)
+        if (p->fft[k]) rocfft_plan_destroy(p->fft[k]);
+    if (p->fftinfo) rocfft_execution_info_destroy(p->fftinfo);
+    free_points(p);
+    dfree(p, &p->fftwork, p->fftwork_bytes);
+    dfree(p, &p->grid, p->grid_elems * 2 * p->rsz * p->ntransf);
+    for (int d = 0; d < 3; ++d) dfree(p, &p->pfac[d], 0);
+    dfree(p, (void **)&p->binstart, 0);
+    dfree(p, (void **)&p->subcount, 0);
+    dfree(p, (void **)&p->nsub, 0);
+    dfree(p, (void **)&p->flag, 0);
+    delete p;
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+"""ctypes binding of libmnufft (include/mnufft.h): argument marshalling only.
+
+Every step of the transform runs in the library's HIP kernels (the FFT in
+rocFFT).  PyTorch provides device memory and the stream; torch is imported
+before the library is loaded so that both share one HIP runtime.  There is
+no CPU fallback: if the library is missing, loading raises.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmnufft.so")
+
+OK = 0
+WARN_EPS_CLAMPED = 1
+ERR_ARG, ERR_ALLOC, ERR_HIP, ERR_FFT, ERR_STATE, ERR_PTS, ERR_UNSUPPORTED = -1, -2, -3, -4, -5, -6, -7
+F32, F64 = 0, 1
+METHOD_AUTO, METHOD_GM, METHOD_GMSORT, METHOD_SM = 0, 1, 2, 3
+METHODS = {"auto": METHOD_AUTO, "gm": METHOD_GM, "gmsort": METHOD_GMSORT, "sm": METHOD_SM}
+
+# Every symbol the public header declares.
+EXPORTS = (
+    "mnufft_default_opts", "mnufft_makeplan", "mnufft_setpts", "mnufft_execute",
+    "mnufft_execute_adjoint", "mnufft_spread", "mnufft_interp", "mnufft_get_sort",
+    "mnufft_get_subproblems", "mnufft_get_info", "mnufft_destroy", "mnufft_strerror",
+    "mnufft_choose_params", "mnufft_correction_factors",
+)
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("method", ctypes.c_int),
+        ("binsize", ctypes.c_int * 3),
+        ("msub", ctypes.c_int),
+        ("validate_pts", ctypes.c_int),
+        ("device", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+        ("reserved", ctypes.c_int * 8),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("type", ctypes.c_int), ("dim", ctypes.c_int), ("prec", ctypes.c_int),
+        ("iflag", ctypes.c_int),
+        ("nmodes", ctypes.c_int64 * 3), ("nfine", ctypes.c_int64 * 3),
+        ("ntransf", ctypes.c_int64), ("M", ctypes.c_int64),
+        ("w", ctypes.c_int), ("beta", ctypes.c_double),
+        ("method", ctypes.c_int), ("binsize", ctypes.c_int * 3), ("msub", ctypes.c_int),
+        ("nbins", ctypes.c_int64), ("nsub_max", ctypes.c_int64),
+        ("device_bytes", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if hasattr(v, "__len__") else v
+        return out
+
+
+class MnufftError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+
+
+_lib = None
+
+
+def load():
+    """Load libmnufft.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    L.mnufft_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    L.mnufft_makeplan.argtypes = [ci, ci, ctypes.POINTER(i64), ci, i64, ctypes.c_double, ci,
+                                  ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+    L.mnufft_setpts.argtypes = [vp, i64, vp, vp, vp]
+    L.mnufft_execute.argtypes = [vp, vp, vp]
+    L.mnufft_execute_adjoint.argtypes = [vp, vp, vp]
+    L.mnufft_spread.argtypes = [vp, vp, vp]
+    L.mnufft_interp.argtypes = [vp, vp, vp]
+    L.mnufft_get_sort.argtypes = [vp, vp, vp]
+    L.mnufft_get_subproblems.argtypes = [vp, vp, vp]
+    L.mnufft_get_info.argtypes = [vp, ctypes.POINTER(Info)]
+    L.mnufft_destroy.argtypes = [vp]
+    L.mnufft_strerror.argtypes = [ci]
+    L.mnufft_strerror.restype = ctypes.c_char_p
+    L.mnufft_choose_params.argtypes = [ctypes.c_double, ci, i64, ctypes.POINTER(ci),
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    L.mnufft_correction_factors.argtypes = [i64, i64, ci, ctypes.c_double,
+                                            ctypes.POINTER(ctypes.c_double)]
+    for name in EXPORTS:
+        getattr(L, name).restype = ctypes.c_char_p if name == "mnufft_strerror" else ci
+    _lib = L
+    return L
+
+
+def strerror(code):
+    try:
+        return load().mnufft_strerror(int(code)).decode()
+    except Exception:  # pragma: no cover
+        return "status %d" % code
+
+
+def check(code, what):
+    if code < 0:
+        raise MnufftError(code, what)
+    return code
+
+
+def default_opts():
+    o = Opts()
+    check(load().mnufft_default_opts(ctypes.byref(o)), "mnufft_default_opts")
+    return o
+
+
+def choose_params(eps, prec, N):
+    """(w, beta, n, status) as the library picks them for one dimension (host only)."""
+    w, beta, n = ctypes.c_int(), ctypes.c_double(), ctypes.c_int64()
+    rc = check(load().mnufft_choose_params(float(eps), int(prec), int(N), ctypes.byref(w),
+                                           ctypes.byref(beta), ctypes.byref(n)),
+               "mnufft_choose_params")
+    return w.value, beta.value, n.value, rc
+
+
+def correction_factors(N, n, w, beta):
+    """The library's per-dimension correction factors (host only), as a list."""
+    out = (ctypes.c_double * int(N))()
+    check(load().mnufft_correction_factors(int(N), int(n), int(w), float(beta), out),
+          "mnufft_correction_factors")
+    return list(out)

@@ -1,0 +1,218 @@
+"""Plan object over the C ABI: plan / set points / execute / destroy (Sec. I-A).
+
+Tensors are torch device tensors; their pointers and torch's current stream
+are handed to libmnufft.  This module only checks shapes and dtypes and
+allocates outputs; all computation happens in the library.
+"""
+import ctypes
+
+import torch
+
+from . import lib as L
+
+_REAL = {torch.complex64: torch.float32, torch.complex128: torch.float64}
+_PREC = {torch.complex64: L.F32, torch.complex128: L.F64}
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _need(t, dtype, device, what):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch.Tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what} must have dtype {dtype}, got {t.dtype}")
+    if t.device != device:
+        raise ValueError(f"{what} must be on {device}, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+
+
+class Plan:
+    """A 2D or 3D type 1 or type 2 NUFFT plan on one GPU.
+
+    nufft_type   1 (nonuniform -> modes) or 2 (modes -> nonuniform)
+    n_modes      (N1, N2) or (N1, N2, N3); arrays of modes have shape
+                 (..., N3, N2, N1), i.e. k1 fastest, modes ascending from -N/2
+    n_trans      number of vectors sharing one set of points
+    eps          requested relative l2 tolerance
+    isign        sign of the exponent; default -1 for type 1, +1 for type 2
+    dtype        torch.complex64 (fp32) or torch.complex128 (fp64)
+    method       "auto", "gm", "gmsort" or "sm"
+    binsize      bin extents m_i (None = library default), msub: points per subproblem
+    """
+
+    def __init__(self, nufft_type, n_modes, n_trans=1, eps=1e-6, isign=None,
+                 dtype=torch.complex64, method="auto", binsize=None, msub=0,
+                 device=None, validate_pts=False):
+        self._lib = L.load()
+        self._h = ctypes.c_void_p(0)
+        if dtype not in _PREC:
+            raise TypeError("dtype must be torch.complex64 or torch.complex128")
+        self.type = int(nufft_type)
+        self.n_modes = tuple(int(n) for n in n_modes)
+        self.dim = len(self.n_modes)
+        self.n_trans = int(n_trans)
+        self.eps = float(eps)
+        self.isign = int(isign if isign is not None else (-1 if self.type == 1 else 1))
+        self.dtype = dtype
+        self.rdtype = _REAL[dtype]
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        o = L.default_opts()
+        o.method = L.METHODS[method] if isinstance(method, str) else int(method)
+        if binsize is not None:
+            for d, m in enumerate(binsize):
+                o.binsize[d] = int(m)
+        o.msub = int(msub)
+        o.validate_pts = int(bool(validate_pts))
+        o.device = self.device.index if self.device.index is not None else -1
+        o.stream = torch.cuda.current_stream(self.device).cuda_stream
+        self._stream = torch.cuda.current_stream(self.device)
+        nm = (ctypes.c_int64 * 3)(*(list(self.n_modes) + [1] * (3 - self.dim)))
+        rc = self._lib.mnufft_makeplan(self.type, self.dim, nm, self.isign, self.n_trans,
+                                       self.eps, _PREC[dtype], ctypes.byref(o),
+                                       ctypes.byref(self._h))
+        L.check(rc, "mnufft_makeplan")
+        self.status = rc
+        self.M = None
+        self._pts = None
+
+    # -- lifetime ------------------------------------------------------------
+    def destroy(self):
+        if self._h and self._h.value:
+            L.check(self._lib.mnufft_destroy(self._h), "mnufft_destroy")
+        self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.destroy()
+
+    # -- info ----------------------------------------------------------------
+    def info(self):
+        inf = L.Info()
+        L.check(self._lib.mnufft_get_info(self._h, ctypes.byref(inf)), "mnufft_get_info")
+        return inf.as_dict()
+
+    @property
+    def fine_shape(self):
+        """Fine grid (n_d, ..., n_1) as a tensor shape (first coordinate fastest)."""
+        n = self.info()["nfine"][: self.dim]
+        return tuple(n[::-1])
+
+    @property
+    def mode_shape(self):
+        return tuple(self.n_modes[::-1])
+
+    # -- points --------------------------------------------------------------
+    def setpts(self, x, y, z=None):
+        M = x.shape[0]
+        for t, nm in ((x, "x"), (y, "y")) + (((z, "z"),) if self.dim == 3 else ()):
+            _need(t, self.rdtype, self.device, nm)
+            if t.ndim != 1 or t.shape[0] != M:
+                raise ValueError("x, y (, z) must be 1-D of equal length")
+        if self.dim == 2 and z is not None:
+            raise ValueError("z given for a 2D plan")
+        rc = self._lib.mnufft_setpts(self._h, M, _ptr(x), _ptr(y),
+                                     _ptr(z) if self.dim == 3 else None)
+        L.check(rc, "mnufft_setpts")
+        self.M = M
+        return self
+
+    # -- execution -------------------------------------------------------------
+    def _c_shape(self):
+        return (self.n_trans, self.M) if self.n_trans > 1 else (self.M,)
+
+    def _f_shape(self):
+        return ((self.n_trans,) if self.n_trans > 1 else ()) + self.mode_shape
+
+    def _run(self, fn, c_in, f_in, what):
+        if self.M is None:
+            raise RuntimeError("setpts must be called before execute")
+        if c_in is not None:
+            _need(c_in, self.dtype, self.device, "c")
+            if c_in.numel() != self.n_trans * self.M:
+                raise ValueError(f"c must hold {self.n_trans} x {self.M} values")
+            f = torch.empty(self._f_shape(), dtype=self.dtype, device=self.device)
+            L.check(fn(self._h, _ptr(c_in), _ptr(f)), what)
+            return f
+        _need(f_in, self.dtype, self.device, "f")
+        if f_in.numel() != self.n_trans * int(torch.tensor(self.n_modes).prod()):
+            raise ValueError(f"f must hold {self.n_trans} x {self.n_modes} values")
+        c = torch.empty(self._c_shape(), dtype=self.dtype, device=self.device)
+        L.check(fn(self._h, _ptr(c), _ptr(f_in)), what)
+        return c
+
+    def execute(self, data):
+        """Type 1: data = strengths c -> modes f.  Type 2: data = modes f -> values c."""
+        if self.type == 1:
+            return self._run(self._lib.mnufft_execute, data, None, "mnufft_execute")
+        return self._run(self._lib.mnufft_execute, None, data, "mnufft_execute")
+
+    def execute_adjoint(self, data):
+        """Adjoint operator on the same points (other type, opposite sign)."""
+        if self.type == 1:
+            return self._run(self._lib.mnufft_execute_adjoint, None, data, "mnufft_execute_adjoint")
+        return self._run(self._lib.mnufft_execute_adjoint, data, None, "mnufft_execute_adjoint")
+
+    def spread(self, c):
+        """Step 1 of type 1 alone for one vector c (M,) -> fine grid."""
+        _need(c, self.dtype, self.device, "c")
+        grid = torch.empty(self.fine_shape, dtype=self.dtype, device=self.device)
+        L.check(self._lib.mnufft_spread(self._h, _ptr(c), _ptr(grid)), "mnufft_spread")
+        return grid
+
+    def interp(self, grid):
+        """Step 3 of type 2 alone: fine grid -> values at the points (M,)."""
+        _need(grid, self.dtype, self.device, "grid")
+        if tuple(grid.shape) != self.fine_shape:
+            raise ValueError(f"grid must have shape {self.fine_shape}")
+        c = torch.empty((self.M,), dtype=self.dtype, device=self.device)
+        L.check(self._lib.mnufft_interp(self._h, _ptr(grid), _ptr(c)), "mnufft_interp")
+        return c
+
+    def get_sort(self):
+        """(perm, binstart) int32 device tensors from the last setpts."""
+        inf = self.info()
+        perm = torch.empty((max(self.M, 0),), dtype=torch.int32, device=self.device)
+        bs = torch.empty((inf["nbins"] + 1,), dtype=torch.int32, device=self.device)
+        L.check(self._lib.mnufft_get_sort(self._h, _ptr(perm), _ptr(bs)), "mnufft_get_sort")
+        return perm, bs
+
+    def get_subproblems(self):
+        """(records (nsub, 4) int32, nsub) from the last setpts."""
+        inf = self.info()
+        cap = max(int(inf["nsub_max"]), 1)
+        sub = torch.zeros((cap, 4), dtype=torch.int32, device=self.device)
+        n = torch.zeros((1,), dtype=torch.int32, device=self.device)
+        L.check(self._lib.mnufft_get_subproblems(self._h, _ptr(sub), _ptr(n)),
+                "mnufft_get_subproblems")
+        k = int(n.item())
+        return sub[:k], k
+
+
+def nufft_type1(points, c, n_modes, eps=1e-6, isign=-1, **kw):
+    """One-shot type 1: points = (x, y[, z]) real tensors, c complex (M,) or (T, M)."""
+    T = c.shape[0] if c.ndim == 2 else 1
+    with Plan(1, n_modes, T, eps, isign, dtype=c.dtype, **kw) as p:
+        p.setpts(*points)
+        return p.execute(c.contiguous())
+
+
+def nufft_type2(points, f, eps=1e-6, isign=+1, **kw):
+    """One-shot type 2: f complex (..., N2, N1) or with a leading transform axis."""
+    dim = len(points)
+    n_modes = tuple(f.shape[-dim:][::-1])
+    T = f.shape[0] if f.ndim == dim + 1 else 1
+    with Plan(2, n_modes, T, eps, isign, dtype=f.dtype, **kw) as p:
+        p.setpts(*points)
+        return p.execute(f.contiguous())

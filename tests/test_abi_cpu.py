@@ -1,0 +1,137 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads and
+exports every symbol the header declares, arguments are rejected before any
+device call, and the host math (parameters, correction factors) agrees with
+the oracle."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import params as oparams
+from paper_2102_08463_amd import lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "mnufft.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+char\s*\*\s*|int\s+)(mnufft_\w+)\s*\(", txt, re.M)))
+
+
+def test_exports_match_header():
+    lib = L.load()
+    names = _header_functions()
+    assert set(names) == set(L.EXPORTS), names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_struct_layouts():
+    # mnufft_opts: 7 ints + pointer + 8 reserved ints, natural alignment
+    assert ctypes.sizeof(L.Opts) == 72
+    assert L.Opts.stream.offset == 32
+
+
+def test_default_opts_and_strerror():
+    o = L.default_opts()
+    assert o.method == L.METHOD_AUTO and o.device == -1 and o.msub == 0
+    assert list(o.binsize) == [0, 0, 0] and not o.stream
+    assert L.load().mnufft_default_opts(None) == L.ERR_ARG
+    for code in (0, 1, -1, -2, -3, -4, -5, -6, -7, 99):
+        assert isinstance(L.strerror(code), str)
+
+
+def _makeplan(type_=1, dim=2, nm=(16, 16, 1), iflag=-1, ntr=1, eps=1e-6, prec=0, opts=None):
+    h = ctypes.c_void_p(0)
+    arr = (ctypes.c_int64 * 3)(*nm)
+    rc = L.load().mnufft_makeplan(type_, dim, arr, iflag, ntr, eps, prec,
+                                  ctypes.byref(opts) if opts is not None else None,
+                                  ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("kw", [
+    dict(type_=3), dict(type_=0), dict(dim=1), dict(dim=4), dict(iflag=0), dict(iflag=2),
+    dict(ntr=0), dict(eps=0.0), dict(eps=1.0), dict(eps=-1e-3), dict(eps=float("nan")),
+    dict(prec=2), dict(nm=(0, 16, 1)), dict(nm=(16, -1, 1)), dict(dim=3, nm=(8, 8, 0)),
+])
+def test_makeplan_rejects_bad_arguments(kw):
+    rc, h = _makeplan(**kw)
+    assert rc == L.ERR_ARG and not h.value
+
+
+def test_makeplan_rejects_bad_opts():
+    for field, val in (("method", 7), ("method", -1), ("msub", -5), ("device", -3)):
+        o = L.default_opts()
+        setattr(o, field, val)
+        rc, h = _makeplan(opts=o)
+        assert rc == L.ERR_ARG and not h.value, field
+    o = L.default_opts()
+    o.reserved[3] = 1
+    assert _makeplan(opts=o)[0] == L.ERR_ARG
+    o = L.default_opts()
+    o.binsize[1] = -2
+    assert _makeplan(opts=o)[0] == L.ERR_ARG
+    # an explicit SM request whose padded bin cannot fit in LDS
+    o = L.default_opts()
+    o.method = L.METHOD_SM
+    o.binsize[0], o.binsize[1], o.binsize[2] = 64, 64, 64
+    assert _makeplan(dim=3, nm=(64, 64, 64), prec=1, opts=o)[0] == L.ERR_ARG
+
+
+def test_null_plan_calls():
+    lib = L.load()
+    nul = ctypes.c_void_p(0)
+    assert lib.mnufft_setpts(nul, 10, None, None, None) == L.ERR_ARG
+    assert lib.mnufft_execute(nul, None, None) == L.ERR_ARG
+    assert lib.mnufft_execute_adjoint(nul, None, None) == L.ERR_ARG
+    assert lib.mnufft_spread(nul, None, None) == L.ERR_ARG
+    assert lib.mnufft_interp(nul, None, None) == L.ERR_ARG
+    assert lib.mnufft_get_sort(nul, None, None) == L.ERR_ARG
+    assert lib.mnufft_get_subproblems(nul, None, None) == L.ERR_ARG
+    assert lib.mnufft_get_info(nul, ctypes.byref(L.Info())) == L.ERR_ARG
+    assert lib.mnufft_destroy(nul) == L.OK
+    h = ctypes.c_void_p(0)
+    assert lib.mnufft_makeplan(1, 2, None, -1, 1, 1e-6, 0, None, ctypes.byref(h)) == L.ERR_ARG
+    arr = (ctypes.c_int64 * 3)(8, 8, 1)
+    assert lib.mnufft_makeplan(1, 2, arr, -1, 1, 1e-6, 0, None, None) == L.ERR_ARG
+
+
+@pytest.mark.parametrize("eps", [1e-1, 1e-2, 1e-5, 1e-6, 1e-7, 1e-9, 1e-12, 1e-15, 3e-4])
+@pytest.mark.parametrize("N", [1, 7, 41, 64, 333, 1024])
+def test_choose_params_match_oracle(eps, N):
+    w, beta, n, rc = L.choose_params(eps, L.F64, N)
+    assert w == oparams.kernel_width(eps)
+    assert math.isclose(beta, oparams.kernel_beta(w))
+    assert n == oparams.fine_grid_size(N, w)
+    assert rc == L.OK
+    w32, _, n32, rc32 = L.choose_params(eps, L.F32, N)
+    assert w32 == min(w, 8)
+    assert rc32 == (L.WARN_EPS_CLAMPED if w > 8 else L.OK)
+    assert n32 == oparams.fine_grid_size(N, w32)
+
+
+def test_choose_params_rejects():
+    for args in ((0.0, 0, 8), (1.0, 0, 8), (1e-3, 2, 8), (1e-3, 0, 0)):
+        with pytest.raises(L.MnufftError):
+            L.choose_params(*args)
+
+
+@pytest.mark.parametrize("w", [2, 3, 6, 7, 9, 13, 16])
+@pytest.mark.parametrize("N,n", [(64, 128), (41, 90), (333, 675), (1, 32)])
+def test_correction_factors_match_oracle(w, N, n):
+    """The library's tanh-sinh factors against the oracle's Gauss-Legendre ones."""
+    beta = oparams.kernel_beta(w)
+    got = np.array(L.correction_factors(N, n, w, beta))
+    ref = oparams.correction_factors(N, n, w, beta)
+    assert np.allclose(got, ref, rtol=1e-12, atol=0)
+
+
+def test_correction_factors_reject():
+    for args in ((0, 8, 6, 13.8), (8, 15, 6, 13.8), (8, 16, 1, 13.8), (8, 16, 17, 13.8),
+                 (8, 16, 6, 0.0)):
+        with pytest.raises(L.MnufftError):
+            L.correction_factors(*args)

@@ -1,0 +1,270 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bit-exact for the bin-sort permutation, bin starts and subproblem list;
+within 10 * eps relative l2 of the exact sums for the transforms; within
+rounding of the oracle's spreader / interpolator for the isolated steps.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import binsort, direct, nufft as onufft
+from tests.gpu_helpers import cdtype, make_complex, make_points, note, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan(*a, **kw):
+    from paper_2102_08463_amd import Plan
+    return Plan(*a, **kw)
+
+
+# ---------------------------------------------------------------------------
+# bin-sort: bit-exact
+SORT_CASES = [
+    # (dim, N, M, kind, prec, binsize, msub)
+    (2, (64, 64), 100_000, "uniform", "f32", None, 1024),
+    (2, (45, 61), 4097, "uniform", "f64", (8, 16), 100),       # odd n, ragged bins and tail
+    (2, (64, 64), 30_000, "cluster", "f32", None, 1024),        # heavy bin, many subproblems
+    (3, (32, 24, 20), 50_001, "uniform", "f32", None, 512),
+    (3, (16, 16, 16), 20_000, "gaussian", "f64", (4, 8, 2), 64),
+    (2, (16, 16), 1, "uniform", "f32", None, 1024),
+    (2, (300, 200), 70_000, "uniform", "f32", (4, 4), 1024),   # 2 radix passes (>256 bins)
+    (3, (128, 128, 128), 300_000, "uniform", "f32", (8, 8, 2), 1024),  # 3 passes (>65536 bins)
+]
+
+
+@pytest.mark.parametrize("case", SORT_CASES, ids=lambda c: f"{c[0]}d-{c[3]}-{c[2]}-{c[4]}")
+def test_sort_bit_exact(case):
+    import torch
+    dim, N, M, kind, prec, binsize, msub = case
+    note(f"sort {case}")
+    pts64, pts = make_points(kind, M, dim, prec, seed=3)
+    p = _plan(1, N, eps=1e-6, dtype=cdtype(prec), binsize=binsize, msub=msub)
+    p.setpts(*pts)
+    perm, bs = p.get_sort()
+    sub, nsub = p.get_subproblems()
+    torch.cuda.synchronize()
+    inf = p.info()
+    ns = inf["nfine"][:dim]
+    ms = inf["binsize"][:dim]
+    keys = binsort.bin_keys(pts64, ns, ms)
+    ref = binsort.permutation(keys)
+    assert np.array_equal(perm.cpu().numpy().astype(np.int64), ref)
+    assert np.array_equal(bs.cpu().numpy().astype(np.int64), binsort.bin_starts(keys, inf["nbins"]))
+    rs = binsort.subproblems(keys, inf["nbins"], msub)
+    assert nsub == len(rs)
+    assert np.array_equal(sub[:, :3].cpu().numpy().astype(np.int64), rs)
+    # repeat: identical result
+    p.setpts(*pts)
+    perm2, _ = p.get_sort()
+    assert torch.equal(perm, perm2)
+    p.destroy()
+
+
+def test_sort_fold_and_edges():
+    """Coordinates at +-pi, fp32 casts just outside the period and points in
+    [-3pi, 3pi) are binned exactly as the oracle folds them."""
+    import torch
+    note("sort fold edges")
+    R = np.random.default_rng(9)
+    base = R.uniform(-math.pi, math.pi, 5000)
+    x = np.concatenate([base + 2 * math.pi * R.integers(-1, 2, 5000),
+                        [math.pi, -math.pi, 3 * math.pi - 1e-6, -3 * math.pi + 1e-6, 0.0]])
+    y = np.concatenate([R.uniform(-math.pi, math.pi, 5000), [0.0, math.pi, -math.pi, 1.0, -1.0]])
+    for dt in (np.float32, np.float64):
+        xs, ys = x.astype(dt), y.astype(dt)
+        p = _plan(1, (40, 30), eps=1e-5, dtype=torch.complex64 if dt == np.float32 else torch.complex128)
+        p.setpts(torch.from_numpy(xs).cuda(), torch.from_numpy(ys).cuda())
+        perm, bs = p.get_sort()
+        inf = p.info()
+        keys = binsort.bin_keys((xs.astype(np.float64), ys.astype(np.float64)),
+                                inf["nfine"][:2], inf["binsize"][:2])
+        assert np.array_equal(perm.cpu().numpy(), binsort.permutation(keys))
+        p.destroy()
+
+
+# ---------------------------------------------------------------------------
+# isolated spreading / interpolation against the oracle's plain loops
+@pytest.mark.parametrize("method", ["gm", "gmsort", "sm"])
+@pytest.mark.parametrize("dim,prec,eps", [(2, "f32", 1e-5), (2, "f64", 1e-12), (3, "f32", 1e-5),
+                                          (3, "f64", 1e-9)])
+@pytest.mark.parametrize("kind", ["uniform", "cluster"])
+def test_spread_interp_steps(method, dim, prec, eps, kind):
+    import torch
+    note(f"spread/interp {method} {dim}d {prec} {eps} {kind}")
+    N = (48, 40) if dim == 2 else (20, 24, 18)
+    M = 20_000 if dim == 2 else 8_000
+    pts64, pts = make_points(kind, M, dim, prec, seed=4)
+    c64, c = make_complex(M, prec)
+    p = _plan(1, N, eps=eps, dtype=cdtype(prec), method=method, msub=300)
+    p.setpts(*pts)
+    inf = p.info()
+    ns, w, beta = inf["nfine"][:dim], inf["w"], inf["beta"]
+    grid = p.spread(c).cpu().numpy()
+    ref = direct.spread(pts64, c64, ns, w, beta)
+    tol = 2e-6 if prec == "f32" else 1e-13
+    assert rel_l2(grid, ref) <= tol
+    # interpolation from a random grid
+    g64, g = make_complex(tuple(ns[::-1]), prec, seed=5)
+    cc = p.interp(g).cpu().numpy()
+    refc = direct.interp(pts64, g64, w, beta)
+    assert rel_l2(cc, refc) <= tol
+    p.destroy()
+
+
+# ---------------------------------------------------------------------------
+# full transforms against the exact sums
+def _type1_check(pts64, pts, N, prec, eps, iflag=-1, method="auto", ntr=1, kk=None, **kw):
+    dim = len(N)
+    M = len(pts64[0])
+    c64, c = make_complex((ntr, M) if ntr > 1 else M, prec)
+    p = _plan(1, N, ntr, eps, iflag, dtype=cdtype(prec), method=method, **kw)
+    p.setpts(*pts)
+    f = p.execute(c).cpu().numpy()
+    p.destroy()
+    c64 = c64.reshape(ntr, M)
+    f = f.reshape((ntr,) + tuple(N[::-1]))
+    errs = []
+    for t in range(ntr):
+        if kk is None:
+            ref = direct.type1(pts64, c64[t], N, iflag=iflag)
+            got = f[t]
+        else:
+            ref = direct.type1(pts64, c64[t], N, iflag=iflag, kk=kk)
+            idx = [np.asarray(k) + n // 2 for k, n in zip(kk, N)]
+            got = f[t][np.ix_(*idx[::-1])]
+        errs.append(rel_l2(got, ref))
+    return max(errs)
+
+
+def _type2_check(pts64, pts, N, prec, eps, iflag=1, method="auto", ntr=1, idx=None, **kw):
+    M = len(pts64[0])
+    shape = ((ntr,) if ntr > 1 else ()) + tuple(N[::-1])
+    f64, f = make_complex(shape, prec, seed=2)
+    p = _plan(2, N, ntr, eps, iflag, dtype=cdtype(prec), method=method, **kw)
+    p.setpts(*pts)
+    c = p.execute(f).cpu().numpy().reshape(ntr, M)
+    p.destroy()
+    f64 = f64.reshape((ntr,) + tuple(N[::-1]))
+    errs = []
+    for t in range(ntr):
+        ref = direct.type2(pts64, f64[t], iflag=iflag, idx=idx)
+        got = c[t] if idx is None else c[t][idx]
+        errs.append(rel_l2(got, ref))
+    return max(errs)
+
+
+def test_config_small_2d_type1():
+    """2D type 1, 64x64 modes, M = 1e5 uniform, eps 1e-5, fp32; all modes checked
+    against the exact sum, and a separate transform of the first 2000 points."""
+    note("2d type1 64x64 M=1e5")
+    pts64, pts = make_points("uniform", 100_000, 2, "f32", seed=0)
+    assert _type1_check(pts64, pts, (64, 64), "f32", 1e-5) <= 1e-4
+    sub64 = tuple(a[:2000] for a in pts64)
+    subt = tuple(t[:2000].contiguous() for t in pts)
+    assert _type1_check(sub64, subt, (64, 64), "f32", 1e-5) <= 1e-4
+
+
+EPS_SWEEP = [("f32", e) for e in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6)] + \
+            [("f64", e) for e in (1e-7, 1e-8, 1e-9, 1e-10, 1e-11, 1e-12)]
+
+
+@pytest.mark.parametrize("prec,eps", EPS_SWEEP)
+@pytest.mark.parametrize("kind", ["uniform", "cluster"])
+def test_eps_sweep_2d(prec, eps, kind):
+    note(f"eps sweep 2d {prec} {eps} {kind}")
+    N = (96, 80)
+    pts64, pts = make_points(kind, 30_000, 2, prec, seed=1)
+    assert _type1_check(pts64, pts, N, prec, eps) <= 10 * eps
+    assert _type2_check(pts64, pts, N, prec, eps) <= 10 * eps
+
+
+@pytest.mark.parametrize("prec,eps", [("f32", 1e-2), ("f32", 1e-5), ("f64", 1e-9), ("f64", 1e-12)])
+@pytest.mark.parametrize("kind", ["uniform", "gaussian"])
+def test_eps_sweep_3d(prec, eps, kind):
+    note(f"eps sweep 3d {prec} {eps} {kind}")
+    N = (24, 20, 16)
+    pts64, pts = make_points(kind, 20_000, 3, prec, seed=2)
+    assert _type1_check(pts64, pts, N, prec, eps) <= 10 * eps
+    assert _type2_check(pts64, pts, N, prec, eps) <= 10 * eps
+
+
+@pytest.mark.parametrize("method", ["gm", "gmsort", "sm"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_methods_and_signs(method, dim):
+    note(f"methods {method} {dim}d")
+    N = (33, 40) if dim == 2 else (17, 12, 22)
+    pts64, pts = make_points("uniform", 12_345, dim, "f32", seed=6)
+    for iflag in (-1, 1):
+        assert _type1_check(pts64, pts, N, "f32", 1e-5, iflag=iflag, method=method) <= 1e-4
+        assert _type2_check(pts64, pts, N, "f32", 1e-5, iflag=iflag, method=method) <= 1e-4
+
+
+def test_many_transforms():
+    note("ntransf 3")
+    pts64, pts = make_points("uniform", 9_999, 2, "f32", seed=8)
+    assert _type1_check(pts64, pts, (30, 31), "f32", 1e-6, ntr=3) <= 1e-5
+    assert _type2_check(pts64, pts, (30, 31), "f32", 1e-6, ntr=3) <= 1e-5
+
+
+def test_odd_bins_and_tiny_grids():
+    note("tiny grids")
+    for N, bs in (((1, 1), None), ((2, 3), None), ((5, 7), (3, 2)), ((64, 64), (64, 64))):
+        pts64, pts = make_points("uniform", 777, 2, "f64", seed=10)
+        assert _type1_check(pts64, pts, N, "f64", 1e-9, binsize=bs) <= 1e-8
+        assert _type2_check(pts64, pts, N, "f64", 1e-9, binsize=bs) <= 1e-8
+
+
+def test_empty_points():
+    import torch
+    note("M=0")
+    p = _plan(1, (16, 16), eps=1e-5)
+    e = torch.empty(0, dtype=torch.float32, device="cuda")
+    p.setpts(e, e)
+    f = p.execute(torch.empty(0, dtype=torch.complex64, device="cuda"))
+    assert f.shape == (16, 16) and torch.count_nonzero(f).item() == 0
+    p.destroy()
+    q = _plan(2, (16, 16), eps=1e-5)
+    q.setpts(e, e)
+    c = q.execute(torch.ones((16, 16), dtype=torch.complex64, device="cuda"))
+    assert c.shape == (0,)
+    q.destroy()
+
+
+@pytest.mark.parametrize("dim,prec", [(2, "f32"), (3, "f64")])
+def test_adjoint_identity_gpu(dim, prec):
+    """<T1 c, f> = <c, T1^H f> with the adjoint on the same sorted points."""
+    import torch
+    note(f"adjoint {dim}d {prec}")
+    N = (40, 36) if dim == 2 else (16, 18, 12)
+    pts64, pts = make_points("uniform", 10_000, dim, prec, seed=12)
+    _, c = make_complex(10_000, prec)
+    _, f = make_complex(tuple(N[::-1]), prec, seed=13)
+    p = _plan(1, N, eps=1e-6 if prec == "f32" else 1e-12, dtype=cdtype(prec))
+    p.setpts(*pts)
+    lhs = torch.vdot(p.execute(c).flatten(), f.flatten()).item()
+    rhs = torch.vdot(c, p.execute_adjoint(f)).item()
+    tol = 1e-5 if prec == "f32" else 1e-12
+    assert abs(lhs - rhs) <= tol * abs(lhs)
+    p.destroy()
+
+
+def test_validate_pts():
+    import torch
+    from paper_2102_08463_amd import lib as L
+    note("validate_pts")
+    p = _plan(1, (16, 16), eps=1e-5, validate_pts=True)
+    x = torch.zeros(100, dtype=torch.float32, device="cuda")
+    p.setpts(x, x)
+    x[7] = float("nan")
+    with pytest.raises(L.MnufftError) as ei:
+        p.setpts(x, x.clone().zero_())
+    assert ei.value.code == L.ERR_PTS
+    x[7] = 20.0
+    with pytest.raises(L.MnufftError):
+        p.setpts(x, x.clone().zero_())
+    with pytest.raises(RuntimeError):
+        p.execute(torch.zeros(100, dtype=torch.complex64, device="cuda"))
+    p.destroy()
