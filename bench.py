@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Throughput of the NUFFT hot path on one MI355X, in nonuniform points per second.
+
+One step = the whole path over one batch of points: set the points (bin-sort),
+a type 1 transform (spread, FFT, deconvolve) and a type 2 transform
+(precorrect, FFT, interpolate) on the same sorted points; the type 2 is the
+adjoint of the type 1 plan (opposite sign), i.e. the paper's type 2 with sign
++1.  Each step therefore moves 2 M points through the method; value =
+2 M K / (time of K steps), inputs resident in HBM, plan creation excluded.
+
+The default workload is 2D with 1024 x 1024 modes, M = 1e7 points iid uniform
+in [-pi, pi)^2, complex64 strengths with N(0,1) parts, eps = 1e-5 (w = 6),
+single precision.  Other workloads (--workload) are for exploration.
+
+Prints one JSON line.  The per-stage HIP-event timers of the library give the
+dominant kernel's average launch time, from which the roofline fraction is
+computed against algorithmic bytes; the oracle is timed on a bounded sample
+of the same workload on the host's cores.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "NU points/sec at eps=1e-5 (2D/3D, type 1/2); batched vs plain speedup"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (dim, modes, M, point kind, eps, precision)
+    "2d": (2, (1024, 1024), 10_000_000, "uniform", 1e-5, "f32"),
+    "2d-cluster": (2, (1024, 1024), 10_000_000, "cluster", 1e-5, "f32"),
+    "2d-small": (2, (64, 64), 100_000, "uniform", 1e-5, "f32"),
+    "3d": (3, (128, 128, 128), 1 << 24, "uniform", 1e-5, "f32"),
+    "3d-gauss": (3, (128, 128, 128), 1 << 24, "gaussian", 1e-5, "f32"),
+}
+
+# Kernel sources whose change invalidates committed hardware-counter figures.
+KERNEL_SOURCES = ["paper_2102_08463_amd/csrc/spread_kernels.h"]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(stage, dim, M, ncells, rsz):
+    """Bytes one spread / interp launch must move at least: per point the
+    sorted coordinates (dim reals), the permutation entry (4 B) and the
+    strength or result (one complex); plus the fine grid once (one complex
+    per cell, written by spreading and read by interpolation)."""
+    per_pt = dim * rsz + 4 + 2 * rsz
+    return M * per_pt + ncells * 2 * rsz
+
+
+def load_traffic(kernel, workload):
+    """Counter-measured HBM bytes per launch from profiles/, if taken on the
+    current kernel source; None otherwise."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    e = d.get(f"{workload}:{kernel}")
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(pts64, c64, f64, modes, eps, sample):
+    """Time the oracle (plain FP64 three-step NUFFT: C/OpenMP spreading and
+    interpolation, scipy FFT) on the first `sample` points: one type 1 and
+    one type 2, like one GPU step."""
+    from oracle import direct, nufft as onufft
+    sub = tuple(a[:sample] for a in pts64)
+    t0 = time.perf_counter()
+    onufft.type1(sub, c64[:sample], modes, eps, iflag=-1)
+    onufft.type2(sub, f64, eps, iflag=+1)
+    dt = time.perf_counter() - t0
+    return {"value": 2 * sample / dt, "unit": "NU points/s", "cores": direct.num_threads(),
+            "kind": "oracle",
+            "sample": f"first {sample} of the same points, one type 1 + one type 2 "
+                      f"(same modes and eps), FP64, {dt:.2f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="2d", choices=sorted(WORKLOADS))
+    ap.add_argument("--method", default="auto")
+    ap.add_argument("--binsize", default=None, help="comma-separated bin extents")
+    ap.add_argument("--msub", type=int, default=0)
+    ap.add_argument("--cpu-sample", type=int, default=1_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the "
+              f"multi-GPU path is a design, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2102_08463_amd import Plan, lib
+
+    if not os.path.exists(lib.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+
+    dim, modes, M, kind, eps, prec = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    rdt = np.float32 if prec == "f32" else np.float64
+    cdt = torch.complex64 if prec == "f32" else torch.complex128
+    print(f"[bench] workload {args.workload}: dim={dim} modes={modes} M={M} {kind} "
+          f"eps={eps} {prec}", file=sys.stderr, flush=True)
+    pts_np = [np.asarray(a, dtype=rdt) for a in workloads.points(kind, M, dim, seed=0)]
+    c_np = workloads.strengths(M, seed=1).astype(np.complex64 if prec == "f32" else np.complex128)
+    f_np = workloads.strengths(tuple(modes[::-1]), seed=2).astype(c_np.dtype)
+    pts = [torch.from_numpy(a).to(dev) for a in pts_np]
+    c = torch.from_numpy(c_np).to(dev)
+    f = torch.from_numpy(f_np).to(dev)
+
+    binsize = tuple(int(v) for v in args.binsize.split(",")) if args.binsize else None
+    plan = Plan(1, modes, 1, eps, -1, dtype=cdt, method=args.method, binsize=binsize,
+                msub=args.msub, device=dev)
+    info = plan.info()
+
+    def step():
+        plan.setpts(*pts)
+        plan.execute(c)
+        plan.execute_adjoint(f)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.timing(reset=True)
+    plan.set_timing(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    stages = plan.timing(reset=True)
+    plan.set_timing(False)
+    K = args.steps
+    ms_per_step = total_ms / K
+    value = 2.0 * M * K / (total_ms * 1e-3)
+
+    rsz = 4 if prec == "f32" else 8
+    ncells = int(np.prod(info["nfine"][:dim]))
+    kern_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
+    dominant = max(("spread", "interp"), key=lambda k: stages[k][0])
+    algo = algorithmic_bytes(dominant, dim, M, ncells, rsz)
+    achieved = algo / (kern_ms[dominant] * 1e-3) / 1e9
+    kernel_name = {"spread": "k_spread_sm" if info["method"] == 3 else "k_spread_gm",
+                   "interp": "k_interp_sm" if info["method"] == 3 else "k_interp_gm"}[dominant]
+    traffic = load_traffic(kernel_name, args.workload)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "NU points/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic",
+        "config": {
+            "workload": f"{dim}D type 1 + type 2 per step (setpts, execute, adjoint), "
+                        f"modes {'x'.join(map(str, modes))}, M={M} {kind} points, "
+                        f"eps={eps:g}, {prec}",
+            "dim": dim, "modes": list(modes), "M": M, "points": kind, "eps": eps,
+            "w": info["w"], "fine_grid": info["nfine"][:dim], "method": info["method"],
+            "binsize": info["binsize"][:dim], "msub": info["msub"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": kernel_name,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": algo,
+            "avg_launch_ms": kern_ms[dominant],
+        },
+        "stage_ms_per_step": {k: v[0] / K for k, v in stages.items()},
+        "exec_pts_per_s": {
+            "type1": M / ((stages["zero"][0] + stages["scale"][0] + stages["spread"][0]
+                           + stages["addback"][0]
+                           + stages["deconv"][0] + stages["fft"][0] / 2) / K * 1e-3),
+            "type2": M / ((stages["precorrect"][0] + stages["interp"][0]
+                           + stages["fft"][0] / 2) / K * 1e-3),
+        },
+    }
+    if not args.no_cpu_baseline:
+        sample = min(args.cpu_sample, M)
+        print(f"[bench] timing the oracle on {sample} points", file=sys.stderr, flush=True)
+        pts64 = tuple(a.astype(np.float64) for a in pts_np)
+        out["cpu_baseline"] = cpu_baseline(pts64, c_np.astype(np.complex128),
+                                           f_np.astype(np.complex128), modes, eps, sample)
+    plan.destroy()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -143,6 +143,24 @@ int mnufft_execute(mnufft_plan p, void *c, void *f);
  * f is output.  Errors as mnufft_execute. */
 int mnufft_execute_adjoint(mnufft_plan p, void *c, void *f);
 
+/* Position gradient by ES-derivative interpolation (for the backward pass
+ * of a type 1 or type 2 transform).  Let v(x) be the type 2 sum of `modes`
+ * with the sign of the plan's type 2 direction (iflag for a type 2 plan,
+ * -iflag for a type 1 plan), computed by the plan's method on its points,
+ * i.e. precorrection, FFT and interpolation (Sec. II-B) with the kernel
+ * replaced by its derivative phi'(z) = -beta z (1 - z^2)^(-1/2) phi(z) in one
+ * dimension.  Then, for every point j and dimension i,
+ *   gx_i[j] = sum over transforms t of Re(conj(wts[t][j]) * d v_t(x_j) / dx_i).
+ * For a type 2 plan (c = A f): modes = f and wts = dL/dRe c + i dL/dIm c give
+ * dL/dx.  For a type 1 plan (f = A c): modes = dL/dRe f + i dL/dIm f and
+ * wts = c give dL/dx.
+ *   modes   ntransf x N1 N2 (N3) complex, k1 fastest
+ *   wts     ntransf x M complex, input point order
+ *   gx, gy, gz   M reals each (gz only in 3D), input order, overwritten
+ * Errors: ERR_STATE, ERR_ARG, ERR_HIP, ERR_FFT. */
+int mnufft_interp_grad(mnufft_plan p, const void *modes, const void *wts, void *gx, void *gy,
+                       void *gz);
+
 /* Step 1 of type 1 alone (Sec. II-A): grid = sum_j c_j psi_per(l h - pi - x_j)
  * for the first transform, with the plan's method.  grid is caller-owned,
  * n1 n2 (n3) complex, first coordinate fastest, overwritten.  Grid point l
@@ -173,6 +191,32 @@ int mnufft_get_info(mnufft_plan p, mnufft_info *info);
 /* Synchronise the plan's stream, free everything the plan owns and the plan
  * itself.  NULL is accepted and ignored.  Errors: ERR_HIP. */
 int mnufft_destroy(mnufft_plan p);
+
+/* Stage timers.  When enabled, the library brackets each stage it enqueues
+ * with a pair of HIP events on the plan's stream, so the figures are device
+ * durations of exactly that stage's kernels (one kernel launch per stage and
+ * transform for SPREAD, INTERP, DECONV and PRECORRECT; two for ADDBACK).  Reading them
+ * synchronises the stream. */
+#define MNUFFT_STAGE_SETPTS     0  /* the whole bin-sort of mnufft_setpts */
+#define MNUFFT_STAGE_ZERO       1  /* clearing the fine grid before spreading */
+#define MNUFFT_STAGE_SPREAD     2  /* type 1 step 1 (Sec. II-A); for SM the LDS tile kernel */
+#define MNUFFT_STAGE_FFT        3  /* rocFFT of the fine grid (either sign) */
+#define MNUFFT_STAGE_DECONV     4  /* type 1 step 3 (Sec. II-A) */
+#define MNUFFT_STAGE_PRECORRECT 5  /* type 2 step 1 (Sec. II-B) */
+#define MNUFFT_STAGE_INTERP     6  /* type 2 step 3 (Sec. II-B) */
+#define MNUFFT_STAGE_ADDBACK    7  /* SM only: adding the padded-bin tiles into the grid
+                                      (Sec. III-A, SM step 3) */
+#define MNUFFT_STAGE_SCALE      8  /* SM only: max |c| pre-pass fixing the fixed-point scale */
+#define MNUFFT_NSTAGES          9
+
+/* Turn the stage timers on (nonzero) or off.  Errors: ERR_ARG. */
+int mnufft_set_timing(mnufft_plan p, int enable);
+
+/* Sum of the recorded durations per stage in milliseconds (ms[MNUFFT_NSTAGES],
+ * host) and the number of recorded intervals (count[MNUFFT_NSTAGES], host,
+ * may be NULL) since the last reset; reset != 0 clears them afterwards.
+ * Synchronises the plan's stream.  Errors: ERR_ARG, ERR_HIP. */
+int mnufft_get_timing(mnufft_plan p, double *ms, int64_t *count, int reset);
 
 /* Host-only helpers (no device call; usable without a GPU). */
 

@@ -28,12 +28,16 @@ def _ki_weight(shape, axis_from_fastest):
     return k.reshape(sh)
 
 
-def type2_grads(pts, f, g, iflag=+1, idx=None):
-    """(grad_f, grad_x list) for c = type2(f) with upstream g (length M).
-    grad_x is evaluated at the indices idx (default all points)."""
+def type2_grad_f(pts, f_shape, g, iflag=+1):
+    """grad_f = A^H g for c = type2(f): the exact type 1 sum with sign -iflag."""
+    return direct.type1(pts, g, tuple(f_shape)[::-1], iflag=-iflag)
+
+
+def type2_grad_x(pts, f, g, iflag=+1, idx=None):
+    """grad_x for c = type2(f) with upstream g, at the indices idx (default all):
+    Re(conj(g_j) sum_k f_k (s i k_i) exp(s i k.x_j)) per dimension i."""
     dim = len(pts)
     f = np.asarray(f, dtype=np.complex128)
-    grad_f = direct.type1(pts, g, f.shape[::-1], iflag=-iflag)
     if idx is None:
         idx = np.arange(len(pts[0]))
     gx = []
@@ -41,7 +45,14 @@ def type2_grads(pts, f, g, iflag=+1, idx=None):
         fi = f * (iflag * 1j) * _ki_weight(f.shape, i)
         dc = direct.type2(pts, fi, iflag=iflag, idx=idx)
         gx.append(np.real(np.conj(np.asarray(g)[idx]) * dc))
-    return grad_f, gx
+    return gx
+
+
+def type2_grads(pts, f, g, iflag=+1, idx=None):
+    """(grad_f, grad_x list) for c = type2(f) with upstream g (length M).
+    grad_x is evaluated at the indices idx (default all points)."""
+    f = np.asarray(f, dtype=np.complex128)
+    return type2_grad_f(pts, f.shape, g, iflag), type2_grad_x(pts, f, g, iflag, idx)
 
 
 def type1_grads(pts, c, Ns, gf, iflag=-1, idx=None):

@@ -33,6 +33,17 @@ struct Pts {
     // unsorted (input order) copies for the GM method
     const void *u_in[3];
     const uint32_t *key_in;
+    // SM spreading: per-subproblem tile slots and their reduction
+    const int32_t *suboff;    // nbins + 1: first subproblem of each bin
+    void *scratch;            // nsub_max slots of ts2 reals
+    int ts2;                  // reals per slot (>= 2 * padded-bin cells, multiple of 8)
+    int G;                    // tiles merged per leader in heavily loaded bins
+    const int32_t *mergelist; // leaders (subproblem indices)
+    const int32_t *nmerge;    // device count of leaders
+    const int2 *cov[3];       // per-dimension cover tables (see k_tile_gather)
+    int kmax[3];
+    void *cmax;               // 1024 partial maxima of |Re c|, |Im c| of the vector being spread
+    int msub;                 // maximum points per subproblem
 };
 
 // ---- bin sort (kernels_sort.hip) ------------------------------------------
@@ -40,19 +51,29 @@ struct Pts {
 size_t radix_hist_elems(int M);
 size_t scan_partial_elems(size_t n);
 
-// key[j] and (optionally, for GM) u_in: bin index and bin-relative
-// coordinates of every point in input order; flag |= 1 if a coordinate is
-// non-finite or outside [-3pi, 3pi).
+// Planes of per-point reals carried along by a radix pass.
+struct Payload {
+    const void *in[3];
+    void *out[3];
+};
+
+// key[j] and u_in[d][j]: bin index and bin-relative coordinates of every
+// point in input order; flag |= 1 if a coordinate is non-finite or outside
+// [-3pi, 3pi).
 hipError_t launch_binkey(const Geom &g, int prec, int M, const void *x, const void *y,
                          const void *z, uint32_t *key, void *const u_in[3], int *flag,
                          hipStream_t s);
 
-// Stable LSD radix sort of (key, index) pairs on the low `bits` bits.
-// Returns in *keys_out / *vals_out the buffers (among the two ping-pong
-// pairs) that hold the sorted keys and the permutation.
-hipError_t radix_sort(int M, int bits, uint32_t *keysA, uint32_t *valsA, uint32_t *keysB,
-                      uint32_t *valsB, uint32_t *hist, uint32_t *partials,
-                      uint32_t **keys_out, uint32_t **vals_out, hipStream_t s);
+// Number of 8-bit passes for keys of `bits` bits (at least one).
+int radix_passes(int bits);
+
+// Stable LSD radix sort of (key, index) pairs on the low `bits` bits, with
+// dim payload planes of the plan precision; pass p reads pays[p].in and
+// writes pays[p].out.  Returns in *keys_out / *vals_out the buffers (among
+// the two ping-pong pairs) that hold the sorted keys and the permutation.
+hipError_t radix_sort(int M, int bits, int prec, int dim, uint32_t *keysA, uint32_t *valsA,
+                      uint32_t *keysB, uint32_t *valsB, const Payload *pays, uint32_t *hist,
+                      uint32_t *partials, uint32_t **keys_out, uint32_t **vals_out, hipStream_t s);
 
 // binstart[b] = first sorted position with key >= b, b = 0..nbins.
 hipError_t launch_binstart(int M, int nbins, const uint32_t *skey, int32_t *binstart,
@@ -63,24 +84,35 @@ hipError_t launch_subproblems(int nbins, int msub, int nsub_max, const int32_t *
                               int32_t *subcount, uint32_t *partials, int32_t *sub,
                               int32_t *nsub, hipStream_t s);
 
-// Sorted bin-relative coordinates: u[i] = g(x[perm[i]]) - binstart(key[i]).
-hipError_t launch_gather_coords(const Geom &g, int prec, int M, const void *x, const void *y,
-                                const void *z, const int32_t *perm, const uint32_t *skey,
-                                void *const u[3], hipStream_t s);
-
 // Exclusive prefix sum of n uint32 values (in and out may alias).
 hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, size_t n, uint32_t *partials,
                           hipStream_t s);
 
 // ---- spreading / interpolation (kernels_spread.hip) -----------------------
-// grid += spread of c (one vector) with the given method.
+// Spreading of c (one vector) with the given method.  part bit 0 runs the
+// accumulation (GM / GMSORT: atomics into a zeroed grid; SM: per-subproblem
+// tiles), bit 1 the SM add-back that writes every grid cell, bit 2 the SM
+// pre-pass computing partial maxima of |c| into P.cmax (zeroed before it).
 hipError_t launch_spread(const Geom &g, int prec, int method, const Pts &P, const void *c,
-                         void *grid, hipStream_t s);
+                         void *grid, hipStream_t s, int part = 7);
 // c = interpolation of grid (one vector) with the given method.
 hipError_t launch_interp(const Geom &g, int prec, int method, const Pts &P, const void *grid,
                          void *c, hipStream_t s);
-// Dynamic LDS bytes the SM kernels need for these bins, and whether it fits.
+// out_i[j] = sum_t Re(conj(wts[t][j]) d/dx_i (interpolation of grid t at x_j)),
+// for ntransf grids (one complex per cell each) and weights (ntransf x M,
+// input order); out planes are M reals in input order.
+hipError_t launch_interp_grad(const Geom &g, int prec, const Pts &P, int ntransf,
+                              const void *grid, const void *wts, void *const out[3],
+                              hipStream_t s);
+// Dynamic LDS bytes the SM kernels need for these bins.
 size_t sm_lds_bytes(const Geom &g, int prec, bool interp);
+// Reals per scratch tile slot of SM spreading.
+int sm_tile_stride(const Geom &g);
+// Leaders of tile groups to merge: subproblems q with (q - suboff[bin]) % G == 0
+// in bins with more than G subproblems (*nmerge must be zero on entry).
+hipError_t launch_merge_list(int nsub_max, const int32_t *nsub, const int32_t *sub,
+                             const int32_t *suboff, int G, int32_t *mergelist, int32_t *nmerge,
+                             hipStream_t s);
 
 // ---- correction (kernels_deconv.hip) --------------------------------------
 // f[t] = p1 p2 p3 * grid[t][k mod n] over the modes, for ntransf transforms.

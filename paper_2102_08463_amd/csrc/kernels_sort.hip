@@ -64,7 +64,7 @@ k_binkey(Geom g, int M, const T *__restrict__ x, const T *__restrict__ y,
         const int b = l / g.m[d];
         k += (uint32_t)b * stride;
         stride *= (uint32_t)g.B[d];
-        if (us[d]) us[d][j] = (T)(gc - (double)b * (double)g.m[d]);
+        us[d][j] = (T)(gc - (double)b * (double)g.m[d]);
     }
     key[j] = k;
     if (bad) atomicOr(flag, 1);
@@ -98,28 +98,44 @@ k_radix_hist(const uint32_t *__restrict__ keys, int M, int shift, int nblk,
     hist[(int64_t)tid * nblk + blockIdx.x] = h[tid];
 }
 
-// Stable scatter of one radix pass.  Wave w of a block owns keys
-// [blk*kTile + w*1024, +1024) and walks them in 16 rounds of 64 consecutive
-// keys, so ranks grow with the input index.
-__global__ void __launch_bounds__(kThreads)
+// Stable scatter of one radix pass over a tile of kTile keys, with kSThreads
+// threads: wave w owns keys [blk*kTile + w*kSItems*64, +kSItems*64) and walks
+// them in kSItems rounds of 64 consecutive keys, so ranks grow with the
+// input index.  The tile is first rearranged in LDS into digit order (key,
+// value and ND payload planes of T, the bin-relative coordinates), then each
+// digit's run is written to its global range with consecutive threads on
+// consecutive addresses.
+constexpr int kSThreads = 512;
+constexpr int kSWaves = kSThreads / 64;
+constexpr int kSItems = kTile / kSThreads;
+
+template <typename T, int ND>
+__global__ void __launch_bounds__(kSThreads)
 k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, int M,
                 int shift, int nblk, const uint32_t *__restrict__ offs,
-                uint32_t *__restrict__ kout, uint32_t *__restrict__ vout)
+                uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, Payload pl)
 {
-    constexpr int kWaves = kThreads / 64;
-    __shared__ uint32_t cnt[kWaves][256];
-    __shared__ uint32_t wbase[kWaves][256];
+    __shared__ uint32_t cnt[kSWaves][256];   // running per-wave digit counts, then prefixes
+    __shared__ uint32_t tstart[256];         // tile-local start of each digit run
+    __shared__ uint32_t gbase[256];          // global start of each digit run
+    extern __shared__ __align__(16) unsigned char stage_raw[];
+    uint32_t *skey = reinterpret_cast<uint32_t *>(stage_raw);
+    uint32_t *sval = skey + kTile;
+    T *spay = reinterpret_cast<T *>(sval + kTile);
+
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
-    for (int w = 0; w < kWaves; ++w) cnt[w][tid] = 0;
+    for (int e = tid; e < kSWaves * 256; e += kSThreads) (&cnt[0][0])[e] = 0;
     __syncthreads();
 
-    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)wave * (64 * kItems);
+    const int64_t tbase = (int64_t)blockIdx.x * kTile;
+    const int64_t base = tbase + (int64_t)wave * (64 * kSItems);
+    const int tcount = (int)std::min<int64_t>(kTile, (int64_t)M - tbase);
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint32_t kk[kItems], vv[kItems], rk[kItems];
+    uint32_t kk[kSItems], vv[kSItems], rk[kSItems];
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
+    for (int r = 0; r < kSItems; ++r) {
         const int64_t idx = base + r * 64 + lane;
         const bool valid = idx < M;
         const uint32_t key = valid ? kin[idx] : 0u;
@@ -143,24 +159,54 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
         rk[r] = old + rank;
     }
     __syncthreads();
-    {
-        const int d = tid;  // 256 threads, one digit each
-        uint32_t run = offs[(int64_t)d * nblk + blockIdx.x];
-        for (int w = 0; w < kWaves; ++w) {
-            wbase[w][d] = run;
-            run += cnt[w][d];
+    if (tid < 256) {
+        // per digit: prefix over waves, then an exclusive scan over digits
+        const int d = tid;
+        uint32_t run = 0;
+        for (int w = 0; w < kSWaves; ++w) {
+            const uint32_t c = cnt[w][d];
+            cnt[w][d] = run;
+            run += c;
         }
+        tstart[d] = run;  // digit total, scanned below
+        gbase[d] = offs[(int64_t)d * nblk + blockIdx.x];
     }
     __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        uint32_t v = 0;
+        if (tid < 256 && tid >= o) v = tstart[tid - o];
+        __syncthreads();
+        if (tid < 256) tstart[tid] += v;
+        __syncthreads();
+    }
+    // tstart[d] now holds the inclusive sum of the digit totals, so digit d's
+    // run in the tile starts at tstart[d - 1] (0 for d = 0).
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
+    for (int r = 0; r < kSItems; ++r) {
         const int64_t idx = base + r * 64 + lane;
         if (idx < M) {
             const uint32_t d = (kk[r] >> shift) & 255u;
-            const uint32_t pos = wbase[wave][d] + rk[r];
-            kout[pos] = kk[r];
-            vout[pos] = vv[r];
+            const uint32_t start = d == 0 ? 0u : tstart[d - 1];
+            const uint32_t lpos = start + cnt[wave][d] + rk[r];
+            if (lpos >= (uint32_t)kTile) continue;  // cannot happen when the counts agree
+            skey[lpos] = kk[r];
+            sval[lpos] = vv[r];
+#pragma unroll
+            for (int q = 0; q < ND; ++q)
+                spay[q * kTile + lpos] = static_cast<const T *>(pl.in[q])[idx];
         }
+    }
+    __syncthreads();
+    for (int e = tid; e < tcount; e += kSThreads) {
+        const uint32_t key = skey[e];
+        const uint32_t d = (key >> shift) & 255u;
+        const uint32_t start = d == 0 ? 0u : tstart[d - 1];
+        const uint32_t gpos = gbase[d] + (uint32_t)e - start;
+        if (gpos >= (uint32_t)M) continue;  // cannot happen when the counts agree
+        kout[gpos] = key;
+        vout[gpos] = sval[e];
+#pragma unroll
+        for (int q = 0; q < ND; ++q) static_cast<T *>(pl.out[q])[gpos] = spay[q * kTile + e];
     }
 }
 
@@ -313,30 +359,6 @@ __global__ void k_subfill(int nbins, int msub, int nsub_max, const int32_t *__re
     reinterpret_cast<int4 *>(sub)[q] = rec;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kThreads)
-k_gather_coords(Geom g, int M, const T *__restrict__ x, const T *__restrict__ y,
-                const T *__restrict__ z, const int32_t *__restrict__ perm,
-                const uint32_t *__restrict__ skey, T *__restrict__ u0, T *__restrict__ u1,
-                T *__restrict__ u2)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= M) return;
-    const int j = perm[i];
-    uint32_t k = skey[i];
-    int bad = 0;
-    const T *xs[3] = {x, y, z};
-    T *us[3] = {u0, u1, u2};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        if (d >= g.dim) break;
-        const int b = (int)(k % (uint32_t)g.B[d]);
-        k /= (uint32_t)g.B[d];
-        const double gc = grid_coord((double)xs[d][j], g.S[d], g.n[d], bad);
-        us[d][i] = (T)(gc - (double)b * (double)g.m[d]);
-    }
-}
-
 inline int nblocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
@@ -374,13 +396,15 @@ hipError_t launch_binkey(const Geom &g, int prec, int M, const void *x, const vo
     return hipGetLastError();
 }
 
-hipError_t radix_sort(int M, int bits, uint32_t *keysA, uint32_t *valsA, uint32_t *keysB,
-                      uint32_t *valsB, uint32_t *hist, uint32_t *partials,
-                      uint32_t **keys_out, uint32_t **vals_out, hipStream_t s)
+int radix_passes(int bits) { return std::max(1, (bits + 7) / 8); }
+
+hipError_t radix_sort(int M, int bits, int prec, int dim, uint32_t *keysA, uint32_t *valsA,
+                      uint32_t *keysB, uint32_t *valsB, const Payload *pays, uint32_t *hist,
+                      uint32_t *partials, uint32_t **keys_out, uint32_t **vals_out, hipStream_t s)
 {
     // Keys start in keysA with implicit values 0..M-1; each pass moves the
-    // pairs to the other buffer.
-    const int passes = std::max(1, (bits + 7) / 8);
+    // pairs to the other buffer.  Pass p moves the payload as pays[p] says.
+    const int passes = radix_passes(bits);
     const int nblk = std::max(1, nblocks(M, kTile));
     uint32_t *kb[2] = {keysA, keysB}, *vb[2] = {valsA, valsB};
     int cur = 0;
@@ -391,9 +415,23 @@ hipError_t radix_sort(int M, int bits, uint32_t *keysA, uint32_t *valsA, uint32_
                                (const uint32_t *)kb[cur], M, shift, nblk, hist);
             hipError_t e = scan_exclusive(hist, hist, (size_t)256 * nblk, partials, s);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kThreads), 0, s,
-                               (const uint32_t *)kb[cur], p == 0 ? nullptr : (const uint32_t *)vb[cur],
-                               M, shift, nblk, (const uint32_t *)hist, kb[1 - cur], vb[1 - cur]);
+            const uint32_t *vin = p == 0 ? nullptr : (const uint32_t *)vb[cur];
+#define MN_SCATTER(TT, DD)                                                                  \
+    do {                                                                                    \
+        const size_t lds = (size_t)kTile * (8 + DD * sizeof(TT));                           \
+        if (lds > 65536)                                                                    \
+            (void)hipFuncSetAttribute((const void *)k_radix_scatter<TT, DD>,                \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+        hipLaunchKernelGGL((k_radix_scatter<TT, DD>), dim3(nblk), dim3(kSThreads), lds, s,   \
+                           (const uint32_t *)kb[cur], vin, M, shift, nblk,                  \
+                           (const uint32_t *)hist, kb[1 - cur], vb[1 - cur], pays[p]);      \
+    } while (0)
+            if (prec == 0) {
+                if (dim == 2) MN_SCATTER(float, 2); else MN_SCATTER(float, 3);
+            } else {
+                if (dim == 2) MN_SCATTER(double, 2); else MN_SCATTER(double, 3);
+            }
+#undef MN_SCATTER
         }
         cur = 1 - cur;
     }
@@ -421,23 +459,6 @@ hipError_t launch_subproblems(int nbins, int msub, int nsub_max, const int32_t *
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_subfill, dim3(nblocks(std::max(nsub_max, 1), 256)), dim3(256), 0, s,
                        nbins, msub, nsub_max, binstart, (const uint32_t *)cnt, sub, nsub);
-    return hipGetLastError();
-}
-
-hipError_t launch_gather_coords(const Geom &g, int prec, int M, const void *x, const void *y,
-                                const void *z, const int32_t *perm, const uint32_t *skey,
-                                void *const u[3], hipStream_t s)
-{
-    if (M == 0) return hipSuccess;
-    const dim3 grid(nblocks(M, kThreads)), blk(kThreads);
-    if (prec == 0)
-        hipLaunchKernelGGL(k_gather_coords<float>, grid, blk, 0, s, g, M, (const float *)x,
-                           (const float *)y, (const float *)z, perm, skey, (float *)u[0],
-                           (float *)u[1], (float *)u[2]);
-    else
-        hipLaunchKernelGGL(k_gather_coords<double>, grid, blk, 0, s, g, M, (const double *)x,
-                           (const double *)y, (const double *)z, perm, skey, (double *)u[0],
-                           (double *)u[1], (double *)u[2]);
     return hipGetLastError();
 }
 

@@ -20,6 +20,7 @@ namespace {
 
 constexpr double kPi = 3.141592653589793;
 constexpr size_t kLdsMax = 160 * 1024;  // LDS per workgroup on gfx950
+constexpr int kMergeGroup = 32;         // tiles summed per leader in heavy bins
 
 // ---- parameter choice (Sec. II) -----------------------------------------
 
@@ -118,6 +119,7 @@ struct mnufft_plan_s {
     int64_t Mcap = -1;
     void *su[3] = {nullptr, nullptr, nullptr};
     void *su_in[3] = {nullptr, nullptr, nullptr};
+    void *su_tmp[3] = {nullptr, nullptr, nullptr};
     uint32_t *keyA = nullptr, *valA = nullptr, *keyB = nullptr, *valB = nullptr;
     uint32_t *key_in = nullptr;
     uint32_t *skey = nullptr;   // alias of keyA/keyB after the sort
@@ -127,12 +129,25 @@ struct mnufft_plan_s {
     uint32_t *hist = nullptr, *partials = nullptr;
     size_t hist_cap = 0, partials_cap = 0;
     int *flag = nullptr;
+    // SM spreading: tile slots, merge list and cover tables
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    int ts2 = 0;
+    int32_t *mergelist = nullptr, *nmerge = nullptr;
+    int2 *cov[3] = {nullptr, nullptr, nullptr};
+    void *cmax = nullptr;
+    size_t cov_bytes[3] = {0, 0, 0};
+    int kmax[3] = {1, 1, 1};
     // FFT
     rocfft_plan fft[2] = {nullptr, nullptr};  // [0]: exponent sign -1, [1]: +1
     rocfft_execution_info fftinfo = nullptr;
     void *fftwork = nullptr;
     size_t fftwork_bytes = 0;
     int64_t devbytes = 0;
+    // stage timers: per stage, event pairs recorded since the last reset
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[MNUFFT_NSTAGES];
+    size_t ev_used[MNUFFT_NSTAGES] = {};
 };
 
 namespace {
@@ -179,6 +194,7 @@ void free_points(mnufft_plan p)
     for (int d = 0; d < 3; ++d) {
         dfree(p, &p->su[d], M * p->rsz);
         dfree(p, &p->su_in[d], M * p->rsz);
+        dfree(p, &p->su_tmp[d], M * p->rsz);
     }
     dfree(p, (void **)&p->keyA, M * 4);
     dfree(p, (void **)&p->valA, M * 4);
@@ -188,6 +204,9 @@ void free_points(mnufft_plan p)
     dfree(p, (void **)&p->sub, (size_t)p->nsub_cap * 16);
     dfree(p, (void **)&p->hist, p->hist_cap * 4);
     dfree(p, (void **)&p->partials, p->partials_cap * 4);
+    dfree(p, &p->scratch, p->scratch_bytes);
+    dfree(p, (void **)&p->mergelist, (size_t)p->nsub_cap * 4);
+    p->scratch_bytes = 0;
     p->Mcap = -1;
     p->nsub_cap = 0;
     p->hist_cap = 0;
@@ -201,6 +220,7 @@ int alloc_points(mnufft_plan p, int64_t M)
     int rc;
     for (int d = 0; d < p->dim; ++d) {
         if ((rc = dalloc(p, &p->su[d], Ma * p->rsz))) return rc;
+        if ((rc = dalloc(p, &p->su_tmp[d], Ma * p->rsz))) return rc;
         if (p->method == MNUFFT_METHOD_GM && (rc = dalloc(p, &p->su_in[d], Ma * p->rsz))) return rc;
     }
     if ((rc = dalloc(p, (void **)&p->keyA, Ma * 4))) return rc;
@@ -210,6 +230,12 @@ int alloc_points(mnufft_plan p, int64_t M)
     if (p->method == MNUFFT_METHOD_GM && (rc = dalloc(p, (void **)&p->key_in, Ma * 4))) return rc;
     p->nsub_cap = (int)(p->g.nbins + (M + p->msub - 1) / p->msub);
     if ((rc = dalloc(p, (void **)&p->sub, (size_t)std::max(p->nsub_cap, 1) * 16))) return rc;
+    if (p->method == MNUFFT_METHOD_SM) {
+        p->scratch_bytes = (size_t)std::max(p->nsub_cap, 1) * p->ts2 * p->rsz;
+        if ((rc = dalloc(p, &p->scratch, p->scratch_bytes))) return rc;
+        if ((rc = dalloc(p, (void **)&p->mergelist, (size_t)std::max(p->nsub_cap, 1) * 4)))
+            return rc;
+    }
     p->hist_cap = mn::radix_hist_elems((int)M);
     if ((rc = dalloc(p, (void **)&p->hist, p->hist_cap * 4))) return rc;
     p->partials_cap = std::max(mn::scan_partial_elems(p->hist_cap),
@@ -264,6 +290,31 @@ int run_fft(mnufft_plan p, int sign)
     return MNUFFT_OK;
 }
 
+// Brackets one stage with events when the timers are on.
+struct StageTimer {
+    mnufft_plan p;
+    int stage;
+    bool on;
+    StageTimer(mnufft_plan pl, int st) : p(pl), stage(st), on(pl->timing)
+    {
+        if (!on) return;
+        auto &v = p->ev[stage];
+        if (p->ev_used[stage] == v.size()) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess) { on = false; return; }
+            if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); on = false; return; }
+            v.emplace_back(a, b);
+        }
+        (void)hipEventRecord(v[p->ev_used[stage]].first, p->stream);
+    }
+    ~StageTimer()
+    {
+        if (!on) return;
+        (void)hipEventRecord(p->ev[stage][p->ev_used[stage]].second, p->stream);
+        ++p->ev_used[stage];
+    }
+};
+
 mn::Pts points_of(mnufft_plan p)
 {
     mn::Pts P{};
@@ -279,6 +330,18 @@ mn::Pts points_of(mnufft_plan p)
     P.nsub = p->nsub;
     P.nsub_max = p->nsub_max;
     P.key_in = p->key_in;
+    P.suboff = p->subcount;
+    P.scratch = p->scratch;
+    P.ts2 = p->ts2;
+    P.G = kMergeGroup;
+    P.mergelist = p->mergelist;
+    P.nmerge = p->nmerge;
+    P.cmax = p->cmax;
+    P.msub = p->msub;
+    for (int d = 0; d < 3; ++d) {
+        P.cov[d] = p->cov[d];
+        P.kmax[d] = p->kmax[d];
+    }
     return P;
 }
 
@@ -288,14 +351,34 @@ size_t grid_bytes(mnufft_plan p) { return p->grid_elems * 2 * p->rsz; }
 int exec_type1(mnufft_plan p, int sign, const void *c, void *f)
 {
     const mn::Pts P = points_of(p);
-    MN_HIP(mn::launch_zero(p->grid, grid_bytes(p) * p->ntransf, p->stream));
+    if (p->method != MNUFFT_METHOD_SM) {  // SM writes every cell itself
+        StageTimer tm(p, MNUFFT_STAGE_ZERO);
+        MN_HIP(mn::launch_zero(p->grid, grid_bytes(p) * p->ntransf, p->stream));
+    }
     for (int64_t t = 0; t < p->ntransf; ++t) {
         const char *ct = (const char *)c + (size_t)t * p->M * 2 * p->rsz;
         char *gt = (char *)p->grid + (size_t)t * grid_bytes(p);
-        MN_HIP(mn::launch_spread(p->g, p->prec, p->method, P, ct, gt, p->stream));
+        if (p->method == MNUFFT_METHOD_SM) {
+            StageTimer tm(p, MNUFFT_STAGE_SCALE);
+            MN_HIP(mn::launch_zero(p->cmax, 1024 * 8, p->stream));
+            MN_HIP(mn::launch_spread(p->g, p->prec, p->method, P, ct, gt, p->stream, 4));
+        }
+        {
+            StageTimer tm(p, MNUFFT_STAGE_SPREAD);
+            MN_HIP(mn::launch_spread(p->g, p->prec, p->method, P, ct, gt, p->stream, 1));
+        }
+        if (p->method == MNUFFT_METHOD_SM) {
+            StageTimer tm(p, MNUFFT_STAGE_ADDBACK);
+            MN_HIP(mn::launch_spread(p->g, p->prec, p->method, P, ct, gt, p->stream, 2));
+        }
     }
-    int rc = run_fft(p, sign);
+    int rc;
+    {
+        StageTimer tm(p, MNUFFT_STAGE_FFT);
+        rc = run_fft(p, sign);
+    }
     if (rc) return rc;
+    StageTimer tm(p, MNUFFT_STAGE_DECONV);
     MN_HIP(mn::launch_deconv(p->dim, p->N, p->g.n, p->prec, (int)p->ntransf, p->grid,
                              p->pfac, f, p->stream));
     return MNUFFT_OK;
@@ -305,14 +388,92 @@ int exec_type1(mnufft_plan p, int sign, const void *c, void *f)
 int exec_type2(mnufft_plan p, int sign, const void *f, void *c)
 {
     const mn::Pts P = points_of(p);
-    MN_HIP(mn::launch_precorrect(p->dim, p->N, p->g.n, p->prec, (int)p->ntransf, f, p->pfac,
-                                 p->grid, p->stream));
-    int rc = run_fft(p, sign);
+    {
+        StageTimer tm(p, MNUFFT_STAGE_PRECORRECT);
+        MN_HIP(mn::launch_precorrect(p->dim, p->N, p->g.n, p->prec, (int)p->ntransf, f,
+                                     p->pfac, p->grid, p->stream));
+    }
+    int rc;
+    {
+        StageTimer tm(p, MNUFFT_STAGE_FFT);
+        rc = run_fft(p, sign);
+    }
     if (rc) return rc;
     for (int64_t t = 0; t < p->ntransf; ++t) {
         char *ct = (char *)c + (size_t)t * p->M * 2 * p->rsz;
         const char *gt = (const char *)p->grid + (size_t)t * grid_bytes(p);
+        StageTimer tm(p, MNUFFT_STAGE_INTERP);
         MN_HIP(mn::launch_interp(p->g, p->prec, p->method, P, gt, ct, p->stream));
+    }
+    return MNUFFT_OK;
+}
+
+// Per-dimension cover table of the SM add-back: for every grid index l, the
+// (bin, offset in its padded tile) pairs whose tile lands on l after periodic
+// wrapping; rows padded to the largest count with bin -1.
+int build_cover(mnufft_plan p, int d)
+{
+    const mn::Geom &g = p->g;
+    const int n = g.n[d], m = g.m[d], B = g.B[d], P = g.pad, pt = m + 2 * P;
+    std::vector<std::vector<int2>> lists((size_t)n);
+    for (int nb = 0; nb < B; ++nb)
+        for (int s = 0; s < pt; ++s) {
+            int l = (nb * m - P + s) % n;
+            if (l < 0) l += n;
+            lists[(size_t)l].push_back(make_int2(nb, s));
+        }
+    int km = 1;
+    for (auto &v : lists) km = std::max(km, (int)v.size());
+    std::vector<int2> tab((size_t)n * km, make_int2(-1, 0));
+    for (int l = 0; l < n; ++l)
+        for (size_t j = 0; j < lists[(size_t)l].size(); ++j) tab[(size_t)l * km + j] = lists[(size_t)l][j];
+    p->kmax[d] = km;
+    p->cov_bytes[d] = tab.size() * sizeof(int2);
+    int rc = dalloc(p, (void **)&p->cov[d], p->cov_bytes[d]);
+    if (rc) return rc;
+    if (hipMemcpy(p->cov[d], tab.data(), p->cov_bytes[d], hipMemcpyHostToDevice) != hipSuccess)
+        return MNUFFT_ERR_HIP;
+    return MNUFFT_OK;
+}
+
+// Bin-sort of Sec. III-A: keys, stable permutation, bin starts, subproblems
+// and the sorted bin-relative coordinates, all enqueued on the plan stream.
+int enqueue_setpts(mnufft_plan p, int64_t M, const void *x, const void *y, const void *z)
+{
+    const mn::Geom &g = p->g;
+    hipStream_t s = p->stream;
+    p->nsub_max = (int)(g.nbins + (M + p->msub - 1) / p->msub);
+    if (p->validate) MN_HIP(mn::launch_zero(p->flag, 16, s));
+    // The bin-relative coordinates ride along with the keys through the radix
+    // passes and must end in su.  Going backwards from the last pass the
+    // destinations alternate su, su_tmp, su, ...; binkey writes the start
+    // buffer (su_in for GM, which keeps an input-order copy).
+    const int passes = mn::radix_passes(bits_for(g.nbins));
+    std::vector<void *const *> bufs(passes + 1);
+    for (int k = 0; k <= passes; ++k) bufs[passes - k] = (k % 2 == 0) ? p->su : p->su_tmp;
+    if (p->method == MNUFFT_METHOD_GM) bufs[0] = p->su_in;
+    std::vector<mn::Payload> pays(passes);
+    for (int q = 0; q < passes; ++q)
+        for (int d = 0; d < 3; ++d) {
+            pays[q].in[d] = bufs[q][d];
+            pays[q].out[d] = bufs[q + 1][d];
+        }
+    void *u0[3] = {bufs[0][0], bufs[0][1], bufs[0][2]};
+    MN_HIP(mn::launch_binkey(g, p->prec, (int)M, x, y, z, p->keyA, u0, p->flag, s));
+    if (p->method == MNUFFT_METHOD_GM && M > 0)
+        MN_HIP(hipMemcpyAsync(p->key_in, p->keyA, (size_t)M * 4, hipMemcpyDeviceToDevice, s));
+    uint32_t *sk = nullptr, *sv = nullptr;
+    MN_HIP(mn::radix_sort((int)M, bits_for(g.nbins), p->prec, p->dim, p->keyA, p->valA, p->keyB,
+                          p->valB, pays.data(), p->hist, p->partials, &sk, &sv, s));
+    p->skey = sk;
+    p->perm = reinterpret_cast<int32_t *>(sv);
+    MN_HIP(mn::launch_binstart((int)M, g.nbins, p->skey, p->binstart, s));
+    MN_HIP(mn::launch_subproblems(g.nbins, p->msub, p->nsub_max, p->binstart, p->subcount,
+                                  p->partials, p->sub, p->nsub, s));
+    if (p->method == MNUFFT_METHOD_SM) {
+        MN_HIP(mn::launch_zero(p->nmerge, 4, s));
+        MN_HIP(mn::launch_merge_list(p->nsub_max, p->nsub, p->sub, p->subcount, kMergeGroup,
+                                     p->mergelist, p->nmerge, s));
     }
     return MNUFFT_OK;
 }
@@ -453,7 +614,8 @@ int mnufft_makeplan(int type, int dim, const int64_t *nmodes, int iflag, int64_t
     }
     g.nbins = (int)nbins;
     p->grid_elems = (size_t)cells;
-    const size_t lds = mn::sm_lds_bytes(g, prec, type == 2);
+    const size_t lds = std::max(mn::sm_lds_bytes(g, prec, false), mn::sm_lds_bytes(g, prec, true));
+    p->ts2 = mn::sm_tile_stride(g);
     if (o.method == MNUFFT_METHOD_AUTO)
         p->method = lds <= kLdsMax ? MNUFFT_METHOD_SM : MNUFFT_METHOD_GMSORT;
     else
@@ -487,6 +649,11 @@ int mnufft_makeplan(int type, int dim, const int64_t *nmodes, int iflag, int64_t
     if (!rc) rc = dalloc(p, (void **)&p->subcount, ((size_t)nbins + 1) * 4);
     if (!rc) rc = dalloc(p, (void **)&p->nsub, 16);
     if (!rc) rc = dalloc(p, (void **)&p->flag, 16);
+    if (!rc && p->method == MNUFFT_METHOD_SM) {
+        rc = dalloc(p, (void **)&p->nmerge, 16);
+        if (!rc) rc = dalloc(p, &p->cmax, 1024 * 8);  // partial maxima, see k_maxabs
+        for (int d = 0; d < dim && !rc; ++d) rc = build_cover(p, d);
+    }
     if (!rc && rocfft_execution_info_create(&p->fftinfo) != rocfft_status_success)
         rc = MNUFFT_ERR_FFT;
     if (!rc) rc = make_fft(p, iflag < 0 ? 0 : 1);
@@ -503,38 +670,23 @@ int mnufft_setpts(mnufft_plan p, int64_t M, const void *x, const void *y, const 
     if (!p || M < 0 || M > 2147483647LL) return MNUFFT_ERR_ARG;
     if (M > 0 && (!x || !y)) return MNUFFT_ERR_ARG;
     if (M > 0 && ((p->dim == 3) != (z != nullptr))) return MNUFFT_ERR_ARG;
+    if (p->g.nbins + (M + p->msub - 1) / p->msub > 2147483647LL) return MNUFFT_ERR_ARG;
     int rc = use_device(p);
     if (rc) return rc;
+    p->M = -1;  // invalid until the whole setup has been enqueued
     if (M > p->Mcap && (rc = alloc_points(p, M))) {
         free_points(p);
-        p->M = -1;
         return rc;
     }
-    const mn::Geom &g = p->g;
-    hipStream_t s = p->stream;
-    p->M = -1;  // invalid until the whole setup has been enqueued
-    p->nsub_max = (int)(g.nbins + (M + p->msub - 1) / p->msub);
-    if (p->validate) MN_HIP(mn::launch_zero(p->flag, 16, s));
-    void *u_in[3] = {nullptr, nullptr, nullptr};
-    if (p->method == MNUFFT_METHOD_GM)
-        for (int d = 0; d < 3; ++d) u_in[d] = p->su_in[d];
-    MN_HIP(mn::launch_binkey(g, p->prec, (int)M, x, y, z, p->keyA, u_in, p->flag, s));
-    if (p->method == MNUFFT_METHOD_GM && M > 0)
-        MN_HIP(hipMemcpyAsync(p->key_in, p->keyA, (size_t)M * 4, hipMemcpyDeviceToDevice, s));
-    uint32_t *sk = nullptr, *sv = nullptr;
-    MN_HIP(mn::radix_sort((int)M, bits_for(g.nbins), p->keyA, p->valA, p->keyB, p->valB,
-                          p->hist, p->partials, &sk, &sv, s));
-    p->skey = sk;
-    p->perm = reinterpret_cast<int32_t *>(sv);
-    MN_HIP(mn::launch_binstart((int)M, g.nbins, p->skey, p->binstart, s));
-    MN_HIP(mn::launch_subproblems(g.nbins, p->msub, p->nsub_max, p->binstart, p->subcount,
-                                  p->partials, p->sub, p->nsub, s));
-    void *u[3] = {p->su[0], p->su[1], p->su[2]};
-    MN_HIP(mn::launch_gather_coords(g, p->prec, (int)M, x, y, z, p->perm, p->skey, u, s));
+    {
+        StageTimer tm(p, MNUFFT_STAGE_SETPTS);
+        rc = enqueue_setpts(p, M, x, y, z);
+    }
+    if (rc) return rc;
     if (p->validate) {
         int h = 0;
-        MN_HIP(hipMemcpyAsync(&h, p->flag, sizeof(int), hipMemcpyDeviceToHost, s));
-        MN_HIP(hipStreamSynchronize(s));
+        MN_HIP(hipMemcpyAsync(&h, p->flag, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+        MN_HIP(hipStreamSynchronize(p->stream));
         if (h) return MNUFFT_ERR_PTS;
     }
     p->M = M;
@@ -565,7 +717,8 @@ int mnufft_spread(mnufft_plan p, const void *c, void *grid)
     if (rc) return rc;
     if (!grid || (p->M > 0 && !c)) return MNUFFT_ERR_ARG;
     if ((rc = use_device(p))) return rc;
-    MN_HIP(mn::launch_zero(grid, grid_bytes(p), p->stream));
+    if (p->method != MNUFFT_METHOD_SM) MN_HIP(mn::launch_zero(grid, grid_bytes(p), p->stream));
+    else MN_HIP(mn::launch_zero(p->cmax, 1024 * 8, p->stream));
     MN_HIP(mn::launch_spread(p->g, p->prec, p->method, points_of(p), c, grid, p->stream));
     return MNUFFT_OK;
 }
@@ -577,6 +730,25 @@ int mnufft_interp(mnufft_plan p, const void *grid, void *c)
     if (!grid || (p->M > 0 && !c)) return MNUFFT_ERR_ARG;
     if ((rc = use_device(p))) return rc;
     MN_HIP(mn::launch_interp(p->g, p->prec, p->method, points_of(p), grid, c, p->stream));
+    return MNUFFT_OK;
+}
+
+int mnufft_interp_grad(mnufft_plan p, const void *modes, const void *wts, void *gx, void *gy,
+                       void *gz)
+{
+    int rc = check_ready(p);
+    if (rc) return rc;
+    if (!modes || (p->M > 0 && (!wts || !gx || !gy || (p->dim == 3 && !gz))))
+        return MNUFFT_ERR_ARG;
+    if ((rc = use_device(p))) return rc;
+    // field = type 2 of `modes` with the sign of the plan's type 2 direction
+    const int sign = p->type == 2 ? p->iflag : -p->iflag;
+    MN_HIP(mn::launch_precorrect(p->dim, p->N, p->g.n, p->prec, (int)p->ntransf, modes,
+                                 p->pfac, p->grid, p->stream));
+    if ((rc = run_fft(p, sign))) return rc;
+    void *out[3] = {gx, gy, p->dim == 3 ? gz : nullptr};
+    MN_HIP(mn::launch_interp_grad(p->g, p->prec, points_of(p), (int)p->ntransf, p->grid, wts,
+                                  out, p->stream));
     return MNUFFT_OK;
 }
 
@@ -603,6 +775,33 @@ int mnufft_get_subproblems(mnufft_plan p, int32_t *sub, int32_t *nsub)
                               p->stream));
     if (nsub)
         MN_HIP(hipMemcpyAsync(nsub, p->nsub, 4, hipMemcpyDeviceToDevice, p->stream));
+    return MNUFFT_OK;
+}
+
+int mnufft_set_timing(mnufft_plan p, int enable)
+{
+    if (!p) return MNUFFT_ERR_ARG;
+    p->timing = enable != 0;
+    return MNUFFT_OK;
+}
+
+int mnufft_get_timing(mnufft_plan p, double *ms, int64_t *count, int reset)
+{
+    if (!p || !ms) return MNUFFT_ERR_ARG;
+    int rc = use_device(p);
+    if (rc) return rc;
+    MN_HIP(hipStreamSynchronize(p->stream));
+    for (int st = 0; st < MNUFFT_NSTAGES; ++st) {
+        double tot = 0.0;
+        for (size_t i = 0; i < p->ev_used[st]; ++i) {
+            float e = 0.f;
+            MN_HIP(hipEventElapsedTime(&e, p->ev[st][i].first, p->ev[st][i].second));
+            tot += e;
+        }
+        ms[st] = tot;
+        if (count) count[st] = (int64_t)p->ev_used[st];
+        if (reset) p->ev_used[st] = 0;
+    }
     return MNUFFT_OK;
 }
 
@@ -640,6 +839,11 @@ int mnufft_destroy(mnufft_plan p)
     for (int k = 0; k < 2; ++k)
         if (p->fft[k]) rocfft_plan_destroy(p->fft[k]);
     if (p->fftinfo) rocfft_execution_info_destroy(p->fftinfo);
+    for (int st = 0; st < MNUFFT_NSTAGES; ++st)
+        for (auto &e : p->ev[st]) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
     free_points(p);
     dfree(p, &p->fftwork, p->fftwork_bytes);
     dfree(p, &p->grid, p->grid_elems * 2 * p->rsz * p->ntransf);
@@ -648,6 +852,9 @@ int mnufft_destroy(mnufft_plan p)
     dfree(p, (void **)&p->subcount, 0);
     dfree(p, (void **)&p->nsub, 0);
     dfree(p, (void **)&p->flag, 0);
+    dfree(p, (void **)&p->nmerge, 0);
+    dfree(p, &p->cmax, 0);
+    for (int d = 0; d < 3; ++d) dfree(p, (void **)&p->cov[d], p->cov_bytes[d]);
     delete p;
     return rc;
 }

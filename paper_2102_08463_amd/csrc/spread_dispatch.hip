@@ -5,18 +5,18 @@ namespace mn {
 namespace detail {
 template <typename T, int DIM>
 hipError_t spread_dim(const Geom &g, int method, const Pts &P, const void *c, void *grid,
-                      hipStream_t s, size_t lds);
+                      hipStream_t s, size_t lds, int part);
 template <typename T, int DIM>
 hipError_t interp_dim(const Geom &g, int method, const Pts &P, const void *grid, void *c,
                       hipStream_t s, size_t lds);
 extern template hipError_t spread_dim<float, 2>(const Geom &, int, const Pts &, const void *,
-                                                void *, hipStream_t, size_t);
+                                                void *, hipStream_t, size_t, int);
 extern template hipError_t spread_dim<float, 3>(const Geom &, int, const Pts &, const void *,
-                                                void *, hipStream_t, size_t);
+                                                void *, hipStream_t, size_t, int);
 extern template hipError_t spread_dim<double, 2>(const Geom &, int, const Pts &, const void *,
-                                                 void *, hipStream_t, size_t);
+                                                 void *, hipStream_t, size_t, int);
 extern template hipError_t spread_dim<double, 3>(const Geom &, int, const Pts &, const void *,
-                                                 void *, hipStream_t, size_t);
+                                                 void *, hipStream_t, size_t, int);
 extern template hipError_t interp_dim<float, 2>(const Geom &, int, const Pts &, const void *,
                                                 void *, hipStream_t, size_t);
 extern template hipError_t interp_dim<float, 3>(const Geom &, int, const Pts &, const void *,
@@ -25,25 +25,88 @@ extern template hipError_t interp_dim<double, 2>(const Geom &, int, const Pts &,
                                                  void *, hipStream_t, size_t);
 extern template hipError_t interp_dim<double, 3>(const Geom &, int, const Pts &, const void *,
                                                  void *, hipStream_t, size_t);
+template <typename T, int DIM>
+hipError_t grad_dim(const Geom &g, const Pts &P, int ntransf, const void *grid, const void *wts,
+                    void *const out[3], hipStream_t s);
+extern template hipError_t grad_dim<float, 2>(const Geom &, const Pts &, int, const void *,
+                                              const void *, void *const[3], hipStream_t);
+extern template hipError_t grad_dim<float, 3>(const Geom &, const Pts &, int, const void *,
+                                              const void *, void *const[3], hipStream_t);
+extern template hipError_t grad_dim<double, 2>(const Geom &, const Pts &, int, const void *,
+                                               const void *, void *const[3], hipStream_t);
+extern template hipError_t grad_dim<double, 3>(const Geom &, const Pts &, int, const void *,
+                                               const void *, void *const[3], hipStream_t);
 }  // namespace detail
-size_t sm_lds_bytes(const Geom &g, int prec, bool /*interp*/)
+
+hipError_t launch_interp_grad(const Geom &g, int prec, const Pts &P, int ntransf,
+                              const void *grid, const void *wts, void *const out[3],
+                              hipStream_t s)
+{
+    if (P.M == 0) return hipSuccess;
+    if (prec == 0)
+        return g.dim == 2 ? detail::grad_dim<float, 2>(g, P, ntransf, grid, wts, out, s)
+                          : detail::grad_dim<float, 3>(g, P, ntransf, grid, wts, out, s);
+    return g.dim == 2 ? detail::grad_dim<double, 2>(g, P, ntransf, grid, wts, out, s)
+                      : detail::grad_dim<double, 3>(g, P, ntransf, grid, wts, out, s);
+}
+
+int sm_tile_stride(const Geom &g)
 {
     const int P = (g.w + 1) / 2;
     size_t cells = 1;
     for (int d = 0; d < g.dim; ++d) cells *= (size_t)(g.m[d] + 2 * P);
-    return cells * 2 * (prec == 0 ? sizeof(float) : sizeof(double));
+    return (int)((2 * cells + 7) / 8 * 8);
+}
+
+size_t sm_lds_bytes(const Geom &g, int prec, bool interp)
+{
+    const size_t rsz = prec == 0 ? sizeof(float) : sizeof(double);
+    if (!interp) return (size_t)sm_tile_stride(g) * 8;  // 64-bit fixed-point accumulators
+    const int P = (g.w + 1) / 2;
+    size_t cells = 1;
+    for (int d = 0; d < g.dim; ++d) cells *= (size_t)(g.m[d] + 2 * P);
+    return cells * 2 * rsz;
+}
+
+namespace {
+__global__ void k_merge_list(int nsub_max, const int32_t *__restrict__ nsubp,
+                             const int32_t *__restrict__ sub, const int32_t *__restrict__ suboff,
+                             int G, int32_t *__restrict__ mergelist, int32_t *__restrict__ nmerge)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nsub_max || q >= *nsubp) return;
+    const int b = reinterpret_cast<const int4 *>(sub)[q].x;
+    const int first = suboff[b], k = suboff[b + 1] - first;
+    if (k > G && (q - first) % G == 0) mergelist[atomicAdd(nmerge, 1)] = q;
+}
+}  // namespace
+
+hipError_t launch_merge_list(int nsub_max, const int32_t *nsub, const int32_t *sub,
+                             const int32_t *suboff, int G, int32_t *mergelist, int32_t *nmerge,
+                             hipStream_t s)
+{
+    if (nsub_max <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_merge_list, dim3((nsub_max + 255) / 256), dim3(256), 0, s, nsub_max,
+                       nsub, sub, suboff, G, mergelist, nmerge);
+    return hipGetLastError();
 }
 
 hipError_t launch_spread(const Geom &g, int prec, int method, const Pts &P, const void *c,
-                         void *grid, hipStream_t s)
+                         void *grid, hipStream_t s, int part)
 {
-    if (P.M == 0) return hipSuccess;
+    if (P.M == 0) {
+        // nothing to accumulate; the SM add-back alone owns writing the grid
+        if (method != 3 || !(part & 2)) return hipSuccess;
+        size_t cells = 1;
+        for (int d = 0; d < g.dim; ++d) cells *= (size_t)g.n[d];
+        return launch_zero(grid, cells * 2 * (prec == 0 ? sizeof(float) : sizeof(double)), s);
+    }
     const size_t lds = method == 3 ? sm_lds_bytes(g, prec, false) : 0;
     if (prec == 0)
-        return g.dim == 2 ? detail::spread_dim<float, 2>(g, method, P, c, grid, s, lds)
-                          : detail::spread_dim<float, 3>(g, method, P, c, grid, s, lds);
-    return g.dim == 2 ? detail::spread_dim<double, 2>(g, method, P, c, grid, s, lds)
-                      : detail::spread_dim<double, 3>(g, method, P, c, grid, s, lds);
+        return g.dim == 2 ? detail::spread_dim<float, 2>(g, method, P, c, grid, s, lds, part)
+                          : detail::spread_dim<float, 3>(g, method, P, c, grid, s, lds, part);
+    return g.dim == 2 ? detail::spread_dim<double, 2>(g, method, P, c, grid, s, lds, part)
+                      : detail::spread_dim<double, 3>(g, method, P, c, grid, s, lds, part);
 }
 
 hipError_t launch_interp(const Geom &g, int prec, int method, const Pts &P, const void *grid,

@@ -10,8 +10,10 @@
 namespace mn {
 namespace detail {
 template hipError_t spread_dim<MN_T, MN_D>(const Geom &, int, const Pts &, const void *, void *,
-                                          hipStream_t, size_t);
+                                          hipStream_t, size_t, int);
 template hipError_t interp_dim<MN_T, MN_D>(const Geom &, int, const Pts &, const void *, void *,
                                           hipStream_t, size_t);
+template hipError_t grad_dim<MN_T, MN_D>(const Geom &, const Pts &, int, const void *, const void *,
+                                        void *const[3], hipStream_t);
 }  // namespace detail
 }  // namespace mn

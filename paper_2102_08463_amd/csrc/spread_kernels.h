@@ -36,6 +36,19 @@ template <typename T> struct Cplx;
 template <> struct Cplx<float> { using type = float2; };
 template <> struct Cplx<double> { using type = double2; };
 
+// 16-byte vector of T, for tile copies.
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { using type = float4; };
+template <> struct Vec16<double> { using type = double2; };
+__device__ __forceinline__ void vadd(float4 &a, const float4 &b)
+{
+    a.x += b.x; a.y += b.y; a.z += b.z; a.w += b.w;
+}
+__device__ __forceinline__ void vadd(double2 &a, const double2 &b)
+{
+    a.x += b.x; a.y += b.y;
+}
+
 // Kernel value at z (|z| <= 1 up to rounding).  `bk` is beta*log2(e) in
 // single precision (the exponential is evaluated as a power of two) and
 // beta in double precision.
@@ -210,34 +223,110 @@ k_interp_gm(Geom g, int M, const uint32_t *__restrict__ key, const T *__restrict
     c[perm ? perm[i] : i] = out;
 }
 
+// Partial maxima of max(|Re c_j|, |Im c_j|) for the fixed-point scale of
+// k_spread_sm: block b writes out[b]; the consumer takes the max over the
+// kMaxParts entries (blocks beyond the launch leave theirs at zero).
+constexpr int kMaxParts = 1024;
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_maxabs(const typename Cplx<T>::type *__restrict__ c, int M, T *__restrict__ out)
+{
+    T m = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < M; i += gridDim.x * blockDim.x) {
+        const auto v = c[i];
+        m = fmax(m, fmax(fabs(v.x), fabs(v.y)));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    __shared__ T wm[kThreads / 64];
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < kThreads / 64; ++k) m = fmax(m, wm[k]);
+        out[blockIdx.x] = m;
+    }
+}
+
+// max over the kMaxParts partial maxima, by one workgroup.
+template <typename T>
+__device__ __forceinline__ T block_cmax(const T *__restrict__ parts)
+{
+    __shared__ T red[kThreads / 64];
+    T m = 0;
+    for (int k = threadIdx.x; k < kMaxParts; k += blockDim.x) m = fmax(m, parts[k]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    m = red[0];
+    for (int k = 1; k < kThreads / 64; ++k) m = fmax(m, red[k]);
+    __syncthreads();
+    return m;
+}
+
 // ----------------------------------------------------------------------------
-// SM spreading.  Grid-stride loop over the subproblem list; the padded bin
-// (p_i = m_i + 2 ceil(w/2), offset binstart - ceil(w/2)) lives in dynamic LDS
-// as interleaved (re, im).
+// SM spreading, step 2 of Sec. III-A: each subproblem accumulates its points
+// into an LDS copy of its padded bin (p_i = m_i + 2 ceil(w/2), offset
+// binstart - ceil(w/2)), then stores the tile to its own scratch slot.
+// Adding the tiles into the grid (SM step 3) is done without atomics by
+// k_tile_merge / k_tile_gather below.
+//
+// The LDS accumulator is 64-bit fixed point: on gfx950 integer LDS atomics
+// (ds_add_u64) sustain roughly ten times the rate of floating-point ones.
+// Every contribution v = c_j * phi * phi is turned into round(v * S) with
+// S = 2^k chosen from cmax = max_j max(|Re c_j|, |Im c_j|):
+//   single precision: S = 2^30 / 2^ceil(log2 cmax), so |v S| <= 2^30 fits an
+//     int32 and the 64-bit sum cannot overflow for fewer than 2^33
+//     contributions; the quantum cmax 2^-30 is below single-precision
+//     rounding of the values;
+//   double precision: S = 2^62 / (2^ceil(log2 msub) 2^ceil(log2 cmax)); a
+//     cell gets at most msub contributions of size <= cmax, so the sum stays
+//     below 2^62, with quantum about msub cmax 2^-62.
+// Grid-stride loop over the subproblem list; the tile is interleaved
+// (re, im) with ts2 >= 2 p1 p2 p3 entries per slot (a multiple of 8).
+template <typename T> struct FixedScale;
+template <> struct FixedScale<float> {
+    __device__ static float scale(float cmax, int /*lg_msub*/, float &inv)
+    {
+        int e;
+        frexpf(cmax, &e);  // cmax < 2^e (e = 0 for cmax = 0)
+        inv = ldexpf(1.0f, e - 30);
+        return ldexpf(1.0f, 30 - e);
+    }
+    __device__ static long long to_fixed(float v) { return (long long)__float2int_rn(v); }
+};
+template <> struct FixedScale<double> {
+    __device__ static double scale(double cmax, int lg_msub, double &inv)
+    {
+        int e;
+        frexp(cmax, &e);
+        inv = ldexp(1.0, e + lg_msub - 62);
+        return ldexp(1.0, 62 - lg_msub - e);
+    }
+    __device__ static long long to_fixed(double v) { return __double2ll_rn(v); }
+};
+
 template <typename T, int DIM, int W>
 __global__ void __launch_bounds__(kThreads)
 k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__ nsubp,
             const T *__restrict__ u0, const T *__restrict__ u1, const T *__restrict__ u2,
             const int32_t *__restrict__ perm, const typename Cplx<T>::type *__restrict__ c,
-            typename Cplx<T>::type *__restrict__ grid, T bk)
+            const T *__restrict__ cmaxp, int lg_msub, T *__restrict__ scratch, int ts2, T bk)
 {
+    using V = typename Vec16<T>::type;
+    constexpr int NV = 16 / sizeof(T);
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *tile = reinterpret_cast<T *>(smem_raw);
+    unsigned long long *tile = reinterpret_cast<unsigned long long *>(smem_raw);
     constexpr int P = (W + 1) / 2;
     const int p1 = g.m[0] + 2 * P, p2 = g.m[1] + 2 * P;
-    const int p3 = DIM == 3 ? g.m[2] + 2 * P : 1;
-    const int tsize = p1 * p2 * p3;
+    const int nvec = ts2 / NV;
     const int nsub = *nsubp;
+    T inv;
+    const T S = FixedScale<T>::scale(block_cmax(cmaxp), lg_msub, inv);
     for (int q = blockIdx.x; q < nsub; q += gridDim.x) {
         const int4 rec = reinterpret_cast<const int4 *>(sub)[q];
-        int b = rec.x;
-        const int bx = b % g.B[0]; b /= g.B[0];
-        const int by = b % g.B[1]; b /= g.B[1];
-        const int bz = b;
-        for (int e = threadIdx.x; e < tsize; e += blockDim.x) {
-            tile[2 * e] = 0;
-            tile[2 * e + 1] = 0;
-        }
+        for (int e = threadIdx.x; e < ts2; e += blockDim.x) tile[e] = 0ull;
         __syncthreads();
         const int end = rec.y + rec.z;
         for (int i = rec.y + threadIdx.x; i < end; i += blockDim.x) {
@@ -245,15 +334,18 @@ k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
             const int sx = taps<T, W>(u0[i] + (T)P, bk, kx);
             const int sy = taps<T, W>(u1[i] + (T)P, bk, ky);
             const auto cv = c[perm[i]];
+            const T cr0 = cv.x * S, ci0 = cv.y * S;
             if constexpr (DIM == 2) {
 #pragma unroll
                 for (int a2 = 0; a2 < W; ++a2) {
-                    const T wr = cv.x * ky[a2], wi = cv.y * ky[a2];
-                    T *row = tile + 2 * ((sy + a2) * p1 + sx);
+                    const T wr = cr0 * ky[a2], wi = ci0 * ky[a2];
+                    unsigned long long *row = tile + 2 * ((sy + a2) * p1 + sx);
 #pragma unroll
                     for (int a1 = 0; a1 < W; ++a1) {
-                        atomicAdd(row + 2 * a1, wr * kx[a1]);
-                        atomicAdd(row + 2 * a1 + 1, wi * kx[a1]);
+                        atomicAdd(row + 2 * a1,
+                                  (unsigned long long)FixedScale<T>::to_fixed(wr * kx[a1]));
+                        atomicAdd(row + 2 * a1 + 1,
+                                  (unsigned long long)FixedScale<T>::to_fixed(wi * kx[a1]));
                     }
                 }
             } else {
@@ -262,36 +354,116 @@ k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
 #pragma unroll 1
                 for (int a3 = 0; a3 < W; ++a3) {
                     const T kz = es_val(z0 + (T)a3 * (T)(2.0 / W), bk);
-                    const T cr = cv.x * kz, ci = cv.y * kz;
+                    const T cr = cr0 * kz, ci = ci0 * kz;
 #pragma unroll
                     for (int a2 = 0; a2 < W; ++a2) {
                         const T wr = cr * ky[a2], wi = ci * ky[a2];
-                        T *row = tile + 2 * (((sz + a3) * p2 + sy + a2) * p1 + sx);
+                        unsigned long long *row = tile + 2 * (((sz + a3) * p2 + sy + a2) * p1 + sx);
 #pragma unroll
                         for (int a1 = 0; a1 < W; ++a1) {
-                            atomicAdd(row + 2 * a1, wr * kx[a1]);
-                            atomicAdd(row + 2 * a1 + 1, wi * kx[a1]);
+                            atomicAdd(row + 2 * a1,
+                                      (unsigned long long)FixedScale<T>::to_fixed(wr * kx[a1]));
+                            atomicAdd(row + 2 * a1 + 1,
+                                      (unsigned long long)FixedScale<T>::to_fixed(wi * kx[a1]));
                         }
                     }
                 }
             }
         }
         __syncthreads();
-        const int o1 = bx * g.m[0] - P, o2 = by * g.m[1] - P, o3 = DIM == 3 ? bz * g.m[2] - P : 0;
-        for (int e = threadIdx.x; e < tsize; e += blockDim.x) {
-            const T re = tile[2 * e], im = tile[2 * e + 1];
-            if (re == (T)0 && im == (T)0) continue;
-            const int s1 = e % p1, r = e / p1;
-            const int s2 = r % p2, s3 = r / p2;
-            const int l1 = wrapmod(o1 + s1, g.n[0]);
-            const int l2 = wrapmod(o2 + s2, g.n[1]);
-            const int l3 = DIM == 3 ? wrapmod(o3 + s3, g.n[2]) : 0;
-            T *dst = reinterpret_cast<T *>(grid) +
-                     2 * (((size_t)l3 * g.n[1] + l2) * g.n[0] + l1);
-            gadd(dst, re);
-            gadd(dst + 1, im);
+        V *dst = reinterpret_cast<V *>(scratch + (size_t)q * ts2);
+        for (int e = threadIdx.x; e < nvec; e += blockDim.x) {
+            T vals[NV];
+#pragma unroll
+            for (int k = 0; k < NV; ++k)
+                vals[k] = (T)((double)(long long)tile[e * NV + k] * (double)inv);
+            V out;
+            __builtin_memcpy(&out, vals, sizeof(V));
+            dst[e] = out;
         }
         __syncthreads();
+    }
+}
+
+// Merge of the tiles of heavily loaded bins: for each leader q (every G-th
+// subproblem of a bin holding more than G of them), tiles q .. q+G-1 are
+// summed into tile q.  Work items are (leader, chunk of 256 vectors).
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_tile_merge(const int32_t *__restrict__ nmergep, const int32_t *__restrict__ mergelist,
+             const int32_t *__restrict__ sub, const int32_t *__restrict__ suboff,
+             T *__restrict__ scratch, int ts2, int G)
+{
+    using V = typename Vec16<T>::type;
+    constexpr int NV = 16 / sizeof(T);
+    const int nvec = ts2 / NV;
+    const int nchunk = (nvec + kThreads - 1) / kThreads;
+    const int total = *nmergep * nchunk;
+    for (int wi = blockIdx.x; wi < total; wi += gridDim.x) {
+        const int q0 = mergelist[wi / nchunk];
+        const int v = (wi % nchunk) * kThreads + threadIdx.x;
+        if (v >= nvec) continue;
+        const int b = reinterpret_cast<const int4 *>(sub)[q0].x;
+        const int last = suboff[b + 1];
+        const int cnt = min(G, last - q0);
+        V *base = reinterpret_cast<V *>(scratch);
+        V acc = base[(size_t)q0 * nvec + v];
+        for (int j = 1; j < cnt; ++j) vadd(acc, base[(size_t)(q0 + j) * nvec + v]);
+        base[(size_t)q0 * nvec + v] = acc;
+    }
+}
+
+// Each fine-grid cell is the sum of the tile cells that cover it (the wrapped
+// add-back of eq. addtoglobal, computed as a gather): per dimension, cov_i
+// lists for grid index l the pairs (bin index, offset in that bin's padded
+// tile) that land on l, up to kmax_i of them (unused entries have bin -1).
+// Bins with more than G tiles are read through their merged leaders.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kThreads)
+k_tile_gather(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__ scratch,
+              int ts2, int G, const int2 *__restrict__ cov0, const int2 *__restrict__ cov1,
+              const int2 *__restrict__ cov2, int k0, int k1, int k2, int P,
+              typename Cplx<T>::type *__restrict__ grid)
+{
+    const int p1 = g.m[0] + 2 * P, p2 = g.m[1] + 2 * P;
+    const size_t ncell = (size_t)g.n[0] * g.n[1] * (DIM == 3 ? g.n[2] : 1);
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < ncell;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int l1 = (int)(e % g.n[0]);
+        const size_t r = e / g.n[0];
+        const int l2 = (int)(r % g.n[1]);
+        const int l3 = DIM == 3 ? (int)(r / g.n[1]) : 0;
+        T ar = 0, ai = 0;
+        for (int j3 = 0; j3 < (DIM == 3 ? k2 : 1); ++j3) {
+            int nb3 = 0, s3 = 0;
+            if constexpr (DIM == 3) {
+                const int2 c3 = cov2[(size_t)l3 * k2 + j3];
+                if (c3.x < 0) break;
+                nb3 = c3.x;
+                s3 = c3.y;
+            }
+            for (int j2 = 0; j2 < k1; ++j2) {
+                const int2 c2 = cov1[(size_t)l2 * k1 + j2];
+                if (c2.x < 0) break;
+                for (int j1 = 0; j1 < k0; ++j1) {
+                    const int2 c1 = cov0[(size_t)l1 * k0 + j1];
+                    if (c1.x < 0) break;
+                    const int b = c1.x + g.B[0] * (c2.x + g.B[1] * nb3);
+                    const int first = suboff[b], k = suboff[b + 1] - first;
+                    const int step = k > G ? G : 1;
+                    const size_t off = 2 * ((size_t)c1.y + (size_t)p1 * (c2.y + (size_t)p2 * s3));
+                    for (int q = first; q < first + k; q += step) {
+                        const T *t = scratch + (size_t)q * ts2 + off;
+                        ar += t[0];
+                        ai += t[1];
+                    }
+                }
+            }
+        }
+        typename Cplx<T>::type out;
+        out.x = ar;
+        out.y = ai;
+        grid[e] = out;
     }
 }
 
@@ -392,21 +564,169 @@ template <> inline double kernel_param<double>(double beta) { return beta; }
 // Persistent grid size for the subproblem loops.
 inline int sm_grid(const Pts &P) { return std::max(1, std::min(P.nsub_max, 256 * 16)); }
 
+// part: bit 0 = accumulate (all methods), bit 1 = SM add-back (merge + gather).
+// ----------------------------------------------------------------------------
+// Position gradient by ES-derivative interpolation.  For a field b on the
+// fine grid and weights v_j (one complex per point), with
+//   c_j = sum_l b_l prod_i phi(z_i),  z_i = 2 (l_i - g_i) / w,  g_i = (x_i + pi) n_i / (2 pi),
+// the kernel returns out_i[j] = sum_t Re(conj(v_tj) dc_tj / dx_i) with
+//   dc_j / dx_i = -(n_i / (pi w)) sum_l b_l phi'(z_i) prod_{i' != i} phi(z_i'),
+//   phi'(z) = -beta z / sqrt(1 - z^2) phi(z)   (0 where 1 - z^2 <= 0).
+// Reads the grid straight from memory in bin-sorted order.
+template <typename T>
+__device__ __forceinline__ void es_val_der(T z, T bk, T beta, T &v, T &dv)
+{
+    const T t = (T)1 - z * z;
+    if (t <= (T)0) {
+        v = es_val(z, bk);
+        dv = 0;
+        return;
+    }
+    const T r = sqrt(t);
+    v = es_val(z, bk);
+    dv = -beta * z / r * v;
+}
+
+template <typename T, int W>
+__device__ __forceinline__ int taps_der(T u, T bk, T beta, T (&k)[W], T (&dk)[W])
+{
+    const T s = ceil(u - (T)(0.5 * W));
+    const T z0 = (s - u) * (T)(2.0 / W);
+#pragma unroll
+    for (int a = 0; a < W; ++a) es_val_der(z0 + (T)a * (T)(2.0 / W), bk, beta, k[a], dk[a]);
+    return (int)s;
+}
+
+template <typename T, int DIM, int W>
+__global__ void __launch_bounds__(kThreads)
+k_interp_grad(Geom g, int M, int ntransf, const uint32_t *__restrict__ key,
+              const T *__restrict__ u0, const T *__restrict__ u1, const T *__restrict__ u2,
+              const int32_t *__restrict__ perm, const typename Cplx<T>::type *__restrict__ grid,
+              const typename Cplx<T>::type *__restrict__ wts, T *__restrict__ o0,
+              T *__restrict__ o1, T *__restrict__ o2, T bk, T beta)
+{
+    using C = typename Cplx<T>::type;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    uint32_t b = key[i];
+    const int bx = b % g.B[0]; b /= g.B[0];
+    const int by = b % g.B[1]; b /= g.B[1];
+    const int bz = b;
+    T kx[W], ky[W], dkx[W], dky[W];
+    const int sx = taps_der<T, W>(u0[i], bk, beta, kx, dkx) + bx * g.m[0];
+    const int sy = taps_der<T, W>(u1[i], bk, beta, ky, dky) + by * g.m[1];
+    T kz[W], dkz[W];
+    int sz = 0;
+    if constexpr (DIM == 3) sz = taps_der<T, W>(u2[i], bk, beta, kz, dkz) + bz * g.m[2];
+    int lx[W];
+#pragma unroll
+    for (int a = 0; a < W; ++a) lx[a] = wrap1(sx + a, g.n[0]);
+    const size_t ncell = (size_t)g.n[0] * g.n[1] * (DIM == 3 ? g.n[2] : 1);
+    const int j = perm[i];
+    T acc[3] = {0, 0, 0};
+    for (int t = 0; t < ntransf; ++t) {
+        const C *gt = grid + (size_t)t * ncell;
+        // D_i = sum over taps of b * (derivative in dimension i) as complex
+        T dr[3] = {0, 0, 0}, di[3] = {0, 0, 0};
+        for (int a3 = 0; a3 < (DIM == 3 ? W : 1); ++a3) {
+            T wz = 1, dwz = 0;
+            size_t plane = 0;
+            if constexpr (DIM == 3) {
+                wz = kz[a3];
+                dwz = dkz[a3];
+                plane = (size_t)wrap1(sz + a3, g.n[2]) * g.n[1];
+            }
+#pragma unroll
+            for (int a2 = 0; a2 < W; ++a2) {
+                const C *row = gt + (plane + (size_t)wrap1(sy + a2, g.n[1])) * g.n[0];
+                T sr = 0, si = 0, xr = 0, xi = 0;  // sum b kx, sum b dkx along the row
+#pragma unroll
+                for (int a1 = 0; a1 < W; ++a1) {
+                    const C v = row[lx[a1]];
+                    sr += v.x * kx[a1];
+                    si += v.y * kx[a1];
+                    xr += v.x * dkx[a1];
+                    xi += v.y * dkx[a1];
+                }
+                dr[0] += xr * ky[a2] * wz;
+                di[0] += xi * ky[a2] * wz;
+                dr[1] += sr * dky[a2] * wz;
+                di[1] += si * dky[a2] * wz;
+                if constexpr (DIM == 3) {
+                    dr[2] += sr * ky[a2] * dwz;
+                    di[2] += si * ky[a2] * dwz;
+                }
+            }
+        }
+        const C v = wts[(size_t)t * M + j];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) acc[d] += v.x * dr[d] + v.y * di[d];  // Re(conj(v) D)
+    }
+    T *outs[3] = {o0, o1, o2};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) outs[d][j] = acc[d] * (-(T)g.n[d] / ((T)3.141592653589793 * (T)W));
+}
+
+template <typename T, int DIM, int W>
+hipError_t grad_w(const Geom &g, const Pts &P, int ntransf, const void *grid, const void *wts,
+                  void *const out[3], hipStream_t s)
+{
+    using C = typename Cplx<T>::type;
+    hipLaunchKernelGGL((k_interp_grad<T, DIM, W>), dim3(cdiv(P.M, kThreads)), dim3(kThreads), 0,
+                       s, g, P.M, ntransf, P.key, (const T *)P.u[0], (const T *)P.u[1],
+                       (const T *)P.u[2], P.perm, (const C *)grid, (const C *)wts, (T *)out[0],
+                       (T *)out[1], (T *)out[2], kernel_param<T>(g.beta), (T)g.beta);
+    return hipGetLastError();
+}
+
+template <typename T, int DIM>
+hipError_t grad_dim(const Geom &g, const Pts &P, int ntransf, const void *grid, const void *wts,
+                    void *const out[3], hipStream_t s)
+{
+    switch (g.w) {
+#define MN_CASE(WW) case WW: return grad_w<T, DIM, WW>(g, P, ntransf, grid, wts, out, s);
+        MN_CASE(2) MN_CASE(3) MN_CASE(4) MN_CASE(5) MN_CASE(6) MN_CASE(7) MN_CASE(8)
+        MN_CASE(9) MN_CASE(10) MN_CASE(11) MN_CASE(12) MN_CASE(13) MN_CASE(14)
+        MN_CASE(15) MN_CASE(16)
+#undef MN_CASE
+    }
+    return hipErrorInvalidValue;
+}
+
 template <typename T, int DIM, int W>
 hipError_t spread_w(const Geom &g, int method, const Pts &P, const void *c, void *grid,
-                    hipStream_t s, size_t lds)
+                    hipStream_t s, size_t lds, int part)
 {
     using C = typename Cplx<T>::type;
     const T bk = kernel_param<T>(g.beta);
     if (method == 3) {
         auto kern = k_spread_sm<T, DIM, W>;
-        if (lds > 65536)
-            (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds);
-        hipLaunchKernelGGL(kern, dim3(sm_grid(P)), dim3(kThreads), lds, s, g, P.sub, P.nsub,
-                           (const T *)P.u[0], (const T *)P.u[1], (const T *)P.u[2], P.perm,
-                           (const C *)c, (C *)grid, bk);
-    } else {
+        if (part & 4) {
+            hipLaunchKernelGGL(k_maxabs<T>, dim3(std::max(1, std::min(cdiv(P.M, kThreads), kMaxParts))),
+                               dim3(kThreads), 0, s, (const C *)c, P.M, (T *)P.cmax);
+        }
+        if (part & 1) {
+            if (lds > 65536)
+                (void)hipFuncSetAttribute((const void *)kern,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            int lg = 0;
+            while ((1 << lg) < P.msub) ++lg;
+            hipLaunchKernelGGL(kern, dim3(sm_grid(P)), dim3(kThreads), lds, s, g, P.sub, P.nsub,
+                               (const T *)P.u[0], (const T *)P.u[1], (const T *)P.u[2], P.perm,
+                               (const C *)c, (const T *)P.cmax, lg, (T *)P.scratch, P.ts2, bk);
+        }
+        if (!(part & 2)) return hipGetLastError();
+        const int nvec = P.ts2 / (16 / (int)sizeof(T));
+        const int nchunk = (nvec + kThreads - 1) / kThreads;
+        const int mgrid = std::max(1, std::min(P.nsub_max / std::max(P.G, 1) * nchunk + nchunk, 8192));
+        hipLaunchKernelGGL(k_tile_merge<T>, dim3(mgrid), dim3(kThreads), 0, s, P.nmerge,
+                           P.mergelist, P.sub, P.suboff, (T *)P.scratch, P.ts2, P.G);
+        const size_t ncell = (size_t)g.n[0] * g.n[1] * (DIM == 3 ? g.n[2] : 1);
+        const int ggrid = (int)std::min<size_t>((ncell + kThreads - 1) / kThreads, 16384);
+        hipLaunchKernelGGL((k_tile_gather<T, DIM>), dim3(ggrid), dim3(kThreads), 0, s, g,
+                           P.suboff, (const T *)P.scratch, P.ts2, P.G, P.cov[0], P.cov[1],
+                           P.cov[2], P.kmax[0], P.kmax[1], P.kmax[2], (W + 1) / 2, (C *)grid);
+    } else if (part & 1) {
         const bool gm = method == 1;
         hipLaunchKernelGGL((k_spread_gm<T, DIM, W>), dim3(cdiv(P.M, kThreads)), dim3(kThreads),
                            0, s, g, P.M, gm ? P.key_in : P.key,
@@ -446,10 +766,10 @@ hipError_t interp_w(const Geom &g, int method, const Pts &P, const void *grid, v
 
 template <typename T, int DIM>
 hipError_t spread_dim(const Geom &g, int method, const Pts &P, const void *c, void *grid,
-                      hipStream_t s, size_t lds)
+                      hipStream_t s, size_t lds, int part)
 {
     switch (g.w) {
-#define MN_CASE(WW) case WW: return spread_w<T, DIM, WW>(g, method, P, c, grid, s, lds);
+#define MN_CASE(WW) case WW: return spread_w<T, DIM, WW>(g, method, P, c, grid, s, lds, part);
         MN_CASE(2) MN_CASE(3) MN_CASE(4) MN_CASE(5) MN_CASE(6) MN_CASE(7) MN_CASE(8)
         MN_CASE(9) MN_CASE(10) MN_CASE(11) MN_CASE(12) MN_CASE(13) MN_CASE(14)
         MN_CASE(15) MN_CASE(16)

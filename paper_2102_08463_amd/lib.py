@@ -23,10 +23,14 @@ METHODS = {"auto": METHOD_AUTO, "gm": METHOD_GM, "gmsort": METHOD_GMSORT, "sm": 
 # Every symbol the public header declares.
 EXPORTS = (
     "mnufft_default_opts", "mnufft_makeplan", "mnufft_setpts", "mnufft_execute",
-    "mnufft_execute_adjoint", "mnufft_spread", "mnufft_interp", "mnufft_get_sort",
+    "mnufft_execute_adjoint", "mnufft_interp_grad", "mnufft_spread", "mnufft_interp",
+    "mnufft_get_sort",
     "mnufft_get_subproblems", "mnufft_get_info", "mnufft_destroy", "mnufft_strerror",
-    "mnufft_choose_params", "mnufft_correction_factors",
+    "mnufft_choose_params", "mnufft_correction_factors", "mnufft_set_timing", "mnufft_get_timing",
 )
+
+
+STAGES = ("setpts", "zero", "spread", "fft", "deconv", "precorrect", "interp", "addback", "scale")
 
 
 class Opts(ctypes.Structure):
@@ -85,6 +89,7 @@ def load():
     L.mnufft_setpts.argtypes = [vp, i64, vp, vp, vp]
     L.mnufft_execute.argtypes = [vp, vp, vp]
     L.mnufft_execute_adjoint.argtypes = [vp, vp, vp]
+    L.mnufft_interp_grad.argtypes = [vp, vp, vp, vp, vp, vp]
     L.mnufft_spread.argtypes = [vp, vp, vp]
     L.mnufft_interp.argtypes = [vp, vp, vp]
     L.mnufft_get_sort.argtypes = [vp, vp, vp]
@@ -97,6 +102,9 @@ def load():
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     L.mnufft_correction_factors.argtypes = [i64, i64, ci, ctypes.c_double,
                                             ctypes.POINTER(ctypes.c_double)]
+    L.mnufft_set_timing.argtypes = [vp, ci]
+    L.mnufft_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(i64), ci]
     for name in EXPORTS:
         getattr(L, name).restype = ctypes.c_char_p if name == "mnufft_strerror" else ci
     _lib = L

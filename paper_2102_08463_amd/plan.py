@@ -113,6 +113,18 @@ class Plan:
     def mode_shape(self):
         return tuple(self.n_modes[::-1])
 
+    def set_timing(self, enable=True):
+        """Turn the library's per-stage HIP-event timers on or off."""
+        L.check(self._lib.mnufft_set_timing(self._h, int(bool(enable))), "mnufft_set_timing")
+
+    def timing(self, reset=True):
+        """{stage: (total ms, intervals)} since the last reset (synchronises)."""
+        ms = (ctypes.c_double * len(L.STAGES))()
+        cnt = (ctypes.c_int64 * len(L.STAGES))()
+        L.check(self._lib.mnufft_get_timing(self._h, ms, cnt, int(bool(reset))),
+                "mnufft_get_timing")
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(L.STAGES)}
+
     # -- points --------------------------------------------------------------
     def setpts(self, x, y, z=None):
         M = x.shape[0]
@@ -163,6 +175,23 @@ class Plan:
         if self.type == 1:
             return self._run(self._lib.mnufft_execute_adjoint, None, data, "mnufft_execute_adjoint")
         return self._run(self._lib.mnufft_execute_adjoint, data, None, "mnufft_execute_adjoint")
+
+    def interp_grad(self, modes, wts):
+        """Position gradients: for each dimension i, the M reals
+        sum_t Re(conj(wts[t, j]) d v_t(x_j)/dx_i), v_t the type 2 sum of modes[t]
+        in the plan's type 2 direction.  Returns a tuple of dim tensors."""
+        _need(modes, self.dtype, self.device, "modes")
+        _need(wts, self.dtype, self.device, "wts")
+        if modes.numel() != self.n_trans * int(torch.tensor(self.n_modes).prod()):
+            raise ValueError("modes has the wrong size")
+        if wts.numel() != self.n_trans * self.M:
+            raise ValueError("wts has the wrong size")
+        outs = [torch.empty((self.M,), dtype=self.rdtype, device=self.device)
+                for _ in range(self.dim)]
+        ptrs = [_ptr(o) for o in outs] + [ctypes.c_void_p(0)] * (3 - self.dim)
+        L.check(self._lib.mnufft_interp_grad(self._h, _ptr(modes), _ptr(wts), *ptrs),
+                "mnufft_interp_grad")
+        return tuple(outs)
 
     def spread(self, c):
         """Step 1 of type 1 alone for one vector c (M,) -> fine grid."""

@@ -1,0 +1,120 @@
+"""Differentiation on the GPU against the oracle.
+
+The backward passes (adjoint transform for coefficients / strengths,
+ES-derivative interpolation for positions) are compared with the exact
+derivative of the direct sums (oracle.grad) and with FP64 central finite
+differences of the exact sums."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import direct, grad as ograd
+from tests.gpu_helpers import cdtype, make_complex, make_points, note, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dim,prec,eps", [(2, "f32", 1e-5), (3, "f32", 1e-5), (2, "f64", 1e-10),
+                                          (3, "f64", 1e-9)])
+@pytest.mark.parametrize("iflag", [-1, 1])
+def test_type2_grads_small(dim, prec, eps, iflag):
+    import torch
+    from paper_2102_08463_amd.autograd import nufft_type2
+    note(f"grad type2 {dim}d {prec} {eps} {iflag}")
+    N = (20, 16) if dim == 2 else (10, 12, 8)
+    M = 3000
+    pts64, pts = make_points("uniform", M, dim, prec, seed=21)
+    f64, f = make_complex(tuple(N[::-1]), prec, seed=22)
+    g64, g = make_complex(M, prec, seed=23)
+    xs = [p.clone().requires_grad_(True) for p in pts]
+    fr = f.clone().requires_grad_(True)
+    c = nufft_type2(xs, fr, eps=eps, isign=iflag)
+    loss = torch.real(torch.vdot(g, c))   # L = Re <g, c>, so dL/dc = g
+    loss.backward()
+    gf_ref, gx_ref = ograd.type2_grads(pts64, f64, g64, iflag=iflag)
+    # the coefficient gradient is a plain adjoint transform (error ~ eps); the
+    # position gradient differentiates the interpolant, whose relative error
+    # grows by the kernel-derivative factor (a few w), so it gets more room
+    tol_f = 30 * eps if prec == "f32" else 100 * eps
+    tol_x = 1e-3 if prec == "f32" else 1000 * eps
+    assert rel_l2(fr.grad.cpu().numpy(), gf_ref) <= tol_f
+    for i in range(dim):
+        assert rel_l2(xs[i].grad.cpu().numpy(), gx_ref[i]) <= tol_x
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("iflag", [-1, 1])
+def test_type1_grads_small(dim, iflag):
+    import torch
+    from paper_2102_08463_amd.autograd import nufft_type1
+    note(f"grad type1 {dim}d {iflag}")
+    N = (18, 14) if dim == 2 else (8, 10, 6)
+    M = 2500
+    pts64, pts = make_points("uniform", M, dim, "f64", seed=31)
+    c64, c = make_complex(M, "f64", seed=32)
+    gm64, gm = make_complex(tuple(N[::-1]), "f64", seed=33)
+    xs = [p.clone().requires_grad_(True) for p in pts]
+    cr = c.clone().requires_grad_(True)
+    fk = nufft_type1(xs, cr, N, eps=1e-11, isign=iflag)
+    loss = torch.real(torch.vdot(gm.flatten(), fk.flatten()))
+    loss.backward()
+    gc_ref, gx_ref = ograd.type1_grads(pts64, c64, N, gm64, iflag=iflag)
+    assert rel_l2(cr.grad.cpu().numpy(), gc_ref) <= 1e-9
+    for i in range(dim):
+        assert rel_l2(xs[i].grad.cpu().numpy(), gx_ref[i]) <= 1e-8
+
+
+def test_gradcheck_fp64_tiny():
+    """torch's own finite-difference gradcheck in FP64 on a tiny type 2."""
+    import torch
+    from paper_2102_08463_amd.autograd import nufft_type2
+    note("gradcheck tiny")
+    R = np.random.default_rng(41)
+    x = torch.tensor(R.uniform(-3, 3, 15), dtype=torch.float64, device="cuda", requires_grad=True)
+    y = torch.tensor(R.uniform(-3, 3, 15), dtype=torch.float64, device="cuda", requires_grad=True)
+    f = torch.tensor(R.standard_normal((6, 5)) + 1j * R.standard_normal((6, 5)),
+                     dtype=torch.complex128, device="cuda", requires_grad=True)
+    fn = lambda xx, yy, ff: nufft_type2((xx, yy), ff, eps=1e-13)
+    assert torch.autograd.gradcheck(fn, (x, y, f), eps=1e-6, atol=1e-6, rtol=1e-5)
+
+
+def test_diff_3d_spiral_64cubed():
+    """Differentiable 3D type 2, 64^3 complex64 modes, M = 4e6 points on a stack
+    of spirals with N(0, 1e-3) jitter, eps 1e-5, fp32: gradients w.r.t. modes
+    (100 modes) and positions (100 points) against the exact derivative and
+    FP64 central differences of the exact sum, relative error 1e-3."""
+    import torch
+    from paper_2102_08463_amd.autograd import nufft_type2
+    note("grad 3d spiral 64^3 M=4e6")
+    N = (64, 64, 64)
+    M = 4_000_000
+    pts64, pts = make_points("spiral_stack", M, 3, "f32", seed=0)
+    M = len(pts64[0])
+    f64, f = make_complex(tuple(N[::-1]), "f32", seed=2)
+    g64, g = make_complex(M, "f32", seed=3)
+    xs = [p.clone().requires_grad_(True) for p in pts]
+    fr = f.clone().requires_grad_(True)
+    c = nufft_type2(xs, fr, eps=1e-5, isign=+1)
+    torch.real(torch.vdot(g, c)).backward()
+    rng = np.random.default_rng(51)
+    # modes: a 5 x 5 x 4 tensor subset; exact gradient = type 1 (sign -1) of g
+    kk = tuple(np.sort(rng.choice(np.arange(-32, 32), size=s, replace=False)) for s in (5, 5, 4))
+    gf_ref = direct.type1(pts64, g64, N, iflag=-1, kk=kk)
+    gf = fr.grad.cpu().numpy()[np.ix_(kk[2] + 32, kk[1] + 32, kk[0] + 32)]
+    assert rel_l2(gf, gf_ref) <= 1e-3
+    # positions: 100 points, exact derivative and central differences
+    idx = rng.choice(M, size=100, replace=False)
+    gx_ref = ograd.type2_grad_x(pts64, f64, g64, iflag=+1, idx=idx)
+    h = 1e-6
+    for i in range(3):
+        got = xs[i].grad.cpu().numpy()[idx]
+        assert rel_l2(got, gx_ref[i]) <= 1e-3
+        pp = [a[idx].copy() for a in pts64]
+        pm = [a[idx].copy() for a in pts64]
+        pp[i] += h
+        pm[i] -= h
+        cp = direct.type2(tuple(pp), f64, iflag=+1)
+        cm = direct.type2(tuple(pm), f64, iflag=+1)
+        fd = np.real(np.conj(g64[idx]) * (cp - cm) / (2 * h))
+        assert rel_l2(got, fd) <= 1e-3

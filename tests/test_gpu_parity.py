@@ -104,7 +104,13 @@ def test_spread_interp_steps(method, dim, prec, eps, kind):
     ns, w, beta = inf["nfine"][:dim], inf["w"], inf["beta"]
     grid = p.spread(c).cpu().numpy()
     ref = direct.spread(pts64, c64, ns, w, beta)
-    tol = 2e-6 if prec == "f32" else 1e-13
+    # Summation-order rounding: a cell that sums K single-precision terms is
+    # off by about sqrt(K) u, u = 2^-24.  Uniform points give K ~ rho w^d
+    # (tens); clustered ones put up to M terms on one cell (sqrt(2e4) u ~ 8.5e-6).
+    if prec == "f32":
+        tol = 2e-5 if kind == "cluster" else 2e-6
+    else:
+        tol = 1e-12 if kind == "cluster" else 1e-13
     assert rel_l2(grid, ref) <= tol
     # interpolation from a random grid
     g64, g = make_complex(tuple(ns[::-1]), prec, seed=5)
