@@ -235,6 +235,121 @@ int mnufft_choose_params(double eps, int prec, int64_t N, int *w, double *beta, 
  * beta <= 0, out NULL). */
 int mnufft_correction_factors(int64_t N, int64_t n, int w, double beta, double *out);
 
+/* ---- autotuning ------------------------------------------------------- */
+
+/* The parameter sets the autotuner searches for a dimension, precision and
+ * tolerance: method SM with several bin shapes (those whose padded bins fit
+ * in LDS) times msub in {256, 1024, 4096, 16384}, then GMSORT and GM, in
+ * this fixed order.  Writes min(count, cap) default-initialised options with
+ * method, binsize and msub set (host array, may be NULL when cap = 0) and
+ * returns the count (>= 0).  Host only.  Errors: ERR_ARG.  (The paper tuned
+ * bins and msub by hand on its GPU: Sec. III-A, first remark.) */
+int mnufft_tune_candidates(int dim, int prec, double eps, mnufft_opts *list, int cap);
+
+/* Time setpts + execute of one transform for each candidate (a plan is
+ * created per candidate, untimed), in milliseconds of device time measured
+ * with HIP events on each candidate's stream: the median of `reps` runs after
+ * one warm-up run; a candidate whose warm-up takes more than cutoff (> 1)
+ * times the best median so far keeps that single time.  Candidates that are
+ * invalid for the problem get -1.  x, y, z, c, f are device arrays as for
+ * mnufft_setpts / mnufft_execute (c and f both needed: input and output);
+ * ms is a host array of ncand entries.  Synchronises.  Errors: ERR_ARG,
+ * ERR_HIP. */
+int mnufft_tune_time(int type, int dim, const int64_t *nmodes, int iflag, double eps, int prec,
+                     int64_t M, const void *x, const void *y, const void *z, void *c, void *f,
+                     const mnufft_opts *cands, int ncand, int reps, double cutoff, double *ms);
+
+/* ---- learned parameter selector --------------------------------------- */
+
+/* Point-density features: the points' (x, y) are counted on a 16 x 16
+ * periodic grid over [-pi, pi)^2 (cell = floor of the folded coordinate
+ * (x + pi) 16 / (2 pi), the bin-sort's recipe on 16 cells) and
+ * feat[cx + 16 cy] = log(1 + 256 count / M) (0 when M = 0).  x, y: device
+ * arrays of M reals of precision prec; feat: device array of 256 floats;
+ * work: device scratch of MNUFFT_DENSITY_WORK_BYTES bytes.  Stream-ordered.
+ * Errors: ERR_ARG, ERR_HIP. */
+#define MNUFFT_DENSITY_WORK_BYTES (512 * 256 * 4)
+int mnufft_density_features(int prec, int64_t M, const void *x, const void *y, float *feat,
+                            void *work, void *stream);
+
+/* A multilayer perceptron F -> H -> H -> K with ReLU after the two hidden
+ * layers, in single precision, all arrays on the device, all calls ordered on
+ * `stream` (a hipStream_t).  Parameters are one flat array laid out as
+ * W1 (F x H, row i holds input i's weights), b1 (H), W2 (H x H), b2 (H),
+ * W3 (H x K), b3 (K); gradients use the same layout.  Errors: ERR_ARG, ERR_HIP. */
+int64_t mnufft_mlp_nparams(int F, int H, int K);
+
+/* H1 = relu(X W1 + b1), H2 = relu(H1 W2 + b2), Y = H2 W3 + b3 for a batch of
+ * B rows (X: B x F, H1, H2: B x H, Y: B x K, row-major). */
+int mnufft_mlp_forward(int F, int H, int K, const float *params, int B, const float *X, float *H1,
+                       float *H2, float *Y, void *stream);
+
+/* Masked mean squared error over the B x K entries:
+ * *loss = sum mask (Y - T)^2 / max(1, sum mask), dY = 2 mask (Y - T) / max(1, sum mask). */
+int mnufft_mlp_loss_grad(int K, int B, const float *Y, const float *T, const float *mask, float *dY,
+                         float *loss, void *stream);
+
+/* Gradient of the loss w.r.t. the parameters given dY and the forward
+ * activations; work holds 2 B H floats. */
+int mnufft_mlp_backward(int F, int H, int K, const float *params, int B, const float *X,
+                        const float *H1, const float *H2, const float *dY, float *work,
+                        float *grads, void *stream);
+
+/* One Adam step (step >= 1) over n parameters with moments m, v. */
+int mnufft_mlp_adam(int64_t n, float *params, const float *grads, float *m, float *v, float lr,
+                    float beta1, float beta2, float eps, int step, void *stream);
+
+/* ---- batches of transforms of uneven size ---------------------------- */
+
+/* A batch runs ntr independent transforms of one type, dimension, sign,
+ * tolerance and precision, each with its own modes and points, as one
+ * workload: one bin-sort over all points (the transforms' bins numbered
+ * consecutively), one subproblem list, and one persistent launch each for
+ * spreading, the add-back of the padded bins, interpolation and the
+ * corrections (method SM, Sec. III-A); only the fine-grid FFTs run per
+ * transform.  Inputs and outputs are concatenated in transform order. */
+typedef struct mnufft_batch_s *mnufft_batch;
+
+/* Create a batch.
+ *   type, dim, iflag, eps, prec   as in mnufft_makeplan, shared by all transforms
+ *   ntr       number of transforms, >= 1
+ *   nmodes    host array ntr x 3: N_1, N_2 (, N_3) of transform t at 3t ..
+ *   npts      host array ntr: points of each transform (>= 0, total <= 2^31 - 1)
+ *   binsize   host array ntr x 3 of bin extents, or NULL; 0 entries take
+ *             opts->binsize or the default (32 x 32; 16 x 16 x 8 in 3D)
+ *   msub      host array ntr of subproblem sizes, or NULL; 0 entries take
+ *             opts->msub or 1024
+ *   opts      NULL or options; method must be AUTO or SM
+ * The padded bins of the largest bin extents must fit in LDS.  Errors:
+ * ERR_ARG, ERR_UNSUPPORTED (method GM / GMSORT), ERR_ALLOC, ERR_HIP, ERR_FFT;
+ * returns MNUFFT_WARN_EPS_CLAMPED like mnufft_makeplan. */
+int mnufft_batch_makeplan(int type, int dim, int ntr, const int64_t *nmodes,
+                          const int64_t *npts, int iflag, double eps, int prec,
+                          const int32_t *binsize, const int32_t *msub,
+                          const mnufft_opts *opts, mnufft_batch *out);
+
+/* Set all points: x, y (, z) device arrays of sum(npts) reals of the batch
+ * precision, transform 0's points first.  Stream-ordered.  Errors: ERR_ARG,
+ * ERR_HIP. */
+int mnufft_batch_setpts(mnufft_batch b, const void *x, const void *y, const void *z);
+
+/* Execute all transforms.  c: sum(npts) complex (concatenated per transform);
+ * f: sum over t of N_1 N_2 (N_3) complex (concatenated, k1 fastest).  Type 1
+ * reads c and overwrites f; type 2 reads f and overwrites c.  Errors:
+ * ERR_STATE, ERR_ARG, ERR_HIP, ERR_FFT. */
+int mnufft_batch_execute(mnufft_batch b, void *c, void *f);
+
+/* Stage timers of a batch (same stages and semantics as for plans). */
+int mnufft_batch_set_timing(mnufft_batch b, int enable);
+int mnufft_batch_get_timing(mnufft_batch b, double *ms, int64_t *count, int reset);
+
+/* totals[6] (host): points, modes, fine-grid cells, bins, subproblem
+ * capacity, device bytes owned.  Errors: ERR_ARG. */
+int mnufft_batch_get_totals(mnufft_batch b, int64_t *totals);
+
+/* Synchronise and free; NULL is ignored.  Errors: ERR_HIP. */
+int mnufft_batch_destroy(mnufft_batch b);
+
 /* Human-readable name of a status code (static storage, never NULL). */
 const char *mnufft_strerror(int status);
 

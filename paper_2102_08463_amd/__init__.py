@@ -6,6 +6,7 @@ package is its thin Python binding.  PyTorch provides device memory and
 streams only.
 """
 from .plan import Plan, nufft_type1, nufft_type2  # noqa: F401
+from .batch import Batch  # noqa: F401
 from . import lib  # noqa: F401
 
-__all__ = ["Plan", "nufft_type1", "nufft_type2", "lib"]
+__all__ = ["Plan", "Batch", "nufft_type1", "nufft_type2", "lib"]

@@ -27,6 +27,10 @@ COMMON = [
 # (source, extra flags, object name)
 UNITS = [
     ("mnufft.cpp", [], "mnufft.o"),
+    ("host_common.cpp", [], "host_common.o"),
+    ("batch.cpp", [], "batch.o"),
+    ("tune.cpp", [], "tune.o"),
+    ("kernels_mlp.hip", [], "kernels_mlp.o"),
     ("kernels_sort.hip", [], "kernels_sort.o"),
     ("kernels_deconv.hip", [], "kernels_deconv.o"),
     ("spread_dispatch.hip", [], "spread_dispatch.o"),

@@ -20,6 +20,50 @@ struct Geom {
     int pad;         // ceil(w / 2): halo of a padded bin (Sec. III-A, SM step 2)
 };
 
+// Per-transform geometry of a batch, kept in a device table.  A batch puts
+// all transforms' bins in one global numbering (bin_off), their points,
+// fine grids and modes back to back (pt_off, grid_off, mode_off), so that one
+// sort, one subproblem list and one launch per stage cover every transform.
+struct TGeom {
+    int n[3], m[3], B[3];
+    int N[3];
+    int bin_off, nbins;
+    int pt_off, M;
+    int msub;
+    int p_off[3];    // offsets into the concatenated correction factors, per dimension
+    int cov_off[3];  // offsets (entries) into the concatenated cover tables, per dimension
+    int kmax[3];
+    long long grid_off;
+    long long mode_off;
+    double S[3];
+};
+
+// Index t of the last table entry whose `field` is <= v (entries sorted by field).
+template <typename F>
+__device__ __forceinline__ int find_transform(const TGeom *tg, int T, long long v, F field)
+{
+    int lo = 0, hi = T - 1;
+    while (lo < hi) {
+        const int mid = lo + ((hi - lo + 1) >> 1);
+        if ((long long)field(tg[mid]) <= v) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Geometry of transform t as a Geom (shared fields from g).
+__device__ __forceinline__ Geom geom_of(const Geom &g, const TGeom &t)
+{
+    Geom r = g;
+    for (int d = 0; d < 3; ++d) {
+        r.n[d] = t.n[d];
+        r.m[d] = t.m[d];
+        r.B[d] = t.B[d];
+        r.S[d] = t.S[d];
+    }
+    r.nbins = t.nbins;
+    return r;
+}
+
 // Sorted-point storage produced by setpts.
 struct Pts {
     int M;
@@ -44,6 +88,10 @@ struct Pts {
     int kmax[3];
     void *cmax;               // 1024 partial maxima of |Re c|, |Im c| of the vector being spread
     int msub;                 // maximum points per subproblem
+    // batches: per-transform geometry (device) and count; nullptr / 1 for a plain plan
+    const TGeom *tg;
+    int T;
+    long long ncells;         // fine-grid cells over all transforms
 };
 
 // ---- bin sort (kernels_sort.hip) ------------------------------------------
@@ -60,9 +108,11 @@ struct Payload {
 // key[j] and u_in[d][j]: bin index and bin-relative coordinates of every
 // point in input order; flag |= 1 if a coordinate is non-finite or outside
 // [-3pi, 3pi).
+// With a batch table tg (T entries), point j belongs to the transform whose
+// pt_off range holds j and gets the global key bin_off + local key.
 hipError_t launch_binkey(const Geom &g, int prec, int M, const void *x, const void *y,
                          const void *z, uint32_t *key, void *const u_in[3], int *flag,
-                         hipStream_t s);
+                         hipStream_t s, const TGeom *tg = nullptr, int T = 1);
 
 // Number of 8-bit passes for keys of `bits` bits (at least one).
 int radix_passes(int bits);
@@ -80,9 +130,10 @@ hipError_t launch_binstart(int M, int nbins, const uint32_t *skey, int32_t *bins
                            hipStream_t s);
 
 // Subproblem list from bin starts; nsub_max = nbins + ceil(M / msub).
+// With a batch table, each bin uses its transform's msub.
 hipError_t launch_subproblems(int nbins, int msub, int nsub_max, const int32_t *binstart,
                               int32_t *subcount, uint32_t *partials, int32_t *sub,
-                              int32_t *nsub, hipStream_t s);
+                              int32_t *nsub, hipStream_t s, const TGeom *tg = nullptr, int T = 1);
 
 // Exclusive prefix sum of n uint32 values (in and out may alias).
 hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, size_t n, uint32_t *partials,
@@ -122,6 +173,12 @@ hipError_t launch_deconv(int dim, const int64_t N[3], const int n[3], int prec, 
 hipError_t launch_precorrect(int dim, const int64_t N[3], const int n[3], int prec,
                              int ntransf, const void *f, const void *const p[3], void *grid,
                              hipStream_t s);
+// Batched correction over all transforms of a batch (concatenated layout).
+hipError_t launch_deconv_batch(const TGeom *tg, int T, long long nmodes, int prec,
+                               const void *grid, const void *const p[3], void *f, hipStream_t s);
+hipError_t launch_precorrect_batch(const TGeom *tg, int T, long long ncells, int prec,
+                                   const void *f, const void *const p[3], void *grid,
+                                   hipStream_t s);
 // Fill n bytes of device memory with zero by a kernel.
 hipError_t launch_zero(void *ptr, size_t bytes, hipStream_t s);
 

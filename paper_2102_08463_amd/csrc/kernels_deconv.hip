@@ -8,6 +8,8 @@
 // l h - pi), so both corrections are a plain product.
 #include "internal.h"
 
+#include <algorithm>
+
 namespace mn {
 namespace {
 
@@ -80,6 +82,73 @@ k_precorrect(int N1, int N2, int N3, int n1, int n2, int n3, int chunks,
     grid[(((size_t)t * n3 + l3) * n2 + l2) * n1 + l1] = v;
 }
 
+// Batched forms: one launch over the concatenated modes (deconvolution) or
+// fine cells (precorrection) of all transforms; element e belongs to the
+// transform whose mode_off / grid_off range holds it.  Correction factors
+// are concatenated per dimension at p_off.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_deconv_batch(const TGeom *__restrict__ tg, int T_, long long nmodes,
+               const typename Cplx<T>::type *__restrict__ grid, const T *__restrict__ p1,
+               const T *__restrict__ p2, const T *__restrict__ p3,
+               typename Cplx<T>::type *__restrict__ f)
+{
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nmodes;
+         e += (long long)gridDim.x * blockDim.x) {
+        const TGeom &t = tg[find_transform(tg, T_, e, [](const TGeom &a) { return a.mode_off; })];
+        const long long el = e - t.mode_off;
+        const int i1 = (int)(el % t.N[0]);
+        const long long r = el / t.N[0];
+        const int i2 = (int)(r % t.N[1]);
+        const int i3 = (int)(r / t.N[1]);
+        const int k1 = i1 - t.N[0] / 2, k2 = i2 - t.N[1] / 2, k3 = i3 - t.N[2] / 2;
+        const int l1 = k1 < 0 ? k1 + t.n[0] : k1;
+        const int l2 = k2 < 0 ? k2 + t.n[1] : k2;
+        const int l3 = k3 < 0 ? k3 + t.n[2] : k3;
+        const T sc = p1[t.p_off[0] + i1] * p2[t.p_off[1] + i2] * p3[t.p_off[2] + i3];
+        auto v = grid[t.grid_off + ((long long)l3 * t.n[1] + l2) * t.n[0] + l1];
+        v.x *= sc;
+        v.y *= sc;
+        f[e] = v;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_precorrect_batch(const TGeom *__restrict__ tg, int T_, long long ncells,
+                   const typename Cplx<T>::type *__restrict__ f, const T *__restrict__ p1,
+                   const T *__restrict__ p2, const T *__restrict__ p3,
+                   typename Cplx<T>::type *__restrict__ grid)
+{
+    auto idx = [](int l, int N, int n) -> int {
+        const int kmin = -(N / 2), kmax = N - 1 - N / 2;
+        if (l <= kmax) return l - kmin;
+        if (l >= n + kmin) return l - n - kmin;
+        return -1;
+    };
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < ncells;
+         e += (long long)gridDim.x * blockDim.x) {
+        const TGeom &t = tg[find_transform(tg, T_, e, [](const TGeom &a) { return a.grid_off; })];
+        const long long el = e - t.grid_off;
+        const int l1 = (int)(el % t.n[0]);
+        const long long r = el / t.n[0];
+        const int l2 = (int)(r % t.n[1]);
+        const int l3 = (int)(r / t.n[1]);
+        const int i1 = idx(l1, t.N[0], t.n[0]), i2 = idx(l2, t.N[1], t.n[1]);
+        const int i3 = idx(l3, t.N[2], t.n[2]);
+        typename Cplx<T>::type v;
+        v.x = 0;
+        v.y = 0;
+        if (i1 >= 0 && i2 >= 0 && i3 >= 0) {
+            const T sc = p1[t.p_off[0] + i1] * p2[t.p_off[1] + i2] * p3[t.p_off[2] + i3];
+            v = f[t.mode_off + ((long long)i3 * t.N[1] + i2) * t.N[0] + i1];
+            v.x *= sc;
+            v.y *= sc;
+        }
+        grid[e] = v;
+    }
+}
+
 template <typename V>
 __global__ void k_zero(V *__restrict__ p, size_t nv, unsigned char *__restrict__ tail, int ntail)
 {
@@ -127,6 +196,39 @@ hipError_t launch_precorrect(int dim, const int64_t N[3], const int n[3], int pr
         hipLaunchKernelGGL(k_precorrect<double>, grd, blk, 0, s, N1, N2, N3, n[0], n[1], n3,
                            chunks, (const double2 *)f, (const double *)p[0],
                            (const double *)p[1], (const double *)p[2], (double2 *)grid);
+    return hipGetLastError();
+}
+
+hipError_t launch_deconv_batch(const TGeom *tg, int T, long long nmodes, int prec,
+                               const void *grid, const void *const p[3], void *f, hipStream_t s)
+{
+    if (nmodes == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<long long>((nmodes + kThreads - 1) / kThreads, 16384);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_deconv_batch<float>, dim3(blocks), dim3(kThreads), 0, s, tg, T, nmodes,
+                           (const float2 *)grid, (const float *)p[0], (const float *)p[1],
+                           (const float *)p[2], (float2 *)f);
+    else
+        hipLaunchKernelGGL(k_deconv_batch<double>, dim3(blocks), dim3(kThreads), 0, s, tg, T, nmodes,
+                           (const double2 *)grid, (const double *)p[0], (const double *)p[1],
+                           (const double *)p[2], (double2 *)f);
+    return hipGetLastError();
+}
+
+hipError_t launch_precorrect_batch(const TGeom *tg, int T, long long ncells, int prec,
+                                   const void *f, const void *const p[3], void *grid,
+                                   hipStream_t s)
+{
+    if (ncells == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<long long>((ncells + kThreads - 1) / kThreads, 16384);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_precorrect_batch<float>, dim3(blocks), dim3(kThreads), 0, s, tg, T,
+                           ncells, (const float2 *)f, (const float *)p[0], (const float *)p[1],
+                           (const float *)p[2], (float2 *)grid);
+    else
+        hipLaunchKernelGGL(k_precorrect_batch<double>, dim3(blocks), dim3(kThreads), 0, s, tg, T,
+                           ncells, (const double2 *)f, (const double *)p[0], (const double *)p[1],
+                           (const double *)p[2], (double2 *)grid);
     return hipGetLastError();
 }
 

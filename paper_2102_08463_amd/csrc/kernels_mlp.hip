@@ -1,0 +1,249 @@
+// Learned parameter selector: point-density features and a small MLP
+// (F -> H -> H -> K, ReLU) with forward, masked mean-squared-error gradient,
+// backward and Adam kernels.  The network predicts the log run time of each
+// autotuner candidate from the features; the selector takes the argmin.
+//
+// Parameter layout (one flat float array): W1 (F x H, row i = input i), b1 (H),
+// W2 (H x H), b2 (H), W3 (H x K), b3 (K).
+#include "../../include/mnufft.h"
+#include "internal.h"
+
+#include <algorithm>
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kHistBlocks = 512;  // partial histograms; see MNUFFT_DENSITY_WORK_BYTES
+constexpr double kPi = 3.141592653589793;
+
+// Y[b][o] = act(bias[o] + sum_i X[b][i] W[i][o]); act = ReLU or identity.
+__global__ void k_dense(int B, int In, int Out, const float *__restrict__ X,
+                        const float *__restrict__ W, const float *__restrict__ bias,
+                        float *__restrict__ Y, int relu)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= B * Out) return;
+    const int b = e / Out, o = e % Out;
+    float acc = bias[o];
+    const float *x = X + (size_t)b * In;
+    for (int i = 0; i < In; ++i) acc = fmaf(x[i], W[(size_t)i * Out + o], acc);
+    Y[e] = relu ? fmaxf(acc, 0.0f) : acc;
+}
+
+// dW[i][o] = sum_b A[b][i] D[b][o]  (A: B x In, D: B x Out)
+__global__ void k_outer_sum(int B, int In, int Out, const float *__restrict__ A,
+                            const float *__restrict__ D, float *__restrict__ dW)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= In * Out) return;
+    const int i = e / Out, o = e % Out;
+    float acc = 0.0f;
+    for (int b = 0; b < B; ++b) acc = fmaf(A[(size_t)b * In + i], D[(size_t)b * Out + o], acc);
+    dW[e] = acc;
+}
+
+// db[o] = sum_b D[b][o]
+__global__ void k_colsum(int B, int Out, const float *__restrict__ D, float *__restrict__ db)
+{
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= Out) return;
+    float acc = 0.0f;
+    for (int b = 0; b < B; ++b) acc += D[(size_t)b * Out + o];
+    db[o] = acc;
+}
+
+// dA[b][i] = (sum_o D[b][o] W[i][o]) * (A[b][i] > 0): back through W and the ReLU.
+__global__ void k_back_relu(int B, int In, int Out, const float *__restrict__ D,
+                            const float *__restrict__ W, const float *__restrict__ A,
+                            float *__restrict__ dA)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= B * In) return;
+    const int b = e / In, i = e % In;
+    float acc = 0.0f;
+    for (int o = 0; o < Out; ++o) acc = fmaf(D[(size_t)b * Out + o], W[(size_t)i * Out + o], acc);
+    dA[e] = A[e] > 0.0f ? acc : 0.0f;
+}
+
+// Masked MSE: loss = sum m (y - t)^2 / sum m; dY = 2 m (y - t) / sum m.  One block.
+__global__ void k_mse(int n, const float *__restrict__ Y, const float *__restrict__ T,
+                      const float *__restrict__ mask, float *__restrict__ dY,
+                      float *__restrict__ loss)
+{
+    __shared__ float sm[kThreads], sl[kThreads];
+    float m = 0.0f, l = 0.0f;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const float r = Y[e] - T[e];
+        m += mask[e];
+        l += mask[e] * r * r;
+    }
+    sm[threadIdx.x] = m;
+    sl[threadIdx.x] = l;
+    __syncthreads();
+    for (int o = kThreads / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            sm[threadIdx.x] += sm[threadIdx.x + o];
+            sl[threadIdx.x] += sl[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    const float msum = fmaxf(sm[0], 1.0f);
+    if (threadIdx.x == 0) *loss = sl[0] / msum;
+    for (int e = threadIdx.x; e < n; e += blockDim.x)
+        dY[e] = 2.0f * mask[e] * (Y[e] - T[e]) / msum;
+}
+
+__global__ void k_adam(long long n, float *__restrict__ p, const float *__restrict__ g,
+                       float *__restrict__ m, float *__restrict__ v, float lr, float b1, float b2,
+                       float eps, float c1, float c2)
+{
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const float gi = g[e];
+    const float mi = b1 * m[e] + (1.0f - b1) * gi;
+    const float vi = b2 * v[e] + (1.0f - b2) * gi * gi;
+    m[e] = mi;
+    v[e] = vi;
+    p[e] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// 16 x 16 cell of a point: the same folded grid coordinate as the bin-sort,
+// on a 16-cell grid per dimension.
+__device__ __forceinline__ int cell16(double x)
+{
+    const double S = 16.0 / (2.0 * kPi);
+    double g = __dmul_rn(__dadd_rn(x, kPi), S);
+    if (g < 0.0) g = __dadd_rn(g, 16.0);
+    if (g >= 16.0) g = __dsub_rn(g, 16.0);
+    if (!(g >= 0.0 && g < 16.0)) {
+        g = __dsub_rn(g, __dmul_rn(floor(__ddiv_rn(g, 16.0)), 16.0));
+        if (!(g >= 0.0 && g < 16.0)) g = 0.0;
+    }
+    return (int)g;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_hist_partial(long long M, const T *__restrict__ x, const T *__restrict__ y,
+               uint32_t *__restrict__ part)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < M;
+         j += (long long)gridDim.x * blockDim.x)
+        atomicAdd(&h[cell16((double)x[j]) + 16 * cell16((double)y[j])], 1u);
+    __syncthreads();
+    part[(size_t)blockIdx.x * 256 + threadIdx.x] = h[threadIdx.x];
+}
+
+// feature[c] = log(1 + 256 count[c] / M): the density relative to uniform.
+__global__ void k_hist_final(long long M, int nblk, const uint32_t *__restrict__ part,
+                             float *__restrict__ feat)
+{
+    const int c = threadIdx.x;
+    unsigned long long s = 0;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * 256 + c];
+    feat[c] = M > 0 ? log1pf(256.0f * (float)((double)s / (double)M)) : 0.0f;
+}
+
+inline int blocks_for(long long n) { return (int)std::max<long long>(1, (n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+extern "C" {
+
+int64_t mnufft_mlp_nparams(int F, int H, int K)
+{
+    if (F < 1 || H < 1 || K < 1) return MNUFFT_ERR_ARG;
+    return (int64_t)F * H + H + (int64_t)H * H + H + (int64_t)H * K + K;
+}
+
+int mnufft_mlp_forward(int F, int H, int K, const float *params, int B, const float *X, float *H1,
+                       float *H2, float *Y, void *stream)
+{
+    if (F < 1 || H < 1 || K < 1 || B < 0 || !params || (B > 0 && (!X || !H1 || !H2 || !Y)))
+        return MNUFFT_ERR_ARG;
+    if (B == 0) return MNUFFT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const float *W1 = params, *b1 = W1 + (size_t)F * H, *W2 = b1 + H, *b2 = W2 + (size_t)H * H;
+    const float *W3 = b2 + H, *b3 = W3 + (size_t)H * K;
+    hipLaunchKernelGGL(k_dense, dim3(blocks_for((long long)B * H)), dim3(kThreads), 0, s, B, F, H,
+                       X, W1, b1, H1, 1);
+    hipLaunchKernelGGL(k_dense, dim3(blocks_for((long long)B * H)), dim3(kThreads), 0, s, B, H, H,
+                       (const float *)H1, W2, b2, H2, 1);
+    hipLaunchKernelGGL(k_dense, dim3(blocks_for((long long)B * K)), dim3(kThreads), 0, s, B, H, K,
+                       (const float *)H2, W3, b3, Y, 0);
+    return hipGetLastError() == hipSuccess ? MNUFFT_OK : MNUFFT_ERR_HIP;
+}
+
+int mnufft_mlp_loss_grad(int K, int B, const float *Y, const float *T, const float *mask, float *dY,
+                         float *loss, void *stream)
+{
+    if (K < 1 || B < 1 || !Y || !T || !mask || !dY || !loss) return MNUFFT_ERR_ARG;
+    hipLaunchKernelGGL(k_mse, dim3(1), dim3(kThreads), 0, (hipStream_t)stream, B * K, Y, T, mask,
+                       dY, loss);
+    return hipGetLastError() == hipSuccess ? MNUFFT_OK : MNUFFT_ERR_HIP;
+}
+
+int mnufft_mlp_backward(int F, int H, int K, const float *params, int B, const float *X,
+                        const float *H1, const float *H2, const float *dY, float *work,
+                        float *grads, void *stream)
+{
+    if (F < 1 || H < 1 || K < 1 || B < 1 || !params || !X || !H1 || !H2 || !dY || !work || !grads)
+        return MNUFFT_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const float *W2 = params + (size_t)F * H + H, *W3 = W2 + (size_t)H * H + H;
+    float *dW1 = grads, *db1 = dW1 + (size_t)F * H, *dW2 = db1 + H, *db2 = dW2 + (size_t)H * H;
+    float *dW3 = db2 + H, *db3 = dW3 + (size_t)H * K;
+    float *dH2 = work, *dH1 = work + (size_t)B * H;
+    hipLaunchKernelGGL(k_outer_sum, dim3(blocks_for((long long)H * K)), dim3(kThreads), 0, s, B, H,
+                       K, H2, dY, dW3);
+    hipLaunchKernelGGL(k_colsum, dim3(blocks_for(K)), dim3(kThreads), 0, s, B, K, dY, db3);
+    hipLaunchKernelGGL(k_back_relu, dim3(blocks_for((long long)B * H)), dim3(kThreads), 0, s, B, H,
+                       K, dY, W3, H2, dH2);
+    hipLaunchKernelGGL(k_outer_sum, dim3(blocks_for((long long)H * H)), dim3(kThreads), 0, s, B, H,
+                       H, H1, (const float *)dH2, dW2);
+    hipLaunchKernelGGL(k_colsum, dim3(blocks_for(H)), dim3(kThreads), 0, s, B, H,
+                       (const float *)dH2, db2);
+    hipLaunchKernelGGL(k_back_relu, dim3(blocks_for((long long)B * H)), dim3(kThreads), 0, s, B, H,
+                       H, (const float *)dH2, W2, H1, dH1);
+    hipLaunchKernelGGL(k_outer_sum, dim3(blocks_for((long long)F * H)), dim3(kThreads), 0, s, B, F,
+                       H, X, (const float *)dH1, dW1);
+    hipLaunchKernelGGL(k_colsum, dim3(blocks_for(H)), dim3(kThreads), 0, s, B, H,
+                       (const float *)dH1, db1);
+    return hipGetLastError() == hipSuccess ? MNUFFT_OK : MNUFFT_ERR_HIP;
+}
+
+int mnufft_mlp_adam(int64_t n, float *params, const float *grads, float *m, float *v, float lr,
+                    float beta1, float beta2, float eps, int step, void *stream)
+{
+    if (n < 0 || step < 1 || !params || !grads || !m || !v) return MNUFFT_ERR_ARG;
+    if (n == 0) return MNUFFT_OK;
+    const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(n)), dim3(kThreads), 0, (hipStream_t)stream, n,
+                       params, grads, m, v, lr, beta1, beta2, eps, c1, c2);
+    return hipGetLastError() == hipSuccess ? MNUFFT_OK : MNUFFT_ERR_HIP;
+}
+
+int mnufft_density_features(int prec, int64_t M, const void *x, const void *y, float *feat,
+                            void *work, void *stream)
+{
+    if ((prec != MNUFFT_F32 && prec != MNUFFT_F64) || M < 0 || !feat || !work ||
+        (M > 0 && (!x || !y)))
+        return MNUFFT_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t *part = (uint32_t *)work;
+    const int nblk = (int)std::min<long long>(kHistBlocks, std::max<long long>(1, (M + kThreads - 1) / kThreads));
+    if (prec == MNUFFT_F32)
+        hipLaunchKernelGGL(k_hist_partial<float>, dim3(nblk), dim3(kThreads), 0, s, (long long)M,
+                           (const float *)x, (const float *)y, part);
+    else
+        hipLaunchKernelGGL(k_hist_partial<double>, dim3(nblk), dim3(kThreads), 0, s, (long long)M,
+                           (const double *)x, (const double *)y, part);
+    hipLaunchKernelGGL(k_hist_final, dim3(1), dim3(256), 0, s, (long long)M, nblk,
+                       (const uint32_t *)part, feat);
+    return hipGetLastError() == hipSuccess ? MNUFFT_OK : MNUFFT_ERR_HIP;
+}
+
+}  // extern "C"

@@ -44,27 +44,34 @@ __device__ __forceinline__ double grid_coord(double x, double S, int n, int &bad
     return g;
 }
 
-template <typename T>
+template <typename T, bool BATCH>
 __global__ void __launch_bounds__(kThreads)
 k_binkey(Geom g, int M, const T *__restrict__ x, const T *__restrict__ y,
          const T *__restrict__ z, uint32_t *__restrict__ key, T *__restrict__ u0,
-         T *__restrict__ u1, T *__restrict__ u2, int *__restrict__ flag)
+         T *__restrict__ u1, T *__restrict__ u2, int *__restrict__ flag,
+         const TGeom *__restrict__ tg, int T_)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= M) return;
     int bad = 0;
+    uint32_t k = 0, stride = 1;
+    Geom gg = g;
+    if constexpr (BATCH) {
+        const int t = find_transform(tg, T_, j, [](const TGeom &a) { return a.pt_off; });
+        gg = geom_of(g, tg[t]);
+        k = (uint32_t)tg[t].bin_off;
+    }
     const T *xs[3] = {x, y, z};
     T *us[3] = {u0, u1, u2};
-    uint32_t k = 0, stride = 1;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        if (d >= g.dim) break;
-        const double gc = grid_coord((double)xs[d][j], g.S[d], g.n[d], bad);
+        if (d >= gg.dim) break;
+        const double gc = grid_coord((double)xs[d][j], gg.S[d], gg.n[d], bad);
         const int l = (int)gc;  // gc >= 0, so truncation is floor; l <= n - 1
-        const int b = l / g.m[d];
+        const int b = l / gg.m[d];
         k += (uint32_t)b * stride;
-        stride *= (uint32_t)g.B[d];
-        us[d][j] = (T)(gc - (double)b * (double)g.m[d]);
+        stride *= (uint32_t)gg.B[d];
+        us[d][j] = (T)(gc - (double)b * (double)gg.m[d]);
     }
     key[j] = k;
     if (bad) atomicOr(flag, 1);
@@ -325,19 +332,27 @@ __global__ void k_binstart(int M, int nbins, const uint32_t *__restrict__ skey,
     binstart[b] = lo;
 }
 
+// msub of bin b: the plan's, or in a batch that of the bin's transform.
+__device__ __forceinline__ int msub_of(int b, int msub, const TGeom *tg, int T)
+{
+    if (!tg) return msub;
+    return tg[find_transform(tg, T, b, [](const TGeom &a) { return a.bin_off; })].msub;
+}
+
 __global__ void k_subcount(int nbins, int msub, const int32_t *__restrict__ binstart,
-                           uint32_t *__restrict__ cnt)
+                           uint32_t *__restrict__ cnt, const TGeom *__restrict__ tg, int T)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b > nbins) return;
     if (b == nbins) { cnt[b] = 0; return; }
     const int c = binstart[b + 1] - binstart[b];
-    cnt[b] = (uint32_t)((c + msub - 1) / msub);
+    const int ms = msub_of(b, msub, tg, T);
+    cnt[b] = (uint32_t)((c + ms - 1) / ms);
 }
 
 __global__ void k_subfill(int nbins, int msub, int nsub_max, const int32_t *__restrict__ binstart,
                           const uint32_t *__restrict__ off, int32_t *__restrict__ sub,
-                          int32_t *__restrict__ nsub)
+                          int32_t *__restrict__ nsub, const TGeom *__restrict__ tg, int T)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     // the count is clamped to the list's capacity so that no consumer can
@@ -351,9 +366,10 @@ __global__ void k_subfill(int nbins, int msub, int nsub_max, const int32_t *__re
         if (off[mid] <= (uint32_t)q) lo = mid; else hi = mid - 1;
     }
     const int b = lo;
+    const int ms = msub_of(b, msub, tg, T);
     const int s = q - (int)off[b];
-    const int start = binstart[b] + s * msub;
-    const int len = std::min(msub, binstart[b + 1] - start);
+    const int start = binstart[b] + s * ms;
+    const int len = std::min(ms, binstart[b + 1] - start);
     int4 rec;
     rec.x = b; rec.y = start; rec.z = len; rec.w = 0;
     reinterpret_cast<int4 *>(sub)[q] = rec;
@@ -381,18 +397,19 @@ hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, size_t n, uint32_t 
 
 hipError_t launch_binkey(const Geom &g, int prec, int M, const void *x, const void *y,
                          const void *z, uint32_t *key, void *const u_in[3], int *flag,
-                         hipStream_t s)
+                         hipStream_t s, const TGeom *tg, int T)
 {
     if (M == 0) return hipSuccess;
     const dim3 grid(nblocks(M, kThreads)), blk(kThreads);
-    if (prec == 0)
-        hipLaunchKernelGGL(k_binkey<float>, grid, blk, 0, s, g, M, (const float *)x,
-                           (const float *)y, (const float *)z, key, (float *)u_in[0],
-                           (float *)u_in[1], (float *)u_in[2], flag);
-    else
-        hipLaunchKernelGGL(k_binkey<double>, grid, blk, 0, s, g, M, (const double *)x,
-                           (const double *)y, (const double *)z, key, (double *)u_in[0],
-                           (double *)u_in[1], (double *)u_in[2], flag);
+#define MN_BK(TT, BB)                                                                        \
+    hipLaunchKernelGGL((k_binkey<TT, BB>), grid, blk, 0, s, g, M, (const TT *)x, (const TT *)y, \
+                       (const TT *)z, key, (TT *)u_in[0], (TT *)u_in[1], (TT *)u_in[2], flag, tg, T)
+    if (prec == 0) {
+        if (tg) MN_BK(float, true); else MN_BK(float, false);
+    } else {
+        if (tg) MN_BK(double, true); else MN_BK(double, false);
+    }
+#undef MN_BK
     return hipGetLastError();
 }
 
@@ -450,15 +467,15 @@ hipError_t launch_binstart(int M, int nbins, const uint32_t *skey, int32_t *bins
 
 hipError_t launch_subproblems(int nbins, int msub, int nsub_max, const int32_t *binstart,
                               int32_t *subcount, uint32_t *partials, int32_t *sub,
-                              int32_t *nsub, hipStream_t s)
+                              int32_t *nsub, hipStream_t s, const TGeom *tg, int T)
 {
     uint32_t *cnt = reinterpret_cast<uint32_t *>(subcount);
     hipLaunchKernelGGL(k_subcount, dim3(nblocks(nbins + 1, 256)), dim3(256), 0, s, nbins, msub,
-                       binstart, cnt);
+                       binstart, cnt, tg, T);
     hipError_t e = scan_exclusive(cnt, cnt, (size_t)nbins + 1, partials, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_subfill, dim3(nblocks(std::max(nsub_max, 1), 256)), dim3(256), 0, s,
-                       nbins, msub, nsub_max, binstart, (const uint32_t *)cnt, sub, nsub);
+                       nbins, msub, nsub_max, binstart, (const uint32_t *)cnt, sub, nsub, tg, T);
     return hipGetLastError();
 }
 

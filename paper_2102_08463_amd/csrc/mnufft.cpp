@@ -4,6 +4,7 @@
 // destroy interface (Sec. I-A) and three-step algorithm (Sec. II); every
 // step on the device runs in the kernels of kernels_*.hip except the FFT.
 #include "../../include/mnufft.h"
+#include "host_common.h"
 #include "internal.h"
 
 #include <rocfft/rocfft.h>
@@ -18,81 +19,15 @@
 
 namespace {
 
-constexpr double kPi = 3.141592653589793;
+constexpr double kPi = mn::host::kPi;
 constexpr size_t kLdsMax = 160 * 1024;  // LDS per workgroup on gfx950
 constexpr int kMergeGroup = 32;         // tiles summed per leader in heavy bins
 
-// ---- parameter choice (Sec. II) -----------------------------------------
-
-// w = ceil(log10(1/eps)) + 1; a guard of 1e-9 keeps decade tolerances (whose
-// logarithm is not exactly an integer in floating point) on the intended side.
-int width_for_eps(double eps) { return (int)std::ceil(std::log10(1.0 / eps) - 1e-9) + 1; }
-
-bool smooth235(int64_t n)
-{
-    for (int64_t p : {2, 3, 5})
-        while (n % p == 0) n /= p;
-    return n == 1;
-}
-
-// Smallest 2^a 3^b 5^c >= max(2N, 2w).
-int64_t fine_size(int64_t N, int w)
-{
-    int64_t n = std::max<int64_t>(2 * N, 2 * (int64_t)w);
-    while (!smooth235(n)) ++n;
-    return n;
-}
-
-// phi_hat(xi) = int_{-1}^{1} phi_beta(z) exp(-i xi z) dz = 2 int_0^1 phi(z) cos(xi z) dz
-// by the tanh-sinh rule z = (1 + tanh u)/2, u = (pi/2) sinh t, which is
-// insensitive to the square-root behaviour of phi at z = 1.
-void es_fourier(double beta, const std::vector<double> &xi, std::vector<double> &out)
-{
-    const double h = 1.0 / 64.0;
-    const int K = 4 * 64;  // t in [-4, 4]: the weights beyond are below 1e-20
-    std::vector<double> zz, ww;
-    zz.reserve(2 * K + 1);
-    ww.reserve(2 * K + 1);
-    for (int k = -K; k <= K; ++k) {
-        const double t = k * h;
-        const double u = 0.5 * kPi * std::sinh(t);
-        const double one_minus_z = 1.0 / (1.0 + std::exp(2.0 * u));
-        const double z = 1.0 - one_minus_z;
-        const double ch = std::cosh(u);
-        const double dz = 0.25 * kPi * std::cosh(t) / (ch * ch);
-        const double s = one_minus_z * (1.0 + z);  // 1 - z^2 without cancellation
-        const double phi = std::exp(beta * (std::sqrt(std::max(s, 0.0)) - 1.0));
-        zz.push_back(z);
-        ww.push_back(h * dz * phi);
-    }
-    out.assign(xi.size(), 0.0);
-    for (size_t i = 0; i < xi.size(); ++i) {
-        double acc = 0.0;
-        for (size_t q = 0; q < zz.size(); ++q) acc += ww[q] * std::cos(xi[i] * zz[q]);
-        out[i] = 2.0 * acc;
-    }
-}
-
-// p_k = (2/w) / phi_hat(alpha k) * (-1)^k for k in I_N, alpha = w pi / n.
-void correction(int64_t N, int64_t n, int w, double beta, std::vector<double> &p)
-{
-    std::vector<double> xi(N), ph;
-    const double alpha = w * kPi / (double)n;
-    for (int64_t i = 0; i < N; ++i) xi[i] = alpha * (double)(i - N / 2);
-    es_fourier(beta, xi, ph);
-    p.resize(N);
-    for (int64_t i = 0; i < N; ++i) {
-        const int64_t k = i - N / 2;
-        p[i] = (2.0 / w) / ph[i] * ((k % 2 == 0) ? 1.0 : -1.0);
-    }
-}
-
-int bits_for(int64_t nbins)
-{
-    int b = 0;
-    while (((int64_t)1 << b) < nbins) ++b;
-    return b;
-}
+using mn::host::bits_for;
+using mn::host::correction;
+using mn::host::fine_size;
+using mn::host::width_for_eps;
+using mn::host::StageTimer;
 
 std::once_flag g_fft_once;
 rocfft_status g_fft_setup = rocfft_status_success;
@@ -144,10 +79,7 @@ struct mnufft_plan_s {
     void *fftwork = nullptr;
     size_t fftwork_bytes = 0;
     int64_t devbytes = 0;
-    // stage timers: per stage, event pairs recorded since the last reset
-    bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[MNUFFT_NSTAGES];
-    size_t ev_used[MNUFFT_NSTAGES] = {};
+    mn::host::Timers tm;  // stage timers
 };
 
 namespace {
@@ -290,31 +222,6 @@ int run_fft(mnufft_plan p, int sign)
     return MNUFFT_OK;
 }
 
-// Brackets one stage with events when the timers are on.
-struct StageTimer {
-    mnufft_plan p;
-    int stage;
-    bool on;
-    StageTimer(mnufft_plan pl, int st) : p(pl), stage(st), on(pl->timing)
-    {
-        if (!on) return;
-        auto &v = p->ev[stage];
-        if (p->ev_used[stage] == v.size()) {
-            hipEvent_t a, b;
-            if (hipEventCreate(&a) != hipSuccess) { on = false; return; }
-            if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); on = false; return; }
-            v.emplace_back(a, b);
-        }
-        (void)hipEventRecord(v[p->ev_used[stage]].first, p->stream);
-    }
-    ~StageTimer()
-    {
-        if (!on) return;
-        (void)hipEventRecord(p->ev[stage][p->ev_used[stage]].second, p->stream);
-        ++p->ev_used[stage];
-    }
-};
-
 mn::Pts points_of(mnufft_plan p)
 {
     mn::Pts P{};
@@ -338,6 +245,9 @@ mn::Pts points_of(mnufft_plan p)
     P.nmerge = p->nmerge;
     P.cmax = p->cmax;
     P.msub = p->msub;
+    P.tg = nullptr;
+    P.T = 1;
+    P.ncells = (long long)p->grid_elems;
     for (int d = 0; d < 3; ++d) {
         P.cov[d] = p->cov[d];
         P.kmax[d] = p->kmax[d];
@@ -352,33 +262,33 @@ int exec_type1(mnufft_plan p, int sign, const void *c, void *f)
 {
     const mn::Pts P = points_of(p);
     if (p->method != MNUFFT_METHOD_SM) {  // SM writes every cell itself
-        StageTimer tm(p, MNUFFT_STAGE_ZERO);
+        StageTimer tm(p->tm, MNUFFT_STAGE_ZERO, p->stream);
         MN_HIP(mn::launch_zero(p->grid, grid_bytes(p) * p->ntransf, p->stream));
     }
     for (int64_t t = 0; t < p->ntransf; ++t) {
         const char *ct = (const char *)c + (size_t)t * p->M * 2 * p->rsz;
         char *gt = (char *)p->grid + (size_t)t * grid_bytes(p);
         if (p->method == MNUFFT_METHOD_SM) {
-            StageTimer tm(p, MNUFFT_STAGE_SCALE);
+            StageTimer tm(p->tm, MNUFFT_STAGE_SCALE, p->stream);
             MN_HIP(mn::launch_zero(p->cmax, 1024 * 8, p->stream));
             MN_HIP(mn::launch_spread(p->g, p->prec, p->method, P, ct, gt, p->stream, 4));
         }
         {
-            StageTimer tm(p, MNUFFT_STAGE_SPREAD);
+            StageTimer tm(p->tm, MNUFFT_STAGE_SPREAD, p->stream);
             MN_HIP(mn::launch_spread(p->g, p->prec, p->method, P, ct, gt, p->stream, 1));
         }
         if (p->method == MNUFFT_METHOD_SM) {
-            StageTimer tm(p, MNUFFT_STAGE_ADDBACK);
+            StageTimer tm(p->tm, MNUFFT_STAGE_ADDBACK, p->stream);
             MN_HIP(mn::launch_spread(p->g, p->prec, p->method, P, ct, gt, p->stream, 2));
         }
     }
     int rc;
     {
-        StageTimer tm(p, MNUFFT_STAGE_FFT);
+        StageTimer tm(p->tm, MNUFFT_STAGE_FFT, p->stream);
         rc = run_fft(p, sign);
     }
     if (rc) return rc;
-    StageTimer tm(p, MNUFFT_STAGE_DECONV);
+    StageTimer tm(p->tm, MNUFFT_STAGE_DECONV, p->stream);
     MN_HIP(mn::launch_deconv(p->dim, p->N, p->g.n, p->prec, (int)p->ntransf, p->grid,
                              p->pfac, f, p->stream));
     return MNUFFT_OK;
@@ -389,20 +299,20 @@ int exec_type2(mnufft_plan p, int sign, const void *f, void *c)
 {
     const mn::Pts P = points_of(p);
     {
-        StageTimer tm(p, MNUFFT_STAGE_PRECORRECT);
+        StageTimer tm(p->tm, MNUFFT_STAGE_PRECORRECT, p->stream);
         MN_HIP(mn::launch_precorrect(p->dim, p->N, p->g.n, p->prec, (int)p->ntransf, f,
                                      p->pfac, p->grid, p->stream));
     }
     int rc;
     {
-        StageTimer tm(p, MNUFFT_STAGE_FFT);
+        StageTimer tm(p->tm, MNUFFT_STAGE_FFT, p->stream);
         rc = run_fft(p, sign);
     }
     if (rc) return rc;
     for (int64_t t = 0; t < p->ntransf; ++t) {
         char *ct = (char *)c + (size_t)t * p->M * 2 * p->rsz;
         const char *gt = (const char *)p->grid + (size_t)t * grid_bytes(p);
-        StageTimer tm(p, MNUFFT_STAGE_INTERP);
+        StageTimer tm(p->tm, MNUFFT_STAGE_INTERP, p->stream);
         MN_HIP(mn::launch_interp(p->g, p->prec, p->method, P, gt, ct, p->stream));
     }
     return MNUFFT_OK;
@@ -414,20 +324,8 @@ int exec_type2(mnufft_plan p, int sign, const void *f, void *c)
 int build_cover(mnufft_plan p, int d)
 {
     const mn::Geom &g = p->g;
-    const int n = g.n[d], m = g.m[d], B = g.B[d], P = g.pad, pt = m + 2 * P;
-    std::vector<std::vector<int2>> lists((size_t)n);
-    for (int nb = 0; nb < B; ++nb)
-        for (int s = 0; s < pt; ++s) {
-            int l = (nb * m - P + s) % n;
-            if (l < 0) l += n;
-            lists[(size_t)l].push_back(make_int2(nb, s));
-        }
-    int km = 1;
-    for (auto &v : lists) km = std::max(km, (int)v.size());
-    std::vector<int2> tab((size_t)n * km, make_int2(-1, 0));
-    for (int l = 0; l < n; ++l)
-        for (size_t j = 0; j < lists[(size_t)l].size(); ++j) tab[(size_t)l * km + j] = lists[(size_t)l][j];
-    p->kmax[d] = km;
+    std::vector<int2> tab;
+    mn::host::cover_table(g.n[d], g.m[d], g.B[d], g.pad, tab, p->kmax[d]);
     p->cov_bytes[d] = tab.size() * sizeof(int2);
     int rc = dalloc(p, (void **)&p->cov[d], p->cov_bytes[d]);
     if (rc) return rc;
@@ -679,7 +577,7 @@ int mnufft_setpts(mnufft_plan p, int64_t M, const void *x, const void *y, const 
         return rc;
     }
     {
-        StageTimer tm(p, MNUFFT_STAGE_SETPTS);
+        StageTimer tm(p->tm, MNUFFT_STAGE_SETPTS, p->stream);
         rc = enqueue_setpts(p, M, x, y, z);
     }
     if (rc) return rc;
@@ -781,7 +679,7 @@ int mnufft_get_subproblems(mnufft_plan p, int32_t *sub, int32_t *nsub)
 int mnufft_set_timing(mnufft_plan p, int enable)
 {
     if (!p) return MNUFFT_ERR_ARG;
-    p->timing = enable != 0;
+    p->tm.on = enable != 0;
     return MNUFFT_OK;
 }
 
@@ -790,19 +688,7 @@ int mnufft_get_timing(mnufft_plan p, double *ms, int64_t *count, int reset)
     if (!p || !ms) return MNUFFT_ERR_ARG;
     int rc = use_device(p);
     if (rc) return rc;
-    MN_HIP(hipStreamSynchronize(p->stream));
-    for (int st = 0; st < MNUFFT_NSTAGES; ++st) {
-        double tot = 0.0;
-        for (size_t i = 0; i < p->ev_used[st]; ++i) {
-            float e = 0.f;
-            MN_HIP(hipEventElapsedTime(&e, p->ev[st][i].first, p->ev[st][i].second));
-            tot += e;
-        }
-        ms[st] = tot;
-        if (count) count[st] = (int64_t)p->ev_used[st];
-        if (reset) p->ev_used[st] = 0;
-    }
-    return MNUFFT_OK;
+    return p->tm.read(p->stream, ms, count, reset);
 }
 
 int mnufft_get_info(mnufft_plan p, mnufft_info *info)
@@ -839,11 +725,7 @@ int mnufft_destroy(mnufft_plan p)
     for (int k = 0; k < 2; ++k)
         if (p->fft[k]) rocfft_plan_destroy(p->fft[k]);
     if (p->fftinfo) rocfft_execution_info_destroy(p->fftinfo);
-    for (int st = 0; st < MNUFFT_NSTAGES; ++st)
-        for (auto &e : p->ev[st]) {
-            (void)hipEventDestroy(e.first);
-            (void)hipEventDestroy(e.second);
-        }
+    p->tm.destroy();
     free_points(p);
     dfree(p, &p->fftwork, p->fftwork_bytes);
     dfree(p, &p->grid, p->grid_elems * 2 * p->rsz * p->ntransf);

@@ -97,9 +97,8 @@ hipError_t launch_spread(const Geom &g, int prec, int method, const Pts &P, cons
     if (P.M == 0) {
         // nothing to accumulate; the SM add-back alone owns writing the grid
         if (method != 3 || !(part & 2)) return hipSuccess;
-        size_t cells = 1;
-        for (int d = 0; d < g.dim; ++d) cells *= (size_t)g.n[d];
-        return launch_zero(grid, cells * 2 * (prec == 0 ? sizeof(float) : sizeof(double)), s);
+        return launch_zero(grid, (size_t)P.ncells * 2 * (prec == 0 ? sizeof(float) : sizeof(double)),
+                           s);
     }
     const size_t lds = method == 3 ? sm_lds_bytes(g, prec, false) : 0;
     if (prec == 0)

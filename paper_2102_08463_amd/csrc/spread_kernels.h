@@ -307,25 +307,32 @@ template <> struct FixedScale<double> {
     __device__ static long long to_fixed(double v) { return __double2ll_rn(v); }
 };
 
-template <typename T, int DIM, int W>
+template <typename T, int DIM, int W, bool BATCH>
 __global__ void __launch_bounds__(kThreads)
 k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__ nsubp,
             const T *__restrict__ u0, const T *__restrict__ u1, const T *__restrict__ u2,
             const int32_t *__restrict__ perm, const typename Cplx<T>::type *__restrict__ c,
-            const T *__restrict__ cmaxp, int lg_msub, T *__restrict__ scratch, int ts2, T bk)
+            const T *__restrict__ cmaxp, int lg_msub, T *__restrict__ scratch, int ts2, T bk,
+            const TGeom *__restrict__ tg, int T_)
 {
     using V = typename Vec16<T>::type;
     constexpr int NV = 16 / sizeof(T);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     unsigned long long *tile = reinterpret_cast<unsigned long long *>(smem_raw);
     constexpr int P = (W + 1) / 2;
-    const int p1 = g.m[0] + 2 * P, p2 = g.m[1] + 2 * P;
     const int nvec = ts2 / NV;
     const int nsub = *nsubp;
     T inv;
     const T S = FixedScale<T>::scale(block_cmax(cmaxp), lg_msub, inv);
     for (int q = blockIdx.x; q < nsub; q += gridDim.x) {
         const int4 rec = reinterpret_cast<const int4 *>(sub)[q];
+        int p1 = g.m[0] + 2 * P, p2 = g.m[1] + 2 * P;
+        if constexpr (BATCH) {
+            const TGeom &tt =
+                tg[find_transform(tg, T_, rec.x, [](const TGeom &a) { return a.bin_off; })];
+            p1 = tt.m[0] + 2 * P;
+            p2 = tt.m[1] + 2 * P;
+        }
         for (int e = threadIdx.x; e < ts2; e += blockDim.x) tile[e] = 0ull;
         __syncthreads();
         const int end = rec.y + rec.z;
@@ -418,21 +425,38 @@ k_tile_merge(const int32_t *__restrict__ nmergep, const int32_t *__restrict__ me
 // lists for grid index l the pairs (bin index, offset in that bin's padded
 // tile) that land on l, up to kmax_i of them (unused entries have bin -1).
 // Bins with more than G tiles are read through their merged leaders.
-template <typename T, int DIM>
+template <typename T, int DIM, bool BATCH>
 __global__ void __launch_bounds__(kThreads)
 k_tile_gather(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__ scratch,
-              int ts2, int G, const int2 *__restrict__ cov0, const int2 *__restrict__ cov1,
-              const int2 *__restrict__ cov2, int k0, int k1, int k2, int P,
-              typename Cplx<T>::type *__restrict__ grid)
+              int ts2, int G, const int2 *__restrict__ cov0_, const int2 *__restrict__ cov1_,
+              const int2 *__restrict__ cov2_, int k0_, int k1_, int k2_, int P,
+              typename Cplx<T>::type *__restrict__ grid, long long ncell_all,
+              const TGeom *__restrict__ tg, int T_)
 {
-    const int p1 = g.m[0] + 2 * P, p2 = g.m[1] + 2 * P;
-    const size_t ncell = (size_t)g.n[0] * g.n[1] * (DIM == 3 ? g.n[2] : 1);
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < ncell;
-         e += (size_t)gridDim.x * blockDim.x) {
-        const int l1 = (int)(e % g.n[0]);
-        const size_t r = e / g.n[0];
-        const int l2 = (int)(r % g.n[1]);
-        const int l3 = DIM == 3 ? (int)(r / g.n[1]) : 0;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < ncell_all;
+         e += (long long)gridDim.x * blockDim.x) {
+        Geom gg = g;
+        const int2 *cov0 = cov0_, *cov1 = cov1_, *cov2 = cov2_;
+        int k0 = k0_, k1 = k1_, k2 = k2_, boff = 0;
+        long long el = e;
+        if constexpr (BATCH) {
+            const TGeom &tt =
+                tg[find_transform(tg, T_, e, [](const TGeom &a) { return a.grid_off; })];
+            gg = geom_of(g, tt);
+            cov0 = cov0_ + tt.cov_off[0];
+            cov1 = cov1_ + tt.cov_off[1];
+            cov2 = DIM == 3 ? cov2_ + tt.cov_off[2] : cov2_;
+            k0 = tt.kmax[0];
+            k1 = tt.kmax[1];
+            k2 = tt.kmax[2];
+            boff = tt.bin_off;
+            el = e - tt.grid_off;
+        }
+        const int p1 = gg.m[0] + 2 * P, p2 = gg.m[1] + 2 * P;
+        const int l1 = (int)(el % gg.n[0]);
+        const long long r = el / gg.n[0];
+        const int l2 = (int)(r % gg.n[1]);
+        const int l3 = DIM == 3 ? (int)(r / gg.n[1]) : 0;
         T ar = 0, ai = 0;
         for (int j3 = 0; j3 < (DIM == 3 ? k2 : 1); ++j3) {
             int nb3 = 0, s3 = 0;
@@ -448,7 +472,7 @@ k_tile_gather(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__ 
                 for (int j1 = 0; j1 < k0; ++j1) {
                     const int2 c1 = cov0[(size_t)l1 * k0 + j1];
                     if (c1.x < 0) break;
-                    const int b = c1.x + g.B[0] * (c2.x + g.B[1] * nb3);
+                    const int b = boff + c1.x + gg.B[0] * (c2.x + gg.B[1] * nb3);
                     const int first = suboff[b], k = suboff[b + 1] - first;
                     const int step = k > G ? G : 1;
                     const size_t off = 2 * ((size_t)c1.y + (size_t)p1 * (c2.y + (size_t)p2 * s3));
@@ -469,35 +493,45 @@ k_tile_gather(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__ 
 
 // SM interpolation: stage the padded bin in LDS, then every point of the
 // subproblem reads its w^d values there.
-template <typename T, int DIM, int W>
+template <typename T, int DIM, int W, bool BATCH>
 __global__ void __launch_bounds__(kThreads)
 k_interp_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__ nsubp,
             const T *__restrict__ u0, const T *__restrict__ u1, const T *__restrict__ u2,
-            const int32_t *__restrict__ perm, const typename Cplx<T>::type *__restrict__ grid,
-            typename Cplx<T>::type *__restrict__ c, T bk)
+            const int32_t *__restrict__ perm, const typename Cplx<T>::type *__restrict__ grid_,
+            typename Cplx<T>::type *__restrict__ c, T bk, const TGeom *__restrict__ tg, int T_)
 {
     using C = typename Cplx<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *tile = reinterpret_cast<C *>(smem_raw);
     constexpr int P = (W + 1) / 2;
-    const int p1 = g.m[0] + 2 * P, p2 = g.m[1] + 2 * P;
-    const int p3 = DIM == 3 ? g.m[2] + 2 * P : 1;
-    const int tsize = p1 * p2 * p3;
     const int nsub = *nsubp;
     for (int q = blockIdx.x; q < nsub; q += gridDim.x) {
         const int4 rec = reinterpret_cast<const int4 *>(sub)[q];
         int b = rec.x;
-        const int bx = b % g.B[0]; b /= g.B[0];
-        const int by = b % g.B[1]; b /= g.B[1];
+        Geom gg = g;
+        const C *grid = grid_;
+        if constexpr (BATCH) {
+            const TGeom &tt =
+                tg[find_transform(tg, T_, rec.x, [](const TGeom &a) { return a.bin_off; })];
+            gg = geom_of(g, tt);
+            grid = grid_ + tt.grid_off;
+            b -= tt.bin_off;
+        }
+        const int p1 = gg.m[0] + 2 * P, p2 = gg.m[1] + 2 * P;
+        const int p3 = DIM == 3 ? gg.m[2] + 2 * P : 1;
+        const int tsize = p1 * p2 * p3;
+        const int bx = b % gg.B[0]; b /= gg.B[0];
+        const int by = b % gg.B[1]; b /= gg.B[1];
         const int bz = b;
-        const int o1 = bx * g.m[0] - P, o2 = by * g.m[1] - P, o3 = DIM == 3 ? bz * g.m[2] - P : 0;
+        const int o1 = bx * gg.m[0] - P, o2 = by * gg.m[1] - P;
+        const int o3 = DIM == 3 ? bz * gg.m[2] - P : 0;
         for (int e = threadIdx.x; e < tsize; e += blockDim.x) {
             const int s1 = e % p1, r = e / p1;
             const int s2 = r % p2, s3 = r / p2;
-            const int l1 = wrapmod(o1 + s1, g.n[0]);
-            const int l2 = wrapmod(o2 + s2, g.n[1]);
-            const int l3 = DIM == 3 ? wrapmod(o3 + s3, g.n[2]) : 0;
-            tile[e] = grid[((size_t)l3 * g.n[1] + l2) * g.n[0] + l1];
+            const int l1 = wrapmod(o1 + s1, gg.n[0]);
+            const int l2 = wrapmod(o2 + s2, gg.n[1]);
+            const int l3 = DIM == 3 ? wrapmod(o3 + s3, gg.n[2]) : 0;
+            tile[e] = grid[((size_t)l3 * gg.n[1] + l2) * gg.n[0] + l1];
         }
         __syncthreads();
         const int end = rec.y + rec.z;
@@ -564,7 +598,6 @@ template <> inline double kernel_param<double>(double beta) { return beta; }
 // Persistent grid size for the subproblem loops.
 inline int sm_grid(const Pts &P) { return std::max(1, std::min(P.nsub_max, 256 * 16)); }
 
-// part: bit 0 = accumulate (all methods), bit 1 = SM add-back (merge + gather).
 // ----------------------------------------------------------------------------
 // Position gradient by ES-derivative interpolation.  For a field b on the
 // fine grid and weights v_j (one complex per point), with
@@ -693,14 +726,16 @@ hipError_t grad_dim(const Geom &g, const Pts &P, int ntransf, const void *grid, 
     return hipErrorInvalidValue;
 }
 
-template <typename T, int DIM, int W>
-hipError_t spread_w(const Geom &g, int method, const Pts &P, const void *c, void *grid,
-                    hipStream_t s, size_t lds, int part)
+// part: bit 0 = accumulate (all methods), bit 1 = SM add-back (merge + gather),
+// bit 2 = SM max|c| pre-pass.  P.tg != nullptr selects the batched kernels.
+template <typename T, int DIM, int W, bool BATCH>
+hipError_t spread_wb(const Geom &g, int method, const Pts &P, const void *c, void *grid,
+                     hipStream_t s, size_t lds, int part)
 {
     using C = typename Cplx<T>::type;
     const T bk = kernel_param<T>(g.beta);
     if (method == 3) {
-        auto kern = k_spread_sm<T, DIM, W>;
+        auto kern = k_spread_sm<T, DIM, W, BATCH>;
         if (part & 4) {
             hipLaunchKernelGGL(k_maxabs<T>, dim3(std::max(1, std::min(cdiv(P.M, kThreads), kMaxParts))),
                                dim3(kThreads), 0, s, (const C *)c, P.M, (T *)P.cmax);
@@ -713,7 +748,8 @@ hipError_t spread_w(const Geom &g, int method, const Pts &P, const void *c, void
             while ((1 << lg) < P.msub) ++lg;
             hipLaunchKernelGGL(kern, dim3(sm_grid(P)), dim3(kThreads), lds, s, g, P.sub, P.nsub,
                                (const T *)P.u[0], (const T *)P.u[1], (const T *)P.u[2], P.perm,
-                               (const C *)c, (const T *)P.cmax, lg, (T *)P.scratch, P.ts2, bk);
+                               (const C *)c, (const T *)P.cmax, lg, (T *)P.scratch, P.ts2, bk,
+                               P.tg, P.T);
         }
         if (!(part & 2)) return hipGetLastError();
         const int nvec = P.ts2 / (16 / (int)sizeof(T));
@@ -721,11 +757,12 @@ hipError_t spread_w(const Geom &g, int method, const Pts &P, const void *c, void
         const int mgrid = std::max(1, std::min(P.nsub_max / std::max(P.G, 1) * nchunk + nchunk, 8192));
         hipLaunchKernelGGL(k_tile_merge<T>, dim3(mgrid), dim3(kThreads), 0, s, P.nmerge,
                            P.mergelist, P.sub, P.suboff, (T *)P.scratch, P.ts2, P.G);
-        const size_t ncell = (size_t)g.n[0] * g.n[1] * (DIM == 3 ? g.n[2] : 1);
-        const int ggrid = (int)std::min<size_t>((ncell + kThreads - 1) / kThreads, 16384);
-        hipLaunchKernelGGL((k_tile_gather<T, DIM>), dim3(ggrid), dim3(kThreads), 0, s, g,
-                           P.suboff, (const T *)P.scratch, P.ts2, P.G, P.cov[0], P.cov[1],
-                           P.cov[2], P.kmax[0], P.kmax[1], P.kmax[2], (W + 1) / 2, (C *)grid);
+        const long long ncell = P.ncells;
+        const int ggrid = (int)std::min<long long>((ncell + kThreads - 1) / kThreads, 16384);
+        hipLaunchKernelGGL((k_tile_gather<T, DIM, BATCH>), dim3(std::max(ggrid, 1)), dim3(kThreads),
+                           0, s, g, P.suboff, (const T *)P.scratch, P.ts2, P.G, P.cov[0], P.cov[1],
+                           P.cov[2], P.kmax[0], P.kmax[1], P.kmax[2], (W + 1) / 2, (C *)grid, ncell,
+                           P.tg, P.T);
     } else if (part & 1) {
         const bool gm = method == 1;
         hipLaunchKernelGGL((k_spread_gm<T, DIM, W>), dim3(cdiv(P.M, kThreads)), dim3(kThreads),
@@ -739,19 +776,27 @@ hipError_t spread_w(const Geom &g, int method, const Pts &P, const void *c, void
 }
 
 template <typename T, int DIM, int W>
-hipError_t interp_w(const Geom &g, int method, const Pts &P, const void *grid, void *c,
-                    hipStream_t s, size_t lds)
+hipError_t spread_w(const Geom &g, int method, const Pts &P, const void *c, void *grid,
+                    hipStream_t s, size_t lds, int part)
+{
+    if (P.tg) return spread_wb<T, DIM, W, true>(g, method, P, c, grid, s, lds, part);
+    return spread_wb<T, DIM, W, false>(g, method, P, c, grid, s, lds, part);
+}
+
+template <typename T, int DIM, int W, bool BATCH>
+hipError_t interp_wb(const Geom &g, int method, const Pts &P, const void *grid, void *c,
+                     hipStream_t s, size_t lds)
 {
     using C = typename Cplx<T>::type;
     const T bk = kernel_param<T>(g.beta);
     if (method == 3) {
-        auto kern = k_interp_sm<T, DIM, W>;
+        auto kern = k_interp_sm<T, DIM, W, BATCH>;
         if (lds > 65536)
             (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds);
+                                      (int)lds);
         hipLaunchKernelGGL(kern, dim3(sm_grid(P)), dim3(kThreads), lds, s, g, P.sub, P.nsub,
                            (const T *)P.u[0], (const T *)P.u[1], (const T *)P.u[2], P.perm,
-                           (const C *)grid, (C *)c, bk);
+                           (const C *)grid, (C *)c, bk, P.tg, P.T);
     } else {
         const bool gm = method == 1;
         hipLaunchKernelGGL((k_interp_gm<T, DIM, W>), dim3(cdiv(P.M, kThreads)), dim3(kThreads),
@@ -762,6 +807,14 @@ hipError_t interp_w(const Geom &g, int method, const Pts &P, const void *grid, v
                            (const C *)grid, (C *)c, bk);
     }
     return hipGetLastError();
+}
+
+template <typename T, int DIM, int W>
+hipError_t interp_w(const Geom &g, int method, const Pts &P, const void *grid, void *c,
+                    hipStream_t s, size_t lds)
+{
+    if (P.tg) return interp_wb<T, DIM, W, true>(g, method, P, grid, c, s, lds);
+    return interp_wb<T, DIM, W, false>(g, method, P, grid, c, s, lds);
 }
 
 template <typename T, int DIM>

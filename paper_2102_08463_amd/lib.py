@@ -27,7 +27,13 @@ EXPORTS = (
     "mnufft_get_sort",
     "mnufft_get_subproblems", "mnufft_get_info", "mnufft_destroy", "mnufft_strerror",
     "mnufft_choose_params", "mnufft_correction_factors", "mnufft_set_timing", "mnufft_get_timing",
+    "mnufft_batch_makeplan", "mnufft_batch_setpts", "mnufft_batch_execute",
+    "mnufft_batch_set_timing", "mnufft_batch_get_timing", "mnufft_batch_get_totals",
+    "mnufft_batch_destroy", "mnufft_tune_candidates", "mnufft_tune_time",
+    "mnufft_density_features", "mnufft_mlp_nparams", "mnufft_mlp_forward",
+    "mnufft_mlp_loss_grad", "mnufft_mlp_backward", "mnufft_mlp_adam",
 )
+DENSITY_WORK_BYTES = 512 * 256 * 4
 
 
 STAGES = ("setpts", "zero", "spread", "fft", "deconv", "precorrect", "interp", "addback", "scale")
@@ -105,8 +111,32 @@ def load():
     L.mnufft_set_timing.argtypes = [vp, ci]
     L.mnufft_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(i64), ci]
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    L.mnufft_batch_makeplan.argtypes = [ci, ci, ci, ctypes.POINTER(i64), ctypes.POINTER(i64), ci,
+                                        ctypes.c_double, ci, i32p, i32p, ctypes.POINTER(Opts),
+                                        ctypes.POINTER(vp)]
+    L.mnufft_batch_setpts.argtypes = [vp, vp, vp, vp]
+    L.mnufft_batch_execute.argtypes = [vp, vp, vp]
+    L.mnufft_batch_set_timing.argtypes = [vp, ci]
+    L.mnufft_batch_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(i64), ci]
+    L.mnufft_batch_get_totals.argtypes = [vp, ctypes.POINTER(i64)]
+    L.mnufft_batch_destroy.argtypes = [vp]
+    L.mnufft_tune_candidates.argtypes = [ci, ci, ctypes.c_double, ctypes.POINTER(Opts), ci]
+    L.mnufft_tune_time.argtypes = [ci, ci, ctypes.POINTER(i64), ci, ctypes.c_double, ci, i64, vp, vp,
+                                   vp, vp, vp, ctypes.POINTER(Opts), ci, ci, ctypes.c_double,
+                                   ctypes.POINTER(ctypes.c_double)]
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.mnufft_density_features.argtypes = [ci, i64, vp, vp, vp, vp, vp]
+    L.mnufft_mlp_nparams.argtypes = [ci, ci, ci]
+    L.mnufft_mlp_forward.argtypes = [ci, ci, ci, vp, ci, vp, vp, vp, vp, vp]
+    L.mnufft_mlp_loss_grad.argtypes = [ci, ci, vp, vp, vp, vp, vp, vp]
+    L.mnufft_mlp_backward.argtypes = [ci, ci, ci, vp, ci, vp, vp, vp, vp, vp, vp, vp]
+    L.mnufft_mlp_adam.argtypes = [i64, vp, vp, vp, vp, ctypes.c_float, ctypes.c_float,
+                                  ctypes.c_float, ctypes.c_float, ci, vp]
     for name in EXPORTS:
         getattr(L, name).restype = ctypes.c_char_p if name == "mnufft_strerror" else ci
+    L.mnufft_mlp_nparams.restype = ctypes.c_int64
     _lib = L
     return L
 
@@ -145,3 +175,19 @@ def correction_factors(N, n, w, beta):
     check(load().mnufft_correction_factors(int(N), int(n), int(w), float(beta), out),
           "mnufft_correction_factors")
     return list(out)
+
+
+def tune_candidates(dim, prec, eps):
+    """The autotuner's candidate options (list of Opts), in the library's order."""
+    n = check(load().mnufft_tune_candidates(int(dim), int(prec), float(eps), None, 0),
+              "mnufft_tune_candidates")
+    arr = (Opts * max(n, 1))()
+    check(load().mnufft_tune_candidates(int(dim), int(prec), float(eps), arr, n),
+          "mnufft_tune_candidates")
+    return [arr[i] for i in range(n)]
+
+
+def describe(o):
+    """Short text form of a candidate's method / bins / msub."""
+    name = {METHOD_AUTO: "auto", METHOD_GM: "gm", METHOD_GMSORT: "gmsort", METHOD_SM: "sm"}[o.method]
+    return f"{name}:{'x'.join(str(b) for b in o.binsize if b)}:{o.msub}"

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _header_functions():
     txt = open(os.path.join(ROOT, "include", "mnufft.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:const\s+char\s*\*\s*|int\s+)(mnufft_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:const\s+char\s*\*\s*|int\s+|int64_t\s+)(mnufft_\w+)\s*\(", txt, re.M)))
 
 
 def test_exports_match_header():
@@ -135,3 +135,30 @@ def test_correction_factors_reject():
                  (8, 16, 6, 0.0)):
         with pytest.raises(L.MnufftError):
             L.correction_factors(*args)
+
+
+def test_batch_makeplan_rejects_bad_arguments():
+    lib = L.load()
+
+    def mk(type_=1, dim=2, ntr=2, nm=(8, 8, 1, 9, 7, 1), npts=(10, 20), iflag=-1, eps=1e-5,
+           prec=0, bs=None, ms=None, opts=None):
+        h = ctypes.c_void_p(0)
+        nma = (ctypes.c_int64 * len(nm))(*nm)
+        npa = (ctypes.c_int64 * len(npts))(*npts)
+        bsa = (ctypes.c_int32 * len(bs))(*bs) if bs else None
+        msa = (ctypes.c_int32 * len(ms))(*ms) if ms else None
+        rc = lib.mnufft_batch_makeplan(type_, dim, ntr, nma, npa, iflag, eps, prec, bsa, msa,
+                                       ctypes.byref(opts) if opts else None, ctypes.byref(h))
+        return rc, h
+
+    for kw in (dict(type_=3), dict(dim=1), dict(ntr=0), dict(iflag=0), dict(eps=1.5),
+               dict(prec=7), dict(nm=(0, 8, 1, 9, 7, 1)), dict(npts=(-1, 5)),
+               dict(bs=(8, -8, 1, 8, 8, 1)), dict(ms=(10, -1))):
+        rc, h = mk(**kw)
+        assert rc == L.ERR_ARG and not h.value, kw
+    o = L.default_opts()
+    o.method = L.METHOD_GMSORT
+    assert mk(opts=o)[0] == L.ERR_UNSUPPORTED
+    assert lib.mnufft_batch_destroy(ctypes.c_void_p(0)) == L.OK
+    assert lib.mnufft_batch_setpts(ctypes.c_void_p(0), None, None, None) == L.ERR_ARG
+    assert lib.mnufft_batch_execute(ctypes.c_void_p(0), None, None) == L.ERR_ARG
