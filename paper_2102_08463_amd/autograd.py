@@ -6,7 +6,9 @@ Backward passes run in the library:
   type 1, f = A(x) c:  grad_c = A^H g       (adjoint execute: type 2, sign -s)
                        grad_x = Re(conj(c) d/dx [type 2, sign -s, of g])
 with complex gradients in torch's convention g = dL/dRe + i dL/dIm.
-The plan (and its bin-sort) is made in forward and reused by backward.
+The plan (and its bin-sort) is made in forward and reused by backward; it
+lives as long as the autograd graph holds the context (backward may run more
+than once with retain_graph) and is freed with it.
 """
 import torch
 
@@ -44,7 +46,6 @@ class _Type2(torch.autograd.Function):
             gr = plan.interp_grad(fc, gc)
             gx, gy = gr[0], gr[1]
             gz = gr[2] if ctx.dim == 3 else None
-        plan.destroy()
         return gf, None, None, None, gx, gy, gz
 
 
@@ -74,7 +75,6 @@ class _Type1(torch.autograd.Function):
             gr = plan.interp_grad(gf, cc)
             gx, gy = gr[0], gr[1]
             gz = gr[2] if ctx.dim == 3 else None
-        plan.destroy()
         return gc, None, None, None, None, gx, gy, gz
 
 
