@@ -101,9 +101,22 @@ def main():
     ap.add_argument("--method", default="auto")
     ap.add_argument("--binsize", default=None, help="comma-separated bin extents")
     ap.add_argument("--msub", type=int, default=0)
-    ap.add_argument("--cpu-sample", type=int, default=1_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=10_000_000,
+                    help="points the oracle is timed on (capped at M); 1e7 is about 20-30 "
+                         "CPU-seconds on 16 host threads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(args.copy_calibration * (1 << 18), dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4, "launches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the "
               f"multi-GPU path is a design, not part of this build.", file=sys.stderr)

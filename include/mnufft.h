@@ -62,9 +62,12 @@ extern "C" {
 
 typedef struct mnufft_opts {
     int   method;       /* MNUFFT_METHOD_*; default AUTO */
-    int   binsize[3];   /* bin extents m_i in fine-grid cells; 0 selects the default
-                           (32 x 32 in 2D, 16 x 16 x 2 in 3D: Sec. III-A, first remark) */
-    int   msub;         /* max points per subproblem, > 0; 0 selects 1024 (same remark) */
+    int   binsize[3];   /* bin extents m_i in fine-grid cells; 0 selects the default,
+                           32 x 32 in 2D and 8 x 8 x 8 in 3D (measured on gfx950; the
+                           paper's V100 choice was 32 x 32 and 16 x 16 x 2, Sec. III-A,
+                           first remark) */
+    int   msub;         /* max points per subproblem, > 0; 0 selects 4096 (the paper
+                           used 1024, same remark) */
     int   validate_pts; /* nonzero: setpts checks that every coordinate is finite and
                            in [-3pi, 3pi) and returns MNUFFT_ERR_PTS otherwise (this
                            synchronises the stream) */
@@ -316,9 +319,9 @@ typedef struct mnufft_batch_s *mnufft_batch;
  *   nmodes    host array ntr x 3: N_1, N_2 (, N_3) of transform t at 3t ..
  *   npts      host array ntr: points of each transform (>= 0, total <= 2^31 - 1)
  *   binsize   host array ntr x 3 of bin extents, or NULL; 0 entries take
- *             opts->binsize or the default (32 x 32; 16 x 16 x 8 in 3D)
+ *             opts->binsize or the plan default
  *   msub      host array ntr of subproblem sizes, or NULL; 0 entries take
- *             opts->msub or 1024
+ *             opts->msub or the plan default
  *   opts      NULL or options; method must be AUTO or SM
  * The padded bins of the largest bin extents must fit in LDS.  Errors:
  * ERR_ARG, ERR_UNSUPPORTED (method GM / GMSORT), ERR_ALLOC, ERR_HIP, ERR_FFT;

@@ -194,7 +194,7 @@ int mnufft_batch_makeplan(int type, int dim, int ntr, const int64_t *nmodes, con
     b->g.beta = beta;
     b->g.pad = (w + 1) / 2;
     const int P = b->g.pad;
-    const int defm[2][3] = {{32, 32, 1}, {16, 16, 8}};
+    const int defm[2][3] = {{32, 32, 1}, {8, 8, 8}};
     b->geo.resize(ntr);
     std::vector<double> pf[3];
     std::vector<int2> cv[3];
@@ -239,7 +239,7 @@ int mnufft_batch_makeplan(int type, int dim, int ntr, const int64_t *nmodes, con
         tg.nbins = (int)nb;
         tg.pt_off = (int)pt_off;
         tg.M = (int)npts[t];
-        tg.msub = msub && msub[t] > 0 ? msub[t] : (o.msub > 0 ? o.msub : 1024);
+        tg.msub = msub && msub[t] > 0 ? msub[t] : (o.msub > 0 ? o.msub : 4096);
         tg.grid_off = grid_off;
         tg.mode_off = mode_off;
         b->msub_max = std::max(b->msub_max, tg.msub);

@@ -488,13 +488,13 @@ int mnufft_makeplan(int type, int dim, const int64_t *nmodes, int iflag, int64_t
     p->device = o.device;
     p->validate = o.validate_pts;
     p->stream = (hipStream_t)o.stream;
-    p->msub = o.msub > 0 ? o.msub : 1024;
+    p->msub = o.msub > 0 ? o.msub : 4096;
     mn::Geom &g = p->g;
     g.dim = dim;
     g.w = w;
     g.beta = beta;
     g.pad = (w + 1) / 2;
-    const int defm[2][3] = {{32, 32, 1}, {16, 16, 2}};
+    const int defm[2][3] = {{32, 32, 1}, {8, 8, 8}};
     int64_t nbins = 1;
     for (int d = 0; d < 3; ++d) {
         p->N[d] = d < dim ? nmodes[d] : 1;
