@@ -92,6 +92,79 @@ def cpu_baseline(pts64, c64, f64, modes, eps, sample):
                       f"(same modes and eps), FP64, {dt:.2f} s wall"}
 
 
+SELECTOR_WEIGHTS = os.path.join(ROOT, "paper_2102_08463_amd", "data", "selector_2d_f32_1e-06.npz")
+
+
+def batched_speedup(kind="uniform", ntype=1, reps=3, eps=1e-6):
+    """Batched workload: 64 2D transforms, modes uniform in {64..512}^2, M
+    lognormal (median 2e5, 1e4..4e6), fp32, eps 1e-6.  Plain: one plan per
+    transform with the library defaults, setpts + execute each, in sequence.
+    Batched: one Batch whose per-transform bins / msub come from the learned
+    selector (batched density features + MLP inference, timed and included);
+    without trained weights the defaults are used.  Plan creation is excluded
+    from both.  Returns a dict of times and the speedup."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2102_08463_amd import Batch, Plan, lib as L
+
+    n_modes, n_points = workloads.batch_descriptors(64)
+    pts = [[torch.from_numpy(np.asarray(a, np.float32)).cuda()
+            for a in workloads.points(kind, M, 2, 100 + t)] for t, M in enumerate(n_points)]
+    data = [torch.from_numpy(workloads.strengths(M if ntype == 1 else nm[::-1], 200 + t)
+                             .astype(np.complex64)).cuda().reshape(-1)
+            for t, (M, nm) in enumerate(zip(n_points, n_modes))]
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record()
+        for _ in range(n):
+            out = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n, out
+
+    plans = [Plan(ntype, nm, 1, eps, None, dtype=torch.complex64) for nm in n_modes]
+    def plain():
+        for p, x, d in zip(plans, pts, data):
+            p.setpts(*x)
+            p.execute(d)
+    t_plain, _ = timed(plain, reps)
+    for p in plans:
+        p.destroy()
+
+    cat = [torch.cat([x[d] for x in pts]) for d in range(2)]
+    dcat = torch.cat(data)
+    sel_ms, choice = 0.0, None
+    binsize = msub = None
+    if os.path.exists(SELECTOR_WEIGHTS):
+        from paper_2102_08463_amd.selector import Selector
+        sel = Selector.load(SELECTOR_WEIGHTS)
+        sm = [i for i, o in enumerate(sel.cands) if o.method == L.METHOD_SM]
+        def select():
+            feats = sel.features_batch(ntype, n_modes, cat[0], cat[1], n_points)
+            _, _, Y = sel.forward(feats)
+            y = Y.cpu().numpy()
+            return [min(sm, key=lambda i: y[t][i]) for t in range(len(n_modes))]
+        sel_ms, choice = timed(select, reps)
+        binsize = [tuple(sel.cands[i].binsize[:2]) for i in choice]
+        msub = [sel.cands[i].msub for i in choice]
+    b = Batch(ntype, n_modes, n_points, eps=eps, binsize=binsize, msub=msub)
+    def batched():
+        b.setpts(*cat)
+        b.execute(dcat)
+    t_batch, _ = timed(batched, reps)
+    b.destroy()
+    return {"transforms": len(n_modes), "points": int(sum(n_points)), "kind": kind,
+            "type": ntype, "plain_ms": t_plain, "batched_ms": t_batch, "selector_ms": sel_ms,
+            "selector": "learned" if choice is not None else "defaults",
+            "speedup": t_plain / (t_batch + sel_ms)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +178,8 @@ def main():
                     help="points the oracle is timed on (capped at M); 1e7 is about 20-30 "
                          "CPU-seconds on 16 host threads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-vs-plain speedup measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -225,6 +300,13 @@ def main():
                            + stages["fft"][0] / 2) / K * 1e-3),
         },
     }
+    if not args.no_batched:
+        print("[bench] batched vs plain (64 transforms)", file=sys.stderr, flush=True)
+        runs = [batched_speedup(kind, ntype) for kind, ntype in
+                (("uniform", 1), ("cluster", 1), ("radial", 1), ("uniform", 2))]
+        out["batched_speedup"] = dict(runs[0], others=[
+            {k: r[k] for k in ("kind", "type", "plain_ms", "batched_ms", "selector_ms", "speedup")}
+            for r in runs[1:]])
     if not args.no_cpu_baseline:
         sample = min(args.cpu_sample, M)
         print(f"[bench] timing the oracle on {sample} points", file=sys.stderr, flush=True)

@@ -275,6 +275,16 @@ int mnufft_tune_time(int type, int dim, const int64_t *nmodes, int iflag, double
 int mnufft_density_features(int prec, int64_t M, const void *x, const void *y, float *feat,
                             void *work, void *stream);
 
+/* The same features for T point sets stored back to back: set t is points
+ * off[t] .. off[t+1]-1 of x, y (off: device array of T + 1 nondecreasing
+ * int64, off[0] = 0); its 256 features go to feat + t * ldf (ldf >= 256).
+ * work: device scratch of T * MNUFFT_DENSITY_BATCH_WORK_BYTES bytes.  Two
+ * kernel launches whatever T.  Errors: ERR_ARG (T < 1 or above 65535, NULL
+ * pointers, ldf < 256), ERR_HIP. */
+#define MNUFFT_DENSITY_BATCH_WORK_BYTES (32 * 256 * 4)
+int mnufft_density_features_batch(int prec, int T, const int64_t *off, const void *x,
+                                  const void *y, float *feat, int ldf, void *work, void *stream);
+
 /* A multilayer perceptron F -> H -> H -> K with ReLU after the two hidden
  * layers, in single precision, all arrays on the device, all calls ordered on
  * `stream` (a hipStream_t).  Parameters are one flat array laid out as

@@ -147,6 +147,36 @@ __global__ void k_hist_final(long long M, int nblk, const uint32_t *__restrict__
     feat[c] = M > 0 ? log1pf(256.0f * (float)((double)s / (double)M)) : 0.0f;
 }
 
+// Batched histograms: block (b, t) counts chunk b of kBatchChunks of set t.
+constexpr int kBatchChunks = 32;  // see MNUFFT_DENSITY_BATCH_WORK_BYTES
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_hist_batch(const int64_t *__restrict__ off, const T *__restrict__ x, const T *__restrict__ y,
+             uint32_t *__restrict__ part)
+{
+    __shared__ uint32_t h[256];
+    const int t = blockIdx.y, b = blockIdx.x;
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const long long a = off[t], n = off[t + 1] - a;
+    const long long lo = a + n * b / kBatchChunks, hi = a + n * (b + 1) / kBatchChunks;
+    for (long long j = lo + threadIdx.x; j < hi; j += kThreads)
+        atomicAdd(&h[cell16((double)x[j]) + 16 * cell16((double)y[j])], 1u);
+    __syncthreads();
+    part[((size_t)t * kBatchChunks + b) * 256 + threadIdx.x] = h[threadIdx.x];
+}
+
+__global__ void k_hist_batch_final(const int64_t *__restrict__ off,
+                                   const uint32_t *__restrict__ part, float *__restrict__ feat,
+                                   int ldf)
+{
+    const int t = blockIdx.x, c = threadIdx.x;
+    const long long M = off[t + 1] - off[t];
+    unsigned long long s = 0;
+    for (int b = 0; b < kBatchChunks; ++b) s += part[((size_t)t * kBatchChunks + b) * 256 + c];
+    feat[(size_t)t * ldf + c] = M > 0 ? log1pf(256.0f * (float)((double)s / (double)M)) : 0.0f;
+}
+
 inline int blocks_for(long long n) { return (int)std::max<long long>(1, (n + kThreads - 1) / kThreads); }
 
 }  // namespace
@@ -243,6 +273,26 @@ int mnufft_density_features(int prec, int64_t M, const void *x, const void *y, f
                            (const double *)x, (const double *)y, part);
     hipLaunchKernelGGL(k_hist_final, dim3(1), dim3(256), 0, s, (long long)M, nblk,
                        (const uint32_t *)part, feat);
+    return hipGetLastError() == hipSuccess ? MNUFFT_OK : MNUFFT_ERR_HIP;
+}
+
+int mnufft_density_features_batch(int prec, int T, const int64_t *off, const void *x,
+                                  const void *y, float *feat, int ldf, void *work, void *stream)
+{
+    if ((prec != MNUFFT_F32 && prec != MNUFFT_F64) || T < 1 || T > 65535 || !off || !x || !y ||
+        !feat || !work || ldf < 256)
+        return MNUFFT_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t *part = (uint32_t *)work;
+    const dim3 grid(kBatchChunks, T);
+    if (prec == MNUFFT_F32)
+        hipLaunchKernelGGL(k_hist_batch<float>, grid, dim3(kThreads), 0, s, off,
+                           (const float *)x, (const float *)y, part);
+    else
+        hipLaunchKernelGGL(k_hist_batch<double>, grid, dim3(kThreads), 0, s, off,
+                           (const double *)x, (const double *)y, part);
+    hipLaunchKernelGGL(k_hist_batch_final, dim3(T), dim3(256), 0, s, off,
+                       (const uint32_t *)part, feat, ldf);
     return hipGetLastError() == hipSuccess ? MNUFFT_OK : MNUFFT_ERR_HIP;
 }
 

@@ -26,6 +26,7 @@
 
 
 #include <algorithm>
+#include <type_traits>
 
 namespace mn {
 namespace detail {
@@ -248,19 +249,19 @@ k_maxabs(const typename Cplx<T>::type *__restrict__ c, int M, T *__restrict__ ou
     }
 }
 
-// max over the kMaxParts partial maxima, by one workgroup.
-template <typename T>
+// max over the kMaxParts partial maxima, by one workgroup of NT threads.
+template <typename T, int NT = kThreads>
 __device__ __forceinline__ T block_cmax(const T *__restrict__ parts)
 {
-    __shared__ T red[kThreads / 64];
+    __shared__ T red[NT / 64];
     T m = 0;
-    for (int k = threadIdx.x; k < kMaxParts; k += blockDim.x) m = fmax(m, parts[k]);
+    for (int k = threadIdx.x; k < kMaxParts; k += NT) m = fmax(m, parts[k]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
     m = red[0];
-    for (int k = 1; k < kThreads / 64; ++k) m = fmax(m, red[k]);
+    for (int k = 1; k < NT / 64; ++k) m = fmax(m, red[k]);
     __syncthreads();
     return m;
 }
@@ -386,6 +387,148 @@ k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
                 vals[k] = (T)((double)(long long)tile[e * NV + k] * (double)inv);
             V out;
             __builtin_memcpy(&out, vals, sizeof(V));
+            dst[e] = out;
+        }
+        __syncthreads();
+    }
+}
+
+// SM spreading in 2D single precision with register windows (w <= 8).
+//
+// Same input, output and fixed-point tile as k_spread_sm, with the LDS atomic
+// traffic cut by summing in registers first.  setpts has ordered the points
+// of every subproblem by first tap cell (s_1, s_2), row-major.  Thread t of
+// the workgroup takes the t-th of kThreads equal runs of consecutive points
+// and sums their w x w footprints into a register window of w rows by w + 1
+// columns anchored at a point's first tap cell: a following point whose
+// first tap lies in the same row, at most one cell to the right of the
+// anchor, goes into the same window (its x weights shifted by one column);
+// any other point, or the kWinMax-th one, flushes the window into the LDS
+// tile (one 64-bit integer atomic per cell and part) and re-anchors it.
+// With about two points per fine cell this replaces 2 w^2 atomics per point
+// by about 2 w (w + 1) per window of several points.
+//
+// A window sums at most kWinMax contributions per cell, each at most cmax S
+// in magnitude, so S = 2^26 / 2^ceil(log2 cmax) (kWinMax = 16) keeps a window
+// sum within int32; the quantum 16 cmax 2^-30 stays below single-precision
+// rounding of the grid values.  Runs and the order inside cells are fixed by
+// setpts and the subproblem length, so results are reproducible bit for bit.
+constexpr int kWinMax = 16;
+
+template <int W>
+__device__ __forceinline__ void rw_flush(unsigned long long *__restrict__ tile, int p1, int ax,
+                                         int ay, bool wide, float (&ar)[W][W + 1],
+                                         float (&ai)[W][W + 1])
+{
+#pragma unroll
+    for (int a2 = 0; a2 < W; ++a2) {
+        unsigned long long *row = tile + 2 * ((ay + a2) * p1 + ax);
+#pragma unroll
+        for (int t = 0; t < W + 1; ++t) {
+            if (t < W || wide) {
+                atomicAdd(row + 2 * t, (unsigned long long)(long long)__float2int_rn(ar[a2][t]));
+                atomicAdd(row + 2 * t + 1,
+                          (unsigned long long)(long long)__float2int_rn(ai[a2][t]));
+            }
+            ar[a2][t] = 0.f;
+            ai[a2][t] = 0.f;
+        }
+    }
+}
+
+template <int W, bool BATCH>
+__global__ void __launch_bounds__(kThreads)
+k_spread_smw(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__ nsubp,
+             const float *__restrict__ u0, const float *__restrict__ u1,
+             const int32_t *__restrict__ perm, const float2 *__restrict__ c,
+             const float *__restrict__ cmaxp, float *__restrict__ scratch, int ts2, float bk,
+             const TGeom *__restrict__ tg, int T_)
+{
+    constexpr int P = (W + 1) / 2;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    unsigned long long *tile = reinterpret_cast<unsigned long long *>(smem_raw);
+    const int tid = threadIdx.x;
+    const int nvec = ts2 / 4;
+    const int nsub = *nsubp;
+    float inv;
+    const float S = FixedScale<float>::scale(block_cmax(cmaxp), 0, inv) * (1.0f / kWinMax);
+    inv *= (float)kWinMax;
+    for (int q = blockIdx.x; q < nsub; q += gridDim.x) {
+        const int4 rec = reinterpret_cast<const int4 *>(sub)[q];
+        int p1 = g.m[0] + 2 * P;
+        if constexpr (BATCH) {
+            const TGeom &tt =
+                tg[find_transform(tg, T_, rec.x, [](const TGeom &a) { return a.bin_off; })];
+            p1 = tt.m[0] + 2 * P;
+        }
+        for (int e = tid; e < ts2; e += kThreads) tile[e] = 0ull;
+        __syncthreads();
+        // this thread's run [lo, hi) of the subproblem's points
+        const int lo = rec.y + (int)(((long long)tid * rec.z) / kThreads);
+        const int hi = rec.y + (int)(((long long)(tid + 1) * rec.z) / kThreads);
+        float ar[W][W + 1], ai[W][W + 1];
+#pragma unroll
+        for (int a2 = 0; a2 < W; ++a2)
+#pragma unroll
+            for (int t = 0; t < W + 1; ++t) ar[a2][t] = ai[a2][t] = 0.f;
+        int ax = 0, ay = 0, wc = 0;
+        bool wide = false;
+        // loads run one point ahead (two for the permutation)
+        float nx = 0.f, ny = 0.f;
+        float2 ncv = make_float2(0.f, 0.f);
+        int pn = 0;
+        if (lo < hi) {
+            nx = u0[lo];
+            ny = u1[lo];
+            ncv = c[perm[lo]];
+            if (lo + 1 < hi) pn = perm[lo + 1];
+        }
+        for (int i = lo; i < hi; ++i) {
+            const float x = nx + (float)P, y = ny + (float)P;
+            const float cr = ncv.x * S, ci = ncv.y * S;
+            if (i + 1 < hi) {
+                nx = u0[i + 1];
+                ny = u1[i + 1];
+                ncv = c[pn];
+                if (i + 2 < hi) pn = perm[i + 2];
+            }
+            float kx[W], ky[W];
+            const int sx = taps<float, W>(x, bk, kx);
+            const int sy = taps<float, W>(y, bk, ky);
+            int dx = sx - ax;
+            if (wc == 0 || sy != ay || dx < 0 || dx > 1 || wc == kWinMax) {
+                if (wc > 0) rw_flush<W>(tile, p1, ax, ay, wide, ar, ai);
+                ax = sx;
+                ay = sy;
+                dx = 0;
+                wc = 0;
+                wide = false;
+            }
+            ++wc;
+            wide = wide || dx != 0;
+            float ks[W + 1];
+#pragma unroll
+            for (int t = 0; t < W + 1; ++t)
+                ks[t] = dx ? (t > 0 ? kx[t - 1] : 0.f) : (t < W ? kx[t] : 0.f);
+#pragma unroll
+            for (int a2 = 0; a2 < W; ++a2) {
+                const float wr = cr * ky[a2], wi = ci * ky[a2];
+#pragma unroll
+                for (int t = 0; t < W + 1; ++t) {
+                    ar[a2][t] += wr * ks[t];
+                    ai[a2][t] += wi * ks[t];
+                }
+            }
+        }
+        if (wc > 0) rw_flush<W>(tile, p1, ax, ay, wide, ar, ai);
+        __syncthreads();
+        float4 *dst = reinterpret_cast<float4 *>(scratch + (size_t)q * ts2);
+        for (int e = tid; e < nvec; e += kThreads) {
+            float4 out;
+            out.x = (float)((double)(long long)tile[4 * e] * (double)inv);
+            out.y = (float)((double)(long long)tile[4 * e + 1] * (double)inv);
+            out.z = (float)((double)(long long)tile[4 * e + 2] * (double)inv);
+            out.w = (float)((double)(long long)tile[4 * e + 3] * (double)inv);
             dst[e] = out;
         }
         __syncthreads();
@@ -741,15 +884,26 @@ hipError_t spread_wb(const Geom &g, int method, const Pts &P, const void *c, voi
                                dim3(kThreads), 0, s, (const C *)c, P.M, (T *)P.cmax);
         }
         if (part & 1) {
-            if (lds > 65536)
-                (void)hipFuncSetAttribute((const void *)kern,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            int lg = 0;
-            while ((1 << lg) < P.msub) ++lg;
-            hipLaunchKernelGGL(kern, dim3(sm_grid(P)), dim3(kThreads), lds, s, g, P.sub, P.nsub,
-                               (const T *)P.u[0], (const T *)P.u[1], (const T *)P.u[2], P.perm,
-                               (const C *)c, (const T *)P.cmax, lg, (T *)P.scratch, P.ts2, bk,
-                               P.tg, P.T);
+            if constexpr (std::is_same<T, float>::value && DIM == 2 && W <= 8) {
+                auto rk = k_spread_smw<W, BATCH>;
+                if (lds > 65536)
+                    (void)hipFuncSetAttribute((const void *)rk,
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                hipLaunchKernelGGL(rk, dim3(sm_grid(P)), dim3(kThreads), lds, s, g, P.sub,
+                                   P.nsub, (const float *)P.u[0], (const float *)P.u[1], P.perm,
+                                   (const float2 *)c, (const float *)P.cmax, (float *)P.scratch,
+                                   P.ts2, (float)bk, P.tg, P.T);
+            } else {
+                if (lds > 65536)
+                    (void)hipFuncSetAttribute((const void *)kern,
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                int lg = 0;
+                while ((1 << lg) < P.msub) ++lg;
+                hipLaunchKernelGGL(kern, dim3(sm_grid(P)), dim3(kThreads), lds, s, g, P.sub,
+                                   P.nsub, (const T *)P.u[0], (const T *)P.u[1], (const T *)P.u[2],
+                                   P.perm, (const C *)c, (const T *)P.cmax, lg, (T *)P.scratch,
+                                   P.ts2, bk, P.tg, P.T);
+            }
         }
         if (!(part & 2)) return hipGetLastError();
         const int nvec = P.ts2 / (16 / (int)sizeof(T));

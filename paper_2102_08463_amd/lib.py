@@ -30,10 +30,11 @@ EXPORTS = (
     "mnufft_batch_makeplan", "mnufft_batch_setpts", "mnufft_batch_execute",
     "mnufft_batch_set_timing", "mnufft_batch_get_timing", "mnufft_batch_get_totals",
     "mnufft_batch_destroy", "mnufft_tune_candidates", "mnufft_tune_time",
-    "mnufft_density_features", "mnufft_mlp_nparams", "mnufft_mlp_forward",
+    "mnufft_density_features", "mnufft_density_features_batch", "mnufft_mlp_nparams", "mnufft_mlp_forward",
     "mnufft_mlp_loss_grad", "mnufft_mlp_backward", "mnufft_mlp_adam",
 )
 DENSITY_WORK_BYTES = 512 * 256 * 4
+DENSITY_BATCH_WORK_BYTES = 32 * 256 * 4  # per point set
 
 
 STAGES = ("setpts", "zero", "spread", "fft", "deconv", "precorrect", "interp", "addback", "scale")
@@ -128,6 +129,7 @@ def load():
                                    ctypes.POINTER(ctypes.c_double)]
     fp = ctypes.POINTER(ctypes.c_float)
     L.mnufft_density_features.argtypes = [ci, i64, vp, vp, vp, vp, vp]
+    L.mnufft_density_features_batch.argtypes = [ci, ci, vp, vp, vp, vp, ci, vp, vp]
     L.mnufft_mlp_nparams.argtypes = [ci, ci, ci]
     L.mnufft_mlp_forward.argtypes = [ci, ci, ci, vp, ci, vp, vp, vp, vp, vp]
     L.mnufft_mlp_loss_grad.argtypes = [ci, ci, vp, vp, vp, vp, vp, vp]

@@ -63,11 +63,38 @@ class Selector:
         L.check(self._lib.mnufft_density_features(prec, M, _vp(points[0]), _vp(points[1]),
                                                   _vp(feat), _vp(self._work), self._stream()),
                 "mnufft_density_features")
+        feat[F_HIST:] = torch.tensor(self._scalars(nufft_type, n_modes, M), dtype=torch.float32)
+        return feat
+
+    def _scalars(self, nufft_type, n_modes, M):
         w, _, _, _ = L.choose_params(self.eps, self.prec, 1)
         ns = [L.choose_params(self.eps, self.prec, N)[2] for N in n_modes] + [1] * (3 - len(n_modes))
-        scal = [math.log2(max(M, 1)) / 24.0] + [math.log2(n) / 12.0 if n > 1 else 0.0 for n in ns] \
+        return [math.log2(max(M, 1)) / 24.0] + [math.log2(n) / 12.0 if n > 1 else 0.0 for n in ns] \
             + [w / 16.0, float(nufft_type - 1)]
-        feat[F_HIST:] = torch.tensor(scal, dtype=torch.float32)
+
+    def features_batch(self, nufft_type, n_modes_list, x, y, counts):
+        """(T, F) float32 device features of T point sets stored back to back in
+        x, y (counts[t] points each): one batched histogram launch pair, one
+        host-to-device copy of the scalar features."""
+        T = len(counts)
+        off = torch.zeros((T + 1,), dtype=torch.int64)
+        off[1:] = torch.cumsum(torch.tensor([int(m) for m in counts], dtype=torch.int64), 0)
+        off = off.to(self.device)
+        feat = torch.empty((T, F), dtype=torch.float32, device=self.device)
+        work = torch.empty((T * L.DENSITY_BATCH_WORK_BYTES // 4,), dtype=torch.int32,
+                           device=self.device)
+        prec = L.F32 if x.dtype == torch.float32 else L.F64
+        L.check(self._lib.mnufft_density_features_batch(prec, T, _vp(off), _vp(x), _vp(y),
+                                                        _vp(feat), F, _vp(work), self._stream()),
+                "mnufft_density_features_batch")
+        memo = {}
+        scal = []
+        for nm, M in zip(n_modes_list, counts):
+            key = tuple(nm)
+            if key not in memo:
+                memo[key] = self._scalars(nufft_type, nm, 1)[1:]
+            scal.append([math.log2(max(int(M), 1)) / 24.0] + memo[key])
+        feat[:, F_HIST:] = torch.tensor(scal, dtype=torch.float32).to(self.device)
         return feat
 
     # -- network -----------------------------------------------------------
