@@ -393,6 +393,120 @@ k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
     }
 }
 
+// SM spreading in single precision with one LDS atomic per tap.
+//
+// Same input and output as k_spread_sm<float>, but both parts of a cell share
+// one 64-bit LDS word: with a scale S, a contribution (a, b) becomes the
+// integers r = round(a S), i = round(b S) and the word is incremented by
+// i 2^32 + r (modulo 2^64).  Integer addition is exact, so the word holds
+// (sum i) 2^32 + (sum r) as long as both sums stay within int32, and the two
+// sums are read back from its low (signed) and high halves.  The scale is
+// chosen per subproblem from A = max(sum_j |Re c_j|, sum_j |Im c_j|) over its
+// points: since the kernel is at most 1, no cell of the subproblem can gather
+// more than A, and S = 2^29 / 2^ceil(log2 A) leaves a factor two for the
+// rounding of A and of the contributions.  The quantum 1 / S <= A 2^-28
+// tracks the subproblem's own strengths.  This halves the atomics of the
+// 64-bit two-word tile, which bound 3D spreading, and halves its LDS.
+template <typename T, int DIM, int W, bool BATCH>
+__global__ void __launch_bounds__(kThreads)
+k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__ nsubp,
+             const float *__restrict__ u0, const float *__restrict__ u1,
+             const float *__restrict__ u2, const int32_t *__restrict__ perm,
+             const float2 *__restrict__ c, float *__restrict__ scratch, int ts2, float bk,
+             const TGeom *__restrict__ tg, int T_)
+{
+    static_assert(std::is_same<T, float>::value, "single precision only");
+    constexpr int P = (W + 1) / 2;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    unsigned long long *tile = reinterpret_cast<unsigned long long *>(smem_raw);  // ts2 / 2 cells
+    __shared__ float red[2][kThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int ncell = ts2 / 2;
+    const int nsub = *nsubp;
+    for (int q = blockIdx.x; q < nsub; q += gridDim.x) {
+        const int4 rec = reinterpret_cast<const int4 *>(sub)[q];
+        int p1 = g.m[0] + 2 * P, p2 = g.m[1] + 2 * P;
+        if constexpr (BATCH) {
+            const TGeom &tt =
+                tg[find_transform(tg, T_, rec.x, [](const TGeom &a) { return a.bin_off; })];
+            p1 = tt.m[0] + 2 * P;
+            p2 = tt.m[1] + 2 * P;
+        }
+        const int end = rec.y + rec.z;
+        // scale of this subproblem
+        float sr = 0.f, si = 0.f;
+        for (int i = rec.y + tid; i < end; i += kThreads) {
+            const float2 cv = c[perm[i]];
+            sr += fabsf(cv.x);
+            si += fabsf(cv.y);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            sr += __shfl_xor(sr, o, 64);
+            si += __shfl_xor(si, o, 64);
+        }
+        if (lane == 0) {
+            red[0][wv] = sr;
+            red[1][wv] = si;
+        }
+        for (int e = tid; e < ncell; e += kThreads) tile[e] = 0ull;
+        __syncthreads();
+        float A = 0.f;
+        for (int k = 0; k < kThreads / 64; ++k) A = fmaxf(A, fmaxf(red[0][k], red[1][k]));
+        int ea;
+        frexpf(A, &ea);  // A < 2^ea
+        const float S = ldexpf(1.0f, 29 - ea), inv = ldexpf(1.0f, ea - 29);
+        for (int i = rec.y + tid; i < end; i += kThreads) {
+            float kx[W], ky[W];
+            const int sx = taps<float, W>(u0[i] + (float)P, bk, kx);
+            const int sy = taps<float, W>(u1[i] + (float)P, bk, ky);
+            const float2 cv = c[perm[i]];
+            const float cr0 = cv.x * S, ci0 = cv.y * S;
+            auto row_add = [&](unsigned long long *row, float wr, float wi) {
+#pragma unroll
+                for (int a1 = 0; a1 < W; ++a1) {
+                    const int r = __float2int_rn(wr * kx[a1]);
+                    const int im = __float2int_rn(wi * kx[a1]);
+                    atomicAdd(row + a1, ((unsigned long long)(unsigned)im << 32) +
+                                            (unsigned long long)(long long)r);
+                }
+            };
+            if constexpr (DIM == 2) {
+#pragma unroll
+                for (int a2 = 0; a2 < W; ++a2)
+                    row_add(tile + (sy + a2) * p1 + sx, cr0 * ky[a2], ci0 * ky[a2]);
+            } else {
+                float z0;
+                const int sz = tap_start<float, W>(u2[i] + (float)P, z0);
+#pragma unroll 1
+                for (int a3 = 0; a3 < W; ++a3) {
+                    const float kz = es_val(z0 + (float)a3 * (float)(2.0 / W), bk);
+                    const float cr = cr0 * kz, ci = ci0 * kz;
+#pragma unroll
+                    for (int a2 = 0; a2 < W; ++a2)
+                        row_add(tile + ((sz + a3) * p2 + sy + a2) * p1 + sx, cr * ky[a2],
+                                ci * ky[a2]);
+                }
+            }
+        }
+        __syncthreads();
+        float4 *dst = reinterpret_cast<float4 *>(scratch + (size_t)q * ts2);
+        for (int e = tid; e < ts2 / 4; e += kThreads) {
+            float v[4];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const long long word = (long long)tile[2 * e + h];
+                const int r = (int)(unsigned)(word & 0xffffffffll);
+                const long long im = (word - (long long)r) >> 32;
+                v[2 * h] = (float)r * inv;
+                v[2 * h + 1] = (float)im * inv;
+            }
+            dst[e] = make_float4(v[0], v[1], v[2], v[3]);
+        }
+        __syncthreads();
+    }
+}
+
 // SM spreading in 2D single precision with register windows (w <= 8).
 //
 // Same input, output and fixed-point tile as k_spread_sm, with the LDS atomic
@@ -879,7 +993,9 @@ hipError_t spread_wb(const Geom &g, int method, const Pts &P, const void *c, voi
     const T bk = kernel_param<T>(g.beta);
     if (method == 3) {
         auto kern = k_spread_sm<T, DIM, W, BATCH>;
-        if (part & 4) {
+        // the single-word kernel scales per subproblem and needs no max|c|
+        constexpr bool packed = std::is_same<T, float>::value && !(DIM == 2 && W <= 8);
+        if ((part & 4) && !packed) {
             hipLaunchKernelGGL(k_maxabs<T>, dim3(std::max(1, std::min(cdiv(P.M, kThreads), kMaxParts))),
                                dim3(kThreads), 0, s, (const C *)c, P.M, (T *)P.cmax);
         }
@@ -893,6 +1009,15 @@ hipError_t spread_wb(const Geom &g, int method, const Pts &P, const void *c, voi
                                    P.nsub, (const float *)P.u[0], (const float *)P.u[1], P.perm,
                                    (const float2 *)c, (const float *)P.cmax, (float *)P.scratch,
                                    P.ts2, (float)bk, P.tg, P.T);
+            } else if constexpr (std::is_same<T, float>::value) {
+                auto pk = k_spread_smp<T, DIM, W, BATCH>;
+                if (lds > 65536)
+                    (void)hipFuncSetAttribute((const void *)pk,
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                hipLaunchKernelGGL(pk, dim3(sm_grid(P)), dim3(kThreads), lds, s, g, P.sub,
+                                   P.nsub, (const float *)P.u[0], (const float *)P.u[1],
+                                   (const float *)P.u[2], P.perm, (const float2 *)c,
+                                   (float *)P.scratch, P.ts2, (float)bk, P.tg, P.T);
             } else {
                 if (lds > 65536)
                     (void)hipFuncSetAttribute((const void *)kern,
