@@ -256,7 +256,8 @@ def main():
     dominant = max(("spread", "interp"), key=lambda k: stages[k][0])
     algo = algorithmic_bytes(dominant, dim, M, ncells, rsz)
     achieved = algo / (kern_ms[dominant] * 1e-3) / 1e9
-    kernel_name = {"spread": "k_spread_sm" if info["method"] == 3 else "k_spread_gm",
+    sm_spread = "k_spread_smp" if prec == "f32" else "k_spread_sm"
+    kernel_name = {"spread": sm_spread if info["method"] == 3 else "k_spread_gm",
                    "interp": "k_interp_sm" if info["method"] == 3 else "k_interp_gm"}[dominant]
     traffic = load_traffic(kernel_name, args.workload)
     out = {

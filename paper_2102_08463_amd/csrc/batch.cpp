@@ -43,8 +43,6 @@ struct mnufft_batch_s {
     uint32_t *keyA = nullptr, *valA = nullptr, *keyB = nullptr, *valB = nullptr;
     uint32_t *skey = nullptr;
     int32_t *perm = nullptr;
-    bool cellsorted = false;     // points reordered by first tap cell (su_tmp, permc)
-    int32_t *permc = nullptr;
     int32_t *binstart = nullptr, *subcount = nullptr, *sub = nullptr, *nsub = nullptr;
     int32_t *mergelist = nullptr, *nmerge = nullptr;
     uint32_t *hist = nullptr, *partials = nullptr;
@@ -94,10 +92,6 @@ mn::Pts batch_points(mnufft_batch b)
     }
     P.key = b->skey;
     P.perm = b->perm;
-    if (b->cellsorted) {
-        for (int d = 0; d < 3; ++d) P.u[d] = b->su_tmp[d];
-        P.perm = b->permc;
-    }
     P.binstart = b->binstart;
     P.sub = b->sub;
     P.nsub = b->nsub;
@@ -372,17 +366,6 @@ int mnufft_batch_setpts(mnufft_batch b, const void *x, const void *y, const void
         if (mn::launch_subproblems(b->nbins, b->msub_max, b->nsub_max, b->binstart, b->subcount,
                                    b->partials, b->sub, b->nsub, s, b->d_geo, b->T))
             return MNUFFT_ERR_HIP;
-        b->cellsorted = false;
-        if (mn::sm_register_windows(b->g, b->prec)) {
-            int32_t *other = b->perm == reinterpret_cast<int32_t *>(b->valA)
-                                 ? reinterpret_cast<int32_t *>(b->valB)
-                                 : reinterpret_cast<int32_t *>(b->valA);
-            if (mn::launch_cellsort(b->g, b->prec, b->nsub_max, b->sub, b->nsub, b->su, b->perm,
-                                    b->su_tmp, other, b->ts2, s, b->d_geo, b->T))
-                return MNUFFT_ERR_HIP;
-            b->permc = other;
-            b->cellsorted = true;
-        }
         if (mn::launch_zero(b->nmerge, 4, s)) return MNUFFT_ERR_HIP;
         if (mn::launch_merge_list(b->nsub_max, b->nsub, b->sub, b->subcount, kMergeGroup,
                                   b->mergelist, b->nmerge, s))
@@ -402,7 +385,7 @@ int mnufft_batch_execute(mnufft_batch b, void *c, void *f)
     const mn::Pts P = batch_points(b);
     int rc;
     if (b->type == 1) {
-        {
+        if (b->prec == MNUFFT_F64) {  // max |c| for the double-precision fixed-point scale
             StageTimer tm(b->tm, MNUFFT_STAGE_SCALE, s);
             if (mn::launch_zero(b->cmax, 1024 * 8, s)) return MNUFFT_ERR_HIP;
             if (mn::launch_spread(b->g, b->prec, MNUFFT_METHOD_SM, P, c, b->grid, s, 4))

@@ -135,14 +135,6 @@ hipError_t launch_subproblems(int nbins, int msub, int nsub_max, const int32_t *
                               int32_t *subcount, uint32_t *partials, int32_t *sub,
                               int32_t *nsub, hipStream_t s, const TGeom *tg = nullptr, int T = 1);
 
-// Inside every subproblem, reorder the sorted points by first tap cell in the
-// padded bin (row-major), stably; writes u_out / perm_out over the same
-// positions (2D; LDS of ts2 / 2 words per workgroup).
-hipError_t launch_cellsort(const Geom &g, int prec, int nsub_max, const int32_t *sub,
-                           const int32_t *nsub, const void *const u_in[3], const int32_t *perm_in,
-                           void *const u_out[3], int32_t *perm_out, int ts2, hipStream_t s,
-                           const TGeom *tg = nullptr, int T = 1);
-
 // Exclusive prefix sum of n uint32 values (in and out may alias).
 hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, size_t n, uint32_t *partials,
                           hipStream_t s);
@@ -165,12 +157,6 @@ hipError_t launch_interp_grad(const Geom &g, int prec, const Pts &P, int ntransf
                               hipStream_t s);
 // Dynamic LDS bytes the SM kernels need for these bins.
 size_t sm_lds_bytes(const Geom &g, int prec, bool interp);
-// 2D single-precision SM spreading with w <= 8 uses register windows over
-// points ordered by first tap cell inside each subproblem (launch_cellsort).
-inline bool sm_register_windows(const Geom &g, int prec)
-{
-    return prec == 0 && g.dim == 2 && g.w <= 8;
-}
 // Reals per scratch tile slot of SM spreading.
 int sm_tile_stride(const Geom &g);
 // Leaders of tile groups to merge: subproblems q with (q - suboff[bin]) % G == 0

@@ -375,134 +375,6 @@ __global__ void k_subfill(int nbins, int msub, int nsub_max, const int32_t *__re
     reinterpret_cast<int4 *>(sub)[q] = rec;
 }
 
-// Order inside each subproblem by first tap cell.  A subproblem's points are
-// rearranged so that their first tap cells (s_1, s_2) in the padded bin
-// (s_i = ceil(u_i + P - w/2), P = ceil(w/2)) ascend in row-major order, equal
-// cells keeping the bin-sorted order.  One workgroup of kCellWaves wavefronts
-// per chunk of up to kCellChunk points of a subproblem (chunks are ordered
-// independently); wavefront v owns the v-th quarter of the chunk:
-//   A. keys into LDS and per-wavefront counts per cell (LDS integer atomics:
-//      counts do not depend on their order);
-//   B. one exclusive scan over cells of the summed counts, and per cell the
-//      running sum over wavefronts: each wavefront's first slot in each cell;
-//   C. every wavefront sweeps its quarter 64 points at a time in order: lanes
-//      holding equal keys are found with one ballot per key bit, each point
-//      gets its wavefront's slot plus its rank among equal keys before it,
-//      and the lowest of them advances the slot (no atomics, so the result
-//      does not depend on any order of LDS operations);
-//   D. every new position reads its point (the inverse order is kept in LDS,
-//      so the stores are coalesced and only the loads scatter, within the
-//      chunk's few kilobytes).
-// The result is deterministic and stays within the chunk's own range.
-constexpr int kCellChunk = 4096;
-constexpr int kCellWaves = 4;
-constexpr int kCellThreads = 64 * kCellWaves;
-
-__device__ __forceinline__ unsigned long long peers_of(int key, int bits, bool ok)
-{
-    unsigned long long m = __ballot(ok);
-    for (int b = 0; b < bits; ++b) {
-        const bool on = (key >> b) & 1;
-        const unsigned long long v = __ballot(on);
-        m &= on ? v : ~v;
-    }
-    return m;
-}
-
-template <typename T, bool BATCH>
-__global__ void __launch_bounds__(kCellThreads)
-k_cellsort(Geom g, int W, const int32_t *__restrict__ sub, const int32_t *__restrict__ nsubp,
-           const T *__restrict__ ui0, const T *__restrict__ ui1, const int32_t *__restrict__ pin,
-           T *__restrict__ uo0, T *__restrict__ uo1, int32_t *__restrict__ pout,
-           const TGeom *__restrict__ tg, int T_)
-{
-    // kCellWaves x ncap counters (ncap >= p1 p2), then 2 x kCellChunk 16-bit slots
-    extern __shared__ uint32_t lds[];
-    __shared__ uint32_t wsum[kCellWaves];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const unsigned long long below = (1ull << lane) - 1ull;
-    const int P = (W + 1) / 2;
-    const T hw = (T)(0.5 * W);
-    const int nsub = *nsubp;
-    int ncap = (g.m[0] + 2 * P) * (g.m[1] + 2 * P);  // the largest padded bin
-    uint16_t *kp = reinterpret_cast<uint16_t *>(lds + kCellWaves * ncap);  // key of point j
-    uint16_t *src = kp + kCellChunk;                                      // point at position o
-    for (int q = blockIdx.x; q < nsub; q += gridDim.x) {
-        const int4 rec = reinterpret_cast<const int4 *>(sub)[q];
-        int m0 = g.m[0], m1 = g.m[1];
-        if constexpr (BATCH) {
-            const TGeom &tt =
-                tg[find_transform(tg, T_, rec.x, [](const TGeom &a) { return a.bin_off; })];
-            m0 = tt.m[0];
-            m1 = tt.m[1];
-        }
-        const int p1 = m0 + 2 * P, p2 = m1 + 2 * P, nh = p1 * p2;
-        const int bits = nh > 1 ? 32 - __clz(nh - 1) : 0;
-        uint32_t *cw = lds + wv * ncap;  // this wavefront's counters
-        for (int c0 = rec.y; c0 < rec.y + rec.z; c0 += kCellChunk) {
-            const int n = min(kCellChunk, rec.y + rec.z - c0);
-            const int lo = n * wv / kCellWaves, hi = n * (wv + 1) / kCellWaves;
-            for (int e = tid; e < kCellWaves * ncap; e += kCellThreads) lds[e] = 0u;
-            __syncthreads();
-            // A. keys (the same rounding as the spreading kernels' first tap) and counts
-            for (int j = lo + lane; j < hi; j += 64) {
-                const int sx = min(max((int)ceil((ui0[c0 + j] + (T)P) - hw), 0), p1 - 1);
-                const int sy = min(max((int)ceil((ui1[c0 + j] + (T)P) - hw), 0), p2 - 1);
-                const int key = sy * p1 + sx;
-                kp[j] = (uint16_t)key;
-                atomicAdd(&cw[key], 1u);
-            }
-            __syncthreads();
-            // B. first slot of each wavefront in each cell
-            {
-                const int per = (nh + kCellThreads - 1) / kCellThreads;
-                const int elo = min(tid * per, nh), ehi = min(elo + per, nh);
-                uint32_t sum = 0;
-                for (int e = elo; e < ehi; ++e)
-                    for (int v = 0; v < kCellWaves; ++v) sum += lds[v * ncap + e];
-                uint32_t x = sum;
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    const uint32_t y = __shfl_up(x, o, 64);
-                    if (lane >= o) x += y;
-                }
-                if (lane == 63) wsum[wv] = x;
-                __syncthreads();
-                uint32_t run = x - sum;
-                for (int v = 0; v < wv; ++v) run += wsum[v];
-                for (int e = elo; e < ehi; ++e)
-                    for (int v = 0; v < kCellWaves; ++v) {
-                        const uint32_t c = lds[v * ncap + e];
-                        lds[v * ncap + e] = run;
-                        run += c;
-                    }
-            }
-            __syncthreads();
-            // C. positions, in order within each wavefront's quarter (a
-            //    wavefront's LDS operations complete in program order)
-            for (int j0 = lo; j0 < hi; j0 += 64) {
-                const bool ok = j0 + lane < hi;
-                const int key = ok ? (int)kp[j0 + lane] : 0;
-                const unsigned long long pe = peers_of(key, bits, ok);
-                const int pos = ok ? (int)cw[key] + __popcll(pe & below) : 0;
-                __builtin_amdgcn_wave_barrier();
-                if (ok && (pe & below) == 0ull) cw[key] += (uint32_t)__popcll(pe);
-                if (ok) src[pos] = (uint16_t)(j0 + lane);
-                __builtin_amdgcn_wave_barrier();
-            }
-            __syncthreads();
-            // D. move
-            for (int o = tid; o < n; o += kCellThreads) {
-                const int j = c0 + (int)src[o];
-                uo0[c0 + o] = ui0[j];
-                uo1[c0 + o] = ui1[j];
-                pout[c0 + o] = pin[j];
-            }
-            __syncthreads();
-        }
-    }
-}
-
 inline int nblocks(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
@@ -604,38 +476,6 @@ hipError_t launch_subproblems(int nbins, int msub, int nsub_max, const int32_t *
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_subfill, dim3(nblocks(std::max(nsub_max, 1), 256)), dim3(256), 0, s,
                        nbins, msub, nsub_max, binstart, (const uint32_t *)cnt, sub, nsub, tg, T);
-    return hipGetLastError();
-}
-
-hipError_t launch_cellsort(const Geom &g, int prec, int nsub_max, const int32_t *sub,
-                           const int32_t *nsub, const void *const u_in[3], const int32_t *perm_in,
-                           void *const u_out[3], int32_t *perm_out, int ts2, hipStream_t s,
-                           const TGeom *tg, int T)
-{
-    (void)ts2;
-    if (nsub_max <= 0) return hipSuccess;
-    const int P = (g.w + 1) / 2;
-    const int64_t ncap = (int64_t)(g.m[0] + 2 * P) * (g.m[1] + 2 * P);
-    if (g.dim != 2 || ncap > 65535) return hipErrorInvalidValue;  // cell keys are 16-bit
-    const size_t lds = (size_t)kCellWaves * ncap * 4 + (size_t)kCellChunk * 4;
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
-    const dim3 grid(std::min(nsub_max, 16384)), block(kCellThreads);
-#define MN_CELLSORT(TT, BB)                                                                   \
-    do {                                                                                      \
-        auto k = k_cellsort<TT, BB>;                                                          \
-        if (lds > 65536)                                                                      \
-            (void)hipFuncSetAttribute((const void *)k,                                       \
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
-        hipLaunchKernelGGL(k, grid, block, lds, s, g, g.w, sub, nsub, (const TT *)u_in[0],   \
-                           (const TT *)u_in[1], perm_in, (TT *)u_out[0], (TT *)u_out[1],      \
-                           perm_out, tg, T);                                                  \
-    } while (0)
-    if (prec == 0) {
-        if (tg) MN_CELLSORT(float, true); else MN_CELLSORT(float, false);
-    } else {
-        if (tg) MN_CELLSORT(double, true); else MN_CELLSORT(double, false);
-    }
-#undef MN_CELLSORT
     return hipGetLastError();
 }
 

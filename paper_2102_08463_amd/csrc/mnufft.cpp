@@ -59,10 +59,6 @@ struct mnufft_plan_s {
     uint32_t *key_in = nullptr;
     uint32_t *skey = nullptr;   // alias of keyA/keyB after the sort
     int32_t *perm = nullptr;    // alias of valA/valB after the sort
-    // SM with register windows: points reordered by first tap cell inside each
-    // subproblem (coordinates in su_tmp, permutation in the free one of valA/valB)
-    bool cellsorted = false;
-    int32_t *permc = nullptr;
     int32_t *binstart = nullptr, *subcount = nullptr, *sub = nullptr, *nsub = nullptr;
     int nsub_max = 0, nsub_cap = 0;
     uint32_t *hist = nullptr, *partials = nullptr;
@@ -236,10 +232,6 @@ mn::Pts points_of(mnufft_plan p)
     }
     P.key = p->skey;
     P.perm = p->perm;
-    if (p->cellsorted) {
-        for (int d = 0; d < 3; ++d) P.u[d] = p->su_tmp[d];
-        P.perm = p->permc;
-    }
     P.binstart = p->binstart;
     P.sub = p->sub;
     P.nsub = p->nsub;
@@ -276,7 +268,9 @@ int exec_type1(mnufft_plan p, int sign, const void *c, void *f)
     for (int64_t t = 0; t < p->ntransf; ++t) {
         const char *ct = (const char *)c + (size_t)t * p->M * 2 * p->rsz;
         char *gt = (char *)p->grid + (size_t)t * grid_bytes(p);
-        if (p->method == MNUFFT_METHOD_SM) {
+        if (p->method == MNUFFT_METHOD_SM && p->prec == MNUFFT_F64) {
+            // max |c| for the double-precision fixed-point scale (single
+            // precision scales each subproblem inside the spreading kernel)
             StageTimer tm(p->tm, MNUFFT_STAGE_SCALE, p->stream);
             MN_HIP(mn::launch_zero(p->cmax, 1024 * 8, p->stream));
             MN_HIP(mn::launch_spread(p->g, p->prec, p->method, P, ct, gt, p->stream, 4));
@@ -376,16 +370,6 @@ int enqueue_setpts(mnufft_plan p, int64_t M, const void *x, const void *y, const
     MN_HIP(mn::launch_binstart((int)M, g.nbins, p->skey, p->binstart, s));
     MN_HIP(mn::launch_subproblems(g.nbins, p->msub, p->nsub_max, p->binstart, p->subcount,
                                   p->partials, p->sub, p->nsub, s));
-    p->cellsorted = false;
-    if (p->method == MNUFFT_METHOD_SM && mn::sm_register_windows(g, p->prec)) {
-        int32_t *other = p->perm == reinterpret_cast<int32_t *>(p->valA)
-                             ? reinterpret_cast<int32_t *>(p->valB)
-                             : reinterpret_cast<int32_t *>(p->valA);
-        MN_HIP(mn::launch_cellsort(g, p->prec, p->nsub_max, p->sub, p->nsub, p->su, p->perm,
-                                   p->su_tmp, other, p->ts2, s));
-        p->permc = other;
-        p->cellsorted = true;
-    }
     if (p->method == MNUFFT_METHOD_SM) {
         MN_HIP(mn::launch_zero(p->nmerge, 4, s));
         MN_HIP(mn::launch_merge_list(p->nsub_max, p->nsub, p->sub, p->subcount, kMergeGroup,
@@ -634,7 +618,7 @@ int mnufft_spread(mnufft_plan p, const void *c, void *grid)
     if (!grid || (p->M > 0 && !c)) return MNUFFT_ERR_ARG;
     if ((rc = use_device(p))) return rc;
     if (p->method != MNUFFT_METHOD_SM) MN_HIP(mn::launch_zero(grid, grid_bytes(p), p->stream));
-    else MN_HIP(mn::launch_zero(p->cmax, 1024 * 8, p->stream));
+    else if (p->prec == MNUFFT_F64) MN_HIP(mn::launch_zero(p->cmax, 1024 * 8, p->stream));
     MN_HIP(mn::launch_spread(p->g, p->prec, p->method, points_of(p), c, grid, p->stream));
     return MNUFFT_OK;
 }

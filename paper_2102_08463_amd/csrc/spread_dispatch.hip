@@ -63,9 +63,7 @@ size_t sm_lds_bytes(const Geom &g, int prec, bool interp)
     const size_t rsz = prec == 0 ? sizeof(float) : sizeof(double);
     // 64-bit fixed-point accumulators: one word per cell in single precision,
     // one per part in double precision
-    // (the 2D single-precision register-window kernel keeps two words per cell)
-    if (!interp)
-        return (size_t)sm_tile_stride(g) * (prec == 0 && !sm_register_windows(g, prec) ? 4 : 8);
+    if (!interp) return (size_t)sm_tile_stride(g) * (prec == 0 ? 4 : 8);
     const int P = (g.w + 1) / 2;
     size_t cells = 1;
     for (int d = 0; d < g.dim; ++d) cells *= (size_t)(g.m[d] + 2 * P);

@@ -275,28 +275,15 @@ __device__ __forceinline__ T block_cmax(const T *__restrict__ parts)
 //
 // The LDS accumulator is 64-bit fixed point: on gfx950 integer LDS atomics
 // (ds_add_u64) sustain roughly ten times the rate of floating-point ones.
-// Every contribution v = c_j * phi * phi is turned into round(v * S) with
-// S = 2^k chosen from cmax = max_j max(|Re c_j|, |Im c_j|):
-//   single precision: S = 2^30 / 2^ceil(log2 cmax), so |v S| <= 2^30 fits an
-//     int32 and the 64-bit sum cannot overflow for fewer than 2^33
-//     contributions; the quantum cmax 2^-30 is below single-precision
-//     rounding of the values;
-//   double precision: S = 2^62 / (2^ceil(log2 msub) 2^ceil(log2 cmax)); a
-//     cell gets at most msub contributions of size <= cmax, so the sum stays
-//     below 2^62, with quantum about msub cmax 2^-62.
+// This kernel serves double precision (single precision uses k_spread_smp,
+// one word per cell).  Every contribution v = c_j * phi * phi is turned into
+// round(v * S) with S = 2^62 / (2^ceil(log2 msub) 2^ceil(log2 cmax)),
+// cmax = max_j max(|Re c_j|, |Im c_j|): a cell gets at most msub
+// contributions of size <= cmax, so the sum stays below 2^62, with quantum
+// about msub cmax 2^-62.
 // Grid-stride loop over the subproblem list; the tile is interleaved
 // (re, im) with ts2 >= 2 p1 p2 p3 entries per slot (a multiple of 8).
 template <typename T> struct FixedScale;
-template <> struct FixedScale<float> {
-    __device__ static float scale(float cmax, int /*lg_msub*/, float &inv)
-    {
-        int e;
-        frexpf(cmax, &e);  // cmax < 2^e (e = 0 for cmax = 0)
-        inv = ldexpf(1.0f, e - 30);
-        return ldexpf(1.0f, 30 - e);
-    }
-    __device__ static long long to_fixed(float v) { return (long long)__float2int_rn(v); }
-};
 template <> struct FixedScale<double> {
     __device__ static double scale(double cmax, int lg_msub, double &inv)
     {
@@ -502,148 +489,6 @@ k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict_
                 v[2 * h + 1] = (float)im * inv;
             }
             dst[e] = make_float4(v[0], v[1], v[2], v[3]);
-        }
-        __syncthreads();
-    }
-}
-
-// SM spreading in 2D single precision with register windows (w <= 8).
-//
-// Same input, output and fixed-point tile as k_spread_sm, with the LDS atomic
-// traffic cut by summing in registers first.  setpts has ordered the points
-// of every subproblem by first tap cell (s_1, s_2), row-major.  Thread t of
-// the workgroup takes the t-th of kThreads equal runs of consecutive points
-// and sums their w x w footprints into a register window of w rows by w + 1
-// columns anchored at a point's first tap cell: a following point whose
-// first tap lies in the same row, at most one cell to the right of the
-// anchor, goes into the same window (its x weights shifted by one column);
-// any other point, or the kWinMax-th one, flushes the window into the LDS
-// tile (one 64-bit integer atomic per cell and part) and re-anchors it.
-// With about two points per fine cell this replaces 2 w^2 atomics per point
-// by about 2 w (w + 1) per window of several points.
-//
-// A window sums at most kWinMax contributions per cell, each at most cmax S
-// in magnitude, so S = 2^26 / 2^ceil(log2 cmax) (kWinMax = 16) keeps a window
-// sum within int32; the quantum 16 cmax 2^-30 stays below single-precision
-// rounding of the grid values.  Runs and the order inside cells are fixed by
-// setpts and the subproblem length, so results are reproducible bit for bit.
-constexpr int kWinMax = 16;
-
-template <int W>
-__device__ __forceinline__ void rw_flush(unsigned long long *__restrict__ tile, int p1, int ax,
-                                         int ay, bool wide, float (&ar)[W][W + 1],
-                                         float (&ai)[W][W + 1])
-{
-#pragma unroll
-    for (int a2 = 0; a2 < W; ++a2) {
-        unsigned long long *row = tile + 2 * ((ay + a2) * p1 + ax);
-#pragma unroll
-        for (int t = 0; t < W + 1; ++t) {
-            if (t < W || wide) {
-                atomicAdd(row + 2 * t, (unsigned long long)(long long)__float2int_rn(ar[a2][t]));
-                atomicAdd(row + 2 * t + 1,
-                          (unsigned long long)(long long)__float2int_rn(ai[a2][t]));
-            }
-            ar[a2][t] = 0.f;
-            ai[a2][t] = 0.f;
-        }
-    }
-}
-
-template <int W, bool BATCH>
-__global__ void __launch_bounds__(kThreads)
-k_spread_smw(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__ nsubp,
-             const float *__restrict__ u0, const float *__restrict__ u1,
-             const int32_t *__restrict__ perm, const float2 *__restrict__ c,
-             const float *__restrict__ cmaxp, float *__restrict__ scratch, int ts2, float bk,
-             const TGeom *__restrict__ tg, int T_)
-{
-    constexpr int P = (W + 1) / 2;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    unsigned long long *tile = reinterpret_cast<unsigned long long *>(smem_raw);
-    const int tid = threadIdx.x;
-    const int nvec = ts2 / 4;
-    const int nsub = *nsubp;
-    float inv;
-    const float S = FixedScale<float>::scale(block_cmax(cmaxp), 0, inv) * (1.0f / kWinMax);
-    inv *= (float)kWinMax;
-    for (int q = blockIdx.x; q < nsub; q += gridDim.x) {
-        const int4 rec = reinterpret_cast<const int4 *>(sub)[q];
-        int p1 = g.m[0] + 2 * P;
-        if constexpr (BATCH) {
-            const TGeom &tt =
-                tg[find_transform(tg, T_, rec.x, [](const TGeom &a) { return a.bin_off; })];
-            p1 = tt.m[0] + 2 * P;
-        }
-        for (int e = tid; e < ts2; e += kThreads) tile[e] = 0ull;
-        __syncthreads();
-        // this thread's run [lo, hi) of the subproblem's points
-        const int lo = rec.y + (int)(((long long)tid * rec.z) / kThreads);
-        const int hi = rec.y + (int)(((long long)(tid + 1) * rec.z) / kThreads);
-        float ar[W][W + 1], ai[W][W + 1];
-#pragma unroll
-        for (int a2 = 0; a2 < W; ++a2)
-#pragma unroll
-            for (int t = 0; t < W + 1; ++t) ar[a2][t] = ai[a2][t] = 0.f;
-        int ax = 0, ay = 0, wc = 0;
-        bool wide = false;
-        // loads run one point ahead (two for the permutation)
-        float nx = 0.f, ny = 0.f;
-        float2 ncv = make_float2(0.f, 0.f);
-        int pn = 0;
-        if (lo < hi) {
-            nx = u0[lo];
-            ny = u1[lo];
-            ncv = c[perm[lo]];
-            if (lo + 1 < hi) pn = perm[lo + 1];
-        }
-        for (int i = lo; i < hi; ++i) {
-            const float x = nx + (float)P, y = ny + (float)P;
-            const float cr = ncv.x * S, ci = ncv.y * S;
-            if (i + 1 < hi) {
-                nx = u0[i + 1];
-                ny = u1[i + 1];
-                ncv = c[pn];
-                if (i + 2 < hi) pn = perm[i + 2];
-            }
-            float kx[W], ky[W];
-            const int sx = taps<float, W>(x, bk, kx);
-            const int sy = taps<float, W>(y, bk, ky);
-            int dx = sx - ax;
-            if (wc == 0 || sy != ay || dx < 0 || dx > 1 || wc == kWinMax) {
-                if (wc > 0) rw_flush<W>(tile, p1, ax, ay, wide, ar, ai);
-                ax = sx;
-                ay = sy;
-                dx = 0;
-                wc = 0;
-                wide = false;
-            }
-            ++wc;
-            wide = wide || dx != 0;
-            float ks[W + 1];
-#pragma unroll
-            for (int t = 0; t < W + 1; ++t)
-                ks[t] = dx ? (t > 0 ? kx[t - 1] : 0.f) : (t < W ? kx[t] : 0.f);
-#pragma unroll
-            for (int a2 = 0; a2 < W; ++a2) {
-                const float wr = cr * ky[a2], wi = ci * ky[a2];
-#pragma unroll
-                for (int t = 0; t < W + 1; ++t) {
-                    ar[a2][t] += wr * ks[t];
-                    ai[a2][t] += wi * ks[t];
-                }
-            }
-        }
-        if (wc > 0) rw_flush<W>(tile, p1, ax, ay, wide, ar, ai);
-        __syncthreads();
-        float4 *dst = reinterpret_cast<float4 *>(scratch + (size_t)q * ts2);
-        for (int e = tid; e < nvec; e += kThreads) {
-            float4 out;
-            out.x = (float)((double)(long long)tile[4 * e] * (double)inv);
-            out.y = (float)((double)(long long)tile[4 * e + 1] * (double)inv);
-            out.z = (float)((double)(long long)tile[4 * e + 2] * (double)inv);
-            out.w = (float)((double)(long long)tile[4 * e + 3] * (double)inv);
-            dst[e] = out;
         }
         __syncthreads();
     }
@@ -992,24 +837,13 @@ hipError_t spread_wb(const Geom &g, int method, const Pts &P, const void *c, voi
     using C = typename Cplx<T>::type;
     const T bk = kernel_param<T>(g.beta);
     if (method == 3) {
-        auto kern = k_spread_sm<T, DIM, W, BATCH>;
-        // the single-word kernel scales per subproblem and needs no max|c|
-        constexpr bool packed = std::is_same<T, float>::value && !(DIM == 2 && W <= 8);
-        if ((part & 4) && !packed) {
+        // the single-precision kernel scales per subproblem and needs no max|c|
+        if ((part & 4) && !std::is_same<T, float>::value) {
             hipLaunchKernelGGL(k_maxabs<T>, dim3(std::max(1, std::min(cdiv(P.M, kThreads), kMaxParts))),
                                dim3(kThreads), 0, s, (const C *)c, P.M, (T *)P.cmax);
         }
         if (part & 1) {
-            if constexpr (std::is_same<T, float>::value && DIM == 2 && W <= 8) {
-                auto rk = k_spread_smw<W, BATCH>;
-                if (lds > 65536)
-                    (void)hipFuncSetAttribute((const void *)rk,
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-                hipLaunchKernelGGL(rk, dim3(sm_grid(P)), dim3(kThreads), lds, s, g, P.sub,
-                                   P.nsub, (const float *)P.u[0], (const float *)P.u[1], P.perm,
-                                   (const float2 *)c, (const float *)P.cmax, (float *)P.scratch,
-                                   P.ts2, (float)bk, P.tg, P.T);
-            } else if constexpr (std::is_same<T, float>::value) {
+            if constexpr (std::is_same<T, float>::value) {
                 auto pk = k_spread_smp<T, DIM, W, BATCH>;
                 if (lds > 65536)
                     (void)hipFuncSetAttribute((const void *)pk,
@@ -1019,6 +853,7 @@ hipError_t spread_wb(const Geom &g, int method, const Pts &P, const void *c, voi
                                    (const float *)P.u[2], P.perm, (const float2 *)c,
                                    (float *)P.scratch, P.ts2, (float)bk, P.tg, P.T);
             } else {
+                auto kern = k_spread_sm<T, DIM, W, BATCH>;
                 if (lds > 65536)
                     (void)hipFuncSetAttribute((const void *)kern,
                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
