@@ -395,7 +395,7 @@ k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
 // tracks the subproblem's own strengths.  This halves the atomics of the
 // 64-bit two-word tile, which bound 3D spreading, and halves its LDS.
 template <typename T, int DIM, int W, bool BATCH>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8)))
 k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__ nsubp,
              const float *__restrict__ u0, const float *__restrict__ u1,
              const float *__restrict__ u2, const int32_t *__restrict__ perm,
@@ -584,6 +584,75 @@ k_tile_gather(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__ 
                         ai += t[1];
                     }
                 }
+            }
+        }
+        typename Cplx<T>::type out;
+        out.x = ar;
+        out.y = ai;
+        grid[e] = out;
+    }
+}
+
+// Fast path of k_tile_gather for a plain plan whose cover tables hold at most
+// two entries per grid index (bins at least as wide as the halo, the usual
+// case): every cell's cover entries, the first tile of each covering bin and
+// those tiles' values are loaded in three rounds of independent loads, not
+// one dependent chain per covering bin.  The sum is taken in the same order.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kThreads)
+k_tile_gather2(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__ scratch,
+               int ts2, int G, const int2 *__restrict__ cov0, const int2 *__restrict__ cov1,
+               const int2 *__restrict__ cov2, int k0, int k1, int k2, int P,
+               typename Cplx<T>::type *__restrict__ grid, long long ncell)
+{
+    constexpr int NZ = DIM == 3 ? 2 : 1, NC = 4 * NZ;
+    const int p1 = g.m[0] + 2 * P, p2 = g.m[1] + 2 * P;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < ncell;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int l1 = (int)(e % g.n[0]);
+        const long long r = e / g.n[0];
+        const int l2 = (int)(r % g.n[1]);
+        const int l3 = DIM == 3 ? (int)(r / g.n[1]) : 0;
+        int2 c1[2], c2[2], c3[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            c1[j] = j < k0 ? cov0[(size_t)l1 * k0 + j] : make_int2(-1, 0);
+            c2[j] = j < k1 ? cov1[(size_t)l2 * k1 + j] : make_int2(-1, 0);
+            c3[j] = (DIM == 3 && j < k2) ? cov2[(size_t)l3 * k2 + j] : make_int2(j == 0 ? 0 : -1, 0);
+        }
+        int bin[NC];
+        size_t off[NC];
+#pragma unroll
+        for (int j3 = 0; j3 < NZ; ++j3)
+#pragma unroll
+            for (int j2 = 0; j2 < 2; ++j2)
+#pragma unroll
+                for (int j1 = 0; j1 < 2; ++j1) {
+                    const int v = (j3 * 2 + j2) * 2 + j1;
+                    const bool ok = c1[j1].x >= 0 && c2[j2].x >= 0 && c3[j3].x >= 0;
+                    bin[v] = ok ? c1[j1].x + g.B[0] * (c2[j2].x + g.B[1] * c3[j3].x) : -1;
+                    off[v] = 2 * ((size_t)c1[j1].y +
+                                  (size_t)p1 * (c2[j2].y + (size_t)p2 * c3[j3].y));
+                }
+        int first[NC], cnt[NC];
+#pragma unroll
+        for (int v = 0; v < NC; ++v) {
+            first[v] = bin[v] >= 0 ? suboff[bin[v]] : 0;
+            cnt[v] = bin[v] >= 0 ? suboff[bin[v] + 1] - first[v] : 0;
+        }
+        T ar = 0, ai = 0;
+#pragma unroll
+        for (int v = 0; v < NC; ++v) {
+            if (cnt[v] > 0) {
+                const T *t = scratch + (size_t)first[v] * ts2 + off[v];
+                ar += t[0];
+                ai += t[1];
+            }
+            const int step = cnt[v] > G ? G : 1;
+            for (int q = first[v] + step; q < first[v] + cnt[v]; q += step) {
+                const T *t = scratch + (size_t)q * ts2 + off[v];
+                ar += t[0];
+                ai += t[1];
             }
         }
         typename Cplx<T>::type out;
@@ -873,6 +942,13 @@ hipError_t spread_wb(const Geom &g, int method, const Pts &P, const void *c, voi
                            P.mergelist, P.sub, P.suboff, (T *)P.scratch, P.ts2, P.G);
         const long long ncell = P.ncells;
         const int ggrid = (int)std::min<long long>((ncell + kThreads - 1) / kThreads, 16384);
+        if (!BATCH && P.kmax[0] <= 2 && P.kmax[1] <= 2 && (DIM == 2 || P.kmax[2] <= 2)) {
+            hipLaunchKernelGGL((k_tile_gather2<T, DIM>), dim3(std::max(ggrid, 1)), dim3(kThreads),
+                               0, s, g, P.suboff, (const T *)P.scratch, P.ts2, P.G, P.cov[0],
+                               P.cov[1], P.cov[2], P.kmax[0], P.kmax[1], P.kmax[2], (W + 1) / 2,
+                               (C *)grid, ncell);
+            return hipGetLastError();
+        }
         hipLaunchKernelGGL((k_tile_gather<T, DIM, BATCH>), dim3(std::max(ggrid, 1)), dim3(kThreads),
                            0, s, g, P.suboff, (const T *)P.scratch, P.ts2, P.G, P.cov[0], P.cov[1],
                            P.cov[2], P.kmax[0], P.kmax[1], P.kmax[2], (W + 1) / 2, (C *)grid, ncell,
