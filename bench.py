@@ -165,6 +165,105 @@ def batched_speedup(kind="uniform", ntype=1, reps=3, eps=1e-6):
             "speedup": t_plain / (t_batch + sel_ms)}
 
 
+def _short_kernel(name):
+    """'void mn::detail::k_x<float, 2>(args)' -> 'k_x<float, 2>'."""
+    name = name.strip().strip('"')
+    if name.startswith("void "):
+        name = name[5:]
+    for ns in ("mn::detail::", "mn::(anonymous namespace)::", "mn::"):
+        name = name.replace(ns, "")
+    depth, cut = 0, len(name)
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            cut = i
+            break
+    return name[:cut]
+
+
+def _base_kernel(name):
+    return _short_kernel(name).split("<")[0]
+
+
+def summarize_profiles(args):
+    """Turn rocprofv3 CSV output (a --kernel-trace --stats run and FETCH_SIZE /
+    WRITE_SIZE --pmc runs of the same bench command, plus the two counters on
+    a plain copy of known size) into a markdown summary and the calibrated
+    per-launch HBM traffic that the bench line reports (profiles/traffic.json)."""
+    import csv
+    import glob
+
+    def csvs(d, suffix):
+        return sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+
+    def counters(d):
+        per = {}
+        for f in csvs(d, "counter_collection.csv"):
+            for row in csv.DictReader(open(f)):
+                per.setdefault(_base_kernel(row["Kernel_Name"]), []).append(float(row["Counter_Value"]))
+        return per
+
+    stats = []
+    for f in csvs(args.stats_dir, "kernel_stats.csv"):
+        for row in csv.DictReader(open(f)):
+            stats.append((_short_kernel(row["Name"]), int(row["Calls"]), float(row["AverageNs"]) / 1e3,
+                          float(row["Percentage"])))
+    stats.sort(key=lambda r: -r[3])
+    fetch, write = counters(args.fetch_dir), counters(args.write_dir)
+    cal_f = max(counters(args.cal_fetch_dir)["__amd_rocclr_copyBuffer"])
+    cal_w = max(counters(args.cal_write_dir)["__amd_rocclr_copyBuffer"])
+    kib = args.cal_mib * 1024.0
+    ff, fw = kib / cal_f, kib / cal_w
+    dim, modes, M, kind, eps, prec = WORKLOADS[args.workload]
+    rsz = 4 if prec == "f32" else 8
+    ncells = 1
+    for n in modes:
+        ncells *= 2 * n  # upsampling 2 (5-smooth sizes of these powers of two are 2N)
+    lines = [f"# {args.title}", "", f"Workload `{args.workload}`: {dim}D, modes {'x'.join(map(str, modes))}, "
+             f"M = {M} {kind} points, eps = {eps:g}, {prec}; one bench step = setpts + type 1 + "
+             f"type 2 (adjoint) with the library defaults.", "", "## Commands (repository root, GPU box)", "",
+             "```"] + args.command + ["```", "",
+             "## Kernel statistics (rocprofv3 --kernel-trace --stats)", "",
+             "| kernel | calls | avg us | share % |", "|---|---|---|---|"]
+    for name, calls, avg, pct in stats[:args.top]:
+        lines.append(f"| `{name}` | {calls} | {avg:.1f} | {pct:.2f} |")
+    lines += ["", "## HBM traffic per launch (PMC, calibrated)", "",
+              f"Calibration: a {args.cal_mib} MiB device copy reads FETCH_SIZE = {cal_f:.0f} KiB and "
+              f"WRITE_SIZE = {cal_w:.0f} KiB per launch, so the factors are {ff:.3f} (fetch) and "
+              f"{fw:.3f} (write).", "",
+              "| kernel | avg us | FETCH_SIZE KiB | WRITE_SIZE KiB | traffic MB | algorithmic MB |",
+              "|---|---|---|---|---|---|"]
+    avg_us = {}
+    for name, calls, avg, pct in stats:
+        avg_us.setdefault(name.split("<")[0], avg)
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    table = json.load(open(path)) if os.path.exists(path) else {}
+    for k in args.kernels.split(","):
+        if k not in fetch or k not in write:
+            continue
+        fk = sum(fetch[k]) / len(fetch[k])
+        wk = sum(write[k]) / len(write[k])
+        traffic = (fk * ff + wk * fw) * 1024.0
+        stage = "spread" if "spread" in k else ("interp" if "interp" in k else None)
+        algo = algorithmic_bytes(stage, dim, M, ncells, rsz) if stage else None
+        lines.append(f"| `{k}` | {avg_us.get(k, float('nan')):.1f} | {fk:.0f} | {wk:.0f} | "
+                     f"{traffic / 1e6:.1f} | {'%.1f' % (algo / 1e6) if algo else '-'} |")
+        if stage:
+            table[f"{args.workload}:{k}"] = {"source_hash": kernel_source_hash(),
+                                            "bytes_per_launch": traffic, "fetch_kib": fk,
+                                            "write_kib": wk, "cal_fetch": ff, "cal_write": fw}
+    if args.note:
+        lines += ["", args.note]
+    with open(args.md_out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    with open(path, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+    print(f"wrote {args.md_out} and {path}")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,7 +281,24 @@ def main():
                     help="skip the batched-vs-plain speedup measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (reference for HBM counters)")
+    ap.add_argument("--summarize-profiles", action="store_true",
+                    help="only summarize rocprofv3 CSV output (see --stats-dir etc.)")
+    ap.add_argument("--stats-dir")
+    ap.add_argument("--fetch-dir")
+    ap.add_argument("--write-dir")
+    ap.add_argument("--cal-fetch-dir")
+    ap.add_argument("--cal-write-dir")
+    ap.add_argument("--cal-mib", type=int, default=256)
+    ap.add_argument("--kernels", default="k_spread_smp,k_interp_sm")
+    ap.add_argument("--md-out")
+    ap.add_argument("--title", default="Kernel times and HBM traffic (MI355X)")
+    ap.add_argument("--command", action="append", default=[])
+    ap.add_argument("--note", default="")
+    ap.add_argument("--top", type=int, default=16)
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args)
+        return
     if args.copy_calibration:
         import torch
         src = torch.ones(args.copy_calibration * (1 << 18), dtype=torch.float32, device="cuda")

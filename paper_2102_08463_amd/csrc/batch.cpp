@@ -261,7 +261,8 @@ int mnufft_batch_makeplan(int type, int dim, int ntr, const int64_t *nmodes, con
     for (int d = 0; d < 3; ++d) b->g.m[d] = mmax[d];
     b->g.nbins = b->nbins;
     b->ts2 = mn::sm_tile_stride(b->g);
-    if (mn::sm_lds_bytes(b->g, prec, false) > kLdsMax || mn::sm_lds_bytes(b->g, prec, true) > kLdsMax) {
+    if (mn::sm_lds_bytes(b->g, prec, false, b->msub_max) > kLdsMax ||
+        mn::sm_lds_bytes(b->g, prec, true, b->msub_max) > kLdsMax) {
         delete b;
         return MNUFFT_ERR_ARG;
     }

@@ -77,9 +77,10 @@ k_binkey(Geom g, int M, const T *__restrict__ x, const T *__restrict__ y,
     if (bad) atomicOr(flag, 1);
 }
 
-// Per-tile digit histogram, stored digit-major: hist[d * nblk + blk].
+// Per-tile digit histogram, stored digit-major: hist[d * nblk + blk]; the
+// digit is (key >> shift) & dmask with dmask + 1 <= 256.
 __global__ void __launch_bounds__(kThreads)
-k_radix_hist(const uint32_t *__restrict__ keys, int M, int shift, int nblk,
+k_radix_hist(const uint32_t *__restrict__ keys, int M, int shift, uint32_t dmask, int nblk,
              uint32_t *__restrict__ hist)
 {
     __shared__ uint32_t h[256];
@@ -90,7 +91,7 @@ k_radix_hist(const uint32_t *__restrict__ keys, int M, int shift, int nblk,
     for (int r = 0; r < kItems; ++r) {
         const int64_t idx = base + (int64_t)r * kThreads + tid;
         const bool valid = idx < M;
-        const uint32_t d = valid ? (keys[idx] >> shift) & 255u : 0u;
+        const uint32_t d = valid ? (keys[idx] >> shift) & dmask : 0u;
         // Lanes are contiguous in idx, so lane 0 is valid whenever any lane is.
         const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)d);
         const bool same = !valid || d == d0;
@@ -119,7 +120,7 @@ constexpr int kSItems = kTile / kSThreads;
 template <typename T, int ND>
 __global__ void __launch_bounds__(kSThreads)
 k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, int M,
-                int shift, int nblk, const uint32_t *__restrict__ offs,
+                int shift, int dbits, int nblk, const uint32_t *__restrict__ offs,
                 uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, Payload pl)
 {
     __shared__ uint32_t cnt[kSWaves][256];   // running per-wave digit counts, then prefixes
@@ -140,6 +141,7 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
     const int64_t base = tbase + (int64_t)wave * (64 * kSItems);
     const int tcount = (int)std::min<int64_t>(kTile, (int64_t)M - tbase);
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t dmask = (1u << dbits) - 1u;
     uint32_t kk[kSItems], vv[kSItems], rk[kSItems];
 #pragma unroll
     for (int r = 0; r < kSItems; ++r) {
@@ -147,10 +149,9 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
         const bool valid = idx < M;
         const uint32_t key = valid ? kin[idx] : 0u;
         const uint32_t val = valid ? (vin ? vin[idx] : (uint32_t)idx) : 0u;
-        const uint32_t d = (key >> shift) & 255u;
+        const uint32_t d = (key >> shift) & dmask;
         uint64_t mask = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < dbits; ++b) {
             const bool bit = (d >> b) & 1u;
             const uint64_t bb = __ballot(bit);
             mask &= bit ? bb : ~bb;
@@ -192,7 +193,7 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
     for (int r = 0; r < kSItems; ++r) {
         const int64_t idx = base + r * 64 + lane;
         if (idx < M) {
-            const uint32_t d = (kk[r] >> shift) & 255u;
+            const uint32_t d = (kk[r] >> shift) & dmask;
             const uint32_t start = d == 0 ? 0u : tstart[d - 1];
             const uint32_t lpos = start + cnt[wave][d] + rk[r];
             if (lpos >= (uint32_t)kTile) continue;  // cannot happen when the counts agree
@@ -206,7 +207,7 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
     __syncthreads();
     for (int e = tid; e < tcount; e += kSThreads) {
         const uint32_t key = skey[e];
-        const uint32_t d = (key >> shift) & 255u;
+        const uint32_t d = (key >> shift) & dmask;
         const uint32_t start = d == 0 ? 0u : tstart[d - 1];
         const uint32_t gpos = gbase[d] + (uint32_t)e - start;
         if (gpos >= (uint32_t)M) continue;  // cannot happen when the counts agree
@@ -421,16 +422,21 @@ hipError_t radix_sort(int M, int bits, int prec, int dim, uint32_t *keysA, uint3
 {
     // Keys start in keysA with implicit values 0..M-1; each pass moves the
     // pairs to the other buffer.  Pass p moves the payload as pays[p] says.
+    // Digits of equal width dbits <= 8 over the passes: fewer digits per pass
+    // mean longer runs of each digit per tile, hence more coalesced writes.
     const int passes = radix_passes(bits);
+    const int dbits = std::max(1, (bits + passes - 1) / passes);
+    const uint32_t dmask = (1u << dbits) - 1u;
     const int nblk = std::max(1, nblocks(M, kTile));
     uint32_t *kb[2] = {keysA, keysB}, *vb[2] = {valsA, valsB};
     int cur = 0;
     for (int p = 0; p < passes; ++p) {
         if (M > 0) {
-            const int shift = 8 * p;
+            const int shift = dbits * p;
             hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kThreads), 0, s,
-                               (const uint32_t *)kb[cur], M, shift, nblk, hist);
-            hipError_t e = scan_exclusive(hist, hist, (size_t)256 * nblk, partials, s);
+                               (const uint32_t *)kb[cur], M, shift, dmask, nblk, hist);
+            // digits above dmask are empty: only the first dmask + 1 rows are scanned
+            hipError_t e = scan_exclusive(hist, hist, (size_t)(dmask + 1) * nblk, partials, s);
             if (e != hipSuccess) return e;
             const uint32_t *vin = p == 0 ? nullptr : (const uint32_t *)vb[cur];
 #define MN_SCATTER(TT, DD)                                                                  \
@@ -440,7 +446,7 @@ hipError_t radix_sort(int M, int bits, int prec, int dim, uint32_t *keysA, uint3
             (void)hipFuncSetAttribute((const void *)k_radix_scatter<TT, DD>,                \
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
         hipLaunchKernelGGL((k_radix_scatter<TT, DD>), dim3(nblk), dim3(kSThreads), lds, s,   \
-                           (const uint32_t *)kb[cur], vin, M, shift, nblk,                  \
+                           (const uint32_t *)kb[cur], vin, M, shift, dbits, nblk,           \
                            (const uint32_t *)hist, kb[1 - cur], vb[1 - cur], pays[p]);      \
     } while (0)
             if (prec == 0) {

@@ -514,7 +514,8 @@ int mnufft_makeplan(int type, int dim, const int64_t *nmodes, int iflag, int64_t
     }
     g.nbins = (int)nbins;
     p->grid_elems = (size_t)cells;
-    const size_t lds = std::max(mn::sm_lds_bytes(g, prec, false), mn::sm_lds_bytes(g, prec, true));
+    const size_t lds = std::max(mn::sm_lds_bytes(g, prec, false, p->msub),
+                                mn::sm_lds_bytes(g, prec, true, p->msub));
     p->ts2 = mn::sm_tile_stride(g);
     if (o.method == MNUFFT_METHOD_AUTO)
         p->method = lds <= kLdsMax ? MNUFFT_METHOD_SM : MNUFFT_METHOD_GMSORT;

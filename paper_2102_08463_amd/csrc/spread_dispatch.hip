@@ -1,6 +1,8 @@
 // Dispatch of spreading / interpolation to the instantiated kernel slices.
 #include "internal.h"
 
+#include <algorithm>
+
 namespace mn {
 namespace detail {
 template <typename T, int DIM>
@@ -58,12 +60,15 @@ int sm_tile_stride(const Geom &g)
     return (int)((2 * cells + 7) / 8 * 8);
 }
 
-size_t sm_lds_bytes(const Geom &g, int prec, bool interp)
+size_t sm_lds_bytes(const Geom &g, int prec, bool interp, int msub)
 {
     const size_t rsz = prec == 0 ? sizeof(float) : sizeof(double);
     // 64-bit fixed-point accumulators: one word per cell in single precision,
     // one per part in double precision
-    if (!interp) return (size_t)sm_tile_stride(g) * (prec == 0 ? 4 : 8);
+    // (single precision also stages smp_stage strengths, 8 bytes each)
+    if (!interp)
+        return prec == 0 ? (size_t)sm_tile_stride(g) * 4 + (size_t)8 * smp_stage(g.dim, msub)
+                         : (size_t)sm_tile_stride(g) * 8;
     const int P = (g.w + 1) / 2;
     size_t cells = 1;
     for (int d = 0; d < g.dim; ++d) cells *= (size_t)(g.m[d] + 2 * P);
@@ -102,7 +107,7 @@ hipError_t launch_spread(const Geom &g, int prec, int method, const Pts &P, cons
         return launch_zero(grid, (size_t)P.ncells * 2 * (prec == 0 ? sizeof(float) : sizeof(double)),
                            s);
     }
-    const size_t lds = method == 3 ? sm_lds_bytes(g, prec, false) : 0;
+    const size_t lds = method == 3 ? sm_lds_bytes(g, prec, false, P.msub) : 0;
     if (prec == 0)
         return g.dim == 2 ? detail::spread_dim<float, 2>(g, method, P, c, grid, s, lds, part)
                           : detail::spread_dim<float, 3>(g, method, P, c, grid, s, lds, part);
@@ -114,7 +119,7 @@ hipError_t launch_interp(const Geom &g, int prec, int method, const Pts &P, cons
                          void *c, hipStream_t s)
 {
     if (P.M == 0) return hipSuccess;
-    const size_t lds = method == 3 ? sm_lds_bytes(g, prec, true) : 0;
+    const size_t lds = method == 3 ? sm_lds_bytes(g, prec, true, P.msub) : 0;
     if (prec == 0)
         return g.dim == 2 ? detail::interp_dim<float, 2>(g, method, P, grid, c, s, lds)
                           : detail::interp_dim<float, 3>(g, method, P, grid, c, s, lds);

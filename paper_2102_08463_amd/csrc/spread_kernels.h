@@ -394,18 +394,23 @@ k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
 // rounding of A and of the contributions.  The quantum 1 / S <= A 2^-28
 // tracks the subproblem's own strengths.  This halves the atomics of the
 // 64-bit two-word tile, which bound 3D spreading, and halves its LDS.
+// The strengths gathered for the scale (up to stage_cap of them) stay in LDS
+// for the accumulation: the random gather through the permutation moves a
+// whole cache line per point and is the kernel's main HBM traffic, so it is
+// done once.
 template <typename T, int DIM, int W, bool BATCH>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8)))
 k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__ nsubp,
              const float *__restrict__ u0, const float *__restrict__ u1,
              const float *__restrict__ u2, const int32_t *__restrict__ perm,
              const float2 *__restrict__ c, float *__restrict__ scratch, int ts2, float bk,
-             const TGeom *__restrict__ tg, int T_)
+             int stage_cap, const TGeom *__restrict__ tg, int T_)
 {
     static_assert(std::is_same<T, float>::value, "single precision only");
     constexpr int P = (W + 1) / 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     unsigned long long *tile = reinterpret_cast<unsigned long long *>(smem_raw);  // ts2 / 2 cells
+    float2 *cs = reinterpret_cast<float2 *>(tile + ts2 / 2);  // first stage_cap strengths
     __shared__ float red[2][kThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int ncell = ts2 / 2;
@@ -420,12 +425,27 @@ k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict_
             p2 = tt.m[1] + 2 * P;
         }
         const int end = rec.y + rec.z;
-        // scale of this subproblem
+        // scale of this subproblem (the gathers are issued kPre at a time so
+        // that their latencies overlap)
+        constexpr int kPre = 8;
         float sr = 0.f, si = 0.f;
-        for (int i = rec.y + tid; i < end; i += kThreads) {
-            const float2 cv = c[perm[i]];
-            sr += fabsf(cv.x);
-            si += fabsf(cv.y);
+        for (int i0 = rec.y + tid; i0 < end; i0 += kPre * kThreads) {
+            int pj[kPre];
+#pragma unroll
+            for (int k = 0; k < kPre; ++k) {
+                const int i = i0 + k * kThreads;
+                pj[k] = i < end ? perm[i] : -1;
+            }
+#pragma unroll
+            for (int k = 0; k < kPre; ++k) {
+                if (pj[k] >= 0) {
+                    const float2 cv = c[pj[k]];
+                    sr += fabsf(cv.x);
+                    si += fabsf(cv.y);
+                    const int j = i0 + k * kThreads - rec.y;
+                    if (j < stage_cap) cs[j] = cv;
+                }
+            }
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
@@ -443,11 +463,30 @@ k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict_
         int ea;
         frexpf(A, &ea);  // A < 2^ea
         const float S = ldexpf(1.0f, 29 - ea), inv = ldexpf(1.0f, ea - 29);
-        for (int i = rec.y + tid; i < end; i += kThreads) {
+        // points of this thread, with the next one's loads issued ahead
+        int i = rec.y + tid;
+        float nu0 = 0.f, nu1 = 0.f, nu2 = 0.f;
+        float2 ncv = make_float2(0.f, 0.f);
+        // strengths past the staged ones are gathered again
+        auto strength = [&](int ii) { return ii - rec.y < stage_cap ? cs[ii - rec.y] : c[perm[ii]]; };
+        if (i < end) {
+            nu0 = u0[i];
+            nu1 = u1[i];
+            if constexpr (DIM == 3) nu2 = u2[i];
+            ncv = strength(i);
+        }
+        for (; i < end; i += kThreads) {
+            const float x0 = nu0, x1 = nu1, x2 = nu2;
+            const float2 cv = ncv;
+            if (i + kThreads < end) {
+                nu0 = u0[i + kThreads];
+                nu1 = u1[i + kThreads];
+                if constexpr (DIM == 3) nu2 = u2[i + kThreads];
+                ncv = strength(i + kThreads);
+            }
             float kx[W], ky[W];
-            const int sx = taps<float, W>(u0[i] + (float)P, bk, kx);
-            const int sy = taps<float, W>(u1[i] + (float)P, bk, ky);
-            const float2 cv = c[perm[i]];
+            const int sx = taps<float, W>(x0 + (float)P, bk, kx);
+            const int sy = taps<float, W>(x1 + (float)P, bk, ky);
             const float cr0 = cv.x * S, ci0 = cv.y * S;
             auto row_add = [&](unsigned long long *row, float wr, float wi) {
 #pragma unroll
@@ -464,7 +503,7 @@ k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict_
                     row_add(tile + (sy + a2) * p1 + sx, cr0 * ky[a2], ci0 * ky[a2]);
             } else {
                 float z0;
-                const int sz = tap_start<float, W>(u2[i] + (float)P, z0);
+                const int sz = tap_start<float, W>(x2 + (float)P, z0);
 #pragma unroll 1
                 for (int a3 = 0; a3 < W; ++a3) {
                     const float kz = es_val(z0 + (float)a3 * (float)(2.0 / W), bk);
@@ -920,7 +959,8 @@ hipError_t spread_wb(const Geom &g, int method, const Pts &P, const void *c, voi
                 hipLaunchKernelGGL(pk, dim3(sm_grid(P)), dim3(kThreads), lds, s, g, P.sub,
                                    P.nsub, (const float *)P.u[0], (const float *)P.u[1],
                                    (const float *)P.u[2], P.perm, (const float2 *)c,
-                                   (float *)P.scratch, P.ts2, (float)bk, P.tg, P.T);
+                                   (float *)P.scratch, P.ts2, (float)bk,
+                                   smp_stage(DIM, P.msub), P.tg, P.T);
             } else {
                 auto kern = k_spread_sm<T, DIM, W, BATCH>;
                 if (lds > 65536)

@@ -14,13 +14,13 @@ namespace {
 constexpr size_t kLdsMax = 160 * 1024;
 
 // LDS bytes of the SM kernels for bins m (both directions use the larger).
-size_t sm_lds(int dim, int prec, int w, const int *m)
+size_t sm_lds(int dim, int prec, int w, const int *m, int msub)
 {
     mn::Geom g{};
     g.dim = dim;
     g.w = w;
     for (int d = 0; d < 3; ++d) g.m[d] = d < dim ? m[d] : 1;
-    return std::max(mn::sm_lds_bytes(g, prec, false), mn::sm_lds_bytes(g, prec, true));
+    return std::max(mn::sm_lds_bytes(g, prec, false, msub), mn::sm_lds_bytes(g, prec, true, msub));
 }
 }  // namespace
 
@@ -51,8 +51,8 @@ int mnufft_tune_candidates(int dim, int prec, double eps, mnufft_opts *list, int
     const int nb = dim == 2 ? 4 : 5;
     for (int i = 0; i < nb; ++i) {
         const int *m = dim == 2 ? bins2[i] : bins3[i];
-        if (sm_lds(dim, prec, w, m) > kLdsMax) continue;
-        for (int msub : msubs) push(MNUFFT_METHOD_SM, m, msub);
+        for (int msub : msubs)
+            if (sm_lds(dim, prec, w, m, msub) <= kLdsMax) push(MNUFFT_METHOD_SM, m, msub);
     }
     const int *mdef = dim == 2 ? bins2[1] : bins3[1];
     push(MNUFFT_METHOD_GMSORT, mdef, 1024);
