@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmnufft.so")
+MICROBENCH = os.path.join(HERE, "microbench")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -70,6 +71,11 @@ def build(jobs=None, verbose=False):
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + " ".join(cmd) + "\n" + r.stdout + r.stderr)
     os.replace(tmp, LIB)
+    # the stand-alone microbenchmarks the kernel design rests on
+    cmd = [HIPCC] + COMMON + ["-o", MICROBENCH, os.path.join(CSRC, "microbench.hip")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("microbenchmark build failed:\n" + " ".join(cmd) + "\n" + r.stderr)
     return LIB
 
 
