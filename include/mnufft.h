@@ -63,7 +63,7 @@ extern "C" {
 typedef struct mnufft_opts {
     int   method;       /* MNUFFT_METHOD_*; default AUTO */
     int   binsize[3];   /* bin extents m_i in fine-grid cells; 0 selects the default,
-                           32 x 32 in 2D and 8 x 8 x 8 in 3D (measured on gfx950; the
+                           32 x 32 in 2D and 16 x 8 x 8 in 3D (measured on gfx950; the
                            paper's V100 choice was 32 x 32 and 16 x 16 x 2, Sec. III-A,
                            first remark) */
     int   msub;         /* max points per subproblem, > 0; 0 selects 4096 (the paper

@@ -496,7 +496,7 @@ int mnufft_makeplan(int type, int dim, const int64_t *nmodes, int iflag, int64_t
     g.w = w;
     g.beta = beta;
     g.pad = (w + 1) / 2;
-    const int defm[2][3] = {{32, 32, 1}, {8, 8, 8}};
+    const int defm[2][3] = {{32, 32, 1}, {16, 8, 8}};
     int64_t nbins = 1;
     for (int d = 0; d < 3; ++d) {
         p->N[d] = d < dim ? nmodes[d] : 1;

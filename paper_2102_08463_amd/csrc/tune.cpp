@@ -36,7 +36,7 @@ int mnufft_tune_candidates(int dim, int prec, double eps, mnufft_opts *list, int
     int64_t n = 0;
     if (mnufft_choose_params(eps, prec, 1, &w, &beta, &n) < 0) return MNUFFT_ERR_ARG;
     static const int bins2[][3] = {{16, 16, 1}, {32, 32, 1}, {64, 32, 1}, {64, 64, 1}};
-    static const int bins3[][3] = {{8, 8, 8}, {16, 16, 2}, {16, 16, 4}, {16, 16, 8}, {32, 16, 4}};
+    static const int bins3[][3] = {{8, 8, 8}, {16, 16, 2}, {16, 16, 4}, {16, 16, 8}, {32, 16, 4}, {16, 8, 8}};
     static const int msubs[] = {256, 1024, 4096, 16384};
     int cnt = 0;
     auto push = [&](int method, const int *m, int msub) {
@@ -48,7 +48,7 @@ int mnufft_tune_candidates(int dim, int prec, double eps, mnufft_opts *list, int
         }
         ++cnt;
     };
-    const int nb = dim == 2 ? 4 : 5;
+    const int nb = dim == 2 ? 4 : 6;
     for (int i = 0; i < nb; ++i) {
         const int *m = dim == 2 ? bins2[i] : bins3[i];
         for (int msub : msubs)
