@@ -49,9 +49,16 @@ struct mnufft_batch_s {
     void *scratch = nullptr, *cmax = nullptr;
     int *flag = nullptr;
     std::map<std::array<int, 3>, rocfft_plan> fft;
-    rocfft_execution_info info = nullptr;
-    void *fftwork = nullptr;
+    // The transforms' FFTs are independent and mostly small: they run spread
+    // over kFftStreams streams (default priority), forked from and joined
+    // back to the batch's stream with events.
+    static constexpr int kFftStreams = 8;
+    hipStream_t fstream[kFftStreams] = {};
+    hipEvent_t fork = nullptr, join[kFftStreams] = {};
+    rocfft_execution_info info[kFftStreams] = {};
+    void *fftwork = nullptr;  // kFftStreams slices of fftwork_bytes
     size_t fftwork_bytes = 0;
+    std::vector<int> fft_order;  // transforms by decreasing grid size
     bool pts_set = false;
     mn::host::Timers tm;
     std::vector<void *> allocs;
@@ -89,6 +96,7 @@ mn::Pts batch_points(mnufft_batch b)
         P.u[d] = b->su[d];
         P.cov[d] = b->cov[d];
         P.kmax[d] = 1;
+        for (const mn::TGeom &t : b->geo) P.kmax[d] = std::max(P.kmax[d], t.kmax[d]);
     }
     P.key = b->skey;
     P.perm = b->perm;
@@ -112,18 +120,34 @@ mn::Pts batch_points(mnufft_batch b)
 
 int run_ffts(mnufft_batch b, int sign)
 {
-    if (rocfft_execution_info_set_stream(b->info, b->stream) != rocfft_status_success)
-        return MNUFFT_ERR_FFT;
-    if (b->fftwork_bytes &&
-        rocfft_execution_info_set_work_buffer(b->info, b->fftwork, b->fftwork_bytes) !=
-            rocfft_status_success)
-        return MNUFFT_ERR_FFT;
     (void)sign;  // plans were made for the batch's single direction
-    for (const auto &t : b->geo) {
-        const std::array<int, 3> key = {t.n[0], t.n[1], t.n[2]};
-        void *buf[1] = {(char *)b->grid + (size_t)t.grid_off * 2 * b->rsz};
-        if (rocfft_execute(b->fft[key], buf, nullptr, b->info) != rocfft_status_success)
+    if (hipEventRecord(b->fork, b->stream) != hipSuccess) return MNUFFT_ERR_HIP;
+    for (int k = 0; k < mnufft_batch_s::kFftStreams; ++k) {
+        if (hipStreamWaitEvent(b->fstream[k], b->fork, 0) != hipSuccess) return MNUFFT_ERR_HIP;
+        if (rocfft_execution_info_set_stream(b->info[k], b->fstream[k]) != rocfft_status_success)
             return MNUFFT_ERR_FFT;
+        if (b->fftwork_bytes &&
+            rocfft_execution_info_set_work_buffer(b->info[k],
+                                                  (char *)b->fftwork + k * b->fftwork_bytes,
+                                                  b->fftwork_bytes) != rocfft_status_success)
+            return MNUFFT_ERR_FFT;
+    }
+    // largest grids first, each to the stream with the least work so far
+    double load[mnufft_batch_s::kFftStreams] = {};
+    for (int t : b->fft_order) {
+        const mn::TGeom &g = b->geo[t];
+        int k = 0;
+        for (int j = 1; j < mnufft_batch_s::kFftStreams; ++j)
+            if (load[j] < load[k]) k = j;
+        load[k] += (double)g.n[0] * g.n[1] * g.n[2];
+        const std::array<int, 3> key = {g.n[0], g.n[1], g.n[2]};
+        void *buf[1] = {(char *)b->grid + (size_t)g.grid_off * 2 * b->rsz};
+        if (rocfft_execute(b->fft[key], buf, nullptr, b->info[k]) != rocfft_status_success)
+            return MNUFFT_ERR_FFT;
+    }
+    for (int k = 0; k < mnufft_batch_s::kFftStreams; ++k) {
+        if (hipEventRecord(b->join[k], b->fstream[k]) != hipSuccess) return MNUFFT_ERR_HIP;
+        if (hipStreamWaitEvent(b->stream, b->join[k], 0) != hipSuccess) return MNUFFT_ERR_HIP;
     }
     return MNUFFT_OK;
 }
@@ -138,8 +162,15 @@ int mnufft_batch_destroy(mnufft_batch b)
     int rc = MNUFFT_OK;
     if (b->device >= 0 && hipSetDevice(b->device) != hipSuccess) rc = MNUFFT_ERR_HIP;
     if (hipStreamSynchronize(b->stream) != hipSuccess) rc = MNUFFT_ERR_HIP;
+    for (int k = 0; k < mnufft_batch_s::kFftStreams; ++k)
+        if (b->fstream[k] && hipStreamSynchronize(b->fstream[k]) != hipSuccess) rc = MNUFFT_ERR_HIP;
     for (auto &kv : b->fft) rocfft_plan_destroy(kv.second);
-    if (b->info) rocfft_execution_info_destroy(b->info);
+    for (int k = 0; k < mnufft_batch_s::kFftStreams; ++k) {
+        if (b->info[k]) rocfft_execution_info_destroy(b->info[k]);
+        if (b->join[k]) (void)hipEventDestroy(b->join[k]);
+        if (b->fstream[k]) (void)hipStreamDestroy(b->fstream[k]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
     b->tm.destroy();
     for (void *p : b->allocs) (void)hipFree(p);
     delete b;
@@ -310,7 +341,20 @@ int mnufft_batch_makeplan(int type, int dim, int ntr, const int64_t *nmodes, con
     if (!rc) rc = balloc(b, &b->scratch, (size_t)std::max(b->nsub_max, 1) * b->ts2 * b->rsz);
     if (!rc) rc = balloc(b, &b->cmax, 1024 * 8);
     if (!rc) rc = balloc(b, (void **)&b->flag, 16);
-    if (!rc && rocfft_execution_info_create(&b->info) != rocfft_status_success) rc = MNUFFT_ERR_FFT;
+    if (!rc && hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
+        rc = MNUFFT_ERR_HIP;
+    for (int k = 0; k < mnufft_batch_s::kFftStreams && !rc; ++k) {
+        if (rocfft_execution_info_create(&b->info[k]) != rocfft_status_success) rc = MNUFFT_ERR_FFT;
+        else if (hipStreamCreateWithFlags(&b->fstream[k], hipStreamNonBlocking) != hipSuccess ||
+                 hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming) != hipSuccess)
+            rc = MNUFFT_ERR_HIP;
+    }
+    b->fft_order.resize(ntr);
+    for (int t = 0; t < ntr; ++t) b->fft_order[t] = t;
+    std::stable_sort(b->fft_order.begin(), b->fft_order.end(), [&](int a, int c) {
+        const mn::TGeom &ga = b->geo[a], &gc = b->geo[c];
+        return (int64_t)ga.n[0] * ga.n[1] * ga.n[2] > (int64_t)gc.n[0] * gc.n[1] * gc.n[2];
+    });
     size_t work = 0;
     for (int t = 0; t < ntr && !rc; ++t) {
         const mn::TGeom &tg = b->geo[t];
@@ -324,7 +368,8 @@ int mnufft_batch_makeplan(int type, int dim, int ntr, const int64_t *nmodes, con
         work = std::max(work, wb);
     }
     if (!rc && work) {
-        rc = balloc(b, &b->fftwork, work);
+        work = (work + 255) / 256 * 256;
+        rc = balloc(b, &b->fftwork, work * mnufft_batch_s::kFftStreams);
         b->fftwork_bytes = work;
     }
     if (rc) {

@@ -50,6 +50,30 @@ __device__ __forceinline__ int find_transform(const TGeom *tg, int T, long long 
     return lo;
 }
 
+// Per-element lookups in a batch go through an LDS copy of one offset field
+// of the table when it is short enough: a binary search in global memory is a
+// chain of dependent loads per element, in LDS it is a few cycles per step.
+constexpr int kTCache = 1024;
+template <typename F>
+__device__ __forceinline__ bool cache_offsets(long long *s, const TGeom *tg, int T, F field)
+{
+    const bool ok = T <= kTCache;
+    if (ok)
+        for (int t = threadIdx.x; t < T; t += blockDim.x) s[t] = (long long)field(tg[t]);
+    __syncthreads();
+    return ok;
+}
+// Index of the last cached offset <= v.
+__device__ __forceinline__ int find_cached(const long long *s, int T, long long v)
+{
+    int lo = 0, hi = T - 1;
+    while (lo < hi) {
+        const int mid = lo + ((hi - lo + 1) >> 1);
+        if (s[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Geometry of transform t as a Geom (shared fields from g).
 __device__ __forceinline__ Geom geom_of(const Geom &g, const TGeom &t)
 {

@@ -93,9 +93,12 @@ k_deconv_batch(const TGeom *__restrict__ tg, int T_, long long nmodes,
                const T *__restrict__ p2, const T *__restrict__ p3,
                typename Cplx<T>::type *__restrict__ f)
 {
+    __shared__ long long soff[kTCache];
+    const auto fld = [](const TGeom &a) { return a.mode_off; };
+    const bool cached = cache_offsets(soff, tg, T_, fld);
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nmodes;
          e += (long long)gridDim.x * blockDim.x) {
-        const TGeom &t = tg[find_transform(tg, T_, e, [](const TGeom &a) { return a.mode_off; })];
+        const TGeom &t = tg[cached ? find_cached(soff, T_, e) : find_transform(tg, T_, e, fld)];
         const long long el = e - t.mode_off;
         const int i1 = (int)(el % t.N[0]);
         const long long r = el / t.N[0];
@@ -126,9 +129,12 @@ k_precorrect_batch(const TGeom *__restrict__ tg, int T_, long long ncells,
         if (l >= n + kmin) return l - n - kmin;
         return -1;
     };
+    __shared__ long long soff[kTCache];
+    const auto fld = [](const TGeom &a) { return a.grid_off; };
+    const bool cached = cache_offsets(soff, tg, T_, fld);
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < ncells;
          e += (long long)gridDim.x * blockDim.x) {
-        const TGeom &t = tg[find_transform(tg, T_, e, [](const TGeom &a) { return a.grid_off; })];
+        const TGeom &t = tg[cached ? find_cached(soff, T_, e) : find_transform(tg, T_, e, fld)];
         const long long el = e - t.grid_off;
         const int l1 = (int)(el % t.n[0]);
         const long long r = el / t.n[0];

@@ -52,12 +52,16 @@ k_binkey(Geom g, int M, const T *__restrict__ x, const T *__restrict__ y,
          const TGeom *__restrict__ tg, int T_)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ long long soff[BATCH ? kTCache : 1];
+    const auto fld = [](const TGeom &a) { return a.pt_off; };
+    bool cached = false;
+    if constexpr (BATCH) cached = cache_offsets(soff, tg, T_, fld);
     if (j >= M) return;
     int bad = 0;
     uint32_t k = 0, stride = 1;
     Geom gg = g;
     if constexpr (BATCH) {
-        const int t = find_transform(tg, T_, j, [](const TGeom &a) { return a.pt_off; });
+        const int t = cached ? find_cached(soff, T_, j) : find_transform(tg, T_, j, fld);
         gg = geom_of(g, tg[t]);
         k = (uint32_t)tg[t].bin_off;
     }

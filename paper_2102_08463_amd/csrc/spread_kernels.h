@@ -574,6 +574,10 @@ k_tile_gather(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__ 
               typename Cplx<T>::type *__restrict__ grid, long long ncell_all,
               const TGeom *__restrict__ tg, int T_)
 {
+    __shared__ long long soff[BATCH ? kTCache : 1];
+    const auto fld = [](const TGeom &a) { return a.grid_off; };
+    bool cached = false;
+    if constexpr (BATCH) cached = cache_offsets(soff, tg, T_, fld);
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < ncell_all;
          e += (long long)gridDim.x * blockDim.x) {
         Geom gg = g;
@@ -582,7 +586,7 @@ k_tile_gather(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__ 
         long long el = e;
         if constexpr (BATCH) {
             const TGeom &tt =
-                tg[find_transform(tg, T_, e, [](const TGeom &a) { return a.grid_off; })];
+                tg[cached ? find_cached(soff, T_, e) : find_transform(tg, T_, e, fld)];
             gg = geom_of(g, tt);
             cov0 = cov0_ + tt.cov_off[0];
             cov1 = cov1_ + tt.cov_off[1];
@@ -632,26 +636,48 @@ k_tile_gather(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__ 
     }
 }
 
-// Fast path of k_tile_gather for a plain plan whose cover tables hold at most
-// two entries per grid index (bins at least as wide as the halo, the usual
-// case): every cell's cover entries, the first tile of each covering bin and
-// those tiles' values are loaded in three rounds of independent loads, not
-// one dependent chain per covering bin.  The sum is taken in the same order.
-template <typename T, int DIM>
+// Fast path of k_tile_gather when every cover table holds at most two
+// entries per grid index (bins at least as wide as the halo, the usual case):
+// every cell's cover entries, the first tile of each covering bin and those
+// tiles' values are loaded in three rounds of independent loads, not one
+// dependent chain per covering bin.  The sum is taken in the same order.
+template <typename T, int DIM, bool BATCH>
 __global__ void __launch_bounds__(kThreads)
 k_tile_gather2(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__ scratch,
-               int ts2, int G, const int2 *__restrict__ cov0, const int2 *__restrict__ cov1,
-               const int2 *__restrict__ cov2, int k0, int k1, int k2, int P,
-               typename Cplx<T>::type *__restrict__ grid, long long ncell)
+               int ts2, int G, const int2 *__restrict__ cov0_, const int2 *__restrict__ cov1_,
+               const int2 *__restrict__ cov2_, int k0_, int k1_, int k2_, int P,
+               typename Cplx<T>::type *__restrict__ grid, long long ncell,
+               const TGeom *__restrict__ tg, int T_)
 {
     constexpr int NZ = DIM == 3 ? 2 : 1, NC = 4 * NZ;
-    const int p1 = g.m[0] + 2 * P, p2 = g.m[1] + 2 * P;
+    __shared__ long long soff[BATCH ? kTCache : 1];
+    const auto fld = [](const TGeom &a) { return a.grid_off; };
+    bool cached = false;
+    if constexpr (BATCH) cached = cache_offsets(soff, tg, T_, fld);
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < ncell;
          e += (long long)gridDim.x * blockDim.x) {
-        const int l1 = (int)(e % g.n[0]);
-        const long long r = e / g.n[0];
-        const int l2 = (int)(r % g.n[1]);
-        const int l3 = DIM == 3 ? (int)(r / g.n[1]) : 0;
+        Geom gg = g;
+        const int2 *cov0 = cov0_, *cov1 = cov1_, *cov2 = cov2_;
+        int k0 = k0_, k1 = k1_, k2 = k2_, boff = 0;
+        long long el = e;
+        if constexpr (BATCH) {
+            const TGeom &tt =
+                tg[cached ? find_cached(soff, T_, e) : find_transform(tg, T_, e, fld)];
+            gg = geom_of(g, tt);
+            cov0 = cov0_ + tt.cov_off[0];
+            cov1 = cov1_ + tt.cov_off[1];
+            cov2 = DIM == 3 ? cov2_ + tt.cov_off[2] : cov2_;
+            k0 = tt.kmax[0];
+            k1 = tt.kmax[1];
+            k2 = tt.kmax[2];
+            boff = tt.bin_off;
+            el = e - tt.grid_off;
+        }
+        const int p1 = gg.m[0] + 2 * P, p2 = gg.m[1] + 2 * P;
+        const int l1 = (int)(el % gg.n[0]);
+        const long long r = el / gg.n[0];
+        const int l2 = (int)(r % gg.n[1]);
+        const int l3 = DIM == 3 ? (int)(r / gg.n[1]) : 0;
         int2 c1[2], c2[2], c3[2];
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
@@ -669,7 +695,7 @@ k_tile_gather2(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__
                 for (int j1 = 0; j1 < 2; ++j1) {
                     const int v = (j3 * 2 + j2) * 2 + j1;
                     const bool ok = c1[j1].x >= 0 && c2[j2].x >= 0 && c3[j3].x >= 0;
-                    bin[v] = ok ? c1[j1].x + g.B[0] * (c2[j2].x + g.B[1] * c3[j3].x) : -1;
+                    bin[v] = ok ? boff + c1[j1].x + gg.B[0] * (c2[j2].x + gg.B[1] * c3[j3].x) : -1;
                     off[v] = 2 * ((size_t)c1[j1].y +
                                   (size_t)p1 * (c2[j2].y + (size_t)p2 * c3[j3].y));
                 }
@@ -982,11 +1008,12 @@ hipError_t spread_wb(const Geom &g, int method, const Pts &P, const void *c, voi
                            P.mergelist, P.sub, P.suboff, (T *)P.scratch, P.ts2, P.G);
         const long long ncell = P.ncells;
         const int ggrid = (int)std::min<long long>((ncell + kThreads - 1) / kThreads, 16384);
-        if (!BATCH && P.kmax[0] <= 2 && P.kmax[1] <= 2 && (DIM == 2 || P.kmax[2] <= 2)) {
-            hipLaunchKernelGGL((k_tile_gather2<T, DIM>), dim3(std::max(ggrid, 1)), dim3(kThreads),
-                               0, s, g, P.suboff, (const T *)P.scratch, P.ts2, P.G, P.cov[0],
-                               P.cov[1], P.cov[2], P.kmax[0], P.kmax[1], P.kmax[2], (W + 1) / 2,
-                               (C *)grid, ncell);
+        // (for a batch, P.kmax holds the largest table width over its transforms)
+        if (P.kmax[0] <= 2 && P.kmax[1] <= 2 && (DIM == 2 || P.kmax[2] <= 2)) {
+            hipLaunchKernelGGL((k_tile_gather2<T, DIM, BATCH>), dim3(std::max(ggrid, 1)),
+                               dim3(kThreads), 0, s, g, P.suboff, (const T *)P.scratch, P.ts2,
+                               P.G, P.cov[0], P.cov[1], P.cov[2], P.kmax[0], P.kmax[1],
+                               P.kmax[2], (W + 1) / 2, (C *)grid, ncell, P.tg, P.T);
             return hipGetLastError();
         }
         hipLaunchKernelGGL((k_tile_gather<T, DIM, BATCH>), dim3(std::max(ggrid, 1)), dim3(kThreads),
