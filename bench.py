@@ -264,6 +264,29 @@ def summarize_profiles(args):
     print(f"wrote {args.md_out} and {path}")
 
 
+def summarize_sweep(args):
+    """Markdown table of bench JSON lines (one per run)."""
+    rows = [json.loads(l) for l in open(args.sweep) if l.strip()]
+    names = {1: "GM", 2: "GM-sort", 3: "SM"}
+    lines = [f"# {args.title}", "", "```"] + args.command + ["```", "",
+             "| points | dim | eps | dtype | w | method | bins | NU pts/s per step | exec type 1 | "
+             "exec type 2 | setpts ms | spread ms | add-back ms | interp ms | FFT ms (both) |",
+             "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for d in rows:
+        c, st = d["config"], d["stage_ms_per_step"]
+        lines.append(
+            f"| {c['points']} | {c['dim']} | {c['eps']:g} | {d['dtype']} | {c['w']} | "
+            f"{names.get(c['method'], c['method'])} | {'x'.join(map(str, c['binsize']))} | "
+            f"{d['value']:.3g} | {d['exec_pts_per_s']['type1']:.3g} | {d['exec_pts_per_s']['type2']:.3g} | "
+            f"{st['setpts']:.3f} | {st['spread']:.3f} | {st['addback']:.3f} | {st['interp']:.3f} | "
+            f"{st['fft']:.3f} |")
+    if args.note:
+        lines += ["", args.note]
+    with open(args.md_out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(f"wrote {args.md_out}")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -273,6 +296,8 @@ def main():
     ap.add_argument("--method", default="auto")
     ap.add_argument("--binsize", default=None, help="comma-separated bin extents")
     ap.add_argument("--msub", type=int, default=0)
+    ap.add_argument("--eps", type=float, default=0.0,
+                    help="override the workload's tolerance (fp32 down to 1e-6, fp64 below)")
     ap.add_argument("--cpu-sample", type=int, default=10_000_000,
                     help="points the oracle is timed on (capped at M); 1e7 is about 20-30 "
                          "CPU-seconds on 16 host threads")
@@ -295,9 +320,14 @@ def main():
     ap.add_argument("--command", action="append", default=[])
     ap.add_argument("--note", default="")
     ap.add_argument("--top", type=int, default=16)
+    ap.add_argument("--summarize-sweep", dest="sweep", default=None, metavar="JSONL",
+                    help="only tabulate bench JSON lines from JSONL into --md-out")
     args = ap.parse_args()
     if args.summarize_profiles:
         summarize_profiles(args)
+        return
+    if args.sweep:
+        summarize_sweep(args)
         return
     if args.copy_calibration:
         import torch
@@ -324,6 +354,8 @@ def main():
         __graft_entry__.build()
 
     dim, modes, M, kind, eps, prec = WORKLOADS[args.workload]
+    if args.eps > 0:
+        eps, prec = args.eps, ("f32" if args.eps >= 1e-6 else "f64")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     rdt = np.float32 if prec == "f32" else np.float64
@@ -375,7 +407,7 @@ def main():
     sm_spread = "k_spread_smp" if prec == "f32" else "k_spread_sm"
     kernel_name = {"spread": sm_spread if info["method"] == 3 else "k_spread_gm",
                    "interp": "k_interp_sm" if info["method"] == 3 else "k_interp_gm"}[dominant]
-    traffic = load_traffic(kernel_name, args.workload)
+    traffic = load_traffic(kernel_name, args.workload) if args.eps <= 0 else None
     out = {
         "metric": METRIC,
         "value": value,
