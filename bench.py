@@ -39,6 +39,12 @@ WORKLOADS = {
     "2d-small": (2, (64, 64), 100_000, "uniform", 1e-5, "f32"),
     "3d": (3, (128, 128, 128), 1 << 24, "uniform", 1e-5, "f32"),
     "3d-gauss": (3, (128, 128, 128), 1 << 24, "gaussian", 1e-5, "f32"),
+    # one GPU's share of the 2D workload split over 8 GPUs (points sharded, full grid)
+    "2d-shard": (2, (1024, 1024), 1_250_000, "uniform", 1e-5, "f32"),
+    # shapes of the application's slicing (3D type 2) and merging (3D type 1) steps,
+    # Sec. V: random Ewald-sphere caps of 32^2 / 128^2 points, eps 1e-12 in fp64
+    "mtip-slice": (3, (41, 41, 41), 1000 * 32 * 32, "ewald32", 1e-12, "f64"),
+    "mtip-merge": (3, (81, 81, 81), 1000 * 128 * 128, "ewald128", 1e-12, "f64"),
 }
 
 # Kernel sources whose change invalidates committed hardware-counter figures.

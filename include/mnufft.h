@@ -65,7 +65,8 @@ typedef struct mnufft_opts {
     int   binsize[3];   /* bin extents m_i in fine-grid cells; 0 selects the default,
                            32 x 32 in 2D and 16 x 8 x 8 in 3D (measured on gfx950; the
                            paper's V100 choice was 32 x 32 and 16 x 16 x 2, Sec. III-A,
-                           first remark) */
+                           first remark), halved along the longest side while the
+                           padded bins of method SM do not fit in 160 KB of LDS */
     int   msub;         /* max points per subproblem, > 0; 0 selects 4096 (the paper
                            used 1024, same remark) */
     int   validate_pts; /* nonzero: setpts checks that every coordinate is finite and

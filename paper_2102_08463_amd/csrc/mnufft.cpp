@@ -497,15 +497,31 @@ int mnufft_makeplan(int type, int dim, const int64_t *nmodes, int iflag, int64_t
     g.beta = beta;
     g.pad = (w + 1) / 2;
     const int defm[2][3] = {{32, 32, 1}, {16, 8, 8}};
-    int64_t nbins = 1;
+    bool user_bins = false;
     for (int d = 0; d < 3; ++d) {
         p->N[d] = d < dim ? nmodes[d] : 1;
         g.n[d] = d < dim ? (int)nf[d] : 1;
         int m = d < dim ? (o.binsize[d] > 0 ? o.binsize[d] : defm[dim - 2][d]) : 1;
-        m = std::min(m, g.n[d]);
-        g.m[d] = m;
-        g.B[d] = (g.n[d] + m - 1) / m;
+        user_bins = user_bins || (d < dim && o.binsize[d] > 0);
+        g.m[d] = std::min(m, g.n[d]);
         g.S[d] = (double)g.n[d] / (2.0 * kPi);
+    }
+    auto lds_of = [&]() {
+        return std::max(mn::sm_lds_bytes(g, prec, false, p->msub),
+                        mn::sm_lds_bytes(g, prec, true, p->msub));
+    };
+    // Default bins whose padded tiles do not fit in LDS (wide kernels, double
+    // precision) are halved along their longest side until they do.
+    while (!user_bins && lds_of() > kLdsMax) {
+        int dl = 0;
+        for (int d = 1; d < dim; ++d)
+            if (g.m[d] > g.m[dl]) dl = d;
+        if (g.m[dl] <= 1) break;
+        g.m[dl] = (g.m[dl] + 1) / 2;
+    }
+    int64_t nbins = 1;
+    for (int d = 0; d < 3; ++d) {
+        g.B[d] = (g.n[d] + g.m[d] - 1) / g.m[d];
         nbins *= g.B[d];
     }
     if (nbins > ((int64_t)1 << 30)) {
@@ -514,8 +530,7 @@ int mnufft_makeplan(int type, int dim, const int64_t *nmodes, int iflag, int64_t
     }
     g.nbins = (int)nbins;
     p->grid_elems = (size_t)cells;
-    const size_t lds = std::max(mn::sm_lds_bytes(g, prec, false, p->msub),
-                                mn::sm_lds_bytes(g, prec, true, p->msub));
+    const size_t lds = lds_of();
     p->ts2 = mn::sm_tile_stride(g);
     if (o.method == MNUFFT_METHOD_AUTO)
         p->method = lds <= kLdsMax ? MNUFFT_METHOD_SM : MNUFFT_METHOD_GMSORT;

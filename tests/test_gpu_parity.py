@@ -274,3 +274,28 @@ def test_validate_pts():
     with pytest.raises(RuntimeError):
         p.execute(torch.zeros(100, dtype=torch.complex64, device="cuda"))
     p.destroy()
+
+
+def test_default_bins_shrink_to_fit_lds():
+    """Wide double-precision kernels: the default 3D bins are halved until the
+    padded tiles fit in LDS, so the plan stays on method SM."""
+    import torch
+    note("default bins shrink (3D fp64 eps 1e-12)")
+    p = _plan(1, (24, 20, 16), eps=1e-12, dtype=torch.complex128)
+    inf = p.info()
+    assert inf["method"] == 3
+    assert inf["binsize"][:3] != [16, 8, 8]
+    p.destroy()
+
+
+@pytest.mark.parametrize("ntype", [1, 2])
+def test_ewald_slices_fp64_3d(ntype):
+    """The application's slice geometry (randomly oriented Ewald caps) in fp64
+    at eps 1e-12, against the exact sums."""
+    note(f"ewald slices fp64 type {ntype}")
+    N = (21, 20, 17)
+    pts64, pts = make_points("ewald10", 60 * 10 * 10, 3, "f64", seed=5)
+    if ntype == 1:
+        assert _type1_check(pts64, pts, N, "f64", 1e-12) <= 1e-11
+    else:
+        assert _type2_check(pts64, pts, N, "f64", 1e-12) <= 1e-11

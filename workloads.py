@@ -15,6 +15,13 @@ Point sets (every coordinate in [-pi, pi) before casting):
   spiral_stack     planes z_p = -pi + 2 pi (p + 1/2)/P, each holding an
                    Archimedean spiral r = pi t, theta = 2 pi turns t, plus
                    N(0, jitter^2) jitter on every coordinate, wrapped
+  ewald<S>         (3D) M // S^2 slices of S x S detector points, each a
+                   spherical cap through the origin (an Ewald sphere of
+                   radius 2 pi seen by a detector of half-width 0.65 pi, all
+                   within |q| < pi), turned
+                   by an independent uniformly random rotation: the shape of
+                   the slicing / merging steps of the paper's application
+                   (Sec. V), with no data from it
 Values: complex with iid N(0, 1) real and imaginary parts.
 
 All draws use numpy's PCG64 generator; results are float64 and the caller
@@ -71,6 +78,30 @@ def spiral_stack(M, planes=64, turns=32, jitter=1e-3, seed=0):
     return (_wrap(x + j[0]), _wrap(y + j[1]), _wrap(z + j[2]))
 
 
+def _rotations(n, g):
+    """n uniformly random rotation matrices (unit quaternions, Shoemake)."""
+    u1, u2, u3 = g.uniform(size=(3, n))
+    a, b = np.sqrt(1 - u1), np.sqrt(u1)
+    w, x = a * np.sin(TWO_PI * u2), a * np.cos(TWO_PI * u2)
+    y, z = b * np.sin(TWO_PI * u3), b * np.cos(TWO_PI * u3)
+    return np.stack([
+        np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)], -1),
+        np.stack([2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)], -1),
+        np.stack([2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)], -1)], -2)
+
+
+def ewald_slices(M, side, seed=0, radius=TWO_PI, half_width=0.65 * math.pi):
+    """M // side^2 randomly oriented Ewald-sphere caps of side x side points."""
+    ns = M // (side * side)
+    t = -half_width + 2 * half_width * (np.arange(side) + 0.5) / side
+    u, v = np.meshgrid(t, t, indexing="xy")
+    u, v = u.ravel(), v.ravel()
+    cap = np.stack([u, v, radius - np.sqrt(radius * radius - u * u - v * v)])  # (3, side^2)
+    R = _rotations(ns, rng(seed))                                               # (ns, 3, 3)
+    q = np.einsum("sij,jk->isk", R, cap).reshape(3, ns * side * side)
+    return tuple(_wrap(q[d]) for d in range(3))
+
+
 def points(kind, M, dim, seed=0):
     if kind == "uniform":
         return uniform(M, dim, seed)
@@ -84,6 +115,9 @@ def points(kind, M, dim, seed=0):
     if kind == "spiral_stack":
         assert dim == 3
         return spiral_stack(M, seed=seed)
+    if kind.startswith("ewald"):
+        assert dim == 3
+        return ewald_slices(M, int(kind[5:]), seed=seed)
     raise ValueError(kind)
 
 
