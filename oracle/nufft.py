@@ -21,13 +21,14 @@ except ImportError:  # pragma: no cover
 class Params:
     """w, beta and the fine grid of Sec. II for given modes and tolerance."""
 
-    def __init__(self, Ns, eps, wmax=16):
+    def __init__(self, Ns, eps, wmax=16, sigma=params.SIGMA):
         self.Ns = tuple(int(N) for N in Ns)
         self.dim = len(self.Ns)
         self.eps = float(eps)
-        self.w = params.kernel_width(eps, wmax=wmax)
-        self.beta = params.kernel_beta(self.w)
-        self.ns = tuple(params.fine_grid_size(N, self.w) for N in self.Ns)
+        self.sigma = sigma
+        self.w = params.kernel_width(eps, wmax=wmax, sigma=sigma)
+        self.beta = params.kernel_beta(self.w, sigma=sigma)
+        self.ns = tuple(params.fine_grid_size(N, self.w, sigma=sigma) for N in self.Ns)
 
     def factors(self):
         return [params.correction_factors(N, n, self.w, self.beta)
@@ -56,11 +57,11 @@ def _outer_factors(fs):
     return out
 
 
-def type1(pts, c, Ns, eps, iflag=-1, workers=None):
+def type1(pts, c, Ns, eps, iflag=-1, workers=None, sigma=params.SIGMA):
     """Approximate f_k = sum_j c_j exp(iflag i k.x_j) for k in I_N (Sec. II-A).
 
     Returns complex of shape (N2, N1) or (N3, N2, N1), k1 fastest."""
-    P = Params(Ns, eps)
+    P = Params(Ns, eps, sigma=sigma)
     workers = workers or direct.num_threads()
     b = direct.spread(pts, c, P.ns, P.w, P.beta)           # step 1
     bhat = _fft_signed(b, iflag, workers)                  # step 2
@@ -69,13 +70,13 @@ def type1(pts, c, Ns, eps, iflag=-1, workers=None):
     return _outer_factors(P.factors()) * sub
 
 
-def type2(pts, f, eps, iflag=+1, workers=None):
+def type2(pts, f, eps, iflag=+1, workers=None, sigma=params.SIGMA):
     """Approximate c_j = sum_k f_k exp(iflag i k.x_j) (Sec. II-B).
 
     f: complex (N2, N1) or (N3, N2, N1), k1 fastest.  Returns complex (M,)."""
     f = np.asarray(f, dtype=np.complex128)
     Ns = f.shape[::-1]
-    P = Params(Ns, eps)
+    P = Params(Ns, eps, sigma=sigma)
     workers = workers or direct.num_threads()
     bhat = np.zeros(P.ns[::-1], dtype=np.complex128)       # step 1: precorrect
     idx = [_fold_index(N, n) for N, n in zip(P.Ns, P.ns)]  # and zero-pad

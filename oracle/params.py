@@ -9,22 +9,31 @@ import numpy as np
 SIGMA = 2  # upsampling factor, fixed to 2 in Sec. II
 
 
-def kernel_width(eps, wmax=16):
-    """Kernel width w = ceil(log10(1/eps)) + 1 (Sec. II).
+def kernel_width(eps, wmax=16, sigma=SIGMA):
+    """Kernel width w = ceil(log10(1/eps)) + 1 (Sec. II, upsampling 2).
 
     Reading: 1e-9 is subtracted before the ceiling so that decade tolerances
     (whose logarithm is not exactly an integer in floating point) give the
     intended width; w is clamped to [2, wmax].
+    Upsampling sigma < 2 is only named as future work (Sec. VI); for it the
+    published rule of the FINUFFT paper (Barnett, Magland, af Klinteberg,
+    SISC 2019) is read in: w = ceil(ln(1/eps) / (pi sqrt(1 - 1/sigma))).
     """
     if not (0.0 < eps < 1.0):
         raise ValueError("eps must lie in (0, 1)")
-    w = int(math.ceil(math.log10(1.0 / eps) - 1e-9)) + 1
+    if sigma == SIGMA:
+        w = int(math.ceil(math.log10(1.0 / eps) - 1e-9)) + 1
+    else:
+        w = int(math.ceil(math.log(1.0 / eps) / (math.pi * math.sqrt(1.0 - 1.0 / sigma)) - 1e-9))
     return max(2, min(wmax, w))
 
 
-def kernel_beta(w):
-    """Shape parameter beta = 2.30 w of the ES kernel (Sec. II)."""
-    return 2.30 * w
+def kernel_beta(w, sigma=SIGMA):
+    """Shape parameter beta = 2.30 w of the ES kernel (Sec. II); for sigma < 2
+    the same paper's beta = 0.97 pi w (1 - 1/(2 sigma))."""
+    if sigma == SIGMA:
+        return 2.30 * w
+    return 0.97 * math.pi * w * (1.0 - 0.5 / sigma)
 
 
 def is_5smooth(n):
@@ -37,9 +46,10 @@ def is_5smooth(n):
     return n == 1
 
 
-def fine_grid_size(N, w):
-    """Smallest 2^q 3^p 5^r that is >= max(sigma N, 2w) (Sec. II)."""
-    n = max(SIGMA * int(N), 2 * int(w))
+def fine_grid_size(N, w, sigma=SIGMA):
+    """Smallest 2^q 3^p 5^r that is >= max(sigma N, 2w) (Sec. II; sigma N
+    rounded up)."""
+    n = max(int(math.ceil(sigma * int(N) - 1e-9)), 2 * int(w))
     while not is_5smooth(n):
         n += 1
     return n

@@ -109,3 +109,29 @@ def test_precision_improves_with_eps():
     ref = direct.type1(pts, c, Ns)
     errs = [nufft.rel_l2(nufft.type1(pts, c, Ns, e), ref) for e in (1e-2, 1e-4, 1e-6, 1e-8, 1e-10)]
     assert all(a > b for a, b in zip(errs, errs[1:]))
+
+
+# Upsampling sigma < 2 (named as future work in Sec. VI; the width / shape rule
+# is the FINUFFT paper's, a reading): pinned only by the exact sums.
+SIGMA_CASES = [((16, 12), 1e-3), ((17, 10), 1e-6), ((12, 13), 1e-9), ((8, 10, 6), 1e-5)]
+
+
+@pytest.mark.parametrize("Ns,eps", SIGMA_CASES)
+@pytest.mark.parametrize("sigma", [1.25, 1.5])
+def test_upsampling_below_two_matches_direct_sums(Ns, eps, sigma):
+    pts = _pts(300, len(Ns))
+    c = _cplx(300)
+    got = nufft.type1(pts, c, Ns, eps, iflag=-1, sigma=sigma)
+    assert nufft.rel_l2(got, direct.type1(pts, c, Ns, iflag=-1)) <= 10 * eps
+    f = _cplx(Ns[::-1])
+    got = nufft.type2(pts, f, eps, iflag=+1, sigma=sigma)
+    assert nufft.rel_l2(got, direct.type2(pts, f, iflag=+1)) <= 10 * eps
+    P = nufft.Params(Ns, eps, sigma=sigma)
+    assert all(n >= math.ceil(sigma * N) and n < 2 * N + 2 * P.w for n, N in zip(P.ns, Ns))
+
+
+def test_sigma_two_keeps_the_paper_rule():
+    for eps in (1e-2, 1e-5, 1e-9, 1e-12):
+        P = nufft.Params((40, 30), eps, sigma=2)
+        assert P.w == params.kernel_width(eps) and P.beta == 2.30 * P.w
+        assert P.ns == tuple(params.fine_grid_size(N, P.w) for N in (40, 30))
