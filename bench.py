@@ -302,6 +302,8 @@ def main():
     ap.add_argument("--method", default="auto")
     ap.add_argument("--binsize", default=None, help="comma-separated bin extents")
     ap.add_argument("--msub", type=int, default=0)
+    ap.add_argument("--upsampfac", type=float, default=0.0,
+                    help="fine-grid upsampling factor sigma (0 = 2)")
     ap.add_argument("--eps", type=float, default=0.0,
                     help="override the workload's tolerance (fp32 down to 1e-6, fp64 below)")
     ap.add_argument("--cpu-sample", type=int, default=10_000_000,
@@ -377,7 +379,7 @@ def main():
 
     binsize = tuple(int(v) for v in args.binsize.split(",")) if args.binsize else None
     plan = Plan(1, modes, 1, eps, -1, dtype=cdt, method=args.method, binsize=binsize,
-                msub=args.msub, device=dev)
+                msub=args.msub, device=dev, upsampfac=args.upsampfac)
     info = plan.info()
 
     def step():
@@ -413,7 +415,8 @@ def main():
     sm_spread = "k_spread_smp" if prec == "f32" else "k_spread_sm"
     kernel_name = {"spread": sm_spread if info["method"] == 3 else "k_spread_gm",
                    "interp": "k_interp_sm" if info["method"] == 3 else "k_interp_gm"}[dominant]
-    traffic = load_traffic(kernel_name, args.workload) if args.eps <= 0 else None
+    traffic = load_traffic(kernel_name, args.workload) \
+        if args.eps <= 0 and args.upsampfac in (0.0, 2.0) else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -434,6 +437,7 @@ def main():
             "dim": dim, "modes": list(modes), "M": M, "points": kind, "eps": eps,
             "w": info["w"], "fine_grid": info["nfine"][:dim], "method": info["method"],
             "binsize": info["binsize"][:dim], "msub": info["msub"],
+            "upsampfac": info["upsampfac"],
         },
         "roofline": {
             "bound": "hbm",

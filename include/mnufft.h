@@ -74,7 +74,10 @@ typedef struct mnufft_opts {
                            synchronises the stream) */
     int   device;       /* HIP device ordinal, -1 = the current device */
     void *stream;       /* hipStream_t all work is ordered on; NULL = the null stream */
-    int   reserved[8];  /* must be zero */
+    double upsampfac;   /* fine-grid upsampling factor sigma: 0 or 2 selects the paper's
+                           2 (Sec. II); values in [1.25, 2) use smaller fine grids with
+                           wider kernels (see mnufft_choose_params_sigma) */
+    int   reserved[6];  /* must be zero */
 } mnufft_opts;
 
 typedef struct mnufft_plan_s *mnufft_plan;
@@ -94,6 +97,7 @@ typedef struct mnufft_info {
     int64_t nbins;         /* prod ceil(n_i / m_i) */
     int64_t nsub_max;      /* capacity of the subproblem list: nbins + ceil(M / msub) */
     int64_t device_bytes;  /* device memory owned by the plan */
+    double  upsampfac;     /* sigma */
 } mnufft_info;
 
 /* Fill *o with the defaults listed in mnufft_opts.  Errors: ERR_ARG if o is NULL. */
@@ -229,6 +233,18 @@ int mnufft_get_timing(mnufft_plan p, double *ms, int64_t *count, int reset);
  * grid n = smallest 2^a 3^b 5^c >= max(2N, 2w).  Outputs are host pointers.
  * Returns MNUFFT_WARN_EPS_CLAMPED when the cap applied.  Errors: ERR_ARG. */
 int mnufft_choose_params(double eps, int prec, int64_t N, int *w, double *beta, int64_t *n);
+
+/* The same for an upsampling factor sigma: sigma = 2 gives exactly the rule
+ * above; sigma in [1.25, 2), which the paper names as future work (Sec. VI),
+ * uses the published rule of the FINUFFT paper (Barnett, Magland and
+ * af Klinteberg, SIAM J. Sci. Comput. 2019): w = ceil(ln(1/eps) / (pi
+ * sqrt(1 - 1/sigma))), beta = 0.97 pi w (1 - 1/(2 sigma)), and n = smallest
+ * 2^a 3^b 5^c >= max(ceil(sigma N), 2w).  In F32 eps is first raised to 1e-7
+ * (the rule above's cap of w = 8 at sigma = 2); w is capped at 16.  Returns
+ * MNUFFT_WARN_EPS_CLAMPED when a cap applied.  Errors: ERR_ARG (also for sigma
+ * outside [1.25, 2]). */
+int mnufft_choose_params_sigma(double eps, int prec, int64_t N, double sigma, int *w,
+                               double *beta, int64_t *n);
 
 /* The N per-dimension correction factors of Sec. II-A step 3, as the library
  * computes them at plan time (host array out, double):

@@ -18,10 +18,11 @@ class Batch:
     n_modes   list of (N1, N2[, N3]) per transform
     n_points  list of M per transform
     binsize   optional list of per-transform bin extents; msub: optional list
+    upsampfac fine-grid upsampling factor sigma (0 = 2; 1.25 .. 2 allowed)
     """
 
     def __init__(self, nufft_type, n_modes, n_points, eps=1e-6, isign=None,
-                 dtype=torch.complex64, binsize=None, msub=None, device=None):
+                 dtype=torch.complex64, binsize=None, msub=None, device=None, upsampfac=0.0):
         self._lib = L.load()
         self._h = ctypes.c_void_p(0)
         self.type = int(nufft_type)
@@ -51,6 +52,7 @@ class Batch:
         o = L.default_opts()
         o.device = self.device.index if self.device.index is not None else -1
         o.stream = torch.cuda.current_stream(self.device).cuda_stream
+        o.upsampfac = float(upsampfac)
         rc = self._lib.mnufft_batch_makeplan(self.type, self.dim, self.T, nm, npts, self.isign,
                                              float(eps), _PREC[dtype], bs, ms, ctypes.byref(o),
                                              ctypes.byref(self._h))

@@ -191,6 +191,8 @@ int mnufft_batch_makeplan(int type, int dim, int ntr, const int64_t *nmodes, con
     mnufft_default_opts(&o);
     if (opts) o = *opts;
     if (o.msub < 0 || o.device < -1) return MNUFFT_ERR_ARG;
+    const double sigma = o.upsampfac == 0.0 ? 2.0 : o.upsampfac;
+    if (!(sigma >= 1.25 && sigma <= 2.0)) return MNUFFT_ERR_ARG;
     if (o.method != MNUFFT_METHOD_AUTO && o.method != MNUFFT_METHOD_SM) return MNUFFT_ERR_UNSUPPORTED;
     int64_t Mtot = 0;
     for (int t = 0; t < ntr; ++t) {
@@ -206,7 +208,7 @@ int mnufft_batch_makeplan(int type, int dim, int ntr, const int64_t *nmodes, con
     int w = 0;
     double beta = 0;
     int64_t ntmp = 0;
-    int warn = mnufft_choose_params(eps, prec, 1, &w, &beta, &ntmp);
+    int warn = mnufft_choose_params_sigma(eps, prec, 1, sigma, &w, &beta, &ntmp);
     if (warn < 0) return warn;
 
     mnufft_batch b = new (std::nothrow) mnufft_batch_s();
@@ -237,7 +239,7 @@ int mnufft_batch_makeplan(int type, int dim, int ntr, const int64_t *nmodes, con
         int64_t cells = 1, nm = 1, nb = 1;
         for (int d = 0; d < 3; ++d) {
             const int64_t N = d < dim ? nmodes[3 * t + d] : 1;
-            const int64_t n = d < dim ? mn::host::fine_size(N, w) : 1;
+            const int64_t n = d < dim ? mn::host::fine_size(N, w, sigma) : 1;
             int m = d < dim ? (binsize && binsize[3 * t + d] > 0
                                    ? binsize[3 * t + d]
                                    : (o.binsize[d] > 0 ? o.binsize[d] : defm[dim - 2][d]))

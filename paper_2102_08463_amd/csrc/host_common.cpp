@@ -18,9 +18,21 @@ static bool smooth235(int64_t n)
     return n == 1;
 }
 
-int64_t fine_size(int64_t N, int w)
+int width_for_eps_sigma(double eps, double sigma)
 {
-    int64_t n = std::max<int64_t>(2 * N, 2 * (int64_t)w);
+    if (sigma == 2.0) return width_for_eps(eps);
+    return (int)std::ceil(std::log(1.0 / eps) / (kPi * std::sqrt(1.0 - 1.0 / sigma)) - 1e-9);
+}
+
+double beta_for(int w, double sigma)
+{
+    return sigma == 2.0 ? 2.30 * w : 0.97 * kPi * w * (1.0 - 0.5 / sigma);
+}
+
+int64_t fine_size(int64_t N, int w, double sigma)
+{
+    const int64_t sn = sigma == 2.0 ? 2 * N : (int64_t)std::ceil(sigma * (double)N - 1e-9);
+    int64_t n = std::max<int64_t>(sn, 2 * (int64_t)w);
     while (!smooth235(n)) ++n;
     return n;
 }

@@ -19,7 +19,10 @@ constexpr double kPi = 3.141592653589793;
 int width_for_eps(double eps);
 
 // Smallest 2^a 3^b 5^c >= max(2N, 2w) (Sec. II).
-int64_t fine_size(int64_t N, int w);
+// General upsampling factor sigma (sigma = 2: the rule above, exactly).
+int width_for_eps_sigma(double eps, double sigma);
+double beta_for(int w, double sigma);
+int64_t fine_size(int64_t N, int w, double sigma = 2.0);
 
 // p_k = (2/w) / phi_hat(alpha k) * (-1)^k for k in I_N, alpha = w pi / n
 // (Sec. II-A step 3; the sign is the lattice phase of grid point l at l h - pi).

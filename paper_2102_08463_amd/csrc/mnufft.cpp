@@ -39,6 +39,7 @@ struct mnufft_plan_s {
     int64_t N[3] = {1, 1, 1};
     int64_t ntransf = 1;
     double eps = 1e-6;
+    double sigma = 2.0;  // upsampling factor
     mn::Geom g{};
     int method = MNUFFT_METHOD_SM;
     int msub = 1024;
@@ -414,27 +415,37 @@ int mnufft_default_opts(mnufft_opts *o)
     return MNUFFT_OK;
 }
 
-int mnufft_choose_params(double eps, int prec, int64_t N, int *w, double *beta, int64_t *n)
+int mnufft_choose_params_sigma(double eps, int prec, int64_t N, double sigma, int *w,
+                               double *beta, int64_t *n)
 {
     if (!(eps > 0.0 && eps < 1.0) || (prec != MNUFFT_F32 && prec != MNUFFT_F64) || N < 1 ||
-        !w || !beta || !n)
+        !(sigma >= 1.25 && sigma <= 2.0) || !w || !beta || !n)
         return MNUFFT_ERR_ARG;
     int rc = MNUFFT_OK;
-    int ww = std::max(2, width_for_eps(eps));
-    const int wmax = prec == MNUFFT_F32 ? 8 : 16;
-    if (ww > wmax) {
-        ww = wmax;
+    // single precision: tolerances below 1e-7 (w = 8 at sigma = 2) are not reachable
+    if (prec == MNUFFT_F32 && eps < 1e-7) {
+        eps = 1e-7;
+        rc = MNUFFT_WARN_EPS_CLAMPED;
+    }
+    int ww = std::max(2, mn::host::width_for_eps_sigma(eps, sigma));
+    if (ww > 16) {
+        ww = 16;
         rc = MNUFFT_WARN_EPS_CLAMPED;
     }
     *w = ww;
-    *beta = 2.30 * ww;
-    *n = fine_size(N, ww);
+    *beta = mn::host::beta_for(ww, sigma);
+    *n = fine_size(N, ww, sigma);
     return rc;
+}
+
+int mnufft_choose_params(double eps, int prec, int64_t N, int *w, double *beta, int64_t *n)
+{
+    return mnufft_choose_params_sigma(eps, prec, N, 2.0, w, beta, n);
 }
 
 int mnufft_correction_factors(int64_t N, int64_t n, int w, double beta, double *out)
 {
-    if (N < 1 || n < 2 * N || w < 2 || w > 16 || !(beta > 0.0) || !out) return MNUFFT_ERR_ARG;
+    if (N < 1 || n <= N || w < 2 || w > 16 || !(beta > 0.0) || !out) return MNUFFT_ERR_ARG;
     std::vector<double> p;
     correction(N, n, w, beta, p);
     std::copy(p.begin(), p.end(), out);
@@ -457,8 +468,10 @@ int mnufft_makeplan(int type, int dim, const int64_t *nmodes, int iflag, int64_t
     if (o.method < MNUFFT_METHOD_AUTO || o.method > MNUFFT_METHOD_SM || o.msub < 0 ||
         o.device < -1)
         return MNUFFT_ERR_ARG;
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < 6; ++i)
         if (o.reserved[i]) return MNUFFT_ERR_ARG;
+    const double sigma = o.upsampfac == 0.0 ? 2.0 : o.upsampfac;
+    if (!(sigma >= 1.25 && sigma <= 2.0)) return MNUFFT_ERR_ARG;
     for (int d = 0; d < dim; ++d)
         if (nmodes[d] < 1 || nmodes[d] > (1 << 24) || o.binsize[d] < 0) return MNUFFT_ERR_ARG;
 
@@ -467,7 +480,7 @@ int mnufft_makeplan(int type, int dim, const int64_t *nmodes, int iflag, int64_t
     int64_t nf[3] = {1, 1, 1};
     int warn = MNUFFT_OK;
     for (int d = 0; d < dim; ++d) {
-        int rc = mnufft_choose_params(eps, prec, nmodes[d], &w, &beta, &nf[d]);
+        int rc = mnufft_choose_params_sigma(eps, prec, nmodes[d], sigma, &w, &beta, &nf[d]);
         if (rc < 0) return rc;
         if (rc > 0) warn = rc;
     }
@@ -491,6 +504,7 @@ int mnufft_makeplan(int type, int dim, const int64_t *nmodes, int iflag, int64_t
     p->validate = o.validate_pts;
     p->stream = (hipStream_t)o.stream;
     p->msub = o.msub > 0 ? o.msub : 4096;
+    p->sigma = sigma;
     mn::Geom &g = p->g;
     g.dim = dim;
     g.w = w;
@@ -731,6 +745,7 @@ int mnufft_get_info(mnufft_plan p, mnufft_info *info)
     info->nbins = p->g.nbins;
     info->nsub_max = p->M >= 0 ? p->nsub_max : 0;
     info->device_bytes = p->devbytes;
+    info->upsampfac = p->sigma;
     return MNUFFT_OK;
 }
 

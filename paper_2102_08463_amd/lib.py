@@ -26,7 +26,8 @@ EXPORTS = (
     "mnufft_execute_adjoint", "mnufft_interp_grad", "mnufft_spread", "mnufft_interp",
     "mnufft_get_sort",
     "mnufft_get_subproblems", "mnufft_get_info", "mnufft_destroy", "mnufft_strerror",
-    "mnufft_choose_params", "mnufft_correction_factors", "mnufft_set_timing", "mnufft_get_timing",
+    "mnufft_choose_params", "mnufft_choose_params_sigma", "mnufft_correction_factors",
+    "mnufft_set_timing", "mnufft_get_timing",
     "mnufft_batch_makeplan", "mnufft_batch_setpts", "mnufft_batch_execute",
     "mnufft_batch_set_timing", "mnufft_batch_get_timing", "mnufft_batch_get_totals",
     "mnufft_batch_destroy", "mnufft_tune_candidates", "mnufft_tune_time",
@@ -48,7 +49,8 @@ class Opts(ctypes.Structure):
         ("validate_pts", ctypes.c_int),
         ("device", ctypes.c_int),
         ("stream", ctypes.c_void_p),
-        ("reserved", ctypes.c_int * 8),
+        ("upsampfac", ctypes.c_double),
+        ("reserved", ctypes.c_int * 6),
     ]
 
 
@@ -61,7 +63,7 @@ class Info(ctypes.Structure):
         ("w", ctypes.c_int), ("beta", ctypes.c_double),
         ("method", ctypes.c_int), ("binsize", ctypes.c_int * 3), ("msub", ctypes.c_int),
         ("nbins", ctypes.c_int64), ("nsub_max", ctypes.c_int64),
-        ("device_bytes", ctypes.c_int64),
+        ("device_bytes", ctypes.c_int64), ("upsampfac", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -107,6 +109,9 @@ def load():
     L.mnufft_strerror.restype = ctypes.c_char_p
     L.mnufft_choose_params.argtypes = [ctypes.c_double, ci, i64, ctypes.POINTER(ci),
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    L.mnufft_choose_params_sigma.argtypes = [ctypes.c_double, ci, i64, ctypes.c_double,
+                                             ctypes.POINTER(ci), ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(i64)]
     L.mnufft_correction_factors.argtypes = [i64, i64, ci, ctypes.c_double,
                                             ctypes.POINTER(ctypes.c_double)]
     L.mnufft_set_timing.argtypes = [vp, ci]
@@ -162,12 +167,14 @@ def default_opts():
     return o
 
 
-def choose_params(eps, prec, N):
-    """(w, beta, n, status) as the library picks them for one dimension (host only)."""
+def choose_params(eps, prec, N, sigma=2.0):
+    """(w, beta, n, status) as the library picks them for one dimension and
+    upsampling factor sigma (host only)."""
     w, beta, n = ctypes.c_int(), ctypes.c_double(), ctypes.c_int64()
-    rc = check(load().mnufft_choose_params(float(eps), int(prec), int(N), ctypes.byref(w),
-                                           ctypes.byref(beta), ctypes.byref(n)),
-               "mnufft_choose_params")
+    rc = check(load().mnufft_choose_params_sigma(float(eps), int(prec), int(N), float(sigma),
+                                                 ctypes.byref(w), ctypes.byref(beta),
+                                                 ctypes.byref(n)),
+               "mnufft_choose_params_sigma")
     return w.value, beta.value, n.value, rc
 
 

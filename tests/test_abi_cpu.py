@@ -30,9 +30,10 @@ def test_exports_match_header():
 
 
 def test_struct_layouts():
-    # mnufft_opts: 7 ints + pointer + 8 reserved ints, natural alignment
+    # mnufft_opts: 7 ints + pointer + double + 6 reserved ints, natural alignment
     assert ctypes.sizeof(L.Opts) == 72
     assert L.Opts.stream.offset == 32
+    assert L.Opts.upsampfac.offset == 40
 
 
 def test_default_opts_and_strerror():
@@ -115,9 +116,27 @@ def test_choose_params_match_oracle(eps, N):
 
 
 def test_choose_params_rejects():
-    for args in ((0.0, 0, 8), (1.0, 0, 8), (1e-3, 2, 8), (1e-3, 0, 0)):
+    for args in ((0.0, 0, 8), (1.0, 0, 8), (1e-3, 2, 8), (1e-3, 0, 0), (1e-3, 0, 8, 1.2),
+                 (1e-3, 0, 8, 2.5)):
         with pytest.raises(L.MnufftError):
             L.choose_params(*args)
+
+
+@pytest.mark.parametrize("sigma", [1.25, 1.5, 2.0])
+@pytest.mark.parametrize("eps", [1e-2, 1e-4, 1e-6, 1e-9, 1e-12])
+@pytest.mark.parametrize("N", [1, 41, 64, 333])
+def test_choose_params_sigma_match_oracle(sigma, eps, N):
+    w, beta, n, rc = L.choose_params(eps, L.F64, N, sigma)
+    wr = oparams.kernel_width(eps, sigma=sigma)
+    assert w == wr
+    assert math.isclose(beta, oparams.kernel_beta(w, sigma=sigma), rel_tol=1e-15)
+    assert n == oparams.fine_grid_size(N, w, sigma=sigma)
+    uncapped = oparams.kernel_width(eps, wmax=99, sigma=sigma)
+    assert rc == (L.WARN_EPS_CLAMPED if uncapped > 16 else L.OK)
+    w32, _, _, rc32 = L.choose_params(eps, L.F32, N, sigma)
+    assert w32 == oparams.kernel_width(max(eps, 1e-7), sigma=sigma)
+    assert rc32 == (L.WARN_EPS_CLAMPED if eps < 1e-7 or
+                    oparams.kernel_width(max(eps, 1e-7), wmax=99, sigma=sigma) > 16 else L.OK)
 
 
 @pytest.mark.parametrize("w", [2, 3, 6, 7, 9, 13, 16])
@@ -131,7 +150,7 @@ def test_correction_factors_match_oracle(w, N, n):
 
 
 def test_correction_factors_reject():
-    for args in ((0, 8, 6, 13.8), (8, 15, 6, 13.8), (8, 16, 1, 13.8), (8, 16, 17, 13.8),
+    for args in ((0, 8, 6, 13.8), (8, 8, 6, 13.8), (8, 16, 1, 13.8), (8, 16, 17, 13.8),
                  (8, 16, 6, 0.0)):
         with pytest.raises(L.MnufftError):
             L.correction_factors(*args)

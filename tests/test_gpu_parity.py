@@ -299,3 +299,21 @@ def test_ewald_slices_fp64_3d(ntype):
         assert _type1_check(pts64, pts, N, "f64", 1e-12) <= 1e-11
     else:
         assert _type2_check(pts64, pts, N, "f64", 1e-12) <= 1e-11
+
+
+@pytest.mark.parametrize("dim,prec,eps", [(2, "f32", 1e-4), (2, "f64", 1e-9), (3, "f32", 1e-4),
+                                          (3, "f64", 1e-8)])
+@pytest.mark.parametrize("sigma", [1.25, 1.5])
+def test_upsampling_below_two(dim, prec, eps, sigma):
+    """Upsampling factors below two (smaller fine grids, wider kernels)."""
+    note(f"upsampfac {sigma} {dim}d {prec} {eps}")
+    N = (45, 38) if dim == 2 else (20, 17, 14)
+    pts64, pts = make_points("uniform", 15_000 if dim == 2 else 6_000, dim, prec, seed=9)
+    assert _type1_check(pts64, pts, N, prec, eps, upsampfac=sigma) <= 10 * eps
+    assert _type2_check(pts64, pts, N, prec, eps, upsampfac=sigma) <= 10 * eps
+    p = _plan(1, N, eps=eps, dtype=cdtype(prec), upsampfac=sigma)
+    inf = p.info()
+    from oracle import params as oparams
+    assert inf["upsampfac"] == sigma
+    assert inf["nfine"][:dim] == [oparams.fine_grid_size(k, inf["w"], sigma=sigma) for k in N]
+    p.destroy()
