@@ -761,20 +761,53 @@ k_interp_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
         const int bz = b;
         const int o1 = bx * gg.m[0] - P, o2 = by * gg.m[1] - P;
         const int o3 = DIM == 3 ? bz * gg.m[2] - P : 0;
-        for (int e = threadIdx.x; e < tsize; e += blockDim.x) {
-            const int s1 = e % p1, r = e / p1;
-            const int s2 = r % p2, s3 = r / p2;
-            const int l1 = wrapmod(o1 + s1, gg.n[0]);
-            const int l2 = wrapmod(o2 + s2, gg.n[1]);
-            const int l3 = DIM == 3 ? wrapmod(o3 + s3, gg.n[2]) : 0;
-            tile[e] = grid[((size_t)l3 * gg.n[1] + l2) * gg.n[0] + l1];
+        // The results of the previous subproblem may still be in flight; on
+        // this GPU one counter tracks vector loads and stores together, so a
+        // wait for a load also waits for the stores issued before it.  Loads
+        // are therefore issued kStage at a time here, and one point ahead in
+        // the loop below, so that each wait covers several of them.
+        constexpr int kStage = 4;
+        for (int e0 = threadIdx.x; e0 < tsize; e0 += kStage * blockDim.x) {
+            C v[kStage];
+#pragma unroll
+            for (int k = 0; k < kStage; ++k) {
+                const int e = e0 + k * blockDim.x;
+                if (e < tsize) {
+                    const int s1 = e % p1, r = e / p1;
+                    const int s2 = r % p2, s3 = r / p2;
+                    const int l1 = wrapmod(o1 + s1, gg.n[0]);
+                    const int l2 = wrapmod(o2 + s2, gg.n[1]);
+                    const int l3 = DIM == 3 ? wrapmod(o3 + s3, gg.n[2]) : 0;
+                    v[k] = grid[((size_t)l3 * gg.n[1] + l2) * gg.n[0] + l1];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kStage; ++k)
+                if (e0 + k * (int)blockDim.x < tsize) tile[e0 + k * blockDim.x] = v[k];
         }
         __syncthreads();
         const int end = rec.y + rec.z;
-        for (int i = rec.y + threadIdx.x; i < end; i += blockDim.x) {
+        int i = rec.y + threadIdx.x;
+        T nu0 = 0, nu1 = 0, nu2 = 0;
+        int npj = 0;
+        if (i < end) {
+            nu0 = u0[i];
+            nu1 = u1[i];
+            if constexpr (DIM == 3) nu2 = u2[i];
+            npj = perm[i];
+        }
+        for (; i < end; i += blockDim.x) {
+            const T x0 = nu0, x1 = nu1, x2 = nu2;
+            const int pj = npj;
+            if (i + (int)blockDim.x < end) {
+                nu0 = u0[i + blockDim.x];
+                nu1 = u1[i + blockDim.x];
+                if constexpr (DIM == 3) nu2 = u2[i + blockDim.x];
+                npj = perm[i + blockDim.x];
+            }
             T kx[W], ky[W];
-            const int sx = taps<T, W>(u0[i] + (T)P, bk, kx);
-            const int sy = taps<T, W>(u1[i] + (T)P, bk, ky);
+            const int sx = taps<T, W>(x0 + (T)P, bk, kx);
+            const int sy = taps<T, W>(x1 + (T)P, bk, ky);
             T ar = 0, ai = 0;
             if constexpr (DIM == 2) {
 #pragma unroll
@@ -792,7 +825,7 @@ k_interp_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
                 }
             } else {
                 T z0;
-                const int sz = tap_start<T, W>(u2[i] + (T)P, z0);
+                const int sz = tap_start<T, W>(x2 + (T)P, z0);
 #pragma unroll 1
                 for (int a3 = 0; a3 < W; ++a3) {
                     const T kz = es_val(z0 + (T)a3 * (T)(2.0 / W), bk);
@@ -817,7 +850,7 @@ k_interp_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
             C out;
             out.x = ar;
             out.y = ai;
-            c[perm[i]] = out;
+            c[pj] = out;
         }
         __syncthreads();
     }
