@@ -1,5 +1,5 @@
 /*
- * Plain FP64 CPU reference for the 2D/3D nonuniform FFT (test infrastructure).
+ * Plain FP64 CPU reference for the 1D/2D/3D nonuniform FFT (test infrastructure).
  *
  * This file is part of the oracle: it is used only by the test-suite, by the
  * smoke check and by the CPU-baseline leg of the benchmark.  It shares no
@@ -14,6 +14,12 @@
  *                      periodised ES kernel of eq. (es)
  *   orc_interp         type 2 step 3 of Sec. II-B: interpolation with the same
  *                      kernel (the exact transpose of orc_spread)
+ *   orc_direct_type3   exact exponential sum of type 3 (nonuniform points to
+ *                      nonuniform frequencies), named in Sec. I-B and Sec. VI
+ *                      as beyond the paper's scope
+ *
+ * Dimension 1 (dim = 1, y = z = NULL) is accepted everywhere: the paper's
+ * formulas restricted to one coordinate.
  *
  * All arithmetic is IEEE double.  Complex arrays are interleaved (re, im).
  * Fine grids are stored with the first coordinate fastest: index
@@ -41,7 +47,8 @@
 /* ---------------------------------------------------------------------- */
 
 /* f[(i3*K2 + i2)*K1 + i1] = sum_j c_j exp(iflag * i * (k1[i1] x_j + k2[i2] y_j
- * + k3[i3] z_j)).  In 2D pass K3 = 1, k3 = {0}, z = NULL.  The product of the
+ * + k3[i3] z_j)).  In 2D pass K3 = 1, k3 = {0}, z = NULL; in 1D also K2 = 1,
+ * k2 = {0}, y = NULL.  The product of the
  * per-dimension exponentials equals the exponential of the sum exactly; each
  * per-dimension factor is one call of sin and cos of k*x in double. */
 void orc_direct_type1(int dim, int64_t M, const double *x, const double *y,
@@ -69,7 +76,7 @@ void orc_direct_type1(int dim, int64_t M, const double *x, const double *y,
                 e1[2 * a + 1] = sin(ph);
             }
             for (int64_t a = 0; a < K2; ++a) {
-                double ph = s * (double)k2[a] * y[j];
+                double ph = (dim >= 2) ? s * (double)k2[a] * y[j] : 0.0;
                 e2[2 * a] = cos(ph);
                 e2[2 * a + 1] = sin(ph);
             }
@@ -112,7 +119,7 @@ void orc_direct_type2(int dim, const int64_t N[3], const double *x,
                       int iflag, int64_t nq, const int64_t *idx, double *out)
 {
     const double s = (iflag >= 0) ? 1.0 : -1.0;
-    const int64_t N1 = N[0], N2 = N[1], N3 = (dim == 3) ? N[2] : 1;
+    const int64_t N1 = N[0], N2 = (dim >= 2) ? N[1] : 1, N3 = (dim == 3) ? N[2] : 1;
 #pragma omp parallel
     {
         double *e1 = (double *)malloc(sizeof(double) * 2 * N1);
@@ -126,7 +133,7 @@ void orc_direct_type2(int dim, const int64_t N[3], const double *x,
                 e1[2 * a] = cos(ph); e1[2 * a + 1] = sin(ph);
             }
             for (int64_t a = 0; a < N2; ++a) {
-                double ph = s * (double)(a - N2 / 2) * y[j];
+                double ph = (dim >= 2) ? s * (double)(a - N2 / 2) * y[j] : 0.0;
                 e2[2 * a] = cos(ph); e2[2 * a + 1] = sin(ph);
             }
             for (int64_t a = 0; a < N3; ++a) {
@@ -203,7 +210,7 @@ void orc_spread(int dim, const int64_t n[3], int w, double beta, int64_t M,
                 const double *x, const double *y, const double *z,
                 const double *c, double *grid)
 {
-    const int64_t n1 = n[0], n2 = n[1], n3 = (dim == 3) ? n[2] : 1;
+    const int64_t n1 = n[0], n2 = (dim >= 2) ? n[1] : 1, n3 = (dim == 3) ? n[2] : 1;
 #pragma omp parallel
     {
         double k1[32], k2[32], k3[32];
@@ -211,12 +218,14 @@ void orc_spread(int dim, const int64_t n[3], int w, double beta, int64_t M,
 #pragma omp for schedule(static)
         for (int64_t j = 0; j < M; ++j) {
             orc_taps(orc_gridcoord(x[j], n1), n1, w, beta, k1, i1);
-            orc_taps(orc_gridcoord(y[j], n2), n2, w, beta, k2, i2);
+            int w2 = 1;
+            k2[0] = 1.0; i2[0] = 0;
+            if (dim >= 2) { orc_taps(orc_gridcoord(y[j], n2), n2, w, beta, k2, i2); w2 = w; }
             int w3 = 1;
             k3[0] = 1.0; i3[0] = 0;
             if (dim == 3) { orc_taps(orc_gridcoord(z[j], n3), n3, w, beta, k3, i3); w3 = w; }
             for (int a3 = 0; a3 < w3; ++a3)
-                for (int a2 = 0; a2 < w; ++a2) {
+                for (int a2 = 0; a2 < w2; ++a2) {
                     const double k23 = k3[a3] * k2[a2];
                     const int64_t row = (i3[a3] * n2 + i2[a2]) * n1;
                     for (int a1 = 0; a1 < w; ++a1) {
@@ -237,7 +246,7 @@ void orc_interp(int dim, const int64_t n[3], int w, double beta, int64_t M,
                 const double *x, const double *y, const double *z,
                 const double *grid, double *c)
 {
-    const int64_t n1 = n[0], n2 = n[1], n3 = (dim == 3) ? n[2] : 1;
+    const int64_t n1 = n[0], n2 = (dim >= 2) ? n[1] : 1, n3 = (dim == 3) ? n[2] : 1;
 #pragma omp parallel
     {
         double k1[32], k2[32], k3[32];
@@ -245,13 +254,15 @@ void orc_interp(int dim, const int64_t n[3], int w, double beta, int64_t M,
 #pragma omp for schedule(static)
         for (int64_t j = 0; j < M; ++j) {
             orc_taps(orc_gridcoord(x[j], n1), n1, w, beta, k1, i1);
-            orc_taps(orc_gridcoord(y[j], n2), n2, w, beta, k2, i2);
+            int w2 = 1;
+            k2[0] = 1.0; i2[0] = 0;
+            if (dim >= 2) { orc_taps(orc_gridcoord(y[j], n2), n2, w, beta, k2, i2); w2 = w; }
             int w3 = 1;
             k3[0] = 1.0; i3[0] = 0;
             if (dim == 3) { orc_taps(orc_gridcoord(z[j], n3), n3, w, beta, k3, i3); w3 = w; }
             double sr = 0.0, si = 0.0;
             for (int a3 = 0; a3 < w3; ++a3)
-                for (int a2 = 0; a2 < w; ++a2) {
+                for (int a2 = 0; a2 < w2; ++a2) {
                     const double k23 = k3[a3] * k2[a2];
                     const int64_t row = (i3[a3] * n2 + i2[a2]) * n1;
                     for (int a1 = 0; a1 < w; ++a1) {
@@ -264,6 +275,42 @@ void orc_interp(int dim, const int64_t n[3], int w, double beta, int64_t M,
             c[2 * j] = sr;
             c[2 * j + 1] = si;
         }
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Type 3: nonuniform points to nonuniform frequencies                    */
+/* ---------------------------------------------------------------------- */
+
+/* out[q] = sum_j c_j exp(iflag * i * (s_k x_j + t_k y_j + u_k z_j)) for the nq
+ * frequencies k = idx[q] (real, arbitrary); t, y are unused in 1D and u, z in
+ * 1D and 2D.  Every phase is formed in double and passed to cos and sin once. */
+void orc_direct_type3(int dim, int64_t M, const double *x, const double *y,
+                      const double *z, const double *c, int iflag,
+                      const double *s, const double *t, const double *u,
+                      int64_t nq, const int64_t *idx, double *out)
+{
+    const double sg = (iflag >= 0) ? 1.0 : -1.0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < nq; ++q) {
+        const int64_t k = idx[q];
+        double tr = 0.0, ti = 0.0, br = 0.0, bi = 0.0;
+        int64_t inblk = 0;
+        for (int64_t j = 0; j < M; ++j) {
+            double ph = s[k] * x[j];
+            if (dim >= 2) ph += t[k] * y[j];
+            if (dim == 3) ph += u[k] * z[j];
+            ph *= sg;
+            const double er = cos(ph), ei = sin(ph);
+            br += c[2 * j] * er - c[2 * j + 1] * ei;
+            bi += c[2 * j] * ei + c[2 * j + 1] * er;
+            if (++inblk == ORC_SUMBLOCK) {
+                tr += br; ti += bi; br = 0.0; bi = 0.0;
+                inblk = 0;
+            }
+        }
+        out[2 * q] = tr + br;
+        out[2 * q + 1] = ti + bi;
     }
 }
 
