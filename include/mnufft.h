@@ -1,5 +1,5 @@
 /*
- * mnufft: 2D/3D nonuniform FFTs of type 1 and type 2 on AMD Instinct MI355X
+ * mnufft: 2D/3D nonuniform FFTs of type 1 and type 2 (and type 3) on AMD Instinct MI355X
  * (gfx950), following the three-step method of cuFINUFFT (arXiv 2102.08463):
  * exponential-of-semicircle spreading / interpolation on an upsampled grid,
  * a fine-grid FFT, and deconvolution by the kernel's Fourier transform.
@@ -98,15 +98,20 @@ typedef struct mnufft_info {
     int64_t nsub_max;      /* capacity of the subproblem list: nbins + ceil(M / msub) */
     int64_t device_bytes;  /* device memory owned by the plan */
     double  upsampfac;     /* sigma */
+    int64_t ntargets;      /* type 3: frequencies K of the last setpts3 (-1 before); else 0.
+                              For type 3, nmodes is the spreading grid nf (the inner type 2's
+                              modes), nfine that type 2's fine grid and binsize / nbins /
+                              method those of the spreading plan; all valid after setpts3 */
 } mnufft_info;
 
 /* Fill *o with the defaults listed in mnufft_opts.  Errors: ERR_ARG if o is NULL. */
 int mnufft_default_opts(mnufft_opts *o);
 
 /* Create a plan (Sec. I-A: plan, set up, execute, destroy).
- *   type     1 or 2
+ *   type     1 or 2; or 3 (see mnufft_setpts3)
  *   dim      2 or 3
- *   nmodes   host array of dim entries N_i >= 1 (the rest ignored)
+ *   nmodes   host array of dim entries N_i >= 1 (the rest ignored); unused and
+ *            may be NULL for type 3
  *   iflag    +1 or -1, the sign in the exponent
  *   ntransf  >= 1 transforms sharing one set of points
  *   eps      requested relative l2 tolerance in (0, 1); sets w and beta (Sec. II)
@@ -136,6 +141,32 @@ int mnufft_makeplan(int type, int dim, const int64_t *nmodes, int iflag,
  * missing in 3D), ERR_PTS, ERR_ALLOC, ERR_HIP. */
 int mnufft_setpts(mnufft_plan p, int64_t M, const void *x, const void *y,
                   const void *z);
+
+/* Type 3: nonuniform points to nonuniform frequencies (named as outside the
+ * paper's scope in Sec. I-B and Sec. VI), by the published reduction of the
+ * FINUFFT paper (Barnett, Magland, af Klinteberg, SIAM J. Sci. Comput. 2019):
+ *   f_k = sum_{j<M} c_j exp(iflag * i * s_k.x_j),   k < K,
+ * for real points x_j and real frequencies s_k of any range.  With C, X the
+ * centre and half-width of the points and D, S those of the frequencies
+ * (per dimension), the strengths are multiplied by exp(iflag i D.(x_j - C)),
+ * spread at (x_j - C) / gamma onto nf cells of spacing h = 2 pi / nf
+ * (nf = smallest even 2^a 3^b 5^c >= max(ceil(2 sigma S X / pi) + w + 1, 2w),
+ * gamma = nf / (2 sigma S); S = 0 is read as 1/X, or 1 when X = 0 too), the
+ * grid is transformed by a type 2 plan (modes -nf/2 .. nf/2 - 1) at
+ * t_k = h gamma (s_k - D), and the result is multiplied by
+ * exp(iflag i s_k.C) prod_d (2/w) / phi_hat(w t_kd / 2).
+ *   x, y, z  device arrays of M reals of the plan precision (z only in 3D)
+ *   s, t, u  device arrays of K reals (u only in 3D)
+ * Reads the bounds of both sets back to the host (synchronises the stream),
+ * then makes the spreading and type 2 plans (again only when nf changes)
+ * and bin-sorts both rescaled sets.  mnufft_execute then takes c (ntransf x M)
+ * and writes f (ntransf x K); the adjoint, spread / interp, gradient and
+ * sort introspection calls return ERR_UNSUPPORTED on a type 3 plan.
+ * M = 0 or K = 0 is allowed.  Errors: ERR_ARG (not a type 3 plan, sizes out
+ * of range, a needed pointer NULL or z / u given in 2D, nf above 2^24 in some
+ * dimension), ERR_PTS (a non-finite coordinate), ERR_ALLOC, ERR_HIP, ERR_FFT. */
+int mnufft_setpts3(mnufft_plan p, int64_t M, const void *x, const void *y, const void *z,
+                   int64_t K, const void *s, const void *t, const void *u);
 
 /* Run the transform (Sec. II-A for type 1, Sec. II-B for type 2).
  *   type 1: c is input (ntransf x M complex), f is output (ntransf x N1 N2 N3)

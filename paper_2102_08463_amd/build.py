@@ -34,6 +34,7 @@ UNITS = [
     ("kernels_mlp.hip", [], "kernels_mlp.o"),
     ("kernels_sort.hip", [], "kernels_sort.o"),
     ("kernels_deconv.hip", [], "kernels_deconv.o"),
+    ("kernels_type3.hip", [], "kernels_type3.o"),
     ("spread_dispatch.hip", [], "spread_dispatch.o"),
     ("spread_inst.hip", ["-DMN_T=float", "-DMN_D=2"], "spread_f2.o"),
     ("spread_inst.hip", ["-DMN_T=float", "-DMN_D=3"], "spread_f3.o"),

@@ -39,12 +39,12 @@ int64_t fine_size(int64_t N, int w, double sigma)
 
 // phi_hat(xi) = int_{-1}^{1} phi_beta(z) exp(-i xi z) dz = 2 int_0^1 phi(z) cos(xi z) dz
 // by the tanh-sinh rule z = (1 + tanh u)/2, u = (pi/2) sinh t, which is
-// insensitive to the square-root behaviour of phi at z = 1.
-static void es_fourier(double beta, const std::vector<double> &xi, std::vector<double> &out)
+// insensitive to the square-root behaviour of phi at z = 1.  Step h, nodes
+// t = k h for |k| <= K; ww carries the kernel value and the Jacobian.
+void es_quadrature(double beta, double h, int K, std::vector<double> &zz, std::vector<double> &ww)
 {
-    const double h = 1.0 / 64.0;
-    const int K = 4 * 64;  // t in [-4, 4]: the weights beyond are below 1e-20
-    std::vector<double> zz, ww;
+    zz.clear();
+    ww.clear();
     zz.reserve(2 * K + 1);
     ww.reserve(2 * K + 1);
     for (int k = -K; k <= K; ++k) {
@@ -59,6 +59,12 @@ static void es_fourier(double beta, const std::vector<double> &xi, std::vector<d
         zz.push_back(z);
         ww.push_back(h * dz * phi);
     }
+}
+
+static void es_fourier(double beta, const std::vector<double> &xi, std::vector<double> &out)
+{
+    std::vector<double> zz, ww;
+    es_quadrature(beta, 1.0 / 64.0, 4 * 64, zz, ww);  // t in [-4, 4]: weights beyond < 1e-20
     out.assign(xi.size(), 0.0);
     for (size_t i = 0; i < xi.size(); ++i) {
         double acc = 0.0;

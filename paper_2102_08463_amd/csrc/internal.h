@@ -129,6 +129,15 @@ struct Payload {
     void *out[3];
 };
 
+// Optional affine map applied to the coordinates before binning, in double:
+// x -> (x - off) * mul (used by type 3, whose rescaled points are never
+// rounded to the plan precision before their bin-relative coordinate is).
+struct PtMap {
+    int on;
+    double off[3];
+    double mul[3];
+};
+
 // key[j] and u_in[d][j]: bin index and bin-relative coordinates of every
 // point in input order; flag |= 1 if a coordinate is non-finite or outside
 // [-3pi, 3pi).
@@ -136,7 +145,8 @@ struct Payload {
 // pt_off range holds j and gets the global key bin_off + local key.
 hipError_t launch_binkey(const Geom &g, int prec, int M, const void *x, const void *y,
                          const void *z, uint32_t *key, void *const u_in[3], int *flag,
-                         hipStream_t s, const TGeom *tg = nullptr, int T = 1);
+                         hipStream_t s, const TGeom *tg = nullptr, int T = 1,
+                         const PtMap *map = nullptr);
 
 // Number of 8-bit passes for keys of `bits` bits (at least one).
 int radix_passes(int bits);
@@ -207,6 +217,31 @@ hipError_t launch_deconv_batch(const TGeom *tg, int T, long long nmodes, int pre
 hipError_t launch_precorrect_batch(const TGeom *tg, int T, long long ncells, int prec,
                                    const void *f, const void *const p[3], void *grid,
                                    hipStream_t s);
+// ---- type 3 (kernels_type3.hip) -------------------------------------------
+// Per-dimension constants of the type 3 factors (see kernels_type3.hip): the
+// rescaled value of v is (v - off) * scale; the phases use mul.
+struct T3Affine {
+    double off[3];
+    double scale[3];
+    double mul[3];
+};
+// Blocks (<= 1024) that launch_t3_bounds uses for n values; part needs
+// 3 * dim doubles per block: (min, max, non-finite flag) per dimension.
+int t3_bounds_blocks(int n);
+hipError_t launch_t3_bounds(int prec, int n, int dim, const void *const a[3], double *part,
+                            hipStream_t s);
+// pre[j] = exp(i sg sum_d mul_d (x_jd - off_d)), complex of the plan precision.
+hipError_t launch_t3_prephase(int prec, int n, int dim, const void *const x[3],
+                              const T3Affine &af, int sg, void *pre, hipStream_t s);
+// post[k] = exp(i sg sum_d mul_d s_kd) prod_d (2/w) / phi_hat(w scale_d (s_kd - off_d) / 2),
+// phi_hat by the nq-node rule quad = (nodes[nq], weights[nq]) (device, double).
+hipError_t launch_t3_postfac(int prec, int n, int dim, const void *const sf[3],
+                             const T3Affine &af, int sg, int w, const double *quad, int nq,
+                             void *post, hipStream_t s);
+// out[t][i] = in[t][i] * fac[i] over ntransf stacked complex vectors of n entries.
+hipError_t launch_cmul(int prec, long long n, int ntransf, const void *in, const void *fac,
+                       void *out, hipStream_t s);
+
 // Fill n bytes of device memory with zero by a kernel.
 hipError_t launch_zero(void *ptr, size_t bytes, hipStream_t s);
 

@@ -49,7 +49,7 @@ __global__ void __launch_bounds__(kThreads)
 k_binkey(Geom g, int M, const T *__restrict__ x, const T *__restrict__ y,
          const T *__restrict__ z, uint32_t *__restrict__ key, T *__restrict__ u0,
          T *__restrict__ u1, T *__restrict__ u2, int *__restrict__ flag,
-         const TGeom *__restrict__ tg, int T_)
+         const TGeom *__restrict__ tg, int T_, PtMap map)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     __shared__ long long soff[BATCH ? kTCache : 1];
@@ -70,7 +70,9 @@ k_binkey(Geom g, int M, const T *__restrict__ x, const T *__restrict__ y,
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         if (d >= gg.dim) break;
-        const double gc = grid_coord((double)xs[d][j], gg.S[d], gg.n[d], bad);
+        double xv = (double)xs[d][j];
+        if (map.on) xv = __dmul_rn(__dsub_rn(xv, map.off[d]), map.mul[d]);
+        const double gc = grid_coord(xv, gg.S[d], gg.n[d], bad);
         const int l = (int)gc;  // gc >= 0, so truncation is floor; l <= n - 1
         const int b = l / gg.m[d];
         k += (uint32_t)b * stride;
@@ -408,13 +410,16 @@ hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, size_t n, uint32_t 
 
 hipError_t launch_binkey(const Geom &g, int prec, int M, const void *x, const void *y,
                          const void *z, uint32_t *key, void *const u_in[3], int *flag,
-                         hipStream_t s, const TGeom *tg, int T)
+                         hipStream_t s, const TGeom *tg, int T, const PtMap *map)
 {
     if (M == 0) return hipSuccess;
     const dim3 grid(nblocks(M, kThreads)), blk(kThreads);
+    PtMap pm{};
+    if (map) pm = *map;
 #define MN_BK(TT, BB)                                                                        \
     hipLaunchKernelGGL((k_binkey<TT, BB>), grid, blk, 0, s, g, M, (const TT *)x, (const TT *)y, \
-                       (const TT *)z, key, (TT *)u_in[0], (TT *)u_in[1], (TT *)u_in[2], flag, tg, T)
+                       (const TT *)z, key, (TT *)u_in[0], (TT *)u_in[1], (TT *)u_in[2], flag, tg, T, \
+                       pm)
     if (prec == 0) {
         if (tg) MN_BK(float, true); else MN_BK(float, false);
     } else {

@@ -81,6 +81,19 @@ struct mnufft_plan_s {
     size_t fftwork_bytes = 0;
     int64_t devbytes = 0;
     mn::host::Timers tm;  // stage timers
+    // type 3: a spreading plan on the rescaled points (grid = the inner
+    // transform's modes) and a type 2 plan at the rescaled frequencies
+    mnufft_opts opts{};
+    mnufft_plan t3spr = nullptr, t3inner = nullptr;
+    int64_t K = -1;                    // frequencies of the last setpts
+    int64_t t3Mcap = -1, t3Kcap = -1;
+    void *t3pre = nullptr, *t3post = nullptr, *t3cp = nullptr;
+    mn::PtMap ptmap{};                 // map applied before binning (type 3 sub-plans)
+    double *t3part = nullptr;          // bounds partials, 2 x 1024 blocks x 3 dims x 3
+    double *t3quad = nullptr;          // kernel-transform quadrature (nodes, weights)
+    int t3nq = 0;
+    double C[3] = {0, 0, 0}, D[3] = {0, 0, 0}, gam[3] = {1, 1, 1}, hstep[3] = {1, 1, 1};
+    int64_t nf3[3] = {1, 1, 1};
 };
 
 namespace {
@@ -258,8 +271,8 @@ mn::Pts points_of(mnufft_plan p)
 
 size_t grid_bytes(mnufft_plan p) { return p->grid_elems * 2 * p->rsz; }
 
-// Type 1 with exponent sign `sign`: c (ntransf x M) -> f (ntransf x N).
-int exec_type1(mnufft_plan p, int sign, const void *c, void *f)
+// Step 1 of type 1 for all ntransf vectors: c (ntransf x M) -> p->grid.
+int spread_all(mnufft_plan p, const void *c)
 {
     const mn::Pts P = points_of(p);
     if (p->method != MNUFFT_METHOD_SM) {  // SM writes every cell itself
@@ -285,7 +298,14 @@ int exec_type1(mnufft_plan p, int sign, const void *c, void *f)
             MN_HIP(mn::launch_spread(p->g, p->prec, p->method, P, ct, gt, p->stream, 2));
         }
     }
-    int rc;
+    return MNUFFT_OK;
+}
+
+// Type 1 with exponent sign `sign`: c (ntransf x M) -> f (ntransf x N).
+int exec_type1(mnufft_plan p, int sign, const void *c, void *f)
+{
+    int rc = spread_all(p, c);
+    if (rc) return rc;
     {
         StageTimer tm(p->tm, MNUFFT_STAGE_FFT, p->stream);
         rc = run_fft(p, sign);
@@ -360,7 +380,8 @@ int enqueue_setpts(mnufft_plan p, int64_t M, const void *x, const void *y, const
             pays[q].out[d] = bufs[q + 1][d];
         }
     void *u0[3] = {bufs[0][0], bufs[0][1], bufs[0][2]};
-    MN_HIP(mn::launch_binkey(g, p->prec, (int)M, x, y, z, p->keyA, u0, p->flag, s));
+    MN_HIP(mn::launch_binkey(g, p->prec, (int)M, x, y, z, p->keyA, u0, p->flag, s, nullptr, 1,
+                             p->ptmap.on ? &p->ptmap : nullptr));
     if (p->method == MNUFFT_METHOD_GM && M > 0)
         MN_HIP(hipMemcpyAsync(p->key_in, p->keyA, (size_t)M * 4, hipMemcpyDeviceToDevice, s));
     uint32_t *sk = nullptr, *sv = nullptr;
@@ -383,6 +404,271 @@ int check_ready(mnufft_plan p)
 {
     if (!p) return MNUFFT_ERR_ARG;
     if (p->M < 0) return MNUFFT_ERR_STATE;
+    return MNUFFT_OK;
+}
+
+mnufft_plan new_plan(int type, int dim, const int64_t *nmodes, int iflag, int64_t ntransf,
+                     double eps, int prec, const mnufft_opts &o, double sigma)
+{
+    mnufft_plan p = new (std::nothrow) mnufft_plan_s();
+    if (!p) return nullptr;
+    p->type = type;
+    p->dim = dim;
+    p->prec = prec;
+    p->iflag = iflag;
+    p->ntransf = ntransf;
+    p->eps = eps;
+    p->rsz = prec == MNUFFT_F32 ? 4 : 8;
+    p->device = o.device;
+    p->validate = o.validate_pts;
+    p->stream = (hipStream_t)o.stream;
+    p->msub = o.msub > 0 ? o.msub : 4096;
+    p->sigma = sigma;
+    p->opts = o;
+    for (int d = 0; d < 3; ++d) p->N[d] = (nmodes && d < dim) ? nmodes[d] : 1;
+    return p;
+}
+
+// Fine grid nf, kernel (w, beta), bins and method of a type 1 / 2 plan (host
+// only).  ERR_ARG when the grid or the bin count is too large or method SM
+// was asked for with padded bins that do not fit in LDS.
+int plan_geometry(mnufft_plan p, const int64_t nf[3], int w, double beta, const mnufft_opts &o)
+{
+    const int dim = p->dim;
+    int64_t cells = 1;
+    for (int d = 0; d < dim; ++d) {
+        if (nf[d] > (int64_t)1 << 30) return MNUFFT_ERR_ARG;
+        cells *= nf[d];
+    }
+    if (cells > ((int64_t)1 << 40) / p->ntransf) return MNUFFT_ERR_ARG;
+    mn::Geom &g = p->g;
+    g.dim = dim;
+    g.w = w;
+    g.beta = beta;
+    g.pad = (w + 1) / 2;
+    const int defm[2][3] = {{32, 32, 1}, {16, 8, 8}};
+    bool user_bins = false;
+    for (int d = 0; d < 3; ++d) {
+        g.n[d] = d < dim ? (int)nf[d] : 1;
+        int m = d < dim ? (o.binsize[d] > 0 ? o.binsize[d] : defm[dim - 2][d]) : 1;
+        user_bins = user_bins || (d < dim && o.binsize[d] > 0);
+        g.m[d] = std::min(m, g.n[d]);
+        g.S[d] = (double)g.n[d] / (2.0 * kPi);
+    }
+    auto lds_of = [&]() {
+        return std::max(mn::sm_lds_bytes(g, p->prec, false, p->msub),
+                        mn::sm_lds_bytes(g, p->prec, true, p->msub));
+    };
+    // Default bins whose padded tiles do not fit in LDS (wide kernels, double
+    // precision) are halved along their longest side until they do.
+    while (!user_bins && lds_of() > kLdsMax) {
+        int dl = 0;
+        for (int d = 1; d < dim; ++d)
+            if (g.m[d] > g.m[dl]) dl = d;
+        if (g.m[dl] <= 1) break;
+        g.m[dl] = (g.m[dl] + 1) / 2;
+    }
+    int64_t nbins = 1;
+    for (int d = 0; d < 3; ++d) {
+        g.B[d] = (g.n[d] + g.m[d] - 1) / g.m[d];
+        nbins *= g.B[d];
+    }
+    if (nbins > ((int64_t)1 << 30)) return MNUFFT_ERR_ARG;
+    g.nbins = (int)nbins;
+    p->grid_elems = (size_t)cells;
+    const size_t lds = lds_of();
+    p->ts2 = mn::sm_tile_stride(g);
+    if (o.method == MNUFFT_METHOD_AUTO)
+        p->method = lds <= kLdsMax ? MNUFFT_METHOD_SM : MNUFFT_METHOD_GMSORT;
+    else
+        p->method = o.method;
+    if (p->method == MNUFFT_METHOD_SM && lds > kLdsMax) return MNUFFT_ERR_ARG;
+    return MNUFFT_OK;
+}
+
+// Device state of a plan after plan_geometry: fine grids, bin tables, cover
+// tables and, with_fft, the correction factors and the rocFFT plan (a type 3
+// plan's spreading plan has neither).
+int plan_device(mnufft_plan p, bool with_fft)
+{
+    const int dim = p->dim;
+    const mn::Geom &g = p->g;
+    std::call_once(g_fft_once, [] { g_fft_setup = rocfft_setup(); });
+    int rc = MNUFFT_OK;
+    if (g_fft_setup != rocfft_status_success) rc = MNUFFT_ERR_FFT;
+    if (!rc) rc = use_device(p);
+    if (!rc) rc = dalloc(p, &p->grid, p->grid_elems * 2 * p->rsz * p->ntransf);
+    for (int d = 0; d < 3 && !rc && with_fft; ++d) {
+        std::vector<double> fac;
+        if (d < dim) correction(p->N[d], g.n[d], g.w, g.beta, fac);
+        else fac.assign(1, 1.0);
+        rc = dalloc(p, &p->pfac[d], fac.size() * p->rsz);
+        if (rc) break;
+        if (p->prec == MNUFFT_F32) {
+            std::vector<float> ff(fac.begin(), fac.end());
+            if (hipMemcpy(p->pfac[d], ff.data(), ff.size() * 4, hipMemcpyHostToDevice))
+                rc = MNUFFT_ERR_HIP;
+        } else if (hipMemcpy(p->pfac[d], fac.data(), fac.size() * 8, hipMemcpyHostToDevice)) {
+            rc = MNUFFT_ERR_HIP;
+        }
+    }
+    if (!rc) rc = dalloc(p, (void **)&p->binstart, ((size_t)g.nbins + 1) * 4);
+    if (!rc) rc = dalloc(p, (void **)&p->subcount, ((size_t)g.nbins + 1) * 4);
+    if (!rc) rc = dalloc(p, (void **)&p->nsub, 16);
+    if (!rc) rc = dalloc(p, (void **)&p->flag, 16);
+    if (!rc && p->method == MNUFFT_METHOD_SM) {
+        rc = dalloc(p, (void **)&p->nmerge, 16);
+        if (!rc) rc = dalloc(p, &p->cmax, 1024 * 8);  // partial maxima, see k_maxabs
+        for (int d = 0; d < dim && !rc; ++d) rc = build_cover(p, d);
+    }
+    if (with_fft) {
+        if (!rc && rocfft_execution_info_create(&p->fftinfo) != rocfft_status_success)
+            rc = MNUFFT_ERR_FFT;
+        if (!rc) rc = make_fft(p, p->iflag < 0 ? 0 : 1);
+    }
+    return rc;
+}
+
+// ---- type 3 ---------------------------------------------------------------
+// Nodes of the kernel-transform rule used for the type 3 deconvolution
+// factors: tanh-sinh with step 1/16 on t in [-3, 3] (97 nodes), within a few
+// 1e-13 of the finer rule the correction factors use over the frequencies
+// that occur (|xi| <= w pi / (2 sigma)).
+constexpr double kT3QuadStep = 1.0 / 16.0;
+constexpr int kT3QuadK = 48;
+
+int make_type3(int dim, int iflag, int64_t ntransf, double eps, int prec, const mnufft_opts &o,
+               double sigma, mnufft_plan *out)
+{
+    int w = 0;
+    double beta = 0;
+    int64_t n1 = 0;
+    const int warn = mnufft_choose_params_sigma(eps, prec, 1, sigma, &w, &beta, &n1);
+    if (warn < 0) return warn;
+    mnufft_plan p = new_plan(3, dim, nullptr, iflag, ntransf, eps, prec, o, sigma);
+    if (!p) return MNUFFT_ERR_ALLOC;
+    p->g.dim = dim;
+    p->g.w = w;
+    p->g.beta = beta;
+    p->method = o.method == MNUFFT_METHOD_AUTO ? MNUFFT_METHOD_SM : o.method;
+    std::vector<double> zz, ww;
+    mn::host::es_quadrature(beta, kT3QuadStep, kT3QuadK, zz, ww);
+    p->t3nq = (int)zz.size();
+    zz.insert(zz.end(), ww.begin(), ww.end());
+    int rc = use_device(p);
+    if (!rc) rc = dalloc(p, (void **)&p->t3quad, zz.size() * 8);
+    if (!rc && hipMemcpy(p->t3quad, zz.data(), zz.size() * 8, hipMemcpyHostToDevice))
+        rc = MNUFFT_ERR_HIP;
+    if (!rc) rc = dalloc(p, (void **)&p->t3part, 2 * 1024 * 3 * 3 * 8);
+    if (rc) {
+        mnufft_destroy(p);
+        return rc;
+    }
+    *out = p;
+    return warn;
+}
+
+// Smallest even 2^a 3^b 5^c >= n.
+int64_t smooth_even(int64_t n)
+{
+    n = std::max<int64_t>(n, 2);
+    n += n & 1;
+    for (;; n += 2) {
+        int64_t r = n;
+        for (int64_t f : {2, 3, 5})
+            while (r % f == 0) r /= f;
+        if (r == 1) return n;
+    }
+}
+
+// (min, max) per dimension of n values from the partials of launch_t3_bounds;
+// false if a value is non-finite.  n = 0 gives (0, 0).
+bool reduce_bounds(const double *part, int nb, int dim, int n, double lo[3], double hi[3])
+{
+    bool ok = true;
+    for (int d = 0; d < dim; ++d) {
+        lo[d] = INFINITY;
+        hi[d] = -INFINITY;
+        for (int b = 0; b < nb; ++b) {
+            const double *q = part + 3 * ((size_t)b * dim + d);
+            lo[d] = std::min(lo[d], q[0]);
+            hi[d] = std::max(hi[d], q[1]);
+            if (q[2] != 0.0) ok = false;
+        }
+        if (n == 0) lo[d] = hi[d] = 0.0;
+    }
+    return ok;
+}
+
+void free_t3_points(mnufft_plan p)
+{
+    const size_t cz = 2 * p->rsz;
+    if (p->t3Mcap >= 0) {
+        const size_t M = (size_t)std::max<int64_t>(p->t3Mcap, 1);
+        dfree(p, &p->t3pre, M * cz);
+        dfree(p, &p->t3cp, M * cz * p->ntransf);
+    }
+    if (p->t3Kcap >= 0) {
+        const size_t K = (size_t)std::max<int64_t>(p->t3Kcap, 1);
+        dfree(p, &p->t3post, K * cz);
+    }
+    p->t3Mcap = p->t3Kcap = -1;
+}
+
+void destroy_t3_plans(mnufft_plan p)
+{
+    if (p->t3spr) mnufft_destroy(p->t3spr);
+    if (p->t3inner) mnufft_destroy(p->t3inner);
+    p->t3spr = p->t3inner = nullptr;
+}
+
+// Spreading plan (grid nf, no FFT) and inner type 2 plan (modes nf) of a
+// type 3 plan, made anew when nf changes.
+int make_t3_plans(mnufft_plan p, const int64_t nf[3])
+{
+    bool same = p->t3spr && p->t3inner;
+    for (int d = 0; d < p->dim && same; ++d) same = p->nf3[d] == nf[d];
+    if (same) return MNUFFT_OK;
+    destroy_t3_plans(p);
+    mnufft_opts o = p->opts;
+    o.validate_pts = 0;  // the rescaled coordinates lie in [-pi, pi) by construction
+    mnufft_plan s = new_plan(1, p->dim, nf, p->iflag, p->ntransf, p->eps, p->prec, o, p->sigma);
+    if (!s) return MNUFFT_ERR_ALLOC;
+    int rc = plan_geometry(s, nf, p->g.w, p->g.beta, o);
+    if (rc) {
+        delete s;
+        return rc;
+    }
+    rc = plan_device(s, false);
+    if (rc) {
+        mnufft_destroy(s);
+        return rc;
+    }
+    s->tm.on = p->tm.on;
+    p->t3spr = s;
+    rc = mnufft_makeplan(2, p->dim, nf, p->iflag, p->ntransf, p->eps, p->prec, &o, &p->t3inner);
+    if (rc < 0) {
+        p->t3inner = nullptr;
+        destroy_t3_plans(p);
+        return rc;
+    }
+    p->t3inner->tm.on = p->tm.on;
+    for (int d = 0; d < 3; ++d) p->nf3[d] = d < p->dim ? nf[d] : 1;
+    return MNUFFT_OK;
+}
+
+// Type 3 with the plan's sign: c (ntransf x M) -> f (ntransf x K).
+int exec_type3(mnufft_plan p, const void *c, void *f)
+{
+    {
+        StageTimer tm(p->tm, MNUFFT_STAGE_DECONV, p->stream);
+        MN_HIP(mn::launch_cmul(p->prec, p->M, (int)p->ntransf, c, p->t3pre, p->t3cp, p->stream));
+    }
+    int rc = spread_all(p->t3spr, p->t3cp);
+    if (rc) return rc;
+    if ((rc = exec_type2(p->t3inner, p->iflag, p->t3spr->grid, f))) return rc;
+    StageTimer tm(p->tm, MNUFFT_STAGE_DECONV, p->stream);
+    MN_HIP(mn::launch_cmul(p->prec, p->K, (int)p->ntransf, f, p->t3post, f, p->stream));
     return MNUFFT_OK;
 }
 
@@ -458,9 +744,9 @@ int mnufft_makeplan(int type, int dim, const int64_t *nmodes, int iflag, int64_t
     if (!out) return MNUFFT_ERR_ARG;
     *out = nullptr;
     // ---- validate everything before touching the device ----
-    if ((type != 1 && type != 2) || (dim != 2 && dim != 3) || !nmodes ||
-        (iflag != 1 && iflag != -1) || ntransf < 1 || !(eps > 0.0 && eps < 1.0) ||
-        (prec != MNUFFT_F32 && prec != MNUFFT_F64))
+    if ((type != 1 && type != 2 && type != 3) || (dim != 2 && dim != 3) ||
+        (!nmodes && type != 3) || (iflag != 1 && iflag != -1) || ntransf < 1 ||
+        !(eps > 0.0 && eps < 1.0) || (prec != MNUFFT_F32 && prec != MNUFFT_F64))
         return MNUFFT_ERR_ARG;
     mnufft_opts o;
     mnufft_default_opts(&o);
@@ -473,7 +759,9 @@ int mnufft_makeplan(int type, int dim, const int64_t *nmodes, int iflag, int64_t
     const double sigma = o.upsampfac == 0.0 ? 2.0 : o.upsampfac;
     if (!(sigma >= 1.25 && sigma <= 2.0)) return MNUFFT_ERR_ARG;
     for (int d = 0; d < dim; ++d)
-        if (nmodes[d] < 1 || nmodes[d] > (1 << 24) || o.binsize[d] < 0) return MNUFFT_ERR_ARG;
+        if ((type != 3 && (nmodes[d] < 1 || nmodes[d] > (1 << 24))) || o.binsize[d] < 0)
+            return MNUFFT_ERR_ARG;
+    if (type == 3) return make_type3(dim, iflag, ntransf, eps, prec, o, sigma, out);
 
     int w = 0;
     double beta = 0;
@@ -484,109 +772,14 @@ int mnufft_makeplan(int type, int dim, const int64_t *nmodes, int iflag, int64_t
         if (rc < 0) return rc;
         if (rc > 0) warn = rc;
     }
-    int64_t cells = 1;
-    for (int d = 0; d < dim; ++d) {
-        if (nf[d] > (int64_t)1 << 30) return MNUFFT_ERR_ARG;
-        cells *= nf[d];
-    }
-    if (cells > ((int64_t)1 << 40) / ntransf) return MNUFFT_ERR_ARG;
-
-    mnufft_plan p = new (std::nothrow) mnufft_plan_s();
+    mnufft_plan p = new_plan(type, dim, nmodes, iflag, ntransf, eps, prec, o, sigma);
     if (!p) return MNUFFT_ERR_ALLOC;
-    p->type = type;
-    p->dim = dim;
-    p->prec = prec;
-    p->iflag = iflag;
-    p->ntransf = ntransf;
-    p->eps = eps;
-    p->rsz = prec == MNUFFT_F32 ? 4 : 8;
-    p->device = o.device;
-    p->validate = o.validate_pts;
-    p->stream = (hipStream_t)o.stream;
-    p->msub = o.msub > 0 ? o.msub : 4096;
-    p->sigma = sigma;
-    mn::Geom &g = p->g;
-    g.dim = dim;
-    g.w = w;
-    g.beta = beta;
-    g.pad = (w + 1) / 2;
-    const int defm[2][3] = {{32, 32, 1}, {16, 8, 8}};
-    bool user_bins = false;
-    for (int d = 0; d < 3; ++d) {
-        p->N[d] = d < dim ? nmodes[d] : 1;
-        g.n[d] = d < dim ? (int)nf[d] : 1;
-        int m = d < dim ? (o.binsize[d] > 0 ? o.binsize[d] : defm[dim - 2][d]) : 1;
-        user_bins = user_bins || (d < dim && o.binsize[d] > 0);
-        g.m[d] = std::min(m, g.n[d]);
-        g.S[d] = (double)g.n[d] / (2.0 * kPi);
-    }
-    auto lds_of = [&]() {
-        return std::max(mn::sm_lds_bytes(g, prec, false, p->msub),
-                        mn::sm_lds_bytes(g, prec, true, p->msub));
-    };
-    // Default bins whose padded tiles do not fit in LDS (wide kernels, double
-    // precision) are halved along their longest side until they do.
-    while (!user_bins && lds_of() > kLdsMax) {
-        int dl = 0;
-        for (int d = 1; d < dim; ++d)
-            if (g.m[d] > g.m[dl]) dl = d;
-        if (g.m[dl] <= 1) break;
-        g.m[dl] = (g.m[dl] + 1) / 2;
-    }
-    int64_t nbins = 1;
-    for (int d = 0; d < 3; ++d) {
-        g.B[d] = (g.n[d] + g.m[d] - 1) / g.m[d];
-        nbins *= g.B[d];
-    }
-    if (nbins > ((int64_t)1 << 30)) {
+    int rc = plan_geometry(p, nf, w, beta, o);
+    if (rc) {
         delete p;
-        return MNUFFT_ERR_ARG;
+        return rc;
     }
-    g.nbins = (int)nbins;
-    p->grid_elems = (size_t)cells;
-    const size_t lds = lds_of();
-    p->ts2 = mn::sm_tile_stride(g);
-    if (o.method == MNUFFT_METHOD_AUTO)
-        p->method = lds <= kLdsMax ? MNUFFT_METHOD_SM : MNUFFT_METHOD_GMSORT;
-    else
-        p->method = o.method;
-    if (p->method == MNUFFT_METHOD_SM && lds > kLdsMax) {
-        delete p;
-        return MNUFFT_ERR_ARG;
-    }
-
-    // ---- device state ----
-    std::call_once(g_fft_once, [] { g_fft_setup = rocfft_setup(); });
-    int rc = MNUFFT_OK;
-    if (g_fft_setup != rocfft_status_success) rc = MNUFFT_ERR_FFT;
-    if (!rc) rc = use_device(p);
-    if (!rc) rc = dalloc(p, &p->grid, (size_t)cells * 2 * p->rsz * ntransf);
-    for (int d = 0; d < 3 && !rc; ++d) {
-        std::vector<double> fac;
-        if (d < dim) correction(p->N[d], nf[d], w, beta, fac);
-        else fac.assign(1, 1.0);
-        rc = dalloc(p, &p->pfac[d], fac.size() * p->rsz);
-        if (rc) break;
-        if (prec == MNUFFT_F32) {
-            std::vector<float> ff(fac.begin(), fac.end());
-            if (hipMemcpy(p->pfac[d], ff.data(), ff.size() * 4, hipMemcpyHostToDevice))
-                rc = MNUFFT_ERR_HIP;
-        } else if (hipMemcpy(p->pfac[d], fac.data(), fac.size() * 8, hipMemcpyHostToDevice)) {
-            rc = MNUFFT_ERR_HIP;
-        }
-    }
-    if (!rc) rc = dalloc(p, (void **)&p->binstart, ((size_t)nbins + 1) * 4);
-    if (!rc) rc = dalloc(p, (void **)&p->subcount, ((size_t)nbins + 1) * 4);
-    if (!rc) rc = dalloc(p, (void **)&p->nsub, 16);
-    if (!rc) rc = dalloc(p, (void **)&p->flag, 16);
-    if (!rc && p->method == MNUFFT_METHOD_SM) {
-        rc = dalloc(p, (void **)&p->nmerge, 16);
-        if (!rc) rc = dalloc(p, &p->cmax, 1024 * 8);  // partial maxima, see k_maxabs
-        for (int d = 0; d < dim && !rc; ++d) rc = build_cover(p, d);
-    }
-    if (!rc && rocfft_execution_info_create(&p->fftinfo) != rocfft_status_success)
-        rc = MNUFFT_ERR_FFT;
-    if (!rc) rc = make_fft(p, iflag < 0 ? 0 : 1);
+    rc = plan_device(p, true);
     if (rc) {
         mnufft_destroy(p);
         return rc;
@@ -597,7 +790,7 @@ int mnufft_makeplan(int type, int dim, const int64_t *nmodes, int iflag, int64_t
 
 int mnufft_setpts(mnufft_plan p, int64_t M, const void *x, const void *y, const void *z)
 {
-    if (!p || M < 0 || M > 2147483647LL) return MNUFFT_ERR_ARG;
+    if (!p || p->type == 3 || M < 0 || M > 2147483647LL) return MNUFFT_ERR_ARG;
     if (M > 0 && (!x || !y)) return MNUFFT_ERR_ARG;
     if (M > 0 && ((p->dim == 3) != (z != nullptr))) return MNUFFT_ERR_ARG;
     if (p->g.nbins + (M + p->msub - 1) / p->msub > 2147483647LL) return MNUFFT_ERR_ARG;
@@ -623,10 +816,100 @@ int mnufft_setpts(mnufft_plan p, int64_t M, const void *x, const void *y, const 
     return MNUFFT_OK;
 }
 
+int mnufft_setpts3(mnufft_plan p, int64_t M, const void *x, const void *y, const void *z,
+                   int64_t K, const void *s, const void *t, const void *u)
+{
+    if (!p || p->type != 3 || M < 0 || M > 2147483647LL || K < 0 || K > 2147483647LL)
+        return MNUFFT_ERR_ARG;
+    const int dim = p->dim;
+    const void *xs[3] = {x, y, dim == 3 ? z : nullptr};
+    const void *ss[3] = {s, t, dim == 3 ? u : nullptr};
+    if ((dim == 2) && (z || u)) return MNUFFT_ERR_ARG;
+    for (int d = 0; d < dim; ++d)
+        if ((M > 0 && !xs[d]) || (K > 0 && !ss[d])) return MNUFFT_ERR_ARG;
+    int rc = use_device(p);
+    if (rc) return rc;
+    p->M = p->K = -1;  // invalid until the whole setup has been enqueued
+    hipStream_t st = p->stream;
+    StageTimer tmr(p->tm, MNUFFT_STAGE_SETPTS, st);
+    // centres and half-widths of the points and the frequencies
+    const int nbx = mn::t3_bounds_blocks((int)M), nbs = mn::t3_bounds_blocks((int)K);
+    double *partx = p->t3part, *parts = p->t3part + 1024 * 3 * 3;
+    MN_HIP(mn::launch_t3_bounds(p->prec, (int)M, dim, xs, partx, st));
+    MN_HIP(mn::launch_t3_bounds(p->prec, (int)K, dim, ss, parts, st));
+    std::vector<double> hp(2 * 1024 * 3 * 3);
+    MN_HIP(hipMemcpyAsync(hp.data(), p->t3part, hp.size() * 8, hipMemcpyDeviceToHost, st));
+    MN_HIP(hipStreamSynchronize(st));
+    double xl[3], xh[3], sl[3], sh[3];
+    const bool okx = reduce_bounds(hp.data(), nbx, dim, (int)M, xl, xh);
+    const bool oks = reduce_bounds(hp.data() + 1024 * 3 * 3, nbs, dim, (int)K, sl, sh);
+    if (!okx || !oks) return MNUFFT_ERR_PTS;
+    // rescaling: gamma = nf / (2 sigma S) puts the rescaled frequencies within
+    // pi / sigma, and nf >= 2 sigma S X / pi + w + 1 keeps every point's taps
+    // inside the grid without wrapping
+    const int w = p->g.w;
+    int64_t nf[3] = {1, 1, 1};
+    for (int d = 0; d < dim; ++d) {
+        p->C[d] = 0.5 * (xh[d] + xl[d]);
+        p->D[d] = 0.5 * (sh[d] + sl[d]);
+        const double X = 0.5 * (xh[d] - xl[d]);
+        double S = 0.5 * (sh[d] - sl[d]);
+        if (S == 0.0) S = X > 0.0 ? 1.0 / X : 1.0;
+        const double need = std::ceil(2.0 * p->sigma * S * X / kPi) + w + 1;
+        if (!(need <= (double)(1 << 24))) return MNUFFT_ERR_ARG;  // space-bandwidth too large
+        nf[d] = smooth_even(std::max<int64_t>((int64_t)need, 2 * (int64_t)w));
+        p->gam[d] = (double)nf[d] / (2.0 * p->sigma * S);
+        p->hstep[d] = 2.0 * kPi / (double)nf[d];
+    }
+    if ((rc = make_t3_plans(p, nf))) return rc;
+    // per-point and per-frequency buffers
+    const size_t cz = 2 * p->rsz;
+    if (M > p->t3Mcap || K > p->t3Kcap) {
+        free_t3_points(p);
+        const size_t Ma = (size_t)std::max<int64_t>(M, 1), Ka = (size_t)std::max<int64_t>(K, 1);
+        rc = dalloc(p, &p->t3pre, Ma * cz);
+        if (!rc) rc = dalloc(p, &p->t3cp, Ma * cz * p->ntransf);
+        if (!rc) rc = dalloc(p, &p->t3post, Ka * cz);
+        p->t3Mcap = M;
+        p->t3Kcap = K;
+        if (rc) {
+            free_t3_points(p);
+            return rc;
+        }
+    }
+    mn::T3Affine ax{}, as{};
+    mn::PtMap mx{}, ms{};
+    mx.on = ms.on = 1;
+    for (int d = 0; d < dim; ++d) {
+        ax.off[d] = mx.off[d] = p->C[d];
+        ax.scale[d] = mx.mul[d] = 1.0 / p->gam[d];  // points: (x - C) / gamma
+        ax.mul[d] = p->D[d];
+        as.off[d] = ms.off[d] = p->D[d];
+        as.scale[d] = ms.mul[d] = p->hstep[d] * p->gam[d];  // frequencies: h gamma (s - D)
+        as.mul[d] = p->C[d];
+    }
+    MN_HIP(mn::launch_t3_prephase(p->prec, (int)M, dim, xs, ax, p->iflag, p->t3pre, st));
+    MN_HIP(mn::launch_t3_postfac(p->prec, (int)K, dim, ss, as, p->iflag, w, p->t3quad, p->t3nq,
+                                 p->t3post, st));
+    // both sets are binned straight from the caller's coordinates through the maps
+    p->t3spr->ptmap = mx;
+    p->t3inner->ptmap = ms;
+    if ((rc = mnufft_setpts(p->t3spr, M, xs[0], xs[1], xs[2]))) return rc;
+    if ((rc = mnufft_setpts(p->t3inner, K, ss[0], ss[1], ss[2]))) return rc;
+    p->M = M;
+    p->K = K;
+    return MNUFFT_OK;
+}
+
 int mnufft_execute(mnufft_plan p, void *c, void *f)
 {
     int rc = check_ready(p);
     if (rc) return rc;
+    if (p->type == 3) {
+        if ((p->K > 0 && !f) || (p->M > 0 && !c)) return MNUFFT_ERR_ARG;
+        if ((rc = use_device(p))) return rc;
+        return exec_type3(p, c, f);
+    }
     if (!f || (p->M > 0 && !c)) return MNUFFT_ERR_ARG;
     if ((rc = use_device(p))) return rc;
     return p->type == 1 ? exec_type1(p, p->iflag, c, f) : exec_type2(p, p->iflag, f, c);
@@ -636,6 +919,7 @@ int mnufft_execute_adjoint(mnufft_plan p, void *c, void *f)
 {
     int rc = check_ready(p);
     if (rc) return rc;
+    if (p->type == 3) return MNUFFT_ERR_UNSUPPORTED;
     if (!f || (p->M > 0 && !c)) return MNUFFT_ERR_ARG;
     if ((rc = use_device(p))) return rc;
     return p->type == 1 ? exec_type2(p, -p->iflag, f, c) : exec_type1(p, -p->iflag, c, f);
@@ -645,6 +929,7 @@ int mnufft_spread(mnufft_plan p, const void *c, void *grid)
 {
     int rc = check_ready(p);
     if (rc) return rc;
+    if (p->type == 3) return MNUFFT_ERR_UNSUPPORTED;
     if (!grid || (p->M > 0 && !c)) return MNUFFT_ERR_ARG;
     if ((rc = use_device(p))) return rc;
     if (p->method != MNUFFT_METHOD_SM) MN_HIP(mn::launch_zero(grid, grid_bytes(p), p->stream));
@@ -657,6 +942,7 @@ int mnufft_interp(mnufft_plan p, const void *grid, void *c)
 {
     int rc = check_ready(p);
     if (rc) return rc;
+    if (p->type == 3) return MNUFFT_ERR_UNSUPPORTED;
     if (!grid || (p->M > 0 && !c)) return MNUFFT_ERR_ARG;
     if ((rc = use_device(p))) return rc;
     MN_HIP(mn::launch_interp(p->g, p->prec, p->method, points_of(p), grid, c, p->stream));
@@ -668,6 +954,7 @@ int mnufft_interp_grad(mnufft_plan p, const void *modes, const void *wts, void *
 {
     int rc = check_ready(p);
     if (rc) return rc;
+    if (p->type == 3) return MNUFFT_ERR_UNSUPPORTED;
     if (!modes || (p->M > 0 && (!wts || !gx || !gy || (p->dim == 3 && !gz))))
         return MNUFFT_ERR_ARG;
     if ((rc = use_device(p))) return rc;
@@ -686,6 +973,7 @@ int mnufft_get_sort(mnufft_plan p, int32_t *perm, int32_t *binstart)
 {
     int rc = check_ready(p);
     if (rc) return rc;
+    if (p->type == 3) return MNUFFT_ERR_UNSUPPORTED;
     if ((rc = use_device(p))) return rc;
     if (perm && p->M > 0)
         MN_HIP(hipMemcpyAsync(perm, p->perm, (size_t)p->M * 4, hipMemcpyDeviceToDevice, p->stream));
@@ -699,6 +987,7 @@ int mnufft_get_subproblems(mnufft_plan p, int32_t *sub, int32_t *nsub)
 {
     int rc = check_ready(p);
     if (rc) return rc;
+    if (p->type == 3) return MNUFFT_ERR_UNSUPPORTED;
     if ((rc = use_device(p))) return rc;
     if (sub && p->nsub_max > 0)
         MN_HIP(hipMemcpyAsync(sub, p->sub, (size_t)p->nsub_max * 16, hipMemcpyDeviceToDevice,
@@ -712,6 +1001,8 @@ int mnufft_set_timing(mnufft_plan p, int enable)
 {
     if (!p) return MNUFFT_ERR_ARG;
     p->tm.on = enable != 0;
+    if (p->t3spr) p->t3spr->tm.on = p->tm.on;
+    if (p->t3inner) p->t3inner->tm.on = p->tm.on;
     return MNUFFT_OK;
 }
 
@@ -720,7 +1011,20 @@ int mnufft_get_timing(mnufft_plan p, double *ms, int64_t *count, int reset)
     if (!p || !ms) return MNUFFT_ERR_ARG;
     int rc = use_device(p);
     if (rc) return rc;
-    return p->tm.read(p->stream, ms, count, reset);
+    if ((rc = p->tm.read(p->stream, ms, count, reset))) return rc;
+    // a type 3 plan adds the stages of its spreading and type 2 plans
+    for (mnufft_plan q : {p->t3spr, p->t3inner}) {
+        if (!q) continue;
+        double qm[MNUFFT_NSTAGES];
+        int64_t qc[MNUFFT_NSTAGES];
+        if ((rc = q->tm.read(q->stream, qm, qc, reset))) return rc;
+        for (int st = 0; st < MNUFFT_NSTAGES; ++st) {
+            if (st == MNUFFT_STAGE_SETPTS) continue;  // inside the type 3 plan's own interval
+            ms[st] += qm[st];
+            if (count) count[st] += qc[st];
+        }
+    }
+    return MNUFFT_OK;
 }
 
 int mnufft_get_info(mnufft_plan p, mnufft_info *info)
@@ -746,6 +1050,20 @@ int mnufft_get_info(mnufft_plan p, mnufft_info *info)
     info->nsub_max = p->M >= 0 ? p->nsub_max : 0;
     info->device_bytes = p->devbytes;
     info->upsampfac = p->sigma;
+    info->ntargets = p->type == 3 ? p->K : 0;
+    if (p->type == 3) {
+        // modes and fine grid of the inner type 2; bins of the spreading plan
+        for (mnufft_plan q : {p->t3spr, p->t3inner})
+            if (q) info->device_bytes += q->devbytes;
+        for (int d = 0; d < 3; ++d) {
+            info->nmodes[d] = p->nf3[d];
+            info->nfine[d] = p->t3inner ? p->t3inner->g.n[d] : 1;
+            info->binsize[d] = p->t3spr ? p->t3spr->g.m[d] : 0;
+        }
+        info->nbins = p->t3spr ? p->t3spr->g.nbins : 0;
+        info->nsub_max = p->t3spr && p->M >= 0 ? p->t3spr->nsub_max : 0;
+        if (p->t3spr) info->method = p->t3spr->method;
+    }
     return MNUFFT_OK;
 }
 
@@ -759,6 +1077,10 @@ int mnufft_destroy(mnufft_plan p)
         if (p->fft[k]) rocfft_plan_destroy(p->fft[k]);
     if (p->fftinfo) rocfft_execution_info_destroy(p->fftinfo);
     p->tm.destroy();
+    destroy_t3_plans(p);
+    free_t3_points(p);
+    dfree(p, (void **)&p->t3part, 0);
+    dfree(p, (void **)&p->t3quad, 0);
     free_points(p);
     dfree(p, &p->fftwork, p->fftwork_bytes);
     dfree(p, &p->grid, p->grid_elems * 2 * p->rsz * p->ntransf);

@@ -22,7 +22,7 @@ METHODS = {"auto": METHOD_AUTO, "gm": METHOD_GM, "gmsort": METHOD_GMSORT, "sm": 
 
 # Every symbol the public header declares.
 EXPORTS = (
-    "mnufft_default_opts", "mnufft_makeplan", "mnufft_setpts", "mnufft_execute",
+    "mnufft_default_opts", "mnufft_makeplan", "mnufft_setpts", "mnufft_setpts3", "mnufft_execute",
     "mnufft_execute_adjoint", "mnufft_interp_grad", "mnufft_spread", "mnufft_interp",
     "mnufft_get_sort",
     "mnufft_get_subproblems", "mnufft_get_info", "mnufft_destroy", "mnufft_strerror",
@@ -64,6 +64,7 @@ class Info(ctypes.Structure):
         ("method", ctypes.c_int), ("binsize", ctypes.c_int * 3), ("msub", ctypes.c_int),
         ("nbins", ctypes.c_int64), ("nsub_max", ctypes.c_int64),
         ("device_bytes", ctypes.c_int64), ("upsampfac", ctypes.c_double),
+        ("ntargets", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -96,6 +97,7 @@ def load():
     L.mnufft_makeplan.argtypes = [ci, ci, ctypes.POINTER(i64), ci, i64, ctypes.c_double, ci,
                                   ctypes.POINTER(Opts), ctypes.POINTER(vp)]
     L.mnufft_setpts.argtypes = [vp, i64, vp, vp, vp]
+    L.mnufft_setpts3.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, vp]
     L.mnufft_execute.argtypes = [vp, vp, vp]
     L.mnufft_execute_adjoint.argtypes = [vp, vp, vp]
     L.mnufft_interp_grad.argtypes = [vp, vp, vp, vp, vp, vp]

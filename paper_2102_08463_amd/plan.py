@@ -30,14 +30,16 @@ def _need(t, dtype, device, what):
 
 
 class Plan:
-    """A 2D or 3D type 1 or type 2 NUFFT plan on one GPU.
+    """A 2D or 3D type 1, 2 or 3 NUFFT plan on one GPU.
 
-    nufft_type   1 (nonuniform -> modes) or 2 (modes -> nonuniform)
+    nufft_type   1 (nonuniform -> modes), 2 (modes -> nonuniform) or
+                 3 (nonuniform points -> nonuniform frequencies)
     n_modes      (N1, N2) or (N1, N2, N3); arrays of modes have shape
-                 (..., N3, N2, N1), i.e. k1 fastest, modes ascending from -N/2
+                 (..., N3, N2, N1), i.e. k1 fastest, modes ascending from -N/2.
+                 For type 3 the dimension (2 or 3) instead
     n_trans      number of vectors sharing one set of points
     eps          requested relative l2 tolerance
-    isign        sign of the exponent; default -1 for type 1, +1 for type 2
+    isign        sign of the exponent; default -1 for types 1 and 3, +1 for type 2
     dtype        torch.complex64 (fp32) or torch.complex128 (fp64)
     method       "auto", "gm", "gmsort" or "sm"
     binsize      bin extents m_i (None = library default), msub: points per subproblem
@@ -52,11 +54,15 @@ class Plan:
         if dtype not in _PREC:
             raise TypeError("dtype must be torch.complex64 or torch.complex128")
         self.type = int(nufft_type)
-        self.n_modes = tuple(int(n) for n in n_modes)
-        self.dim = len(self.n_modes)
+        if self.type == 3:
+            self.dim = int(n_modes) if isinstance(n_modes, int) else len(n_modes)
+            self.n_modes = None
+        else:
+            self.n_modes = tuple(int(n) for n in n_modes)
+            self.dim = len(self.n_modes)
         self.n_trans = int(n_trans)
         self.eps = float(eps)
-        self.isign = int(isign if isign is not None else (-1 if self.type == 1 else 1))
+        self.isign = int(isign if isign is not None else (1 if self.type == 2 else -1))
         self.dtype = dtype
         self.rdtype = _REAL[dtype]
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
@@ -72,13 +78,15 @@ class Plan:
         o.device = self.device.index if self.device.index is not None else -1
         o.stream = torch.cuda.current_stream(self.device).cuda_stream
         self._stream = torch.cuda.current_stream(self.device)
-        nm = (ctypes.c_int64 * 3)(*(list(self.n_modes) + [1] * (3 - self.dim)))
+        nm = None if self.type == 3 else \
+            (ctypes.c_int64 * 3)(*(list(self.n_modes) + [1] * (3 - self.dim)))
         rc = self._lib.mnufft_makeplan(self.type, self.dim, nm, self.isign, self.n_trans,
                                        self.eps, _PREC[dtype], ctypes.byref(o),
                                        ctypes.byref(self._h))
         L.check(rc, "mnufft_makeplan")
         self.status = rc
         self.M = None
+        self.K = None
         self._pts = None
 
     # -- lifetime ------------------------------------------------------------
@@ -128,7 +136,10 @@ class Plan:
         return {name: (ms[i], cnt[i]) for i, name in enumerate(L.STAGES)}
 
     # -- points --------------------------------------------------------------
-    def setpts(self, x, y, z=None):
+    def setpts(self, x, y, z=None, s=None, t=None, u=None):
+        """Set the points (x, y[, z]); for type 3 also the frequencies (s, t[, u])."""
+        if self.type == 3:
+            return self._setpts3((x, y, z), (s, t, u))
         M = x.shape[0]
         for t, nm in ((x, "x"), (y, "y")) + (((z, "z"),) if self.dim == 3 else ()):
             _need(t, self.rdtype, self.device, nm)
@@ -140,6 +151,22 @@ class Plan:
                                      _ptr(z) if self.dim == 3 else None)
         L.check(rc, "mnufft_setpts")
         self.M = M
+        return self
+
+    def _setpts3(self, pts, freqs):
+        pts, freqs = pts[: self.dim], freqs[: self.dim]
+        if any(a is None for a in pts + freqs):
+            raise ValueError(f"type 3 needs {self.dim} point and {self.dim} frequency arrays")
+        M, K = pts[0].shape[0], freqs[0].shape[0]
+        for arrs, n, nm in ((pts, M, "points"), (freqs, K, "frequencies")):
+            for a in arrs:
+                _need(a, self.rdtype, self.device, nm)
+                if a.ndim != 1 or a.shape[0] != n:
+                    raise ValueError(f"{nm} must be 1-D arrays of equal length")
+        pp = [_ptr(a) for a in pts] + [None] * (3 - self.dim)
+        ff = [_ptr(a) for a in freqs] + [None] * (3 - self.dim)
+        L.check(self._lib.mnufft_setpts3(self._h, M, *pp, K, *ff), "mnufft_setpts3")
+        self.M, self.K = M, K
         return self
 
     # -- execution -------------------------------------------------------------
@@ -167,7 +194,18 @@ class Plan:
         return c
 
     def execute(self, data):
-        """Type 1: data = strengths c -> modes f.  Type 2: data = modes f -> values c."""
+        """Type 1: data = strengths c -> modes f.  Type 2: data = modes f -> values c.
+        Type 3: data = strengths c (M,) or (n_trans, M) -> f (K,) or (n_trans, K)."""
+        if self.type == 3:
+            if self.M is None:
+                raise RuntimeError("setpts must be called before execute")
+            _need(data, self.dtype, self.device, "c")
+            if data.numel() != self.n_trans * self.M:
+                raise ValueError(f"c must hold {self.n_trans} x {self.M} values")
+            f = torch.empty((self.n_trans, self.K) if self.n_trans > 1 else (self.K,),
+                            dtype=self.dtype, device=self.device)
+            L.check(self._lib.mnufft_execute(self._h, _ptr(data), _ptr(f)), "mnufft_execute")
+            return f
         if self.type == 1:
             return self._run(self._lib.mnufft_execute, data, None, "mnufft_execute")
         return self._run(self._lib.mnufft_execute, None, data, "mnufft_execute")
@@ -247,3 +285,13 @@ def nufft_type2(points, f, eps=1e-6, isign=+1, **kw):
     with Plan(2, n_modes, T, eps, isign, dtype=f.dtype, **kw) as p:
         p.setpts(*points)
         return p.execute(f.contiguous())
+
+
+def nufft_type3(points, c, freqs, eps=1e-6, isign=-1, **kw):
+    """One-shot type 3: points = (x, y[, z]) and freqs = (s, t[, u]) real tensors,
+    c complex (M,) or (T, M); returns f complex (K,) or (T, K)."""
+    T = c.shape[0] if c.ndim == 2 else 1
+    dim = len(points)
+    with Plan(3, dim, T, eps, isign, dtype=c.dtype, **kw) as p:
+        p.setpts(*points, *([None] * (3 - dim)), *freqs)
+        return p.execute(c.contiguous())

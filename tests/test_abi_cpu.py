@@ -34,6 +34,9 @@ def test_struct_layouts():
     assert ctypes.sizeof(L.Opts) == 72
     assert L.Opts.stream.offset == 32
     assert L.Opts.upsampfac.offset == 40
+    # mnufft_info ends with upsampfac (double) and ntargets (int64)
+    assert L.Info.ntargets.offset == L.Info.upsampfac.offset + 8
+    assert ctypes.sizeof(L.Info) == L.Info.ntargets.offset + 8
 
 
 def test_default_opts_and_strerror():
@@ -55,7 +58,8 @@ def _makeplan(type_=1, dim=2, nm=(16, 16, 1), iflag=-1, ntr=1, eps=1e-6, prec=0,
 
 
 @pytest.mark.parametrize("kw", [
-    dict(type_=3), dict(type_=0), dict(dim=1), dict(dim=4), dict(iflag=0), dict(iflag=2),
+    dict(type_=4), dict(type_=0), dict(type_=3, dim=4), dict(type_=3, eps=0.0),
+    dict(type_=3, iflag=0), dict(type_=3, ntr=0), dict(dim=1), dict(dim=4), dict(iflag=0), dict(iflag=2),
     dict(ntr=0), dict(eps=0.0), dict(eps=1.0), dict(eps=-1e-3), dict(eps=float("nan")),
     dict(prec=2), dict(nm=(0, 16, 1)), dict(nm=(16, -1, 1)), dict(dim=3, nm=(8, 8, 0)),
 ])
@@ -87,6 +91,7 @@ def test_null_plan_calls():
     lib = L.load()
     nul = ctypes.c_void_p(0)
     assert lib.mnufft_setpts(nul, 10, None, None, None) == L.ERR_ARG
+    assert lib.mnufft_setpts3(nul, 10, None, None, None, 5, None, None, None) == L.ERR_ARG
     assert lib.mnufft_execute(nul, None, None) == L.ERR_ARG
     assert lib.mnufft_execute_adjoint(nul, None, None) == L.ERR_ARG
     assert lib.mnufft_spread(nul, None, None) == L.ERR_ARG

@@ -1,0 +1,180 @@
+"""GPU parity of the type 3 transform (points and frequencies both
+nonuniform; named as beyond the paper in Sec. I-B and Sec. VI).
+
+The HIP path (C ABI: mnufft_setpts3 + mnufft_execute) is compared with the
+exact sums of the oracle within 10 eps (relative l2), and, in double
+precision, element by element with the oracle's type 3 steps, which take the
+same grid size, kernel and rescaling.  Edge cases: no points, no
+frequencies, all points at one place, all frequencies equal in one
+dimension, a second setpts3 that changes the grid, several vectors, and
+non-finite input.
+"""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import direct, nufft as onufft, params as oparams
+from tests.gpu_helpers import REAL, cdtype, make_complex, note, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(arrs, prec):
+    import torch
+    cast = [np.asarray(a, dtype=REAL[prec]) for a in arrs]
+    return tuple(a.astype(np.float64) for a in cast), \
+        tuple(torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in cast)
+
+
+def _sets(M, K, dim, prec, seed, **kw):
+    x, s = workloads.type3_sets(M, K, dim, seed=seed, **kw)
+    x64, xd = _dev(x, prec)
+    s64, sd = _dev(s, prec)
+    return x64, xd, s64, sd
+
+
+def _run(dim, prec, eps, iflag, xd, sd, c, ntr=1, **kw):
+    from paper_2102_08463_amd import Plan
+    p = Plan(3, dim, ntr, eps, iflag, dtype=cdtype(prec), **kw)
+    pad = [None] * (3 - dim)
+    p.setpts(*xd, *pad, *sd)
+    f = p.execute(c)
+    return p, f.cpu().numpy()
+
+
+CASES = [
+    # (dim, M, K, prec, eps, iflag, box kwargs)
+    (2, 20_000, 3_000, "f64", 1e-12, 1, dict(xc=1.5, xw=3.0, sc=-20.0, sw=60.0)),
+    (2, 20_000, 3_000, "f64", 1e-6, -1, dict(xc=-4.0, xw=10.0, sc=5.0, sw=30.0)),
+    (2, 20_000, 3_000, "f32", 1e-5, -1, dict(xc=0.3, xw=3.0, sc=40.0, sw=64.0)),
+    (2, 30_000, 2_000, "f32", 1e-3, 1, dict(xc=2.0, xw=50.0, sc=0.0, sw=2.0)),
+    (3, 20_000, 2_000, "f64", 1e-9, -1, dict(xc=0.5, xw=2.0, sc=-3.0, sw=16.0)),
+    (3, 20_000, 2_000, "f32", 1e-4, 1, dict(xc=-1.0, xw=3.0, sc=2.0, sw=12.0)),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}d-{c[3]}-eps{c[4]:g}-s{c[5]}")
+def test_type3_within_eps_of_exact(case):
+    dim, M, K, prec, eps, iflag, box = case
+    note(f"type3 exact {case}")
+    x64, xd, s64, sd = _sets(M, K, dim, prec, seed=dim * 7 + M % 97, **box)
+    c64, c = make_complex(M, prec, seed=4)
+    p, f = _run(dim, prec, eps, iflag, xd, sd, c)
+    ex = direct.type3(x64, c64, s64, iflag=iflag)
+    err = rel_l2(f, ex)
+    assert err <= 10 * eps, err
+    inf = p.info()
+    assert inf["type"] == 3 and inf["M"] == M and inf["ntargets"] == K
+    p.destroy()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_type3_matches_oracle_steps_elementwise(dim):
+    """Double precision: same nf, w, beta and rescaling as the oracle's steps,
+    so the two agree to rounding, cell by cell of the output."""
+    eps = 1e-10
+    note(f"type3 oracle steps {dim}d")
+    M, K = (15_000, 2_500) if dim == 2 else (12_000, 1_500)
+    x64, xd, s64, sd = _sets(M, K, dim, "f64", seed=31 + dim, xc=0.7, xw=4.0, sc=-6.0, sw=20.0)
+    c64, c = make_complex(M, "f64", seed=6)
+    p, f = _run(dim, "f64", eps, 1, xd, sd, c)
+    w = oparams.kernel_width(eps)
+    nf = [t[-1] for t in onufft.type3_params(x64, s64, w)]
+    assert p.info()["nmodes"][:dim] == nf
+    ref = onufft.type3(x64, c64, s64, eps, iflag=1)
+    assert np.max(np.abs(f - ref)) <= 1e-12 * np.max(np.abs(ref))
+    p.destroy()
+
+
+def test_type3_several_vectors():
+    import torch
+    note("type3 ntransf=3")
+    M, K = 8_000, 1_000
+    x64, xd, s64, sd = _sets(M, K, 2, "f32", seed=8, xc=1.0, xw=5.0, sc=3.0, sw=25.0)
+    c64, c = make_complex((3, M), "f32", seed=9)
+    p, f = _run(2, "f32", 1e-5, -1, xd, sd, c, ntr=3)
+    assert f.shape == (3, K)
+    for t in range(3):
+        assert rel_l2(f[t], direct.type3(x64, c64[t], s64, iflag=-1)) <= 1e-4
+    p.destroy()
+    torch.cuda.synchronize()
+
+
+def test_type3_edge_cases():
+    import torch
+    from paper_2102_08463_amd import Plan, lib as L
+    note("type3 edges")
+    dt = torch.complex128
+    g = np.random.default_rng(12)
+    # all points at one place: f = exp(i s.x0) sum c
+    x = tuple(torch.full((500,), v, dtype=torch.float64, device="cuda") for v in (0.4, -1.1))
+    s64 = (g.uniform(-30, 30, 300), g.uniform(-30, 30, 300))
+    s = tuple(torch.from_numpy(a).cuda() for a in s64)
+    c64 = g.standard_normal(500) + 1j * g.standard_normal(500)
+    c = torch.from_numpy(c64).cuda()
+    p = Plan(3, 2, 1, 1e-10, 1, dtype=dt)
+    p.setpts(*x, None, *s)
+    f = p.execute(c).cpu().numpy()
+    ref = np.exp(1j * (0.4 * s64[0] - 1.1 * s64[1])) * c64.sum()
+    assert rel_l2(f, ref) <= 1e-9
+    # all frequencies equal in the second dimension
+    x64 = (g.uniform(-3, 5, 700), g.uniform(-2, 2, 700))
+    xd = tuple(torch.from_numpy(a).cuda() for a in x64)
+    s64b = (g.uniform(-20, 10, 200), np.full(200, 3.5))
+    sdb = tuple(torch.from_numpy(a).cuda() for a in s64b)
+    c64b = g.standard_normal(700) + 1j * g.standard_normal(700)
+    p.setpts(*xd, None, *sdb)
+    f = p.execute(torch.from_numpy(c64b).cuda()).cpu().numpy()
+    assert rel_l2(f, direct.type3(x64, c64b, s64b, iflag=1)) <= 1e-9
+    # a wider set on the same plan: the grid grows and the result still holds
+    x64c = (g.uniform(-40, 40, 3000), g.uniform(-10, 30, 3000))
+    s64c = (g.uniform(-15, 15, 400), g.uniform(-8, 8, 400))
+    nf_before = p.info()["nmodes"][:2]
+    p.setpts(*(torch.from_numpy(a).cuda() for a in x64c), None,
+             *(torch.from_numpy(a).cuda() for a in s64c))
+    assert p.info()["nmodes"][:2] != nf_before
+    c64c = g.standard_normal(3000) + 1j * g.standard_normal(3000)
+    f = p.execute(torch.from_numpy(c64c).cuda()).cpu().numpy()
+    assert rel_l2(f, direct.type3(x64c, c64c, s64c, iflag=1)) <= 1e-9
+    # no points: f = 0; no frequencies: empty output
+    e = torch.empty((0,), dtype=torch.float64, device="cuda")
+    p.setpts(e, e, None, *sdb)
+    f = p.execute(torch.empty((0,), dtype=dt, device="cuda")).cpu().numpy()
+    assert f.shape == (200,) and np.all(f == 0)
+    p.setpts(*xd, None, e, e)
+    f = p.execute(torch.from_numpy(c64b).cuda())
+    assert f.shape == (0,)
+    # non-finite coordinates are refused
+    bad = xd[0].clone()
+    bad[17] = float("nan")
+    with pytest.raises(L.MnufftError) as ei:
+        p.setpts(bad, xd[1], None, *sdb)
+    assert ei.value.code == L.ERR_PTS
+    # calls that a type 3 plan does not provide
+    p.setpts(*xd, None, *sdb)
+    lib = L.load()
+    assert lib.mnufft_execute_adjoint(p._h, None, None) == L.ERR_UNSUPPORTED
+    assert lib.mnufft_get_sort(p._h, None, None) == L.ERR_UNSUPPORTED
+    assert lib.mnufft_setpts(p._h, 10, None, None, None) == L.ERR_ARG
+    p.destroy()
+    torch.cuda.synchronize()
+
+
+def test_type3_full_size_sampled():
+    """The benchmark's type 3 workload (2D, M = K = 1e7, points on [-pi, pi)^2,
+    frequencies on [-512, 512)^2, eps 1e-5, fp32): sampled outputs against
+    the exact sum over all points."""
+    import torch
+    note("type3 full size sampled")
+    M = K = 10_000_000
+    x64, xd, s64, sd = _sets(M, K, 2, "f32", seed=0)
+    c64, c = make_complex(M, "f32", seed=1)
+    p, f = _run(2, "f32", 1e-5, -1, xd, sd, c)
+    idx = np.random.default_rng(3).choice(K, 48, replace=False)
+    ex = direct.type3(x64, c64, s64, iflag=-1, idx=idx)
+    assert rel_l2(f[idx], ex) <= 1e-4
+    p.destroy()
+    torch.cuda.synchronize()

@@ -22,6 +22,9 @@ Point sets (every coordinate in [-pi, pi) before casting):
                    by an independent uniformly random rotation: the shape of
                    the slicing / merging steps of the paper's application
                    (Sec. V), with no data from it
+Type 3 sets (``type3_sets``): points iid uniform on a box of centre xc and
+half-width xw per coordinate, frequencies iid uniform on a box of centre sc
+and half-width sw (off-centre boxes exercise the shifts of the reduction).
 Values: complex with iid N(0, 1) real and imaginary parts.
 
 All draws use numpy's PCG64 generator; results are float64 and the caller
@@ -119,6 +122,14 @@ def points(kind, M, dim, seed=0):
         assert dim == 3
         return ewald_slices(M, int(kind[5:]), seed=seed)
     raise ValueError(kind)
+
+
+def type3_sets(M, K, dim, seed=0, xc=0.0, xw=math.pi, sc=0.0, sw=512.0):
+    """(points, frequencies) of a type 3 problem: d arrays of M and d of K."""
+    g = rng(seed)
+    x = g.uniform(xc - xw, xc + xw, size=(dim, M))
+    s = g.uniform(sc - sw, sc + sw, size=(dim, K))
+    return tuple(x), tuple(s)
 
 
 def strengths(shape, seed=1):
