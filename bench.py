@@ -47,6 +47,15 @@ WORKLOADS = {
     "mtip-merge": (3, (81, 81, 81), 1000 * 128 * 128, "ewald128", 1e-12, "f64"),
 }
 
+# Type 3 workloads (points and frequencies both nonuniform; beyond the paper,
+# Sec. I-B / Sec. VI): dim, M points uniform on [-xw, xw)^d, K frequencies
+# uniform on [-sw, sw)^d, eps, precision.  sw = N/2 makes the spreading grid
+# about that of a type 1 with N modes per dimension.
+T3_WORKLOADS = {
+    "2d-type3": (2, 10_000_000, 10_000_000, math.pi, 512.0, 1e-5, "f32"),
+    "3d-type3": (3, 1 << 24, 1 << 24, math.pi, 64.0, 1e-5, "f32"),
+}
+
 # Kernel sources whose change invalidates committed hardware-counter figures.
 KERNEL_SOURCES = ["paper_2102_08463_amd/csrc/spread_kernels.h"]
 
@@ -298,7 +307,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="2d", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="2d", choices=sorted(WORKLOADS) + sorted(T3_WORKLOADS))
     ap.add_argument("--method", default="auto")
     ap.add_argument("--binsize", default=None, help="comma-separated bin extents")
     ap.add_argument("--msub", type=int, default=0)
@@ -361,6 +370,8 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
 
+    if args.workload in T3_WORKLOADS:
+        return bench_type3(args)
     dim, modes, M, kind, eps, prec = WORKLOADS[args.workload]
     if args.eps > 0:
         eps, prec = args.eps, ("f32" if args.eps >= 1e-6 else "f64")
@@ -472,6 +483,109 @@ def main():
         pts64 = tuple(a.astype(np.float64) for a in pts_np)
         out["cpu_baseline"] = cpu_baseline(pts64, c_np.astype(np.complex128),
                                            f_np.astype(np.complex128), modes, eps, sample)
+    plan.destroy()
+    print(json.dumps(out), flush=True)
+
+
+def bench_type3(args):
+    """One step = setpts3 + execute of a type 3 plan; value = (M + K) / step
+    time (both sets are nonuniform points).  The roofline line covers the
+    longer of the spreading kernel (on the nf grid) and the interpolation
+    kernel (on the inner type 2's fine grid)."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2102_08463_amd import Plan
+
+    dim, M, K, xw, sw, eps, prec = T3_WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    rdt = np.float32 if prec == "f32" else np.float64
+    cdt = torch.complex64 if prec == "f32" else torch.complex128
+    print(f"[bench] workload {args.workload}: dim={dim} M={M} K={K} eps={eps} {prec}",
+          file=sys.stderr, flush=True)
+    x_np, s_np = workloads.type3_sets(M, K, dim, seed=0, xw=xw, sw=sw)
+    x_np = [np.asarray(a, dtype=rdt) for a in x_np]
+    s_np = [np.asarray(a, dtype=rdt) for a in s_np]
+    c_np = workloads.strengths(M, seed=1).astype(np.complex64 if prec == "f32" else np.complex128)
+    xs = [torch.from_numpy(a).to(dev) for a in x_np]
+    ss = [torch.from_numpy(a).to(dev) for a in s_np]
+    c = torch.from_numpy(c_np).to(dev)
+    plan = Plan(3, dim, 1, eps, -1, dtype=cdt, method=args.method, msub=args.msub, device=dev,
+                upsampfac=args.upsampfac)
+    pad = [None] * (3 - dim)
+
+    def step():
+        plan.setpts(*xs, *pad, *ss)
+        plan.execute(c)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.timing(reset=True)
+    plan.set_timing(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    stages = plan.timing(reset=True)
+    plan.set_timing(False)
+    info = plan.info()
+    steps = args.steps
+    rsz = 4 if prec == "f32" else 8
+    kern_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
+    dominant = max(("spread", "interp"), key=lambda k: stages[k][0])
+    ncells = int(np.prod(info["nmodes"][:dim] if dominant == "spread" else info["nfine"][:dim]))
+    algo = algorithmic_bytes(dominant, dim, M if dominant == "spread" else K, ncells, rsz)
+    achieved = algo / (kern_ms[dominant] * 1e-3) / 1e9
+    kernel_name = {"spread": "k_spread_smp" if prec == "f32" else "k_spread_sm",
+                   "interp": "k_interp_sm"}[dominant]
+    out = {
+        "metric": "type 3 nonuniform points (M + K) per second",
+        "value": (M + K) * steps / (total_ms * 1e-3),
+        "unit": "NU points/s",
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": total_ms / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": prec, "data": "synthetic",
+        "config": {
+            "workload": f"{dim}D type 3 per step (setpts3, execute), M={M} points uniform on "
+                        f"[-{xw:g}, {xw:g})^{dim}, K={K} frequencies uniform on "
+                        f"[-{sw:g}, {sw:g})^{dim}, eps={eps:g}, {prec}",
+            "dim": dim, "M": M, "K": K, "eps": eps, "w": info["w"],
+            "spread_grid": info["nmodes"][:dim], "inner_fine_grid": info["nfine"][:dim],
+            "method": info["method"], "binsize": info["binsize"][:dim],
+            "upsampfac": info["upsampfac"],
+        },
+        "roofline": {
+            "bound": "hbm", "kernel": kernel_name, "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None, "algorithmic_bytes_per_launch": algo,
+            "avg_launch_ms": kern_ms[dominant],
+        },
+        "stage_ms_per_step": {k: v[0] / steps for k, v in stages.items()},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import direct, nufft as onufft
+        # 3D: the oracle's FP64 fine grid alone is a few GB; 2e6 points keep the
+        # sample near 20 CPU-seconds
+        n = min(args.cpu_sample, M, K, 2_000_000 if dim == 3 else M)
+        print(f"[bench] timing the oracle on {n} points and {n} frequencies", file=sys.stderr,
+              flush=True)
+        x64 = tuple(a[:n].astype(np.float64) for a in x_np)
+        s64 = tuple(a[:n].astype(np.float64) for a in s_np)
+        t0 = time.perf_counter()
+        onufft.type3(x64, c_np[:n].astype(np.complex128), s64, eps, iflag=-1)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 2 * n / dt, "unit": "NU points/s",
+                               "cores": direct.num_threads(), "kind": "oracle",
+                               "sample": f"first {n} points and {n} frequencies of the same "
+                                         f"sets, one type 3, FP64, {dt:.2f} s wall"}
     plan.destroy()
     print(json.dumps(out), flush=True)
 

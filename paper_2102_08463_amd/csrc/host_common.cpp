@@ -41,7 +41,8 @@ int64_t fine_size(int64_t N, int w, double sigma)
 // by the tanh-sinh rule z = (1 + tanh u)/2, u = (pi/2) sinh t, which is
 // insensitive to the square-root behaviour of phi at z = 1.  Step h, nodes
 // t = k h for |k| <= K; ww carries the kernel value and the Jacobian.
-void es_quadrature(double beta, double h, int K, std::vector<double> &zz, std::vector<double> &ww)
+static void es_quadrature(double beta, double h, int K, std::vector<double> &zz,
+                          std::vector<double> &ww)
 {
     zz.clear();
     ww.clear();
@@ -61,7 +62,7 @@ void es_quadrature(double beta, double h, int K, std::vector<double> &zz, std::v
     }
 }
 
-static void es_fourier(double beta, const std::vector<double> &xi, std::vector<double> &out)
+void es_fourier(double beta, const std::vector<double> &xi, std::vector<double> &out)
 {
     std::vector<double> zz, ww;
     es_quadrature(beta, 1.0 / 64.0, 4 * 64, zz, ww);  // t in [-4, 4]: weights beyond < 1e-20

@@ -28,9 +28,9 @@ int64_t fine_size(int64_t N, int w, double sigma = 2.0);
 // (Sec. II-A step 3; the sign is the lattice phase of grid point l at l h - pi).
 void correction(int64_t N, int64_t n, int w, double beta, std::vector<double> &p);
 
-// Tanh-sinh nodes zz in (0, 1) and weights ww (kernel value included) with
-// phi_hat(xi) = 2 sum_q ww[q] cos(xi zz[q]); step h, 2K + 1 nodes.
-void es_quadrature(double beta, double h, int K, std::vector<double> &zz, std::vector<double> &ww);
+// phi_hat(xi) = int_{-1}^{1} phi_beta(z) cos(xi z) dz at every xi (tanh-sinh
+// quadrature, 513 nodes).
+void es_fourier(double beta, const std::vector<double> &xi, std::vector<double> &out);
 
 // Bits needed to hold bin indices 0 .. nbins - 1.
 int bits_for(int64_t nbins);

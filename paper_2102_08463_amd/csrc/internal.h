@@ -234,9 +234,9 @@ hipError_t launch_t3_bounds(int prec, int n, int dim, const void *const a[3], do
 hipError_t launch_t3_prephase(int prec, int n, int dim, const void *const x[3],
                               const T3Affine &af, int sg, void *pre, hipStream_t s);
 // post[k] = exp(i sg sum_d mul_d s_kd) prod_d (2/w) / phi_hat(w scale_d (s_kd - off_d) / 2),
-// phi_hat by the nq-node rule quad = (nodes[nq], weights[nq]) (device, double).
+// log phi_hat from cheb = (ximax, nc Chebyshev terms in 2 (xi/ximax)^2 - 1) (device, double).
 hipError_t launch_t3_postfac(int prec, int n, int dim, const void *const sf[3],
-                             const T3Affine &af, int sg, int w, const double *quad, int nq,
+                             const T3Affine &af, int sg, int w, const double *cheb, int nc,
                              void *post, hipStream_t s);
 // out[t][i] = in[t][i] * fac[i] over ntransf stacked complex vectors of n entries.
 hipError_t launch_cmul(int prec, long long n, int ntransf, const void *in, const void *fac,

@@ -91,27 +91,32 @@ k_t3_prephase(int n, int dim, Planes x, T3Affine af, int sg,
 }
 
 // post[k] = exp(i sg sum_d s_kd C_d) prod_d (2/w) / phi_hat(w t_kd / 2) with
-// t_kd = hg_d (s_kd - D_d) and phi_hat(xi) = 2 sum_q qw[q] cos(xi qz[q]) (the
-// quadrature nodes and kernel-weighted weights are built on the host).
+// t_kd = scale_d (s_kd - off_d).  log phi_hat(xi) comes from its Chebyshev
+// expansion in u = 2 (xi / ximax)^2 - 1: cheb = (ximax, c_0 .. c_{nc-1}),
+// summed by Clenshaw's recurrence.
 template <typename T>
 __global__ void __launch_bounds__(kT3Threads)
 k_t3_postfac(int n, int dim, Planes s, T3Affine af, int sg, int w,
-             const double *__restrict__ quad, int nq, typename C2<T>::type *__restrict__ post)
+             const double *__restrict__ cheb, int nc, typename C2<T>::type *__restrict__ post)
 {
-    extern __shared__ double q[];
-    for (int k = threadIdx.x; k < 2 * nq; k += blockDim.x) q[k] = quad[k];
-    __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double ph = 0.0, fac = 1.0;
+    const double ximax = cheb[0];
+    double ph = 0.0, lsum = 0.0;
     for (int d = 0; d < dim; ++d) {
         const double sv = (double)static_cast<const T *>(s.p[d])[i];
         ph += sv * af.mul[d];
-        const double xi = 0.5 * (double)w * (af.scale[d] * (sv - af.off[d]));
-        double acc = 0.0;
-        for (int k = 0; k < nq; ++k) acc += q[nq + k] * cos(xi * q[k]);
-        fac *= (2.0 / (double)w) / (2.0 * acc);
+        const double r = 0.5 * (double)w * (af.scale[d] * (sv - af.off[d])) / ximax;
+        const double u = 2.0 * r * r - 1.0;
+        double b1 = 0.0, b2 = 0.0;
+        for (int k = nc - 1; k >= 1; --k) {
+            const double b0 = cheb[1 + k] + 2.0 * u * b1 - b2;
+            b2 = b1;
+            b1 = b0;
+        }
+        lsum += cheb[1] + u * b1 - b2;
     }
+    const double fac = pow(2.0 / (double)w, (double)dim) * exp(-lsum);
     double sn, cs;
     sincos((double)sg * ph, &sn, &cs);
     typename C2<T>::type v;
@@ -182,17 +187,16 @@ hipError_t launch_t3_prephase(int prec, int n, int dim, const void *const x[3],
 }
 
 hipError_t launch_t3_postfac(int prec, int n, int dim, const void *const sf[3],
-                             const T3Affine &af, int sg, int w, const double *quad, int nq,
+                             const T3Affine &af, int sg, int w, const double *cheb, int nc,
                              void *post, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    const size_t lds = 2 * (size_t)nq * sizeof(double);
     if (prec == 0)
-        hipLaunchKernelGGL(k_t3_postfac<float>, dim3(blocks_for(n)), dim3(kT3Threads), lds, s, n,
-                           dim, planes(sf), af, sg, w, quad, nq, static_cast<float2 *>(post));
+        hipLaunchKernelGGL(k_t3_postfac<float>, dim3(blocks_for(n)), dim3(kT3Threads), 0, s, n,
+                           dim, planes(sf), af, sg, w, cheb, nc, static_cast<float2 *>(post));
     else
-        hipLaunchKernelGGL(k_t3_postfac<double>, dim3(blocks_for(n)), dim3(kT3Threads), lds, s,
-                           n, dim, planes(sf), af, sg, w, quad, nq, static_cast<double2 *>(post));
+        hipLaunchKernelGGL(k_t3_postfac<double>, dim3(blocks_for(n)), dim3(kT3Threads), 0, s, n,
+                           dim, planes(sf), af, sg, w, cheb, nc, static_cast<double2 *>(post));
     return hipGetLastError();
 }
 

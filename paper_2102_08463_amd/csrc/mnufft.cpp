@@ -90,7 +90,7 @@ struct mnufft_plan_s {
     void *t3pre = nullptr, *t3post = nullptr, *t3cp = nullptr;
     mn::PtMap ptmap{};                 // map applied before binning (type 3 sub-plans)
     double *t3part = nullptr;          // bounds partials, 2 x 1024 blocks x 3 dims x 3
-    double *t3quad = nullptr;          // kernel-transform quadrature (nodes, weights)
+    double *t3quad = nullptr;          // ximax and the Chebyshev terms of log phi_hat
     int t3nq = 0;
     double C[3] = {0, 0, 0}, D[3] = {0, 0, 0}, gam[3] = {1, 1, 1}, hstep[3] = {1, 1, 1};
     int64_t nf3[3] = {1, 1, 1};
@@ -530,12 +530,31 @@ int plan_device(mnufft_plan p, bool with_fft)
 }
 
 // ---- type 3 ---------------------------------------------------------------
-// Nodes of the kernel-transform rule used for the type 3 deconvolution
-// factors: tanh-sinh with step 1/16 on t in [-3, 3] (97 nodes), within a few
-// 1e-13 of the finer rule the correction factors use over the frequencies
-// that occur (|xi| <= w pi / (2 sigma)).
-constexpr double kT3QuadStep = 1.0 / 16.0;
-constexpr int kT3QuadK = 48;
+// The type 3 deconvolution needs phi_hat at w t / 2 for every frequency, with
+// |t| <= pi / sigma.  log phi_hat is smooth and even there, so it is
+// expanded once per plan in Chebyshev polynomials of u = 2 (xi / ximax)^2 - 1
+// on [0, ximax], ximax = 1.01 w pi / (2 sigma): 20 terms fit it to about
+// 1e-14 relative for every w <= 16 and sigma in [1.25, 2], and a frequency
+// then costs 20 fused multiply-adds instead of a quadrature.
+constexpr int kT3Cheb = 20;
+
+void t3_cheb(int w, double beta, double sigma, std::vector<double> &out)
+{
+    const double ximax = 1.01 * w * kPi / (2.0 * sigma);
+    std::vector<double> xi(kT3Cheb), ph;
+    for (int j = 0; j < kT3Cheb; ++j) {
+        const double u = std::cos(kPi * (j + 0.5) / kT3Cheb);
+        xi[j] = ximax * std::sqrt(0.5 * (u + 1.0));
+    }
+    mn::host::es_fourier(beta, xi, ph);
+    out.assign(kT3Cheb + 1, 0.0);
+    out[0] = ximax;
+    for (int k = 0; k < kT3Cheb; ++k) {
+        double a = 0.0;
+        for (int j = 0; j < kT3Cheb; ++j) a += std::log(ph[j]) * std::cos(kPi * k * (j + 0.5) / kT3Cheb);
+        out[1 + k] = (k == 0 ? 1.0 : 2.0) * a / kT3Cheb;
+    }
+}
 
 int make_type3(int dim, int iflag, int64_t ntransf, double eps, int prec, const mnufft_opts &o,
                double sigma, mnufft_plan *out)
@@ -551,10 +570,9 @@ int make_type3(int dim, int iflag, int64_t ntransf, double eps, int prec, const 
     p->g.w = w;
     p->g.beta = beta;
     p->method = o.method == MNUFFT_METHOD_AUTO ? MNUFFT_METHOD_SM : o.method;
-    std::vector<double> zz, ww;
-    mn::host::es_quadrature(beta, kT3QuadStep, kT3QuadK, zz, ww);
-    p->t3nq = (int)zz.size();
-    zz.insert(zz.end(), ww.begin(), ww.end());
+    std::vector<double> zz;
+    t3_cheb(w, beta, sigma, zz);
+    p->t3nq = kT3Cheb;
     int rc = use_device(p);
     if (!rc) rc = dalloc(p, (void **)&p->t3quad, zz.size() * 8);
     if (!rc && hipMemcpy(p->t3quad, zz.data(), zz.size() * 8, hipMemcpyHostToDevice))
