@@ -1,5 +1,5 @@
 /*
- * mnufft: 2D/3D nonuniform FFTs of type 1 and type 2 (and type 3) on AMD Instinct MI355X
+ * mnufft: 1D/2D/3D nonuniform FFTs of type 1 and type 2 (and type 3) on AMD Instinct MI355X
  * (gfx950), following the three-step method of cuFINUFFT (arXiv 2102.08463):
  * exponential-of-semicircle spreading / interpolation on an upsampled grid,
  * a fine-grid FFT, and deconvolution by the kernel's Fourier transform.
@@ -11,7 +11,8 @@
  * MNUFFT_F32, double2 for MNUFFT_F64.  A plan is not re-entrant: calls on
  * one plan must not overlap.
  *
- * Problem statement (Sec. I, eqs. 2d1 / 2d2 and their 3D analogue):
+ * Problem statement (Sec. I, eqs. 2d1 / 2d2 and their 3D analogue; 1D, which
+ * the paper leaves out (Sec. I-B), is the same with one coordinate):
  *   type 1:  f_k = sum_{j<M} c_j exp(iflag * i * k.x_j),   k in I_N1 x I_N2 (x I_N3)
  *   type 2:  c_j = sum_k f_k exp(iflag * i * k.x_j),       j < M
  * with I_N = {k integer : -N/2 <= k < N/2} (eq. I) and points x_j in
@@ -63,7 +64,7 @@ extern "C" {
 typedef struct mnufft_opts {
     int   method;       /* MNUFFT_METHOD_*; default AUTO */
     int   binsize[3];   /* bin extents m_i in fine-grid cells; 0 selects the default,
-                           32 x 32 in 2D and 16 x 8 x 8 in 3D (measured on gfx950; the
+                           64 in 1D, 32 x 32 in 2D and 16 x 8 x 8 in 3D (measured on gfx950; the
                            paper's V100 choice was 32 x 32 and 16 x 16 x 2, Sec. III-A,
                            first remark), halved along the longest side while the
                            padded bins of method SM do not fit in 160 KB of LDS */
@@ -109,7 +110,7 @@ int mnufft_default_opts(mnufft_opts *o);
 
 /* Create a plan (Sec. I-A: plan, set up, execute, destroy).
  *   type     1 or 2; or 3 (see mnufft_setpts3)
- *   dim      2 or 3
+ *   dim      1, 2 or 3
  *   nmodes   host array of dim entries N_i >= 1 (the rest ignored); unused and
  *            may be NULL for type 3
  *   iflag    +1 or -1, the sign in the exponent
@@ -129,7 +130,8 @@ int mnufft_makeplan(int type, int dim, const int64_t *nmodes, int iflag,
                     const mnufft_opts *opts, mnufft_plan *out);
 
 /* Set the M nonuniform points (Sec. III-A bin-sort; the paper's setup stage).
- *   x, y, z  device arrays of M reals of the plan precision (z = NULL in 2D);
+ *   x, y, z  device arrays of M reals of the plan precision (z = NULL in 2D,
+ *            y = z = NULL in 1D);
  *            coordinates in [-pi, pi); values in [-3pi, 3pi) are folded by
  *            whole periods, exactly.
  * Bins the points on the fine grid, builds the stable bin-sort permutation
@@ -137,8 +139,8 @@ int mnufft_makeplan(int type, int dim, const int64_t *nmodes, int iflag,
  * keeps its own sorted copy of the coordinates, so the caller may reuse x/y/z
  * once the stream has passed this call.  Stream-ordered, no host
  * synchronisation unless validate_pts is set.  M = 0 is allowed.
- * Errors: ERR_ARG (M < 0, M > 2^31 - 1, NULL x or y, z given in 2D or
- * missing in 3D), ERR_PTS, ERR_ALLOC, ERR_HIP. */
+ * Errors: ERR_ARG (M < 0, M > 2^31 - 1, NULL x, or y / z given for an absent
+ * dimension or missing for a present one), ERR_PTS, ERR_ALLOC, ERR_HIP. */
 int mnufft_setpts(mnufft_plan p, int64_t M, const void *x, const void *y,
                   const void *z);
 
@@ -155,15 +157,15 @@ int mnufft_setpts(mnufft_plan p, int64_t M, const void *x, const void *y,
  * grid is transformed by a type 2 plan (modes -nf/2 .. nf/2 - 1) at
  * t_k = h gamma (s_k - D), and the result is multiplied by
  * exp(iflag i s_k.C) prod_d (2/w) / phi_hat(w t_kd / 2).
- *   x, y, z  device arrays of M reals of the plan precision (z only in 3D)
- *   s, t, u  device arrays of K reals (u only in 3D)
+ *   x, y, z  device arrays of M reals of the plan precision (y from 2D, z only in 3D)
+ *   s, t, u  device arrays of K reals (t from 2D, u only in 3D)
  * Reads the bounds of both sets back to the host (synchronises the stream),
  * then makes the spreading and type 2 plans (again only when nf changes)
  * and bin-sorts both rescaled sets.  mnufft_execute then takes c (ntransf x M)
  * and writes f (ntransf x K); the adjoint, spread / interp, gradient and
  * sort introspection calls return ERR_UNSUPPORTED on a type 3 plan.
  * M = 0 or K = 0 is allowed.  Errors: ERR_ARG (not a type 3 plan, sizes out
- * of range, a needed pointer NULL or z / u given in 2D, nf above 2^24 in some
+ * of range, a needed pointer NULL or a pointer given for an absent dimension, nf above 2^24 in some
  * dimension), ERR_PTS (a non-finite coordinate), ERR_ALLOC, ERR_HIP, ERR_FFT. */
 int mnufft_setpts3(mnufft_plan p, int64_t M, const void *x, const void *y, const void *z,
                    int64_t K, const void *s, const void *t, const void *u);
@@ -195,7 +197,7 @@ int mnufft_execute_adjoint(mnufft_plan p, void *c, void *f);
  * wts = c give dL/dx.
  *   modes   ntransf x N1 N2 (N3) complex, k1 fastest
  *   wts     ntransf x M complex, input point order
- *   gx, gy, gz   M reals each (gz only in 3D), input order, overwritten
+ *   gx, gy, gz   M reals each (gy from 2D, gz only in 3D), input order, overwritten
  * Errors: ERR_STATE, ERR_ARG, ERR_HIP, ERR_FFT. */
 int mnufft_interp_grad(mnufft_plan p, const void *modes, const void *wts, void *gx, void *gy,
                        void *gz);

@@ -36,6 +36,8 @@ UNITS = [
     ("kernels_deconv.hip", [], "kernels_deconv.o"),
     ("kernels_type3.hip", [], "kernels_type3.o"),
     ("spread_dispatch.hip", [], "spread_dispatch.o"),
+    ("spread_inst.hip", ["-DMN_T=float", "-DMN_D=1"], "spread_f1.o"),
+    ("spread_inst.hip", ["-DMN_T=double", "-DMN_D=1"], "spread_d1.o"),
     ("spread_inst.hip", ["-DMN_T=float", "-DMN_D=2"], "spread_f2.o"),
     ("spread_inst.hip", ["-DMN_T=float", "-DMN_D=3"], "spread_f3.o"),
     ("spread_inst.hip", ["-DMN_T=double", "-DMN_D=2"], "spread_d2.o"),

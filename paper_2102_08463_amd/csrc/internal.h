@@ -194,7 +194,7 @@ size_t sm_lds_bytes(const Geom &g, int prec, bool interp, int msub);
 // Single-precision SM spreading keeps up to this many gathered strengths of
 // a subproblem in LDS, so the strengths are read from HBM once (fewer in 3D,
 // where bins hold fewer points and LDS occupancy matters more).
-inline int smp_stage(int dim, int msub) { return msub < (dim == 2 ? 4096 : 1024) ? msub : (dim == 2 ? 4096 : 1024); }
+inline int smp_stage(int dim, int msub) { return msub < (dim <= 2 ? 4096 : 1024) ? msub : (dim <= 2 ? 4096 : 1024); }
 // Reals per scratch tile slot of SM spreading.
 int sm_tile_stride(const Geom &g);
 // Leaders of tile groups to merge: subproblems q with (q - suboff[bin]) % G == 0

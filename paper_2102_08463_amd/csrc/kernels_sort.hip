@@ -466,9 +466,13 @@ hipError_t radix_sort(int M, int bits, int prec, int dim, uint32_t *keysA, uint3
                            (const uint32_t *)hist, kb[1 - cur], vb[1 - cur], pays[p]);      \
     } while (0)
             if (prec == 0) {
-                if (dim == 2) MN_SCATTER(float, 2); else MN_SCATTER(float, 3);
+                if (dim == 1) MN_SCATTER(float, 1);
+                else if (dim == 2) MN_SCATTER(float, 2);
+                else MN_SCATTER(float, 3);
             } else {
-                if (dim == 2) MN_SCATTER(double, 2); else MN_SCATTER(double, 3);
+                if (dim == 1) MN_SCATTER(double, 1);
+                else if (dim == 2) MN_SCATTER(double, 2);
+                else MN_SCATTER(double, 3);
             }
 #undef MN_SCATTER
         }

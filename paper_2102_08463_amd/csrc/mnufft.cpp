@@ -271,6 +271,10 @@ mn::Pts points_of(mnufft_plan p)
 
 size_t grid_bytes(mnufft_plan p) { return p->grid_elems * 2 * p->rsz; }
 
+// SM spreading with the two-word accumulator (double precision, and single
+// precision in 1D) needs max |c| before the tile kernel.
+bool needs_cmax(mnufft_plan p) { return p->prec == MNUFFT_F64 || p->dim == 1; }
+
 // Step 1 of type 1 for all ntransf vectors: c (ntransf x M) -> p->grid.
 int spread_all(mnufft_plan p, const void *c)
 {
@@ -282,8 +286,8 @@ int spread_all(mnufft_plan p, const void *c)
     for (int64_t t = 0; t < p->ntransf; ++t) {
         const char *ct = (const char *)c + (size_t)t * p->M * 2 * p->rsz;
         char *gt = (char *)p->grid + (size_t)t * grid_bytes(p);
-        if (p->method == MNUFFT_METHOD_SM && p->prec == MNUFFT_F64) {
-            // max |c| for the double-precision fixed-point scale (single
+        if (p->method == MNUFFT_METHOD_SM && needs_cmax(p)) {
+            // max |c| for the two-word fixed-point scale (2D / 3D single
             // precision scales each subproblem inside the spreading kernel)
             StageTimer tm(p->tm, MNUFFT_STAGE_SCALE, p->stream);
             MN_HIP(mn::launch_zero(p->cmax, 1024 * 8, p->stream));
@@ -446,11 +450,14 @@ int plan_geometry(mnufft_plan p, const int64_t nf[3], int w, double beta, const 
     g.w = w;
     g.beta = beta;
     g.pad = (w + 1) / 2;
-    const int defm[2][3] = {{32, 32, 1}, {16, 8, 8}};
+    // 1D bins stay short: sorted points carry their coordinate relative to the
+    // bin start in the plan precision, and in single precision a 1024-cell bin
+    // would leave those coordinates only about 6e-5 cells of resolution
+    const int defm[3][3] = {{64, 1, 1}, {32, 32, 1}, {16, 8, 8}};
     bool user_bins = false;
     for (int d = 0; d < 3; ++d) {
         g.n[d] = d < dim ? (int)nf[d] : 1;
-        int m = d < dim ? (o.binsize[d] > 0 ? o.binsize[d] : defm[dim - 2][d]) : 1;
+        int m = d < dim ? (o.binsize[d] > 0 ? o.binsize[d] : defm[dim - 1][d]) : 1;
         user_bins = user_bins || (d < dim && o.binsize[d] > 0);
         g.m[d] = std::min(m, g.n[d]);
         g.S[d] = (double)g.n[d] / (2.0 * kPi);
@@ -762,7 +769,7 @@ int mnufft_makeplan(int type, int dim, const int64_t *nmodes, int iflag, int64_t
     if (!out) return MNUFFT_ERR_ARG;
     *out = nullptr;
     // ---- validate everything before touching the device ----
-    if ((type != 1 && type != 2 && type != 3) || (dim != 2 && dim != 3) ||
+    if ((type != 1 && type != 2 && type != 3) || dim < 1 || dim > 3 ||
         (!nmodes && type != 3) || (iflag != 1 && iflag != -1) || ntransf < 1 ||
         !(eps > 0.0 && eps < 1.0) || (prec != MNUFFT_F32 && prec != MNUFFT_F64))
         return MNUFFT_ERR_ARG;
@@ -809,8 +816,9 @@ int mnufft_makeplan(int type, int dim, const int64_t *nmodes, int iflag, int64_t
 int mnufft_setpts(mnufft_plan p, int64_t M, const void *x, const void *y, const void *z)
 {
     if (!p || p->type == 3 || M < 0 || M > 2147483647LL) return MNUFFT_ERR_ARG;
-    if (M > 0 && (!x || !y)) return MNUFFT_ERR_ARG;
-    if (M > 0 && ((p->dim == 3) != (z != nullptr))) return MNUFFT_ERR_ARG;
+    if (p->dim == 1 && (y || z)) return MNUFFT_ERR_ARG;
+    if (M > 0 && (!x || (p->dim >= 2 && !y))) return MNUFFT_ERR_ARG;
+    if (M > 0 && p->dim >= 2 && ((p->dim == 3) != (z != nullptr))) return MNUFFT_ERR_ARG;
     if (p->g.nbins + (M + p->msub - 1) / p->msub > 2147483647LL) return MNUFFT_ERR_ARG;
     int rc = use_device(p);
     if (rc) return rc;
@@ -840,9 +848,9 @@ int mnufft_setpts3(mnufft_plan p, int64_t M, const void *x, const void *y, const
     if (!p || p->type != 3 || M < 0 || M > 2147483647LL || K < 0 || K > 2147483647LL)
         return MNUFFT_ERR_ARG;
     const int dim = p->dim;
-    const void *xs[3] = {x, y, dim == 3 ? z : nullptr};
-    const void *ss[3] = {s, t, dim == 3 ? u : nullptr};
-    if ((dim == 2) && (z || u)) return MNUFFT_ERR_ARG;
+    const void *xs[3] = {x, dim >= 2 ? y : nullptr, dim == 3 ? z : nullptr};
+    const void *ss[3] = {s, dim >= 2 ? t : nullptr, dim == 3 ? u : nullptr};
+    if ((dim < 3 && (z || u)) || (dim < 2 && (y || t))) return MNUFFT_ERR_ARG;
     for (int d = 0; d < dim; ++d)
         if ((M > 0 && !xs[d]) || (K > 0 && !ss[d])) return MNUFFT_ERR_ARG;
     int rc = use_device(p);
@@ -951,7 +959,7 @@ int mnufft_spread(mnufft_plan p, const void *c, void *grid)
     if (!grid || (p->M > 0 && !c)) return MNUFFT_ERR_ARG;
     if ((rc = use_device(p))) return rc;
     if (p->method != MNUFFT_METHOD_SM) MN_HIP(mn::launch_zero(grid, grid_bytes(p), p->stream));
-    else if (p->prec == MNUFFT_F64) MN_HIP(mn::launch_zero(p->cmax, 1024 * 8, p->stream));
+    else if (needs_cmax(p)) MN_HIP(mn::launch_zero(p->cmax, 1024 * 8, p->stream));
     MN_HIP(mn::launch_spread(p->g, p->prec, p->method, points_of(p), c, grid, p->stream));
     return MNUFFT_OK;
 }
@@ -973,7 +981,7 @@ int mnufft_interp_grad(mnufft_plan p, const void *modes, const void *wts, void *
     int rc = check_ready(p);
     if (rc) return rc;
     if (p->type == 3) return MNUFFT_ERR_UNSUPPORTED;
-    if (!modes || (p->M > 0 && (!wts || !gx || !gy || (p->dim == 3 && !gz))))
+    if (!modes || (p->M > 0 && (!wts || !gx || (p->dim >= 2 && !gy) || (p->dim == 3 && !gz))))
         return MNUFFT_ERR_ARG;
     if ((rc = use_device(p))) return rc;
     // field = type 2 of `modes` with the sign of the plan's type 2 direction
@@ -981,7 +989,7 @@ int mnufft_interp_grad(mnufft_plan p, const void *modes, const void *wts, void *
     MN_HIP(mn::launch_precorrect(p->dim, p->N, p->g.n, p->prec, (int)p->ntransf, modes,
                                  p->pfac, p->grid, p->stream));
     if ((rc = run_fft(p, sign))) return rc;
-    void *out[3] = {gx, gy, p->dim == 3 ? gz : nullptr};
+    void *out[3] = {gx, p->dim >= 2 ? gy : nullptr, p->dim == 3 ? gz : nullptr};
     MN_HIP(mn::launch_interp_grad(p->g, p->prec, points_of(p), (int)p->ntransf, p->grid, wts,
                                   out, p->stream));
     return MNUFFT_OK;

@@ -11,33 +11,19 @@ hipError_t spread_dim(const Geom &g, int method, const Pts &P, const void *c, vo
 template <typename T, int DIM>
 hipError_t interp_dim(const Geom &g, int method, const Pts &P, const void *grid, void *c,
                       hipStream_t s, size_t lds);
-extern template hipError_t spread_dim<float, 2>(const Geom &, int, const Pts &, const void *,
-                                                void *, hipStream_t, size_t, int);
-extern template hipError_t spread_dim<float, 3>(const Geom &, int, const Pts &, const void *,
-                                                void *, hipStream_t, size_t, int);
-extern template hipError_t spread_dim<double, 2>(const Geom &, int, const Pts &, const void *,
-                                                 void *, hipStream_t, size_t, int);
-extern template hipError_t spread_dim<double, 3>(const Geom &, int, const Pts &, const void *,
-                                                 void *, hipStream_t, size_t, int);
-extern template hipError_t interp_dim<float, 2>(const Geom &, int, const Pts &, const void *,
-                                                void *, hipStream_t, size_t);
-extern template hipError_t interp_dim<float, 3>(const Geom &, int, const Pts &, const void *,
-                                                void *, hipStream_t, size_t);
-extern template hipError_t interp_dim<double, 2>(const Geom &, int, const Pts &, const void *,
-                                                 void *, hipStream_t, size_t);
-extern template hipError_t interp_dim<double, 3>(const Geom &, int, const Pts &, const void *,
-                                                 void *, hipStream_t, size_t);
+#define MN_EXTERN(TT, DD)                                                                  \
+    extern template hipError_t spread_dim<TT, DD>(const Geom &, int, const Pts &, const void *, \
+                                                  void *, hipStream_t, size_t, int);          \
+    extern template hipError_t interp_dim<TT, DD>(const Geom &, int, const Pts &, const void *, \
+                                                  void *, hipStream_t, size_t);               \
+    extern template hipError_t grad_dim<TT, DD>(const Geom &, const Pts &, int, const void *,   \
+                                                const void *, void *const[3], hipStream_t);
 template <typename T, int DIM>
 hipError_t grad_dim(const Geom &g, const Pts &P, int ntransf, const void *grid, const void *wts,
                     void *const out[3], hipStream_t s);
-extern template hipError_t grad_dim<float, 2>(const Geom &, const Pts &, int, const void *,
-                                              const void *, void *const[3], hipStream_t);
-extern template hipError_t grad_dim<float, 3>(const Geom &, const Pts &, int, const void *,
-                                              const void *, void *const[3], hipStream_t);
-extern template hipError_t grad_dim<double, 2>(const Geom &, const Pts &, int, const void *,
-                                               const void *, void *const[3], hipStream_t);
-extern template hipError_t grad_dim<double, 3>(const Geom &, const Pts &, int, const void *,
-                                               const void *, void *const[3], hipStream_t);
+MN_EXTERN(float, 1) MN_EXTERN(float, 2) MN_EXTERN(float, 3)
+MN_EXTERN(double, 1) MN_EXTERN(double, 2) MN_EXTERN(double, 3)
+#undef MN_EXTERN
 }  // namespace detail
 
 hipError_t launch_interp_grad(const Geom &g, int prec, const Pts &P, int ntransf,
@@ -45,11 +31,13 @@ hipError_t launch_interp_grad(const Geom &g, int prec, const Pts &P, int ntransf
                               hipStream_t s)
 {
     if (P.M == 0) return hipSuccess;
-    if (prec == 0)
-        return g.dim == 2 ? detail::grad_dim<float, 2>(g, P, ntransf, grid, wts, out, s)
-                          : detail::grad_dim<float, 3>(g, P, ntransf, grid, wts, out, s);
-    return g.dim == 2 ? detail::grad_dim<double, 2>(g, P, ntransf, grid, wts, out, s)
-                      : detail::grad_dim<double, 3>(g, P, ntransf, grid, wts, out, s);
+#define MN_GRAD(TT)                                                                          \
+    (g.dim == 1   ? detail::grad_dim<TT, 1>(g, P, ntransf, grid, wts, out, s)                \
+     : g.dim == 2 ? detail::grad_dim<TT, 2>(g, P, ntransf, grid, wts, out, s)                \
+                  : detail::grad_dim<TT, 3>(g, P, ntransf, grid, wts, out, s))
+    const hipError_t e = prec == 0 ? MN_GRAD(float) : MN_GRAD(double);
+#undef MN_GRAD
+    return e;
 }
 
 int sm_tile_stride(const Geom &g)
@@ -66,9 +54,11 @@ size_t sm_lds_bytes(const Geom &g, int prec, bool interp, int msub)
     // 64-bit fixed-point accumulators: one word per cell in single precision,
     // one per part in double precision
     // (single precision also stages smp_stage strengths, 8 bytes each)
+    // (1D single precision uses the two-word accumulator of double precision)
     if (!interp)
-        return prec == 0 ? (size_t)sm_tile_stride(g) * 4 + (size_t)8 * smp_stage(g.dim, msub)
-                         : (size_t)sm_tile_stride(g) * 8;
+        return prec == 0 && g.dim >= 2
+                   ? (size_t)sm_tile_stride(g) * 4 + (size_t)8 * smp_stage(g.dim, msub)
+                   : (size_t)sm_tile_stride(g) * 8;
     const int P = (g.w + 1) / 2;
     size_t cells = 1;
     for (int d = 0; d < g.dim; ++d) cells *= (size_t)(g.m[d] + 2 * P);
@@ -108,11 +98,13 @@ hipError_t launch_spread(const Geom &g, int prec, int method, const Pts &P, cons
                            s);
     }
     const size_t lds = method == 3 ? sm_lds_bytes(g, prec, false, P.msub) : 0;
-    if (prec == 0)
-        return g.dim == 2 ? detail::spread_dim<float, 2>(g, method, P, c, grid, s, lds, part)
-                          : detail::spread_dim<float, 3>(g, method, P, c, grid, s, lds, part);
-    return g.dim == 2 ? detail::spread_dim<double, 2>(g, method, P, c, grid, s, lds, part)
-                      : detail::spread_dim<double, 3>(g, method, P, c, grid, s, lds, part);
+#define MN_SPREAD(TT)                                                                        \
+    (g.dim == 1   ? detail::spread_dim<TT, 1>(g, method, P, c, grid, s, lds, part)           \
+     : g.dim == 2 ? detail::spread_dim<TT, 2>(g, method, P, c, grid, s, lds, part)           \
+                  : detail::spread_dim<TT, 3>(g, method, P, c, grid, s, lds, part))
+    const hipError_t e = prec == 0 ? MN_SPREAD(float) : MN_SPREAD(double);
+#undef MN_SPREAD
+    return e;
 }
 
 hipError_t launch_interp(const Geom &g, int prec, int method, const Pts &P, const void *grid,
@@ -120,11 +112,13 @@ hipError_t launch_interp(const Geom &g, int prec, int method, const Pts &P, cons
 {
     if (P.M == 0) return hipSuccess;
     const size_t lds = method == 3 ? sm_lds_bytes(g, prec, true, P.msub) : 0;
-    if (prec == 0)
-        return g.dim == 2 ? detail::interp_dim<float, 2>(g, method, P, grid, c, s, lds)
-                          : detail::interp_dim<float, 3>(g, method, P, grid, c, s, lds);
-    return g.dim == 2 ? detail::interp_dim<double, 2>(g, method, P, grid, c, s, lds)
-                      : detail::interp_dim<double, 3>(g, method, P, grid, c, s, lds);
+#define MN_INTERP(TT)                                                                        \
+    (g.dim == 1   ? detail::interp_dim<TT, 1>(g, method, P, grid, c, s, lds)                 \
+     : g.dim == 2 ? detail::interp_dim<TT, 2>(g, method, P, grid, c, s, lds)                 \
+                  : detail::interp_dim<TT, 3>(g, method, P, grid, c, s, lds))
+    const hipError_t e = prec == 0 ? MN_INTERP(float) : MN_INTERP(double);
+#undef MN_INTERP
+    return e;
 }
 
 }  // namespace mn

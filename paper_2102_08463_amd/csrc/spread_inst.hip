@@ -1,10 +1,10 @@
 // One (precision, dimension) slice of the spreading / interpolation kernels,
-// selected by MN_T (float or double) and MN_D (2 or 3) on the compiler
-// command line, so that the 4 slices compile in parallel.
+// selected by MN_T (float or double) and MN_D (1, 2 or 3) on the compiler
+// command line, so that the 6 slices compile in parallel.
 #include "spread_kernels.h"
 
 #if !defined(MN_T) || !defined(MN_D)
-#error "compile with -DMN_T=float|double -DMN_D=2|3"
+#error "compile with -DMN_T=float|double -DMN_D=1|2|3"
 #endif
 
 namespace mn {

@@ -119,12 +119,20 @@ k_spread_gm(Geom g, int M, const uint32_t *__restrict__ key, const T *__restrict
     const int bz = b;
     T kx[W], ky[W];
     const int sx = taps<T, W>(u0[i], bk, kx) + bx * g.m[0];
-    const int sy = taps<T, W>(u1[i], bk, ky) + by * g.m[1];
+    int sy = 0;
+    if constexpr (DIM >= 2) sy = taps<T, W>(u1[i], bk, ky) + by * g.m[1];
     const auto cv = c[perm ? perm[i] : i];
     int lx[W];
 #pragma unroll
     for (int a = 0; a < W; ++a) lx[a] = wrap1(sx + a, g.n[0]);
-    if constexpr (DIM == 2) {
+    if constexpr (DIM == 1) {
+        T *row = reinterpret_cast<T *>(grid);
+#pragma unroll
+        for (int a1 = 0; a1 < W; ++a1) {
+            gadd(row + 2 * lx[a1], cv.x * kx[a1]);
+            gadd(row + 2 * lx[a1] + 1, cv.y * kx[a1]);
+        }
+    } else if constexpr (DIM == 2) {
 #pragma unroll
         for (int a2 = 0; a2 < W; ++a2) {
             const T wr = cv.x * ky[a2], wi = cv.y * ky[a2];
@@ -174,12 +182,20 @@ k_interp_gm(Geom g, int M, const uint32_t *__restrict__ key, const T *__restrict
     const int bz = b;
     T kx[W], ky[W];
     const int sx = taps<T, W>(u0[i], bk, kx) + bx * g.m[0];
-    const int sy = taps<T, W>(u1[i], bk, ky) + by * g.m[1];
+    int sy = 0;
+    if constexpr (DIM >= 2) sy = taps<T, W>(u1[i], bk, ky) + by * g.m[1];
     int lx[W];
 #pragma unroll
     for (int a = 0; a < W; ++a) lx[a] = wrap1(sx + a, g.n[0]);
     T ar = 0, ai = 0;
-    if constexpr (DIM == 2) {
+    if constexpr (DIM == 1) {
+#pragma unroll
+        for (int a1 = 0; a1 < W; ++a1) {
+            const auto v = grid[lx[a1]];
+            ar += v.x * kx[a1];
+            ai += v.y * kx[a1];
+        }
+    } else if constexpr (DIM == 2) {
 #pragma unroll
         for (int a2 = 0; a2 < W; ++a2) {
             const auto *row = grid + (size_t)wrap1(sy + a2, g.n[1]) * g.n[0];
@@ -275,8 +291,10 @@ __device__ __forceinline__ T block_cmax(const T *__restrict__ parts)
 //
 // The LDS accumulator is 64-bit fixed point: on gfx950 integer LDS atomics
 // (ds_add_u64) sustain roughly ten times the rate of floating-point ones.
-// This kernel serves double precision (single precision uses k_spread_smp,
-// one word per cell).  Every contribution v = c_j * phi * phi is turned into
+// This kernel serves double precision and 1D single precision (2D / 3D single
+// precision uses k_spread_smp, one word per cell, whose per-subproblem scale
+// is too coarse for 1D bins: a 1D subproblem spreads many points over few
+// taps each, so its strength sum overstates every cell's by far).  Every contribution v = c_j * phi * phi is turned into
 // round(v * S) with S = 2^62 / (2^ceil(log2 msub) 2^ceil(log2 cmax)),
 // cmax = max_j max(|Re c_j|, |Im c_j|): a cell gets at most msub
 // contributions of size <= cmax, so the sum stays below 2^62, with quantum
@@ -284,6 +302,16 @@ __device__ __forceinline__ T block_cmax(const T *__restrict__ parts)
 // Grid-stride loop over the subproblem list; the tile is interleaved
 // (re, im) with ts2 >= 2 p1 p2 p3 entries per slot (a multiple of 8).
 template <typename T> struct FixedScale;
+template <> struct FixedScale<float> {
+    __device__ static float scale(float cmax, int lg_msub, float &inv)
+    {
+        int e;
+        frexpf(cmax, &e);
+        inv = ldexpf(1.0f, e + lg_msub - 62);
+        return ldexpf(1.0f, 62 - lg_msub - e);
+    }
+    __device__ static long long to_fixed(float v) { return __float2ll_rn(v); }
+};
 template <> struct FixedScale<double> {
     __device__ static double scale(double cmax, int lg_msub, double &inv)
     {
@@ -327,10 +355,20 @@ k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
         for (int i = rec.y + threadIdx.x; i < end; i += blockDim.x) {
             T kx[W], ky[W];
             const int sx = taps<T, W>(u0[i] + (T)P, bk, kx);
-            const int sy = taps<T, W>(u1[i] + (T)P, bk, ky);
+            int sy = 0;
+            if constexpr (DIM >= 2) sy = taps<T, W>(u1[i] + (T)P, bk, ky);
             const auto cv = c[perm[i]];
             const T cr0 = cv.x * S, ci0 = cv.y * S;
-            if constexpr (DIM == 2) {
+            if constexpr (DIM == 1) {
+                unsigned long long *row = tile + 2 * sx;
+#pragma unroll
+                for (int a1 = 0; a1 < W; ++a1) {
+                    atomicAdd(row + 2 * a1,
+                              (unsigned long long)FixedScale<T>::to_fixed(cr0 * kx[a1]));
+                    atomicAdd(row + 2 * a1 + 1,
+                              (unsigned long long)FixedScale<T>::to_fixed(ci0 * kx[a1]));
+                }
+            } else if constexpr (DIM == 2) {
 #pragma unroll
                 for (int a2 = 0; a2 < W; ++a2) {
                     const T wr = cr0 * ky[a2], wi = ci0 * ky[a2];
@@ -406,7 +444,7 @@ k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict_
              const float2 *__restrict__ c, float *__restrict__ scratch, int ts2, float bk,
              int stage_cap, const TGeom *__restrict__ tg, int T_)
 {
-    static_assert(std::is_same<T, float>::value, "single precision only");
+    static_assert(std::is_same<T, float>::value && DIM >= 2, "2D / 3D single precision only");
     constexpr int P = (W + 1) / 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     unsigned long long *tile = reinterpret_cast<unsigned long long *>(smem_raw);  // ts2 / 2 cells
@@ -471,7 +509,7 @@ k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict_
         auto strength = [&](int ii) { return ii - rec.y < stage_cap ? cs[ii - rec.y] : c[perm[ii]]; };
         if (i < end) {
             nu0 = u0[i];
-            nu1 = u1[i];
+            if constexpr (DIM >= 2) nu1 = u1[i];
             if constexpr (DIM == 3) nu2 = u2[i];
             ncv = strength(i);
         }
@@ -480,13 +518,14 @@ k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict_
             const float2 cv = ncv;
             if (i + kThreads < end) {
                 nu0 = u0[i + kThreads];
-                nu1 = u1[i + kThreads];
+                if constexpr (DIM >= 2) nu1 = u1[i + kThreads];
                 if constexpr (DIM == 3) nu2 = u2[i + kThreads];
                 ncv = strength(i + kThreads);
             }
             float kx[W], ky[W];
             const int sx = taps<float, W>(x0 + (float)P, bk, kx);
-            const int sy = taps<float, W>(x1 + (float)P, bk, ky);
+            int sy = 0;
+            if constexpr (DIM >= 2) sy = taps<float, W>(x1 + (float)P, bk, ky);
             const float cr0 = cv.x * S, ci0 = cv.y * S;
             auto row_add = [&](unsigned long long *row, float wr, float wi) {
 #pragma unroll
@@ -602,6 +641,7 @@ k_tile_gather(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__ 
         const long long r = el / gg.n[0];
         const int l2 = (int)(r % gg.n[1]);
         const int l3 = DIM == 3 ? (int)(r / gg.n[1]) : 0;
+        if constexpr (DIM == 1) k1 = 1;  // one row: the single entry (bin 0, offset 0)
         T ar = 0, ai = 0;
         for (int j3 = 0; j3 < (DIM == 3 ? k2 : 1); ++j3) {
             int nb3 = 0, s3 = 0;
@@ -612,7 +652,7 @@ k_tile_gather(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__ 
                 s3 = c3.y;
             }
             for (int j2 = 0; j2 < k1; ++j2) {
-                const int2 c2 = cov1[(size_t)l2 * k1 + j2];
+                const int2 c2 = DIM >= 2 ? cov1[(size_t)l2 * k1 + j2] : make_int2(0, 0);
                 if (c2.x < 0) break;
                 for (int j1 = 0; j1 < k0; ++j1) {
                     const int2 c1 = cov0[(size_t)l1 * k0 + j1];
@@ -649,7 +689,7 @@ k_tile_gather2(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__
                typename Cplx<T>::type *__restrict__ grid, long long ncell,
                const TGeom *__restrict__ tg, int T_)
 {
-    constexpr int NZ = DIM == 3 ? 2 : 1, NC = 4 * NZ;
+    constexpr int NY = DIM >= 2 ? 2 : 1, NZ = DIM == 3 ? 2 : 1, NC = 2 * NY * NZ;
     __shared__ long long soff[BATCH ? kTCache : 1];
     const auto fld = [](const TGeom &a) { return a.grid_off; };
     bool cached = false;
@@ -682,7 +722,8 @@ k_tile_gather2(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             c1[j] = j < k0 ? cov0[(size_t)l1 * k0 + j] : make_int2(-1, 0);
-            c2[j] = j < k1 ? cov1[(size_t)l2 * k1 + j] : make_int2(-1, 0);
+            c2[j] = DIM >= 2 ? (j < k1 ? cov1[(size_t)l2 * k1 + j] : make_int2(-1, 0))
+                             : make_int2(j == 0 ? 0 : -1, 0);
             c3[j] = (DIM == 3 && j < k2) ? cov2[(size_t)l3 * k2 + j] : make_int2(j == 0 ? 0 : -1, 0);
         }
         int bin[NC];
@@ -690,10 +731,10 @@ k_tile_gather2(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__
 #pragma unroll
         for (int j3 = 0; j3 < NZ; ++j3)
 #pragma unroll
-            for (int j2 = 0; j2 < 2; ++j2)
+            for (int j2 = 0; j2 < NY; ++j2)
 #pragma unroll
                 for (int j1 = 0; j1 < 2; ++j1) {
-                    const int v = (j3 * 2 + j2) * 2 + j1;
+                    const int v = (j3 * NY + j2) * 2 + j1;
                     const bool ok = c1[j1].x >= 0 && c2[j2].x >= 0 && c3[j3].x >= 0;
                     bin[v] = ok ? boff + c1[j1].x + gg.B[0] * (c2[j2].x + gg.B[1] * c3[j3].x) : -1;
                     off[v] = 2 * ((size_t)c1[j1].y +
@@ -753,13 +794,13 @@ k_interp_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
             grid = grid_ + tt.grid_off;
             b -= tt.bin_off;
         }
-        const int p1 = gg.m[0] + 2 * P, p2 = gg.m[1] + 2 * P;
+        const int p1 = gg.m[0] + 2 * P, p2 = DIM >= 2 ? gg.m[1] + 2 * P : 1;
         const int p3 = DIM == 3 ? gg.m[2] + 2 * P : 1;
         const int tsize = p1 * p2 * p3;
         const int bx = b % gg.B[0]; b /= gg.B[0];
         const int by = b % gg.B[1]; b /= gg.B[1];
         const int bz = b;
-        const int o1 = bx * gg.m[0] - P, o2 = by * gg.m[1] - P;
+        const int o1 = bx * gg.m[0] - P, o2 = DIM >= 2 ? by * gg.m[1] - P : 0;
         const int o3 = DIM == 3 ? bz * gg.m[2] - P : 0;
         // The results of the previous subproblem may still be in flight; on
         // this GPU one counter tracks vector loads and stores together, so a
@@ -776,7 +817,7 @@ k_interp_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
                     const int s1 = e % p1, r = e / p1;
                     const int s2 = r % p2, s3 = r / p2;
                     const int l1 = wrapmod(o1 + s1, gg.n[0]);
-                    const int l2 = wrapmod(o2 + s2, gg.n[1]);
+                    const int l2 = DIM >= 2 ? wrapmod(o2 + s2, gg.n[1]) : 0;
                     const int l3 = DIM == 3 ? wrapmod(o3 + s3, gg.n[2]) : 0;
                     v[k] = grid[((size_t)l3 * gg.n[1] + l2) * gg.n[0] + l1];
                 }
@@ -792,7 +833,7 @@ k_interp_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
         int npj = 0;
         if (i < end) {
             nu0 = u0[i];
-            nu1 = u1[i];
+            if constexpr (DIM >= 2) nu1 = u1[i];
             if constexpr (DIM == 3) nu2 = u2[i];
             npj = perm[i];
         }
@@ -801,15 +842,24 @@ k_interp_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
             const int pj = npj;
             if (i + (int)blockDim.x < end) {
                 nu0 = u0[i + blockDim.x];
-                nu1 = u1[i + blockDim.x];
+                if constexpr (DIM >= 2) nu1 = u1[i + blockDim.x];
                 if constexpr (DIM == 3) nu2 = u2[i + blockDim.x];
                 npj = perm[i + blockDim.x];
             }
             T kx[W], ky[W];
             const int sx = taps<T, W>(x0 + (T)P, bk, kx);
-            const int sy = taps<T, W>(x1 + (T)P, bk, ky);
+            int sy = 0;
+            if constexpr (DIM >= 2) sy = taps<T, W>(x1 + (T)P, bk, ky);
             T ar = 0, ai = 0;
-            if constexpr (DIM == 2) {
+            if constexpr (DIM == 1) {
+                const C *row = tile + sx;
+#pragma unroll
+                for (int a1 = 0; a1 < W; ++a1) {
+                    const C v = row[a1];
+                    ar += v.x * kx[a1];
+                    ai += v.y * kx[a1];
+                }
+            } else if constexpr (DIM == 2) {
 #pragma unroll
                 for (int a2 = 0; a2 < W; ++a2) {
                     const C *row = tile + (sy + a2) * p1 + sx;
@@ -916,14 +966,20 @@ k_interp_grad(Geom g, int M, int ntransf, const uint32_t *__restrict__ key,
     const int bz = b;
     T kx[W], ky[W], dkx[W], dky[W];
     const int sx = taps_der<T, W>(u0[i], bk, beta, kx, dkx) + bx * g.m[0];
-    const int sy = taps_der<T, W>(u1[i], bk, beta, ky, dky) + by * g.m[1];
+    int sy = 0;
+    if constexpr (DIM >= 2) {
+        sy = taps_der<T, W>(u1[i], bk, beta, ky, dky) + by * g.m[1];
+    } else {
+        ky[0] = 1;  // one row, weight one
+        dky[0] = 0;
+    }
     T kz[W], dkz[W];
     int sz = 0;
     if constexpr (DIM == 3) sz = taps_der<T, W>(u2[i], bk, beta, kz, dkz) + bz * g.m[2];
     int lx[W];
 #pragma unroll
     for (int a = 0; a < W; ++a) lx[a] = wrap1(sx + a, g.n[0]);
-    const size_t ncell = (size_t)g.n[0] * g.n[1] * (DIM == 3 ? g.n[2] : 1);
+    const size_t ncell = (size_t)g.n[0] * (DIM >= 2 ? g.n[1] : 1) * (DIM == 3 ? g.n[2] : 1);
     const int j = perm[i];
     T acc[3] = {0, 0, 0};
     for (int t = 0; t < ntransf; ++t) {
@@ -939,8 +995,8 @@ k_interp_grad(Geom g, int M, int ntransf, const uint32_t *__restrict__ key,
                 plane = (size_t)wrap1(sz + a3, g.n[2]) * g.n[1];
             }
 #pragma unroll
-            for (int a2 = 0; a2 < W; ++a2) {
-                const C *row = gt + (plane + (size_t)wrap1(sy + a2, g.n[1])) * g.n[0];
+            for (int a2 = 0; a2 < (DIM >= 2 ? W : 1); ++a2) {
+                const C *row = gt + (plane + (DIM >= 2 ? (size_t)wrap1(sy + a2, g.n[1]) : 0)) * g.n[0];
                 T sr = 0, si = 0, xr = 0, xi = 0;  // sum b kx, sum b dkx along the row
 #pragma unroll
                 for (int a1 = 0; a1 < W; ++a1) {
@@ -952,8 +1008,10 @@ k_interp_grad(Geom g, int M, int ntransf, const uint32_t *__restrict__ key,
                 }
                 dr[0] += xr * ky[a2] * wz;
                 di[0] += xi * ky[a2] * wz;
-                dr[1] += sr * dky[a2] * wz;
-                di[1] += si * dky[a2] * wz;
+                if constexpr (DIM >= 2) {
+                    dr[1] += sr * dky[a2] * wz;
+                    di[1] += si * dky[a2] * wz;
+                }
                 if constexpr (DIM == 3) {
                     dr[2] += sr * ky[a2] * dwz;
                     di[2] += si * ky[a2] * dwz;
@@ -1004,13 +1062,15 @@ hipError_t spread_wb(const Geom &g, int method, const Pts &P, const void *c, voi
     using C = typename Cplx<T>::type;
     const T bk = kernel_param<T>(g.beta);
     if (method == 3) {
-        // the single-precision kernel scales per subproblem and needs no max|c|
-        if ((part & 4) && !std::is_same<T, float>::value) {
+        // the packed single-precision kernel (2D / 3D) scales per subproblem
+        // and needs no max|c|
+        constexpr bool packed = std::is_same<T, float>::value && DIM >= 2;
+        if ((part & 4) && !packed) {
             hipLaunchKernelGGL(k_maxabs<T>, dim3(std::max(1, std::min(cdiv(P.M, kThreads), kMaxParts))),
                                dim3(kThreads), 0, s, (const C *)c, P.M, (T *)P.cmax);
         }
         if (part & 1) {
-            if constexpr (std::is_same<T, float>::value) {
+            if constexpr (packed) {
                 auto pk = k_spread_smp<T, DIM, W, BATCH>;
                 if (lds > 65536)
                     (void)hipFuncSetAttribute((const void *)pk,
@@ -1042,7 +1102,7 @@ hipError_t spread_wb(const Geom &g, int method, const Pts &P, const void *c, voi
         const long long ncell = P.ncells;
         const int ggrid = (int)std::min<long long>((ncell + kThreads - 1) / kThreads, 16384);
         // (for a batch, P.kmax holds the largest table width over its transforms)
-        if (P.kmax[0] <= 2 && P.kmax[1] <= 2 && (DIM == 2 || P.kmax[2] <= 2)) {
+        if (P.kmax[0] <= 2 && (DIM == 1 || P.kmax[1] <= 2) && (DIM <= 2 || P.kmax[2] <= 2)) {
             hipLaunchKernelGGL((k_tile_gather2<T, DIM, BATCH>), dim3(std::max(ggrid, 1)),
                                dim3(kThreads), 0, s, g, P.suboff, (const T *)P.scratch, P.ts2,
                                P.G, P.cov[0], P.cov[1], P.cov[2], P.kmax[0], P.kmax[1],

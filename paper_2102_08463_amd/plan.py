@@ -30,13 +30,13 @@ def _need(t, dtype, device, what):
 
 
 class Plan:
-    """A 2D or 3D type 1, 2 or 3 NUFFT plan on one GPU.
+    """A 1D, 2D or 3D type 1, 2 or 3 NUFFT plan on one GPU.
 
     nufft_type   1 (nonuniform -> modes), 2 (modes -> nonuniform) or
                  3 (nonuniform points -> nonuniform frequencies)
-    n_modes      (N1, N2) or (N1, N2, N3); arrays of modes have shape
+    n_modes      (N1,), (N1, N2) or (N1, N2, N3); arrays of modes have shape
                  (..., N3, N2, N1), i.e. k1 fastest, modes ascending from -N/2.
-                 For type 3 the dimension (2 or 3) instead
+                 For type 3 the dimension (1, 2 or 3) instead
     n_trans      number of vectors sharing one set of points
     eps          requested relative l2 tolerance
     isign        sign of the exponent; default -1 for types 1 and 3, +1 for type 2
@@ -136,24 +136,30 @@ class Plan:
         return {name: (ms[i], cnt[i]) for i, name in enumerate(L.STAGES)}
 
     # -- points --------------------------------------------------------------
-    def setpts(self, x, y, z=None, s=None, t=None, u=None):
-        """Set the points (x, y[, z]); for type 3 also the frequencies (s, t[, u])."""
+    def setpts(self, x, y=None, z=None, s=None, t=None, u=None):
+        """Set the points (x[, y[, z]]); for type 3 also the frequencies (s[, t[, u]])."""
         if self.type == 3:
             return self._setpts3((x, y, z), (s, t, u))
         M = x.shape[0]
-        for t, nm in ((x, "x"), (y, "y")) + (((z, "z"),) if self.dim == 3 else ()):
-            _need(t, self.rdtype, self.device, nm)
-            if t.ndim != 1 or t.shape[0] != M:
-                raise ValueError("x, y (, z) must be 1-D of equal length")
-        if self.dim == 2 and z is not None:
-            raise ValueError("z given for a 2D plan")
-        rc = self._lib.mnufft_setpts(self._h, M, _ptr(x), _ptr(y),
-                                     _ptr(z) if self.dim == 3 else None)
+        given = (x, y, z)
+        for d, nm in enumerate("xyz"):
+            a = given[d]
+            if d >= self.dim:
+                if a is not None:
+                    raise ValueError(f"{nm} given for a {self.dim}D plan")
+                continue
+            _need(a, self.rdtype, self.device, nm)
+            if a.ndim != 1 or a.shape[0] != M:
+                raise ValueError("the coordinate arrays must be 1-D of equal length")
+        ptrs = [_ptr(a) if d < self.dim else None for d, a in enumerate(given)]
+        rc = self._lib.mnufft_setpts(self._h, M, *ptrs)
         L.check(rc, "mnufft_setpts")
         self.M = M
         return self
 
     def _setpts3(self, pts, freqs):
+        if any(a is not None for a in pts[self.dim:] + freqs[self.dim:]):
+            raise ValueError(f"coordinates given for an absent dimension of a {self.dim}D plan")
         pts, freqs = pts[: self.dim], freqs[: self.dim]
         if any(a is None for a in pts + freqs):
             raise ValueError(f"type 3 needs {self.dim} point and {self.dim} frequency arrays")
@@ -270,7 +276,7 @@ class Plan:
 
 
 def nufft_type1(points, c, n_modes, eps=1e-6, isign=-1, **kw):
-    """One-shot type 1: points = (x, y[, z]) real tensors, c complex (M,) or (T, M)."""
+    """One-shot type 1: points = (x[, y[, z]]) real tensors, c complex (M,) or (T, M)."""
     T = c.shape[0] if c.ndim == 2 else 1
     with Plan(1, n_modes, T, eps, isign, dtype=c.dtype, **kw) as p:
         p.setpts(*points)
