@@ -38,6 +38,8 @@ WORKLOADS = {
     "2d-cluster": (2, (1024, 1024), 10_000_000, "cluster", 1e-5, "f32"),
     "2d-small": (2, (64, 64), 100_000, "uniform", 1e-5, "f32"),
     "3d": (3, (128, 128, 128), 1 << 24, "uniform", 1e-5, "f32"),
+    # 1D (beyond the paper, Sec. I-B): 2^20 modes, 1e7 points
+    "1d": (1, (1 << 20,), 10_000_000, "uniform", 1e-5, "f32"),
     "3d-gauss": (3, (128, 128, 128), 1 << 24, "gaussian", 1e-5, "f32"),
     # one GPU's share of the 2D workload split over 8 GPUs (points sharded, full grid)
     "2d-shard": (2, (1024, 1024), 1_250_000, "uniform", 1e-5, "f32"),
@@ -227,24 +229,39 @@ def summarize_profiles(args):
             stats.append((_short_kernel(row["Name"]), int(row["Calls"]), float(row["AverageNs"]) / 1e3,
                           float(row["Percentage"])))
     stats.sort(key=lambda r: -r[3])
-    fetch, write = counters(args.fetch_dir), counters(args.write_dir)
-    cal_f = max(counters(args.cal_fetch_dir)["__amd_rocclr_copyBuffer"])
-    cal_w = max(counters(args.cal_write_dir)["__amd_rocclr_copyBuffer"])
-    kib = args.cal_mib * 1024.0
-    ff, fw = kib / cal_f, kib / cal_w
-    dim, modes, M, kind, eps, prec = WORKLOADS[args.workload]
-    rsz = 4 if prec == "f32" else 8
-    ncells = 1
-    for n in modes:
-        ncells *= 2 * n  # upsampling 2 (5-smooth sizes of these powers of two are 2N)
-    lines = [f"# {args.title}", "", f"Workload `{args.workload}`: {dim}D, modes {'x'.join(map(str, modes))}, "
-             f"M = {M} {kind} points, eps = {eps:g}, {prec}; one bench step = setpts + type 1 + "
-             f"type 2 (adjoint) with the library defaults.", "", "## Commands (repository root, GPU box)", "",
+    if args.workload in T3_WORKLOADS:
+        dim, M, K, xw, sw, eps, prec = T3_WORKLOADS[args.workload]
+        desc = (f"{dim}D type 3, M = {M} points uniform on [-{xw:g}, {xw:g})^{dim}, K = {K} "
+                f"frequencies uniform on [-{sw:g}, {sw:g})^{dim}, eps = {eps:g}, {prec}; one bench "
+                f"step = setpts3 + execute with the library defaults.")
+    else:
+        dim, modes, M, kind, eps, prec = WORKLOADS[args.workload]
+        desc = (f"{dim}D, modes {'x'.join(map(str, modes))}, M = {M} {kind} points, eps = "
+                f"{eps:g}, {prec}; one bench step = setpts + type 1 + type 2 (adjoint) with the "
+                f"library defaults.")
+    lines = [f"# {args.title}", "", f"Workload `{args.workload}`: {desc}", "",
+             "## Commands (repository root, GPU box)", "",
              "```"] + args.command + ["```", "",
              "## Kernel statistics (rocprofv3 --kernel-trace --stats)", "",
              "| kernel | calls | avg us | share % |", "|---|---|---|---|"]
     for name, calls, avg, pct in stats[:args.top]:
         lines.append(f"| `{name}` | {calls} | {avg:.1f} | {pct:.2f} |")
+    if not args.fetch_dir or args.workload in T3_WORKLOADS:
+        if args.note:
+            lines += ["", args.note]
+        with open(args.md_out, "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+        print(f"wrote {args.md_out}")
+        return
+    fetch, write = counters(args.fetch_dir), counters(args.write_dir)
+    cal_f = max(counters(args.cal_fetch_dir)["__amd_rocclr_copyBuffer"])
+    cal_w = max(counters(args.cal_write_dir)["__amd_rocclr_copyBuffer"])
+    kib = args.cal_mib * 1024.0
+    ff, fw = kib / cal_f, kib / cal_w
+    rsz = 4 if prec == "f32" else 8
+    ncells = 1
+    for n in modes:
+        ncells *= 2 * n  # upsampling 2 (5-smooth sizes of these powers of two are 2N)
     lines += ["", "## HBM traffic per launch (PMC, calibrated)", "",
               f"Calibration: a {args.cal_mib} MiB device copy reads FETCH_SIZE = {cal_f:.0f} KiB and "
               f"WRITE_SIZE = {cal_w:.0f} KiB per launch, so the factors are {ff:.3f} (fetch) and "
@@ -423,7 +440,7 @@ def main():
     dominant = max(("spread", "interp"), key=lambda k: stages[k][0])
     algo = algorithmic_bytes(dominant, dim, M, ncells, rsz)
     achieved = algo / (kern_ms[dominant] * 1e-3) / 1e9
-    sm_spread = "k_spread_smp" if prec == "f32" else "k_spread_sm"
+    sm_spread = "k_spread_smp" if prec == "f32" and dim >= 2 else "k_spread_sm"
     kernel_name = {"spread": sm_spread if info["method"] == 3 else "k_spread_gm",
                    "interp": "k_interp_sm" if info["method"] == 3 else "k_interp_gm"}[dominant]
     traffic = load_traffic(kernel_name, args.workload) \
