@@ -1,4 +1,4 @@
-"""Differentiable type 1 / type 2 transforms (torch.autograd.Function).
+"""Differentiable 1D / 2D / 3D type 1 / type 2 transforms (torch.autograd.Function).
 
 Backward passes run in the library:
   type 2, c = A(x) f:  grad_f = A^H g       (adjoint execute: type 1, sign -s)
@@ -22,11 +22,11 @@ def _points(ctx_pts, dim):
 class _Type2(torch.autograd.Function):
     @staticmethod
     def forward(ctx, f, eps, isign, method, x, y, z):
-        dim = 2 if z is None else 3
+        dim = 1 if y is None else (2 if z is None else 3)
         n_modes = tuple(f.shape[-dim:][::-1])
         T = f.shape[0] if f.ndim == dim + 1 else 1
         plan = Plan(2, n_modes, T, eps, isign, dtype=f.dtype, method=method, device=f.device)
-        pts = [x.detach(), y.detach()] + ([z.detach()] if dim == 3 else [])
+        pts = [p.detach() for p in (x, y, z)[:dim]]
         plan.setpts(*[p.contiguous() for p in pts])
         fc = f.detach().contiguous()
         c = plan.execute(fc)
@@ -43,9 +43,8 @@ class _Type2(torch.autograd.Function):
         gf = plan.execute_adjoint(gc).reshape(fc.shape) if ctx.needs_input_grad[0] else None
         gx = gy = gz = None
         if any(ctx.needs_input_grad[4:4 + ctx.dim]):
-            gr = plan.interp_grad(fc, gc)
-            gx, gy = gr[0], gr[1]
-            gz = gr[2] if ctx.dim == 3 else None
+            gr = list(plan.interp_grad(fc, gc)) + [None] * (3 - ctx.dim)
+            gx, gy, gz = gr
         return gf, None, None, None, gx, gy, gz
 
 
@@ -55,7 +54,7 @@ class _Type1(torch.autograd.Function):
         dim = len(n_modes)
         T = c.shape[0] if c.ndim == 2 else 1
         plan = Plan(1, n_modes, T, eps, isign, dtype=c.dtype, method=method, device=c.device)
-        pts = [x.detach(), y.detach()] + ([z.detach()] if dim == 3 else [])
+        pts = [p.detach() for p in (x, y, z)[:dim]]
         plan.setpts(*[p.contiguous() for p in pts])
         cc = c.detach().contiguous()
         f = plan.execute(cc)
@@ -72,20 +71,19 @@ class _Type1(torch.autograd.Function):
         gc = plan.execute_adjoint(gf).reshape(cc.shape) if ctx.needs_input_grad[0] else None
         gx = gy = gz = None
         if any(ctx.needs_input_grad[5:5 + ctx.dim]):
-            gr = plan.interp_grad(gf, cc)
-            gx, gy = gr[0], gr[1]
-            gz = gr[2] if ctx.dim == 3 else None
+            gr = list(plan.interp_grad(gf, cc)) + [None] * (3 - ctx.dim)
+            gx, gy, gz = gr
         return gc, None, None, None, None, gx, gy, gz
 
 
 def nufft_type2(points, f, eps=1e-6, isign=+1, method="auto"):
-    """Differentiable type 2: c_j = sum_k f_k exp(isign i k.x_j), w.r.t. f and the points."""
-    z = points[2] if len(points) == 3 else None
-    return _Type2.apply(f, eps, isign, method, points[0], points[1], z)
+    """Differentiable type 2: c_j = sum_k f_k exp(isign i k.x_j), w.r.t. f and the points
+    (points = (x,), (x, y) or (x, y, z))."""
+    p = list(points) + [None] * (3 - len(points))
+    return _Type2.apply(f, eps, isign, method, p[0], p[1], p[2])
 
 
 def nufft_type1(points, c, n_modes, eps=1e-6, isign=-1, method="auto"):
     """Differentiable type 1: f_k = sum_j c_j exp(isign i k.x_j), w.r.t. c and the points."""
-    z = points[2] if len(points) == 3 else None
-    return _Type1.apply(c, tuple(int(n) for n in n_modes), eps, isign, method,
-                        points[0], points[1], z)
+    p = list(points) + [None] * (3 - len(points))
+    return _Type1.apply(c, tuple(int(n) for n in n_modes), eps, isign, method, p[0], p[1], p[2])

@@ -6,8 +6,10 @@
 //   paper_2102_08463_amd/microbench        (built by build.py)
 //
 // LDS: 2048 workgroups x 256 threads, each lane walks an address stream in a
-// 32 KB LDS array (consecutive lanes on consecutive words; random words; or
-// sorted runs where about 2.4 lanes share a word, like points sorted by cell),
+// 32 KB LDS array (consecutive lanes on consecutive words; random words;
+// sorted runs where about 2.4 lanes share a word, like points sorted by cell;
+// or groups of 8 lanes on 8 consecutive words at a random base per group,
+// all 8 or only 6 of them active, like one row of taps per point),
 // 8 operations per step, 512 steps; the rate is lane-operations per clock per
 // CU at 2.4 GHz and 256 CUs.  Every address is masked into the array.
 // HBM: 1e7 items, a random permutation p and its inverse q; out[p[i]] = in[i]
@@ -31,7 +33,8 @@ __device__ __forceinline__ uint32_t mix(uint32_t x)
 }
 
 // MODE 0 f32 atomic, 1 u32 atomic, 2 u64 atomic, 3 u32 read, 4 u64 read.
-// PAT 0 consecutive, 1 random, 2 sorted runs with repeats.
+// PAT 0 consecutive, 1 random, 2 sorted runs with repeats, 3 random groups of
+// 8 consecutive words, 4 the same with lanes 6 and 7 of each group idle.
 template <int MODE, int PAT>
 __global__ void __launch_bounds__(256) k_lds(float *out, int salt)
 {
@@ -41,15 +44,20 @@ __global__ void __launch_bounds__(256) k_lds(float *out, int salt)
     for (int i = threadIdx.x; i < kWords; i += 256) lu[i] = 0;
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const uint32_t r = mix(threadIdx.x * 7919u + salt), st = (mix(threadIdx.x + 99u * salt) | 1u) & 1023u;
-    const uint32_t off = PAT == 0 ? lane + wv * 1024 : (PAT == 1 ? r : (lane * 27u) / 64u + wv * 1024);
+    constexpr bool grouped = PAT >= 3;
+    const uint32_t who = grouped ? threadIdx.x >> 3 : threadIdx.x;
+    const uint32_t r = mix(who * 7919u + salt), st = (mix(who + 99u * salt) | 1u) & 1023u;
+    const uint32_t off = PAT == 0 ? lane + wv * 1024
+                         : (PAT == 1 ? r : (grouped ? r + (lane & 7) : (lane * 27u) / 64u + wv * 1024));
+    const bool active = PAT != 4 || (lane & 7) < 6;
     unsigned long long acc = 0;
 #pragma unroll 1
     for (int it = 0; it < kSteps; ++it) {
-        const uint32_t base = PAT == 1 ? off + it * st : off + it * 97u;
+        const uint32_t base = (PAT == 1 || grouped) ? off + it * st : off + it * 97u;
+        if (!active) continue;
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const uint32_t a = (base + u * (PAT == 1 ? 613u : 38u)) & (kWords - 1);
+            const uint32_t a = (base + u * ((PAT == 1 || grouped) ? 613u : 38u)) & (kWords - 1);
             if (MODE == 0) atomicAdd(&lf[a], 1.0f);
             else if (MODE == 1) atomicAdd(&l32[a], 1u);
             else if (MODE == 2) atomicAdd(&lu[a], 1ull);
@@ -76,7 +84,7 @@ void run_lds(float *d, const char *name)
     (void)hipEventSynchronize(e1);
     float ms = 0;
     (void)hipEventElapsedTime(&ms, e0, e1);
-    const double ops = 5.0 * blocks * 256.0 * kSteps * 8;
+    const double ops = 5.0 * blocks * 256.0 * kSteps * 8 * (PAT == 4 ? 0.75 : 1.0);
     printf("lds  %-26s %6.2f lane-ops/clk/CU\n", name, ops / (ms * 1e-3) / 256.0 / 2.4e9);
 }
 
@@ -107,10 +115,12 @@ int main()
     run_lds<1, 2>(d, "u32 atomic sorted runs");
     run_lds<2, 0>(d, "u64 atomic consecutive"); run_lds<2, 1>(d, "u64 atomic random");
     run_lds<2, 2>(d, "u64 atomic sorted runs");
+    run_lds<2, 3>(d, "u64 atomic 8-word groups"); run_lds<2, 4>(d, "u64 atomic 6-of-8 groups");
     run_lds<0, 0>(d, "f32 atomic consecutive"); run_lds<0, 1>(d, "f32 atomic random");
     run_lds<3, 0>(d, "u32 read consecutive"); run_lds<3, 1>(d, "u32 read random");
     run_lds<4, 0>(d, "u64 read consecutive"); run_lds<4, 1>(d, "u64 read random");
     run_lds<4, 2>(d, "u64 read sorted runs");
+    run_lds<4, 3>(d, "u64 read 8-word groups"); run_lds<4, 4>(d, "u64 read 6-of-8 groups");
     (void)hipFree(d);
 
     const int n = 10000000;

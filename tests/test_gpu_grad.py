@@ -79,6 +79,23 @@ def test_gradcheck_fp64_tiny():
     assert torch.autograd.gradcheck(fn, (x, y, f), eps=1e-6, atol=1e-6, rtol=1e-5)
 
 
+def test_gradcheck_fp64_tiny_1d():
+    """torch's finite-difference gradcheck of the 1D type 1 and type 2 wrappers."""
+    import torch
+    from paper_2102_08463_amd.autograd import nufft_type1, nufft_type2
+    note("gradcheck tiny 1d")
+    R = np.random.default_rng(43)
+    x = torch.tensor(R.uniform(-3, 3, 12), dtype=torch.float64, device="cuda", requires_grad=True)
+    f = torch.tensor(R.standard_normal(7) + 1j * R.standard_normal(7),
+                     dtype=torch.complex128, device="cuda", requires_grad=True)
+    c = torch.tensor(R.standard_normal(12) + 1j * R.standard_normal(12),
+                     dtype=torch.complex128, device="cuda", requires_grad=True)
+    assert torch.autograd.gradcheck(lambda xx, ff: nufft_type2((xx,), ff, eps=1e-13), (x, f),
+                                    eps=1e-6, atol=1e-6, rtol=1e-5)
+    assert torch.autograd.gradcheck(lambda xx, cc: nufft_type1((xx,), cc, (9,), eps=1e-13),
+                                    (x, c), eps=1e-6, atol=1e-6, rtol=1e-5)
+
+
 def test_diff_3d_spiral_64cubed():
     """Differentiable 3D type 2, 64^3 complex64 modes, M = 4e6 points on a stack
     of spirals with N(0, 1e-3) jitter, eps 1e-5, fp32: gradients w.r.t. modes
