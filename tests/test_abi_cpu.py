@@ -62,6 +62,7 @@ def _makeplan(type_=1, dim=2, nm=(16, 16, 1), iflag=-1, ntr=1, eps=1e-6, prec=0,
     dict(type_=3, iflag=0), dict(type_=3, ntr=0), dict(dim=0), dict(type_=3, dim=0), dict(dim=4), dict(iflag=0), dict(iflag=2),
     dict(ntr=0), dict(eps=0.0), dict(eps=1.0), dict(eps=-1e-3), dict(eps=float("nan")),
     dict(prec=2), dict(nm=(0, 16, 1)), dict(nm=(16, -1, 1)), dict(dim=3, nm=(8, 8, 0)),
+    dict(dim=1, nm=((1 << 24) + 1, 1, 1)),
 ])
 def test_makeplan_rejects_bad_arguments(kw):
     rc, h = _makeplan(**kw)

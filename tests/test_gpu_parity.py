@@ -317,3 +317,55 @@ def test_upsampling_below_two(dim, prec, eps, sigma):
     assert inf["upsampfac"] == sigma
     assert inf["nfine"][:dim] == [oparams.fine_grid_size(k, inf["w"], sigma=sigma) for k in N]
     p.destroy()
+
+
+# ---------------------------------------------------------------------------
+# widest kernels: w = 14, 15, 16 (eps 1e-13 .. 1e-15, double precision) in 2D
+# and 3D, where the default 3D bins shrink so the padded tiles fit in LDS; the
+# error floor there is the rounding of the sums, not eps.
+@pytest.mark.parametrize("dim,eps", [(2, 1e-13), (2, 1e-15), (3, 1e-14), (3, 1e-15)])
+def test_widest_kernels_fp64(dim, eps):
+    note(f"widest kernels {dim}d eps {eps}")
+    N = (40, 36) if dim == 2 else (16, 20, 18)
+    M = 6_000 if dim == 2 else 3_000
+    pts64, pts = make_points("uniform", M, dim, "f64", seed=21)
+    p = _plan(1, N, eps=eps, dtype=cdtype("f64"))
+    w = p.info()["w"]
+    p.destroy()
+    assert w == {1e-13: 14, 1e-14: 15, 1e-15: 16}[eps]
+    tol = max(10 * eps, 2e-13)
+    assert _type1_check(pts64, pts, N, "f64", eps) <= tol
+    assert _type2_check(pts64, pts, N, "f64", eps) <= tol
+
+
+def test_width_clamp_warning():
+    """eps beyond the widest kernel: the plan is made at w = 16 (f64) / 8 (f32)
+    and the status says the width was capped."""
+    import torch
+    from paper_2102_08463_amd import lib as L
+    note("width clamp")
+    p = _plan(1, (32, 32), eps=1e-17, dtype=torch.complex128)
+    assert p.status == L.WARN_EPS_CLAMPED and p.info()["w"] == 16
+    p.destroy()
+    q = _plan(2, (32, 32), eps=1e-9, dtype=torch.complex64)
+    assert q.status == L.WARN_EPS_CLAMPED and q.info()["w"] == 8
+    q.destroy()
+
+
+def test_largest_1d_mode_count():
+    """N = 2^24, the largest mode count a dimension accepts (fine grid 2^25):
+    sampled modes of a type 1 against the exact sum."""
+    import torch
+    note("1d N=2^24")
+    N, M = 1 << 24, 2_000_000
+    pts64, pts = make_points("uniform", M, 1, "f32", seed=22)
+    c64, c = make_complex(M, "f32", seed=23)
+    p = _plan(1, (N,), eps=1e-5, dtype=torch.complex64)
+    assert p.info()["nfine"][0] == 1 << 25
+    p.setpts(*pts)
+    f = p.execute(c).cpu().numpy()
+    p.destroy()
+    ks = np.sort(np.random.default_rng(24).choice(N, 24, replace=False))
+    ks = np.concatenate([ks, [0, N - 1]])
+    ex = direct.type1(pts64, c64, (N,), kk=(ks - N // 2,))
+    assert rel_l2(f[ks], ex) <= 1e-4
