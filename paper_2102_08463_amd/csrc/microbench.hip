@@ -32,7 +32,8 @@ __device__ __forceinline__ uint32_t mix(uint32_t x)
     return x;
 }
 
-// MODE 0 f32 atomic, 1 u32 atomic, 2 u64 atomic, 3 u32 read, 4 u64 read.
+// MODE 0 f32 atomic, 1 u32 atomic, 2 u64 atomic, 3 u32 read, 4 u64 read,
+// 5 128-bit read (two adjacent u64 words at an even word address).
 // PAT 0 consecutive, 1 random, 2 sorted runs with repeats, 3 random groups of
 // 8 consecutive words, 4 the same with lanes 6 and 7 of each group idle.
 template <int MODE, int PAT>
@@ -62,7 +63,11 @@ __global__ void __launch_bounds__(256) k_lds(float *out, int salt)
             else if (MODE == 1) atomicAdd(&l32[a], 1u);
             else if (MODE == 2) atomicAdd(&lu[a], 1ull);
             else if (MODE == 3) acc += l32[a];
-            else acc += lu[a];
+            else if (MODE == 4) acc += lu[a];
+            else {
+                const ulonglong2 v = *reinterpret_cast<const ulonglong2 *>(&lu[a & ~1u]);
+                acc += v.x + v.y;
+            }
         }
     }
     __syncthreads();
@@ -121,6 +126,7 @@ int main()
     run_lds<4, 0>(d, "u64 read consecutive"); run_lds<4, 1>(d, "u64 read random");
     run_lds<4, 2>(d, "u64 read sorted runs");
     run_lds<4, 3>(d, "u64 read 8-word groups"); run_lds<4, 4>(d, "u64 read 6-of-8 groups");
+    run_lds<5, 0>(d, "u128 read consecutive"); run_lds<5, 1>(d, "u128 read random");
     (void)hipFree(d);
 
     const int n = 10000000;
