@@ -226,6 +226,16 @@ int mnufft_get_sort(mnufft_plan p, int32_t *perm, int32_t *binstart);
  * records in use.  Errors: ERR_STATE, ERR_HIP. */
 int mnufft_get_subproblems(mnufft_plan p, int32_t *sub, int32_t *nsub);
 
+/* Move the plan to another stream (hipStream_t; NULL = the null stream): every
+ * later call is ordered on it; ordering against work already enqueued on the
+ * old stream is the caller's.  The call also creates the FFT plan of the
+ * direction not used so far, so that afterwards mnufft_execute and
+ * mnufft_execute_adjoint enqueue kernels only (no allocation, no host
+ * synchronisation) and can be captured into a HIP graph once each has run
+ * eagerly.  A type 3 plan moves its inner plans too; mnufft_setpts3 itself
+ * synchronises and is not capturable.  Errors: ERR_ARG, ERR_ALLOC, ERR_FFT. */
+int mnufft_set_stream(mnufft_plan p, void *stream);
+
 /* Describe the plan (host memory).  Errors: ERR_ARG. */
 int mnufft_get_info(mnufft_plan p, mnufft_info *info);
 

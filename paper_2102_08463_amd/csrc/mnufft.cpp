@@ -1023,6 +1023,25 @@ int mnufft_get_subproblems(mnufft_plan p, int32_t *sub, int32_t *nsub)
     return MNUFFT_OK;
 }
 
+int mnufft_set_stream(mnufft_plan p, void *stream)
+{
+    if (!p) return MNUFFT_ERR_ARG;
+    int rc = use_device(p);
+    if (rc) return rc;
+    // both FFT directions exist from here on, so execute / execute_adjoint
+    // allocate nothing and can be captured into a graph
+    for (mnufft_plan q : {p, p->t3inner}) {
+        if (!q || !q->fftinfo) continue;
+        if ((rc = make_fft(q, 0)) || (rc = make_fft(q, 1))) return rc;
+    }
+    for (mnufft_plan q : {p, p->t3spr, p->t3inner}) {
+        if (!q) continue;
+        q->stream = (hipStream_t)stream;
+        q->opts.stream = stream;
+    }
+    return MNUFFT_OK;
+}
+
 int mnufft_set_timing(mnufft_plan p, int enable)
 {
     if (!p) return MNUFFT_ERR_ARG;

@@ -27,7 +27,7 @@ EXPORTS = (
     "mnufft_get_sort",
     "mnufft_get_subproblems", "mnufft_get_info", "mnufft_destroy", "mnufft_strerror",
     "mnufft_choose_params", "mnufft_choose_params_sigma", "mnufft_correction_factors",
-    "mnufft_set_timing", "mnufft_get_timing",
+    "mnufft_set_timing", "mnufft_get_timing", "mnufft_set_stream",
     "mnufft_batch_makeplan", "mnufft_batch_setpts", "mnufft_batch_execute",
     "mnufft_batch_set_timing", "mnufft_batch_get_timing", "mnufft_batch_get_totals",
     "mnufft_batch_destroy", "mnufft_tune_candidates", "mnufft_tune_time",
@@ -117,6 +117,7 @@ def load():
     L.mnufft_correction_factors.argtypes = [i64, i64, ci, ctypes.c_double,
                                             ctypes.POINTER(ctypes.c_double)]
     L.mnufft_set_timing.argtypes = [vp, ci]
+    L.mnufft_set_stream.argtypes = [vp, vp]
     L.mnufft_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(i64), ci]
     i32p = ctypes.POINTER(ctypes.c_int32)

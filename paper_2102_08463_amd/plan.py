@@ -123,6 +123,14 @@ class Plan:
     def mode_shape(self):
         return tuple(self.n_modes[::-1])
 
+    def set_stream(self, stream):
+        """Order the plan's later work on `stream` (a torch.cuda.Stream); after
+        one eager call of each direction, execute / execute_adjoint can be
+        captured into a CUDA/HIP graph on that stream."""
+        L.check(self._lib.mnufft_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)),
+                "mnufft_set_stream")
+        self._stream = stream
+
     def set_timing(self, enable=True):
         """Turn the library's per-stage HIP-event timers on or off."""
         L.check(self._lib.mnufft_set_timing(self._h, int(bool(enable))), "mnufft_set_timing")
