@@ -31,6 +31,10 @@ if ROOT not in sys.path:
 
 METRIC = "NU points/sec at eps=1e-5 (2D/3D, type 1/2); batched vs plain speedup"
 HBM_PEAK_GBS = 8000.0
+# LDS 64-bit atomic ceiling at random addresses, measured on this GPU by the
+# library's microbenchmark (paper_2102_08463_amd/csrc/microbench.hip):
+# 4.97 lane-ops per clock and CU x 256 CUs x 2.4 GHz.
+LDS_U64_ATOMIC_PEAK = 4.97 * 256 * 2.4e9
 
 WORKLOADS = {
     # name: (dim, modes, M, point kind, eps, precision)
@@ -437,6 +441,11 @@ def main():
     rsz = 4 if prec == "f32" else 8
     ncells = int(np.prod(info["nfine"][:dim]))
     kern_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
+    per_step = {k: v[0] / K for k, v in stages.items()}
+    setpts_ms = per_step["setpts"]
+    t1_ms = (per_step["zero"] + per_step["scale"] + per_step["spread"] + per_step["addback"]
+             + per_step["deconv"] + per_step["fft"] / 2)
+    t2_ms = per_step["precorrect"] + per_step["interp"] + per_step["fft"] / 2
     dominant = max(("spread", "interp"), key=lambda k: stages[k][0])
     algo = algorithmic_bytes(dominant, dim, M, ncells, rsz)
     achieved = algo / (kern_ms[dominant] * 1e-3) / 1e9
@@ -479,14 +488,18 @@ def main():
             "avg_launch_ms": kern_ms[dominant],
         },
         "stage_ms_per_step": {k: v[0] / K for k, v in stages.items()},
-        "exec_pts_per_s": {
-            "type1": M / ((stages["zero"][0] + stages["scale"][0] + stages["spread"][0]
-                           + stages["addback"][0]
-                           + stages["deconv"][0] + stages["fft"][0] / 2) / K * 1e-3),
-            "type2": M / ((stages["precorrect"][0] + stages["interp"][0]
-                           + stages["fft"][0] / 2) / K * 1e-3),
-        },
+        "exec_pts_per_s": {"type1": M / (t1_ms * 1e-3), "type2": M / (t2_ms * 1e-3)},
+        "total_pts_per_s": {"type1": M / ((setpts_ms + t1_ms) * 1e-3),
+                            "type2": M / ((setpts_ms + t2_ms) * 1e-3)},
     }
+    if info["method"] == 3 and kern_ms["spread"] > 0:
+        # one 64-bit LDS atomic per tap (two per tap for the two-word accumulator)
+        words = 1 if (prec == "f32" and dim >= 2) else 2
+        ops = M * info["w"] ** dim * words
+        rate = ops / (kern_ms["spread"] * 1e-3)
+        out["lds_atomic"] = {"kernel": sm_spread, "ops_per_launch": ops, "achieved": rate,
+                             "peak": LDS_U64_ATOMIC_PEAK, "unit": "ops/s",
+                             "frac": rate / LDS_U64_ATOMIC_PEAK}
     if not args.no_batched:
         print("[bench] batched vs plain (64 transforms)", file=sys.stderr, flush=True)
         runs = [batched_speedup(kind, ntype) for kind, ntype in
