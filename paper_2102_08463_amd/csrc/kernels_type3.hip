@@ -16,6 +16,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace mn {
 namespace {
 
@@ -29,6 +31,25 @@ struct Planes {
     const void *p[3];
 };
 
+// (cos ph, sin ph) for a phase formed in double.  Double precision plans
+// evaluate it in double; single precision plans reduce ph by whole turns in
+// double (exact to about 1e-16 ph) and take the single-precision sine and
+// cosine of the remainder in [-pi, pi], which is all a float result keeps.
+template <typename T>
+__device__ __forceinline__ void unit_phase(double ph, double &sn, double &cs)
+{
+    if constexpr (std::is_same<T, double>::value) {
+        sincos(ph, &sn, &cs);
+    } else {
+        const double turns = rint(ph * 0.15915494309189535);  // ph / (2 pi), rounded
+        const float r = (float)fma(-turns, 6.283185307179586, ph);
+        float s, c;
+        sincosf(r, &s, &c);
+        sn = s;
+        cs = c;
+    }
+}
+
 // Per block and dimension: (min, max, 1 if a value is non-finite else 0).
 template <typename T>
 __global__ void __launch_bounds__(kT3Threads)
@@ -38,10 +59,19 @@ k_t3_bounds(int n, int dim, Planes a, double *__restrict__ part)
     for (int d = 0; d < dim; ++d) {
         const T *v = static_cast<const T *>(a.p[d]);
         double lo = INFINITY, hi = -INFINITY, bad = 0.0;
-        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-            const double x = (double)v[i];
-            if (!isfinite(x)) bad = 1.0;
-            else { lo = fmin(lo, x); hi = fmax(hi, x); }
+        // four independent loads in flight per thread and step
+        constexpr int U = 4;
+        const int stride = gridDim.x * blockDim.x;
+        for (int i0 = blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += U * stride) {
+            T x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) x[u] = i0 + u * stride < n ? v[i0 + u * stride] : v[i0];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const double xv = (double)x[u];
+                if (!isfinite(xv)) bad = 1.0;
+                else { lo = fmin(lo, xv); hi = fmax(hi, xv); }
+            }
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
@@ -83,7 +113,7 @@ k_t3_prephase(int n, int dim, Planes x, T3Affine af, int sg,
     for (int d = 0; d < dim; ++d)
         ph += af.mul[d] * ((double)static_cast<const T *>(x.p[d])[i] - af.off[d]);
     double sn, cs;
-    sincos((double)sg * ph, &sn, &cs);
+    unit_phase<T>((double)sg * ph, sn, cs);
     typename C2<T>::type v;
     v.x = (T)cs;
     v.y = (T)sn;
@@ -116,9 +146,10 @@ k_t3_postfac(int n, int dim, Planes s, T3Affine af, int sg, int w,
         }
         lsum += cheb[1] + u * b1 - b2;
     }
-    const double fac = pow(2.0 / (double)w, (double)dim) * exp(-lsum);
+    double fac = exp(-lsum);
+    for (int d = 0; d < dim; ++d) fac *= 2.0 / (double)w;
     double sn, cs;
-    sincos((double)sg * ph, &sn, &cs);
+    unit_phase<T>((double)sg * ph, sn, cs);
     typename C2<T>::type v;
     v.x = (T)(fac * cs);
     v.y = (T)(fac * sn);
