@@ -1,4 +1,4 @@
-"""MI355X-native 2D/3D nonuniform FFTs (types 1 and 2, and 3) after cuFINUFFT.
+"""MI355X-native 1D/2D/3D nonuniform FFTs (types 1, 2 and 3) after cuFINUFFT.
 
 The transforms run in libmnufft.so (hand-written HIP kernels for gfx950 plus
 rocFFT for the fine-grid FFT) behind the C ABI in include/mnufft.h; this
