@@ -178,3 +178,27 @@ def test_type3_full_size_sampled():
     assert rel_l2(f[idx], ex) <= 1e-4
     p.destroy()
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("method,sigma", [("gmsort", 2.0), ("gm", 2.0), ("sm", 1.25), ("sm", 1.5)])
+def test_type3_methods_and_upsampling(method, sigma):
+    """The inner plans follow the plan's method and upsampling factor; the oracle's
+    type 3 steps take the same sigma."""
+    note(f"type3 method {method} sigma {sigma}")
+    M, K, eps = 10_000, 1_500, 1e-9
+    x64, xd, s64, sd = _sets(M, K, 2, "f64", seed=61, xc=-0.5, xw=3.0, sc=4.0, sw=30.0)
+    c64, c = make_complex(M, "f64", seed=62)
+    p, f = _run(2, "f64", eps, -1, xd, sd, c, method=method, upsampfac=sigma)
+    assert rel_l2(f, direct.type3(x64, c64, s64, iflag=-1)) <= 10 * eps
+    if method == "sm":
+        # Same steps as the oracle, so the two agree far below eps.  The SM
+        # spread accumulates in 64-bit fixed point (quantum msub max|c| 2^-62
+        # per contribution, about 100 double roundings), and the kernel
+        # transform's fall-off, phi_hat(0) / phi_hat(edge) ~ 1.5e3 per dimension
+        # at sigma = 1.25 and w = 15, magnifies grid noise up to ~2e6 at the
+        # corner frequencies; there the agreement is 1e-9 of the largest output
+        # (still below eps), elsewhere 1e-12.
+        ref = onufft.type3(x64, c64, s64, eps, iflag=-1, sigma=sigma)
+        tol = 1e-12 if sigma >= 1.5 else 2e-9
+        assert np.max(np.abs(f - ref)) <= tol * np.max(np.abs(ref))
+    p.destroy()
