@@ -292,13 +292,14 @@ __device__ __forceinline__ T block_cmax(const T *__restrict__ parts)
 // The LDS accumulator is 64-bit fixed point: on gfx950 integer LDS atomics
 // (ds_add_u64) sustain roughly ten times the rate of floating-point ones.
 // This kernel serves double precision and 1D single precision (2D / 3D single
-// precision uses k_spread_smp, one word per cell, whose per-subproblem scale
-// is too coarse for 1D bins: a 1D subproblem spreads many points over few
-// taps each, so its strength sum overstates every cell's by far).  Every contribution v = c_j * phi * phi is turned into
-// round(v * S) with S = 2^62 / (2^ceil(log2 msub) 2^ceil(log2 cmax)),
-// cmax = max_j max(|Re c_j|, |Im c_j|): a cell gets at most msub
-// contributions of size <= cmax, so the sum stays below 2^62, with quantum
-// about msub cmax 2^-62.
+// precision uses k_spread_smp, one word per cell, whose scale bounds a cell by
+// the subproblem's whole strength sum; a 1D subproblem of thousands of points,
+// each touching only w cells, would overstate every cell by far).  Every
+// contribution v = c_j * phi * phi is turned into round(v * S) with
+// S = 2^62 / (2^ceil(log2 n_q) 2^ceil(log2 cmax)), n_q <= msub the points of
+// subproblem q and cmax = max_j max(|Re c_j|, |Im c_j|): a cell gets at most
+// n_q contributions of size <= cmax, so the sum stays below 2^62, with quantum
+// about n_q cmax 2^-62.
 // Grid-stride loop over the subproblem list; the tile is interleaved
 // (re, im) with ts2 >= 2 p1 p2 p3 entries per slot (a multiple of 8).
 template <typename T> struct FixedScale;
@@ -338,10 +339,15 @@ k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
     constexpr int P = (W + 1) / 2;
     const int nvec = ts2 / NV;
     const int nsub = *nsubp;
-    T inv;
-    const T S = FixedScale<T>::scale(block_cmax(cmaxp), lg_msub, inv);
+    const T cmax = block_cmax(cmaxp);
     for (int q = blockIdx.x; q < nsub; q += gridDim.x) {
         const int4 rec = reinterpret_cast<const int4 *>(sub)[q];
+        // a cell gets at most one contribution per point of the subproblem,
+        // so its own point count (<= msub) bounds the sum
+        int lg = 0;
+        while ((1 << lg) < rec.z && lg < lg_msub) ++lg;
+        T inv;
+        const T S = FixedScale<T>::scale(cmax, lg, inv);
         int p1 = g.m[0] + 2 * P, p2 = g.m[1] + 2 * P;
         if constexpr (BATCH) {
             const TGeom &tt =
