@@ -186,6 +186,35 @@ def batched_speedup(kind="uniform", ntype=1, reps=3, eps=1e-6):
             "speedup": t_plain / (t_batch + sel_ms)}
 
 
+def sorted_order_kernels(plan, modes, pts, c, f, eps, cdt, args, dim, M, ncells, rsz, reps=10):
+    """Spreading and interpolation kernel times when the strengths / results
+    are kept in bin-sorted order (mnufft_execute_sorted), with the HBM
+    fraction on the same algorithmic bytes: what a caller that reuses the
+    points and keeps its vectors sorted gets."""
+    from paper_2102_08463_amd import Plan
+    perm, _ = plan.get_sort()
+    cs = c[perm.long()].contiguous()
+    p2 = Plan(2, modes, 1, eps, 1, dtype=cdt, method=args.method,
+              binsize=tuple(int(v) for v in args.binsize.split(",")) if args.binsize else None,
+              msub=args.msub, upsampfac=args.upsampfac)
+    p2.setpts(*pts)
+    res = {}
+    for name, pl, x, stage in (("spread", plan, cs, "spread"), ("interp", p2, f, "interp")):
+        pl.execute_sorted(x)
+        pl.timing(reset=True)
+        pl.set_timing(True)
+        for _ in range(reps):
+            pl.execute_sorted(x)
+        st = pl.timing(reset=True)
+        pl.set_timing(False)
+        ms = st[stage][0] / max(st[stage][1], 1)
+        algo = algorithmic_bytes(stage, dim, M, ncells, rsz)
+        res[f"{name}_ms"] = ms
+        res[f"{name}_frac"] = algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+    p2.destroy()
+    return res
+
+
 def _short_kernel(name):
     """'void mn::detail::k_x<float, 2>(args)' -> 'k_x<float, 2>'."""
     name = name.strip().strip('"')
@@ -500,6 +529,9 @@ def main():
         out["lds_atomic"] = {"kernel": sm_spread, "ops_per_launch": ops, "achieved": rate,
                              "peak": LDS_U64_ATOMIC_PEAK, "unit": "ops/s",
                              "frac": rate / LDS_U64_ATOMIC_PEAK}
+    if info["method"] == 3:
+        out["sorted_order"] = sorted_order_kernels(plan, modes, pts, c, f, eps, cdt, args,
+                                                   dim, M, ncells, rsz)
     if not args.no_batched:
         print("[bench] batched vs plain (64 transforms)", file=sys.stderr, flush=True)
         runs = [batched_speedup(kind, ntype) for kind, ntype in

@@ -177,6 +177,17 @@ int mnufft_setpts3(mnufft_plan p, int64_t M, const void *x, const void *y, const
  * Errors: ERR_STATE (no setpts), ERR_ARG (NULL pointer with M > 0), ERR_HIP, ERR_FFT. */
 int mnufft_execute(mnufft_plan p, void *c, void *f);
 
+/* mnufft_execute with the point-indexed array c in bin-sorted order instead
+ * of the caller's point order: c[t][i] belongs to the point at sorted
+ * position i, i.e. to input point perm[i] (mnufft_get_sort).  Spreading then
+ * reads, and interpolation writes, c contiguously instead of through the
+ * permutation, which is what bounds those kernels for random points; a
+ * caller that applies the transform many times to the same points (an
+ * iterative solver) can keep its vectors in this order.  Results equal
+ * mnufft_execute's bit for bit after the permutation.  Errors as
+ * mnufft_execute; ERR_UNSUPPORTED for type 3 and method GM (no sort). */
+int mnufft_execute_sorted(mnufft_plan p, void *c, void *f);
+
 /* Apply the adjoint of the plan's operator on the same sorted points: the
  * other type with the opposite sign (type 2 is the adjoint of type 1, Sec. I).
  * Same array roles as mnufft_execute with the directions swapped: for a

@@ -93,7 +93,7 @@ struct Pts {
     int M;
     const void *u[3];        // bin-relative coordinates g_i - binstart_i (plan precision), sorted
     const uint32_t *key;     // bin index per sorted point
-    const int32_t *perm;     // sorted position -> input index
+    const int32_t *perm;     // sorted position -> input index; null: c in sorted order
     const int32_t *binstart; // nbins + 1
     const int32_t *sub;      // subproblem records (bin, start, len, 0)
     const int32_t *nsub;     // device count of records

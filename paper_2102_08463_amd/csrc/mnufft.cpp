@@ -275,10 +275,12 @@ size_t grid_bytes(mnufft_plan p) { return p->grid_elems * 2 * p->rsz; }
 // precision in 1D) needs max |c| before the tile kernel.
 bool needs_cmax(mnufft_plan p) { return p->prec == MNUFFT_F64 || p->dim == 1; }
 
-// Step 1 of type 1 for all ntransf vectors: c (ntransf x M) -> p->grid.
-int spread_all(mnufft_plan p, const void *c)
+// Step 1 of type 1 for all ntransf vectors: c (ntransf x M) -> p->grid; c in
+// bin-sorted order when `sorted`.
+int spread_all(mnufft_plan p, const void *c, bool sorted = false)
 {
-    const mn::Pts P = points_of(p);
+    mn::Pts P = points_of(p);
+    if (sorted) P.perm = nullptr;
     if (p->method != MNUFFT_METHOD_SM) {  // SM writes every cell itself
         StageTimer tm(p->tm, MNUFFT_STAGE_ZERO, p->stream);
         MN_HIP(mn::launch_zero(p->grid, grid_bytes(p) * p->ntransf, p->stream));
@@ -306,9 +308,9 @@ int spread_all(mnufft_plan p, const void *c)
 }
 
 // Type 1 with exponent sign `sign`: c (ntransf x M) -> f (ntransf x N).
-int exec_type1(mnufft_plan p, int sign, const void *c, void *f)
+int exec_type1(mnufft_plan p, int sign, const void *c, void *f, bool sorted = false)
 {
-    int rc = spread_all(p, c);
+    int rc = spread_all(p, c, sorted);
     if (rc) return rc;
     {
         StageTimer tm(p->tm, MNUFFT_STAGE_FFT, p->stream);
@@ -321,10 +323,12 @@ int exec_type1(mnufft_plan p, int sign, const void *c, void *f)
     return MNUFFT_OK;
 }
 
-// Type 2 with exponent sign `sign`: f (ntransf x N) -> c (ntransf x M).
-int exec_type2(mnufft_plan p, int sign, const void *f, void *c)
+// Type 2 with exponent sign `sign`: f (ntransf x N) -> c (ntransf x M); c in
+// bin-sorted order when `sorted`.
+int exec_type2(mnufft_plan p, int sign, const void *f, void *c, bool sorted = false)
 {
-    const mn::Pts P = points_of(p);
+    mn::Pts P = points_of(p);
+    if (sorted) P.perm = nullptr;
     {
         StageTimer tm(p->tm, MNUFFT_STAGE_PRECORRECT, p->stream);
         MN_HIP(mn::launch_precorrect(p->dim, p->N, p->g.n, p->prec, (int)p->ntransf, f,
@@ -939,6 +943,17 @@ int mnufft_execute(mnufft_plan p, void *c, void *f)
     if (!f || (p->M > 0 && !c)) return MNUFFT_ERR_ARG;
     if ((rc = use_device(p))) return rc;
     return p->type == 1 ? exec_type1(p, p->iflag, c, f) : exec_type2(p, p->iflag, f, c);
+}
+
+int mnufft_execute_sorted(mnufft_plan p, void *c, void *f)
+{
+    int rc = check_ready(p);
+    if (rc) return rc;
+    if (p->type == 3 || p->method == MNUFFT_METHOD_GM) return MNUFFT_ERR_UNSUPPORTED;
+    if (!f || (p->M > 0 && !c)) return MNUFFT_ERR_ARG;
+    if ((rc = use_device(p))) return rc;
+    return p->type == 1 ? exec_type1(p, p->iflag, c, f, true)
+                        : exec_type2(p, p->iflag, f, c, true);
 }
 
 int mnufft_execute_adjoint(mnufft_plan p, void *c, void *f)

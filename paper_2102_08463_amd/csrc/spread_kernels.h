@@ -10,6 +10,10 @@
 // l sits at l h - pi) touches, per dimension, the w cells l0 .. l0 + w - 1
 // with l0 = ceil(g - w/2) and weights phi(2 (l - g) / w).
 //
+// Strengths (spreading) and results (interpolation) are in the caller's point
+// order, reached through the sort permutation; with a null permutation they
+// are in bin-sorted order instead (mnufft_execute_sorted).
+//
 // Methods (Sec. III-A / III-B):
 //   GM      one thread per point in input order, global atomics
 //   GMSORT  one thread per point in bin-sorted order, global atomics
@@ -103,7 +107,8 @@ __device__ __forceinline__ void gadd(T *p, T v) { unsafeAtomicAdd(p, v); }
 
 // ----------------------------------------------------------------------------
 // GM / GM-sort spreading: thread i handles point i of the given order.
-// perm == nullptr means input order (GM).
+// c is read at perm[i]; perm == nullptr reads c[i], i.e. c in the order of
+// the coordinate arrays given (input order for GM, sorted order otherwise).
 template <typename T, int DIM, int W>
 __global__ void __launch_bounds__(kThreads)
 k_spread_gm(Geom g, int M, const uint32_t *__restrict__ key, const T *__restrict__ u0,
@@ -363,7 +368,7 @@ k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
             const int sx = taps<T, W>(u0[i] + (T)P, bk, kx);
             int sy = 0;
             if constexpr (DIM >= 2) sy = taps<T, W>(u1[i] + (T)P, bk, ky);
-            const auto cv = c[perm[i]];
+            const auto cv = c[perm ? perm[i] : i];
             const T cr0 = cv.x * S, ci0 = cv.y * S;
             if constexpr (DIM == 1) {
                 unsigned long long *row = tile + 2 * sx;
@@ -478,7 +483,7 @@ k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict_
 #pragma unroll
             for (int k = 0; k < kPre; ++k) {
                 const int i = i0 + k * kThreads;
-                pj[k] = i < end ? perm[i] : -1;
+                pj[k] = i < end ? (perm ? perm[i] : i) : -1;
             }
 #pragma unroll
             for (int k = 0; k < kPre; ++k) {
@@ -512,7 +517,9 @@ k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict_
         float nu0 = 0.f, nu1 = 0.f, nu2 = 0.f;
         float2 ncv = make_float2(0.f, 0.f);
         // strengths past the staged ones are gathered again
-        auto strength = [&](int ii) { return ii - rec.y < stage_cap ? cs[ii - rec.y] : c[perm[ii]]; };
+        auto strength = [&](int ii) {
+            return ii - rec.y < stage_cap ? cs[ii - rec.y] : c[perm ? perm[ii] : ii];
+        };
         if (i < end) {
             nu0 = u0[i];
             if constexpr (DIM >= 2) nu1 = u1[i];
@@ -841,7 +848,7 @@ k_interp_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
             nu0 = u0[i];
             if constexpr (DIM >= 2) nu1 = u1[i];
             if constexpr (DIM == 3) nu2 = u2[i];
-            npj = perm[i];
+            npj = perm ? perm[i] : i;
         }
         for (; i < end; i += blockDim.x) {
             const T x0 = nu0, x1 = nu1, x2 = nu2;
@@ -850,7 +857,7 @@ k_interp_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
                 nu0 = u0[i + blockDim.x];
                 if constexpr (DIM >= 2) nu1 = u1[i + blockDim.x];
                 if constexpr (DIM == 3) nu2 = u2[i + blockDim.x];
-                npj = perm[i + blockDim.x];
+                npj = perm ? perm[i + blockDim.x] : i + (int)blockDim.x;
             }
             T kx[W], ky[W];
             const int sx = taps<T, W>(x0 + (T)P, bk, kx);

@@ -23,6 +23,7 @@ METHODS = {"auto": METHOD_AUTO, "gm": METHOD_GM, "gmsort": METHOD_GMSORT, "sm": 
 # Every symbol the public header declares.
 EXPORTS = (
     "mnufft_default_opts", "mnufft_makeplan", "mnufft_setpts", "mnufft_setpts3", "mnufft_execute",
+    "mnufft_execute_sorted",
     "mnufft_execute_adjoint", "mnufft_interp_grad", "mnufft_spread", "mnufft_interp",
     "mnufft_get_sort",
     "mnufft_get_subproblems", "mnufft_get_info", "mnufft_destroy", "mnufft_strerror",
@@ -99,6 +100,7 @@ def load():
     L.mnufft_setpts.argtypes = [vp, i64, vp, vp, vp]
     L.mnufft_setpts3.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, vp]
     L.mnufft_execute.argtypes = [vp, vp, vp]
+    L.mnufft_execute_sorted.argtypes = [vp, vp, vp]
     L.mnufft_execute_adjoint.argtypes = [vp, vp, vp]
     L.mnufft_interp_grad.argtypes = [vp, vp, vp, vp, vp, vp]
     L.mnufft_spread.argtypes = [vp, vp, vp]

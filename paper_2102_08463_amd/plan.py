@@ -224,6 +224,13 @@ class Plan:
             return self._run(self._lib.mnufft_execute, data, None, "mnufft_execute")
         return self._run(self._lib.mnufft_execute, None, data, "mnufft_execute")
 
+    def execute_sorted(self, data):
+        """As execute, with the point-indexed side (c) in bin-sorted order:
+        c[..., i] belongs to input point perm[i] of get_sort()."""
+        if self.type == 1:
+            return self._run(self._lib.mnufft_execute_sorted, data, None, "mnufft_execute_sorted")
+        return self._run(self._lib.mnufft_execute_sorted, None, data, "mnufft_execute_sorted")
+
     def execute_adjoint(self, data):
         """Adjoint operator on the same points (other type, opposite sign)."""
         if self.type == 1:
