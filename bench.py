@@ -371,6 +371,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-plain speedup measurement")
+    ap.add_argument("--no-sorted", action="store_true",
+                    help="skip the sorted-order kernel measurement (profiling runs, so that "
+                         "every spread / interp launch is of the timed kind)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (reference for HBM counters)")
     ap.add_argument("--summarize-profiles", action="store_true",
@@ -529,7 +532,7 @@ def main():
         out["lds_atomic"] = {"kernel": sm_spread, "ops_per_launch": ops, "achieved": rate,
                              "peak": LDS_U64_ATOMIC_PEAK, "unit": "ops/s",
                              "frac": rate / LDS_U64_ATOMIC_PEAK}
-    if info["method"] == 3:
+    if info["method"] == 3 and not args.no_sorted:
         out["sorted_order"] = sorted_order_kernels(plan, modes, pts, c, f, eps, cdt, args,
                                                    dim, M, ncells, rsz)
     if not args.no_batched:
