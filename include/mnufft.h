@@ -309,6 +309,14 @@ int mnufft_choose_params_sigma(double eps, int prec, int64_t N, double sigma, in
  * beta <= 0, out NULL). */
 int mnufft_correction_factors(int64_t N, int64_t n, int w, double beta, double *out);
 
+/* Grid of the type 3 reduction for one dimension (see mnufft_setpts3): from
+ * the half-width X of the points and S of the frequencies, *nf = smallest even
+ * 2^a 3^b 5^c >= max(ceil(2 sigma S X / pi) + w + 1, 2w) and
+ * *gamma = nf / (2 sigma S), with S = 0 read as 1/X (1 if X = 0 too).  Host
+ * only; outputs are host pointers.  Errors: ERR_ARG (X or S negative or not a
+ * number, sigma outside [1.25, 2], w outside 2..16, nf above 2^24). */
+int mnufft_type3_grid(double X, double S, double sigma, int w, int64_t *nf, double *gamma);
+
 /* ---- autotuning ------------------------------------------------------- */
 
 /* The parameter sets the autotuner searches for a dimension, precision and

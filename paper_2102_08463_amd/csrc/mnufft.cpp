@@ -758,6 +758,19 @@ int mnufft_choose_params(double eps, int prec, int64_t N, int *w, double *beta, 
     return mnufft_choose_params_sigma(eps, prec, N, 2.0, w, beta, n);
 }
 
+int mnufft_type3_grid(double X, double S, double sigma, int w, int64_t *nf, double *gamma)
+{
+    if (!(X >= 0.0) || !(S >= 0.0) || !(sigma >= 1.25 && sigma <= 2.0) || w < 2 || w > 16 ||
+        !nf || !gamma)
+        return MNUFFT_ERR_ARG;
+    if (S == 0.0) S = X > 0.0 ? 1.0 / X : 1.0;
+    const double need = std::ceil(2.0 * sigma * S * X / kPi) + w + 1;
+    if (!(need <= (double)(1 << 24))) return MNUFFT_ERR_ARG;
+    *nf = smooth_even(std::max<int64_t>((int64_t)need, 2 * (int64_t)w));
+    *gamma = (double)*nf / (2.0 * sigma * S);
+    return MNUFFT_OK;
+}
+
 int mnufft_correction_factors(int64_t N, int64_t n, int w, double beta, double *out)
 {
     if (N < 1 || n <= N || w < 2 || w > 16 || !(beta > 0.0) || !out) return MNUFFT_ERR_ARG;
@@ -882,13 +895,9 @@ int mnufft_setpts3(mnufft_plan p, int64_t M, const void *x, const void *y, const
     for (int d = 0; d < dim; ++d) {
         p->C[d] = 0.5 * (xh[d] + xl[d]);
         p->D[d] = 0.5 * (sh[d] + sl[d]);
-        const double X = 0.5 * (xh[d] - xl[d]);
-        double S = 0.5 * (sh[d] - sl[d]);
-        if (S == 0.0) S = X > 0.0 ? 1.0 / X : 1.0;
-        const double need = std::ceil(2.0 * p->sigma * S * X / kPi) + w + 1;
-        if (!(need <= (double)(1 << 24))) return MNUFFT_ERR_ARG;  // space-bandwidth too large
-        nf[d] = smooth_even(std::max<int64_t>((int64_t)need, 2 * (int64_t)w));
-        p->gam[d] = (double)nf[d] / (2.0 * p->sigma * S);
+        rc = mnufft_type3_grid(0.5 * (xh[d] - xl[d]), 0.5 * (sh[d] - sl[d]), p->sigma, w, &nf[d],
+                               &p->gam[d]);
+        if (rc) return rc;  // space-bandwidth product too large
         p->hstep[d] = 2.0 * kPi / (double)nf[d];
     }
     if ((rc = make_t3_plans(p, nf))) return rc;

@@ -28,6 +28,7 @@ EXPORTS = (
     "mnufft_get_sort",
     "mnufft_get_subproblems", "mnufft_get_info", "mnufft_destroy", "mnufft_strerror",
     "mnufft_choose_params", "mnufft_choose_params_sigma", "mnufft_correction_factors",
+    "mnufft_type3_grid",
     "mnufft_set_timing", "mnufft_get_timing", "mnufft_set_stream",
     "mnufft_batch_makeplan", "mnufft_batch_setpts", "mnufft_batch_execute",
     "mnufft_batch_set_timing", "mnufft_batch_get_timing", "mnufft_batch_get_totals",
@@ -118,6 +119,8 @@ def load():
                                              ctypes.POINTER(i64)]
     L.mnufft_correction_factors.argtypes = [i64, i64, ci, ctypes.c_double,
                                             ctypes.POINTER(ctypes.c_double)]
+    L.mnufft_type3_grid.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, ci,
+                                    ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
     L.mnufft_set_timing.argtypes = [vp, ci]
     L.mnufft_set_stream.argtypes = [vp, vp]
     L.mnufft_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double),

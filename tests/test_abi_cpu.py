@@ -187,3 +187,33 @@ def test_batch_makeplan_rejects_bad_arguments():
     assert lib.mnufft_batch_destroy(ctypes.c_void_p(0)) == L.OK
     assert lib.mnufft_batch_setpts(ctypes.c_void_p(0), None, None, None) == L.ERR_ARG
     assert lib.mnufft_batch_execute(ctypes.c_void_p(0), None, None) == L.ERR_ARG
+
+
+def test_type3_grid_matches_oracle():
+    """The library's type 3 grid rule (host helper used by mnufft_setpts3)
+    against the oracle's type3_params on the same half-widths."""
+    from oracle import nufft as onufft
+    lib = L.load()
+    R = np.random.default_rng(5)
+    nf = ctypes.c_int64(0)
+    gam = ctypes.c_double(0.0)
+    cases = [(math.pi, 512.0), (0.0, 3.0), (2.5, 0.0), (0.0, 0.0), (40.0, 1.5), (1e-3, 7e4)]
+    cases += [(float(R.uniform(0, 50)), float(R.uniform(0, 300))) for _ in range(40)]
+    for X, S in cases:
+        for sigma in (2.0, 1.5, 1.25):
+            for w in (2, 6, 13, 16):
+                assert lib.mnufft_type3_grid(X, S, sigma, w, ctypes.byref(nf), ctypes.byref(gam)) == L.OK
+                # one dimension with points on [C - X, C + X], frequencies on [D - S, D + S]
+                pts, frq = (np.array([1.0 - X, 1.0 + X]),), (np.array([-2.0 - S, -2.0 + S]),)
+                C, D, g, h, n = onufft.type3_params(pts, frq, w, sigma)[0]
+                assert nf.value == n, (X, S, sigma, w)
+                assert gam.value == pytest.approx(g, rel=1e-15)
+
+
+def test_type3_grid_rejects():
+    lib = L.load()
+    nf = ctypes.c_int64(0)
+    gam = ctypes.c_double(0.0)
+    for args in ((-1.0, 1.0, 2.0, 6), (1.0, -1.0, 2.0, 6), (float("nan"), 1.0, 2.0, 6),
+                 (1.0, 1.0, 1.0, 6), (1.0, 1.0, 2.0, 1), (1.0, 1.0, 2.0, 17), (1e6, 1e6, 2.0, 6)):
+        assert lib.mnufft_type3_grid(*args, ctypes.byref(nf), ctypes.byref(gam)) == L.ERR_ARG, args
