@@ -304,7 +304,7 @@ def summarize_profiles(args):
     avg_us = {}
     for name, calls, avg, pct in stats:
         avg_us.setdefault(name.split("<")[0], avg)
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = args.traffic_out or os.path.join(ROOT, "profiles", "traffic.json")
     table = json.load(open(path)) if os.path.exists(path) else {}
     for k in args.kernels.split(","):
         if k not in fetch or k not in write:
@@ -386,6 +386,8 @@ def main():
     ap.add_argument("--cal-mib", type=int, default=256)
     ap.add_argument("--kernels", default="k_spread_smp,k_interp_sm")
     ap.add_argument("--md-out")
+    ap.add_argument("--traffic-out", default=None,
+                    help="per-launch traffic table to update (default profiles/traffic.json)")
     ap.add_argument("--title", default="Kernel times and HBM traffic (MI355X)")
     ap.add_argument("--command", action="append", default=[])
     ap.add_argument("--note", default="")

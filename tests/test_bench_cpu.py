@@ -1,0 +1,67 @@
+"""Host-side checks of bench.py that need no GPU: the one-GPU rule, the
+algorithmic byte count behind the roofline line, and the rocprofv3 summary
+(calibrated traffic) on a small synthetic set of profiler CSV files."""
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_algorithmic_bytes():
+    # 2D fp32: per point 2 coordinates + permutation + complex strength = 20 B, grid 8 B per cell
+    assert bench.algorithmic_bytes("spread", 2, 10_000_000, 2048 * 2048, 4) == \
+        10_000_000 * 20 + 2048 * 2048 * 8
+    # 3D fp64: 3 x 8 + 4 + 16 = 44 B per point, 16 B per cell
+    assert bench.algorithmic_bytes("interp", 3, 1000, 64 ** 3, 8) == 1000 * 44 + 64 ** 3 * 16
+
+
+def _write(path, header, rows):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def test_summarize_profiles_calibrates_traffic(tmp_path):
+    d = str(tmp_path)
+    spread = "void mn::detail::k_spread_smp<float, 2, 6, false>(mn::Geom, int const*)"
+    interp = "void mn::detail::k_interp_sm<float, 2, 6, false>(mn::Geom, int const*)"
+    _write(f"{d}/stats/run_kernel_stats.csv", ["Name", "Calls", "AverageNs", "Percentage"],
+           [[spread, 2, 250000, 40.0], [interp, 2, 240000, 38.0]])
+    cc = ["Kernel_Name", "Counter_Value"]
+    _write(f"{d}/fetch/run_counter_collection.csv", cc, [[spread, 600000], [spread, 600000],
+                                                          [interp, 100000]])
+    _write(f"{d}/write/run_counter_collection.csv", cc, [[spread, 40000], [interp, 300000]])
+    # a 256 MiB copy reads half its bytes on FETCH_SIZE and all on WRITE_SIZE
+    _write(f"{d}/cf/run_counter_collection.csv", cc, [["__amd_rocclr_copyBuffer", 131072]])
+    _write(f"{d}/cw/run_counter_collection.csv", cc, [["__amd_rocclr_copyBuffer", 262144]])
+    traffic = f"{d}/traffic.json"
+    md = f"{d}/summary.md"
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--summarize-profiles",
+                        "--stats-dir", f"{d}/stats", "--fetch-dir", f"{d}/fetch",
+                        "--write-dir", f"{d}/write", "--cal-fetch-dir", f"{d}/cf",
+                        "--cal-write-dir", f"{d}/cw", "--workload", "2d", "--md-out", md,
+                        "--traffic-out", traffic], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    t = json.load(open(traffic))
+    e = t["2d:k_spread_smp"]
+    assert e["cal_fetch"] == pytest.approx(2.0) and e["cal_write"] == pytest.approx(1.0)
+    assert e["bytes_per_launch"] == pytest.approx((600000 * 2.0 + 40000) * 1024)
+    assert e["source_hash"] == bench.kernel_source_hash()
+    assert t["2d:k_interp_sm"]["bytes_per_launch"] == pytest.approx((100000 * 2.0 + 300000) * 1024)
+    text = open(md).read()
+    assert "k_spread_smp<float, 2, 6, false>" in text and "250.0" in text
