@@ -217,3 +217,33 @@ def test_type3_grid_rejects():
     for args in ((-1.0, 1.0, 2.0, 6), (1.0, -1.0, 2.0, 6), (float("nan"), 1.0, 2.0, 6),
                  (1.0, 1.0, 1.0, 6), (1.0, 1.0, 2.0, 1), (1.0, 1.0, 2.0, 17), (1e6, 1e6, 2.0, 6)):
         assert lib.mnufft_type3_grid(*args, ctypes.byref(nf), ctypes.byref(gam)) == L.ERR_ARG, args
+
+
+@pytest.mark.parametrize("dim,prec,eps", [(2, 0, 1e-6), (2, 1, 1e-12), (3, 0, 1e-5), (3, 1, 1e-9)])
+def test_tune_candidates_fixed_order_and_lds_fit(dim, prec, eps):
+    """The autotuner's candidate list (host only): SM bin shapes x msub in a
+    fixed order, each within the 160 KB of LDS per workgroup, then GM-sort
+    and GM; msub values from {256, 1024, 4096, 16384}."""
+    lib = L.load()
+    cands = L.tune_candidates(dim, prec, eps)
+    assert len(cands) == lib.mnufft_tune_candidates(dim, prec, eps, None, 0)
+    methods = [o.method for o in cands]
+    assert methods[-2:] == [L.METHOD_GMSORT, L.METHOD_GM]
+    assert all(m == L.METHOD_SM for m in methods[:-2]) and len(methods) > 2
+    w = oparams.kernel_width(eps, wmax=8 if prec == 0 else 16)
+    P = (w + 1) // 2
+    seen = set()
+    for o in cands[:-2]:
+        m = [o.binsize[d] for d in range(dim)]
+        assert o.msub in (256, 1024, 4096, 16384)
+        cells = int(np.prod([mi + 2 * P for mi in m]))
+        rs = 4 if prec == 0 else 8
+        # interpolation stages the padded bin as complex values; spreading needs at most
+        # two 64-bit words per cell plus (single precision) a staging area of strengths
+        assert cells * 2 * rs <= 160 * 1024
+        key = (tuple(m), o.msub)
+        assert key not in seen
+        seen.add(key)
+    # the same list on every call
+    assert [L.describe(o) for o in L.tune_candidates(dim, prec, eps)] == \
+        [L.describe(o) for o in cands]
