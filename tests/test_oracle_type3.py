@@ -179,3 +179,28 @@ def test_type3_taps_stay_inside_grid(eps):
             first = np.ceil(g - w / 2)
             assert first.min() >= 0 and (first + w - 1).max() <= nf - 1
             assert np.abs(h * gam * (sd - D)).max() <= math.pi / 2 + 1e-12
+
+
+def test_1d_spread_interp_are_transposes():
+    M, n, w, beta = 500, 64, 7, 16.1
+    x = (R.uniform(-math.pi, math.pi, M),)
+    c, g = _cplx(M), _cplx(n)
+    a = np.vdot(direct.spread(x, c, (n,), w, beta), g)
+    b = np.vdot(c, direct.interp(x, g, w, beta))
+    assert abs(a - b) <= 1e-12 * abs(a)
+
+
+def test_1d_single_point_footprint_by_brute_force():
+    """One point spreads exp(beta (sqrt(1 - z^2) - 1)), z = 2 (l - g) / w, onto
+    exactly the w cells l0 .. l0 + w - 1 with l0 = ceil(g - w/2), wrapped."""
+    n, w = 40, 6
+    beta = params.kernel_beta(w)
+    for xv in (-math.pi, -3.0, 0.1234, 2.9, math.pi - 1e-9):
+        grid = direct.spread((np.array([xv]),), np.array([1.0 + 0j]), (n,), w, beta)
+        g = (xv + math.pi) * n / (2 * math.pi)
+        ref = np.zeros(n)
+        for l in range(-n, 2 * n):
+            z = 2.0 * (l - g) / w
+            if l >= math.ceil(g - w / 2) and l < math.ceil(g - w / 2) + w and abs(z) <= 1:
+                ref[l % n] += math.exp(beta * (math.sqrt(1 - z * z) - 1))
+        assert np.allclose(grid.real, ref, rtol=0, atol=1e-14) and np.all(grid.imag == 0)
