@@ -31,10 +31,6 @@ if ROOT not in sys.path:
 
 METRIC = "NU points/sec at eps=1e-5 (2D/3D, type 1/2); batched vs plain speedup"
 HBM_PEAK_GBS = 8000.0
-# LDS 64-bit atomic ceiling at random addresses, measured on this GPU by the
-# library's microbenchmark (paper_2102_08463_amd/csrc/microbench.hip):
-# 4.97 lane-ops per clock and CU x 256 CUs x 2.4 GHz.
-LDS_U64_ATOMIC_PEAK = 4.97 * 256 * 2.4e9
 
 WORKLOADS = {
     # name: (dim, modes, M, point kind, eps, precision)
@@ -97,33 +93,88 @@ def load_traffic(kernel, workload):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(pts64, c64, f64, modes, eps, sample):
+def load_counters(kernel, workload):
+    """Counter-derived utilisation (VALU busy, LDS busy, LDS bank-conflict
+    stall, occupancy) of one kernel from profiles/counters.json, if taken on
+    the current kernel source; None otherwise."""
+    path = os.path.join(ROOT, "profiles", "counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    e = d.get(f"{workload}:{kernel}")
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return {k: e[k] for k in ("valu_busy", "lds_util", "lds_bank_conflict", "occupancy",
+                              "valu_insts_per_cu_cycle") if k in e}
+
+
+def cpu_model():
+    """The host CPU's model string (first 'model name' of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(data, sample, sample_1core):
     """Time the oracle (plain FP64 three-step NUFFT: C/OpenMP spreading and
-    interpolation, scipy FFT) on the first `sample` points: one type 1 and
-    one type 2, like one GPU step."""
+    interpolation, scipy FFT) on the first `sample` points with all host
+    threads, and on the first `sample_1core` points with one thread: one
+    type 1 and one type 2 each, like one GPU step."""
     from oracle import direct, nufft as onufft
-    sub = tuple(a[:sample] for a in pts64)
-    t0 = time.perf_counter()
-    onufft.type1(sub, c64[:sample], modes, eps, iflag=-1)
-    onufft.type2(sub, f64, eps, iflag=+1)
-    dt = time.perf_counter() - t0
-    return {"value": 2 * sample / dt, "unit": "NU points/s", "cores": direct.num_threads(),
-            "kind": "oracle",
-            "sample": f"first {sample} of the same points, one type 1 + one type 2 "
-                      f"(same modes and eps), FP64, {dt:.2f} s wall"}
+    pts64, c64, f64 = data["pts64"], data["c64"], data["f64"]
+    modes, eps = data["modes"], data["eps"]
+    nall = direct.num_threads()
+
+    def run(n, threads):
+        direct.set_threads(threads)
+        sub = tuple(a[:n] for a in pts64)
+        t0 = time.perf_counter()
+        onufft.type1(sub, c64[:n], modes, eps, iflag=-1, workers=threads)
+        onufft.type2(sub, f64, eps, iflag=+1, workers=threads)
+        return time.perf_counter() - t0
+
+    M = len(c64)
+    n = min(sample, M)
+    print(f"[bench] timing the oracle on {n} points, {nall} threads", file=sys.stderr, flush=True)
+    dt = run(n, nall)
+    n1 = min(sample_1core, M)
+    print(f"[bench] timing the oracle on {n1} points, 1 thread", file=sys.stderr, flush=True)
+    dt1 = run(n1, 1)
+    direct.set_threads(nall)
+    model = cpu_model()
+    return {"value": 2 * n / dt, "unit": "NU points/s", "cores": nall, "kind": "oracle",
+            "cpu": model,
+            "sample": f"first {n} of the same points ({data['workload']} workload), one type 1 + "
+                      f"one type 2 (same modes and eps), FP64, {nall} threads (C loops and FFT), "
+                      f"{dt:.2f} s wall",
+            "one_core": {"value": 2 * n1 / dt1, "unit": "NU points/s", "cores": 1,
+                         "sample": f"first {n1} of the same points, one type 1 + one type 2, "
+                                   f"one thread, {dt1:.2f} s wall"}}
 
 
-SELECTOR_WEIGHTS = os.path.join(ROOT, "paper_2102_08463_amd", "data", "selector_2d_f32_1e-06.npz")
+SELECTOR_WEIGHTS = os.path.join(ROOT, "paper_2102_08463_amd", "data", "selector_2d_f32_1e-06.bin")
 
 
-def batched_speedup(kind="uniform", ntype=1, reps=3, eps=1e-6):
+def batched_speedup(kind="uniform", ntype=1, reps=3, eps=1e-6, autotune=False):
     """Batched workload: 64 2D transforms, modes uniform in {64..512}^2, M
-    lognormal (median 2e5, 1e4..4e6), fp32, eps 1e-6.  Plain: one plan per
-    transform with the library defaults, setpts + execute each, in sequence.
-    Batched: one Batch whose per-transform bins / msub come from the learned
-    selector (batched density features + MLP inference, timed and included);
-    without trained weights the defaults are used.  Plan creation is excluded
-    from both.  Returns a dict of times and the speedup."""
+    lognormal (median 2e5, 1e4..4e6), fp32, eps 1e-6.
+      plain            one plan per transform with the library defaults,
+                       setpts + execute each, in sequence
+      batched_default  one Batch with the library's default bins and msub
+      batched_selected one Batch with the learned selector's bins and msub
+                       (mnufft_batch_select: batched density features, one
+                       network pass and the argmin on the device), the
+                       selection time included in its speedup
+      batched_autotuned (autotune=True) one Batch with the autotuner's picks
+                       per transform, its speedup given with and without the
+                       search time
+    Plan creation is excluded throughout."""
     import numpy as np
     import torch
 
@@ -150,6 +201,7 @@ def batched_speedup(kind="uniform", ntype=1, reps=3, eps=1e-6):
         return e0.elapsed_time(e1) / n, out
 
     plans = [Plan(ntype, nm, 1, eps, None, dtype=torch.complex64) for nm in n_modes]
+
     def plain():
         for p, x, d in zip(plans, pts, data):
             p.setpts(*x)
@@ -160,30 +212,44 @@ def batched_speedup(kind="uniform", ntype=1, reps=3, eps=1e-6):
 
     cat = [torch.cat([x[d] for x in pts]) for d in range(2)]
     dcat = torch.cat(data)
-    sel_ms, choice = 0.0, None
-    binsize = msub = None
+
+    def run_batch(binsize, msub):
+        b = Batch(ntype, n_modes, n_points, eps=eps, binsize=binsize, msub=msub)
+
+        def batched():
+            b.setpts(*cat)
+            b.execute(dcat)
+        t, _ = timed(batched, reps)
+        b.destroy()
+        return t
+
+    out = {"transforms": len(n_modes), "points": int(sum(n_points)), "kind": kind, "type": ntype,
+           "plain_ms": t_plain, "batched_default_ms": run_batch(None, None)}
+    out["speedup_defaults"] = t_plain / out["batched_default_ms"]
     if os.path.exists(SELECTOR_WEIGHTS):
-        from paper_2102_08463_amd.selector import Selector
-        sel = Selector.load(SELECTOR_WEIGHTS)
-        sm = [i for i, o in enumerate(sel.cands) if o.method == L.METHOD_SM]
-        def select():
-            feats = sel.features_batch(ntype, n_modes, cat[0], cat[1], n_points)
-            _, _, Y = sel.forward(feats)
-            y = Y.cpu().numpy()
-            return [min(sm, key=lambda i: y[t][i]) for t in range(len(n_modes))]
-        sel_ms, choice = timed(select, reps)
-        binsize = [tuple(sel.cands[i].binsize[:2]) for i in choice]
-        msub = [sel.cands[i].msub for i in choice]
-    b = Batch(ntype, n_modes, n_points, eps=eps, binsize=binsize, msub=msub)
-    def batched():
-        b.setpts(*cat)
-        b.execute(dcat)
-    t_batch, _ = timed(batched, reps)
-    b.destroy()
-    return {"transforms": len(n_modes), "points": int(sum(n_points)), "kind": kind,
-            "type": ntype, "plain_ms": t_plain, "batched_ms": t_batch, "selector_ms": sel_ms,
-            "selector": "learned" if choice is not None else "defaults",
-            "speedup": t_plain / (t_batch + sel_ms)}
+        L.selector_load(SELECTOR_WEIGHTS)
+        sel_t = []
+        for _ in range(reps + 1):
+            t0 = time.perf_counter()
+            bins, msub, src = L.batch_select(ntype, n_modes, n_points, cat[0], cat[1], eps,
+                                             mode="learned")
+            sel_t.append((time.perf_counter() - t0) * 1e3)
+        out["selector_ms"] = float(np.median(sel_t[1:]))
+        out["selector_fallbacks"] = int(sum(src))
+        out["batched_selected_ms"] = run_batch(bins, msub)
+        out["speedup"] = t_plain / (out["batched_selected_ms"] + out["selector_ms"])
+    else:
+        out["speedup"] = out["speedup_defaults"]
+    if autotune:
+        t0 = time.perf_counter()
+        bins, msub, _ = L.batch_select(ntype, n_modes, n_points, cat[0], cat[1], eps,
+                                       mode="autotune")
+        out["autotune_search_ms"] = (time.perf_counter() - t0) * 1e3
+        out["batched_autotuned_ms"] = run_batch(bins, msub)
+        out["speedup_autotuned"] = t_plain / out["batched_autotuned_ms"]
+        out["speedup_autotuned_with_search"] = t_plain / (out["batched_autotuned_ms"] +
+                                                          out["autotune_search_ms"])
+    return out
 
 
 def sorted_order_kernels(plan, modes, pts, c, f, eps, cdt, args, dim, M, ncells, rsz, reps=10):
@@ -279,6 +345,8 @@ def summarize_profiles(args):
              "| kernel | calls | avg us | share % |", "|---|---|---|---|"]
     for name, calls, avg, pct in stats[:args.top]:
         lines.append(f"| `{name}` | {calls} | {avg:.1f} | {pct:.2f} |")
+    if args.sq_dir:
+        lines += sq_summary(args, counters_raw(args.sq_dir), stats)
     if not args.fetch_dir or args.workload in T3_WORKLOADS:
         if args.note:
             lines += ["", args.note]
@@ -329,6 +397,70 @@ def summarize_profiles(args):
     print(f"wrote {args.md_out} and {path}")
 
 
+# Counter instances summed into one value per dispatch by rocprofv3: the
+# graphics-block activity counter is reported once per XCD.
+XCDS = 8
+CUS = 256
+
+
+def counters_raw(d):
+    """{kernel: {counter: [values per dispatch]}} from a --pmc run's CSV."""
+    import csv
+    import glob
+    per = {}
+    for f in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+        for row in csv.DictReader(open(f)):
+            per.setdefault(_base_kernel(row["Kernel_Name"]), {}).setdefault(
+                row["Counter_Name"], []).append(float(row["Counter_Value"]))
+    return per
+
+
+def sq_fractions(c):
+    """Utilisation of one kernel from its SQ counters (averages per dispatch):
+    VALU busy = SQ_ACTIVE_INST_VALU / (CUs x cycles), LDS busy =
+    SQ_LDS_IDX_ACTIVE / (CUs x cycles), bank-conflict stall =
+    SQ_LDS_BANK_CONFLICT / (CUs x cycles), occupancy = resident waves over
+    the 32 a CU can hold (SQ_WAVE_CYCLES counted in quad-cycles), with cycles
+    the kernel's GRBM_GUI_ACTIVE of one XCD (the CSV sums the XCDs)."""
+    a = {k: sum(v) / len(v) for k, v in c.items()}
+    cyc = a["GRBM_GUI_ACTIVE"] / XCDS
+    out = {"cycles": cyc,
+           "valu_busy": a["SQ_ACTIVE_INST_VALU"] / (CUS * cyc),
+           "valu_insts_per_cu_cycle": a["SQ_INSTS_VALU"] / (CUS * cyc),
+           "lds_util": a["SQ_LDS_IDX_ACTIVE"] / (CUS * cyc),
+           "lds_bank_conflict": a["SQ_LDS_BANK_CONFLICT"] / (CUS * cyc)}
+    if "SQ_WAVE_CYCLES" in a:
+        out["occupancy"] = 4.0 * a["SQ_WAVE_CYCLES"] / (cyc * CUS * 32)
+    return out
+
+
+def sq_summary(args, raw, stats):
+    """Markdown rows of the SQ fractions per kernel; records them in the
+    counters table (profiles/counters.json) for the spread / interp kernels."""
+    lines = ["", "## Utilisation from SQ counters (rocprofv3 --pmc)", "",
+             "Fractions of the kernel's active cycles (GRBM_GUI_ACTIVE of one XCD) summed "
+             "over the 256 CUs: VALU busy (SQ_ACTIVE_INST_VALU), VALU wave-instructions "
+             "issued per CU and cycle (one is the issue limit), LDS busy (SQ_LDS_IDX_ACTIVE), "
+             "cycles the LDS stalled on bank conflicts (SQ_LDS_BANK_CONFLICT), and occupancy "
+             "(resident waves / 32 per CU, from SQ_WAVE_CYCLES).", "",
+             "| kernel | VALU busy | VALU insts / CU / cycle | LDS busy | LDS bank-conflict "
+             "stall | occupancy |", "|---|---|---|---|---|---|"]
+    path = args.counters_out or os.path.join(ROOT, "profiles", "counters.json")
+    table = json.load(open(path)) if os.path.exists(path) else {}
+    for k in args.kernels.split(",") + ["k_tile_gather2", "k_radix_scatter", "k_binkey"]:
+        if k not in raw or "GRBM_GUI_ACTIVE" not in raw[k]:
+            continue
+        fr = sq_fractions(raw[k])
+        lines.append(f"| `{k}` | {fr['valu_busy']:.2f} | {fr['valu_insts_per_cu_cycle']:.2f} | "
+                     f"{fr['lds_util']:.2f} | {fr['lds_bank_conflict']:.2f} | "
+                     f"{fr.get('occupancy', float('nan')):.2f} |")
+        if "spread" in k or "interp" in k:
+            table[f"{args.workload}:{k}"] = dict(fr, source_hash=kernel_source_hash())
+    with open(path, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+    return lines
+
+
 def summarize_sweep(args):
     """Markdown table of bench JSON lines (one per run)."""
     rows = [json.loads(l) for l in open(args.sweep) if l.strip()]
@@ -368,6 +500,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=10_000_000,
                     help="points the oracle is timed on (capped at M); 1e7 is about 20-30 "
                          "CPU-seconds on 16 host threads")
+    ap.add_argument("--cpu-sample-1core", type=int, default=1_000_000,
+                    help="points the oracle is timed on with one thread")
+    ap.add_argument("--no-3d", action="store_true",
+                    help="leave the 3D entry out of the default 2D line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-plain speedup measurement")
@@ -384,6 +520,9 @@ def main():
     ap.add_argument("--cal-fetch-dir")
     ap.add_argument("--cal-write-dir")
     ap.add_argument("--cal-mib", type=int, default=256)
+    ap.add_argument("--sq-dir", help="rocprofv3 --pmc output with the SQ / GRBM counters")
+    ap.add_argument("--counters-out", default=None,
+                    help="counter table to update (default profiles/counters.json)")
     ap.add_argument("--kernels", default="k_spread_smp,k_interp_sm")
     ap.add_argument("--md-out")
     ap.add_argument("--traffic-out", default=None,
@@ -427,14 +566,55 @@ def main():
 
     if args.workload in T3_WORKLOADS:
         return bench_type3(args)
-    dim, modes, M, kind, eps, prec = WORKLOADS[args.workload]
-    if args.eps > 0:
-        eps, prec = args.eps, ("f32" if args.eps >= 1e-6 else "f64")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    res, data = measure(args, args.workload, dev)
+    out = {
+        "metric": METRIC,
+        "value": res["value"],
+        "unit": "NU points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": res["dtype"],
+        "data": "synthetic",
+    }
+    out.update({k: v for k, v in res.items() if k not in ("value", "ms_per_step", "dtype")})
+    if args.workload == "2d" and args.eps <= 0 and not args.no_3d:
+        # the metric covers 2D and 3D: the 3D workload (128^3 modes, M = 2^24
+        # uniform points, eps 1e-5, fp32) as a second keyed entry
+        res3, _ = measure(args, "3d", dev, sorted_order=False)
+        out["3d"] = dict(res3, steps=args.steps, warmup=args.warmup)
+    if not args.no_batched:
+        print("[bench] batched vs plain (64 transforms)", file=sys.stderr, flush=True)
+        runs = [batched_speedup(kind, ntype, autotune=(k == 0)) for k, (kind, ntype) in
+                enumerate((("uniform", 1), ("cluster", 1), ("radial", 1), ("uniform", 2)))]
+        out["batched_speedup"] = dict(runs[0], others=runs[1:])
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(data, args.cpu_sample, args.cpu_sample_1core)
+    print(json.dumps(out), flush=True)
+
+
+def measure(args, workload, dev, sorted_order=True):
+    """One workload: W warm-up and K timed steps of setpts + type 1 + type 2
+    (adjoint) on the same points, with the library's stage timers on the
+    plan's stream.  Returns (result dict, host copies of the inputs)."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2102_08463_amd import Plan
+
+    dim, modes, M, kind, eps, prec = WORKLOADS[workload]
+    if args.eps > 0:
+        eps, prec = args.eps, ("f32" if args.eps >= 1e-6 else "f64")
     rdt = np.float32 if prec == "f32" else np.float64
     cdt = torch.complex64 if prec == "f32" else torch.complex128
-    print(f"[bench] workload {args.workload}: dim={dim} modes={modes} M={M} {kind} "
+    print(f"[bench] workload {workload}: dim={dim} modes={modes} M={M} {kind} "
           f"eps={eps} {prec}", file=sys.stderr, flush=True)
     pts_np = [np.asarray(a, dtype=rdt) for a in workloads.points(kind, M, dim, seed=0)]
     c_np = workloads.strengths(M, seed=1).astype(np.complex64 if prec == "f32" else np.complex128)
@@ -469,7 +649,6 @@ def main():
     stages = plan.timing(reset=True)
     plan.set_timing(False)
     K = args.steps
-    ms_per_step = total_ms / K
     value = 2.0 * M * K / (total_ms * 1e-3)
 
     rsz = 4 if prec == "f32" else 8
@@ -484,23 +663,31 @@ def main():
     algo = algorithmic_bytes(dominant, dim, M, ncells, rsz)
     achieved = algo / (kern_ms[dominant] * 1e-3) / 1e9
     sm_spread = "k_spread_smp" if prec == "f32" and dim >= 2 else "k_spread_sm"
-    kernel_name = {"spread": sm_spread if info["method"] == 3 else "k_spread_gm",
-                   "interp": "k_interp_sm" if info["method"] == 3 else "k_interp_gm"}[dominant]
-    traffic = load_traffic(kernel_name, args.workload) \
-        if args.eps <= 0 and args.upsampfac in (0.0, 2.0) else None
-    out = {
-        "metric": METRIC,
+    names = {"spread": sm_spread if info["method"] == 3 else "k_spread_gm",
+             "interp": "k_interp_sm" if info["method"] == 3 else "k_interp_gm"}
+    default_shape = args.eps <= 0 and args.upsampfac in (0.0, 2.0) and not args.binsize \
+        and not args.msub and args.method == "auto"
+
+    def roof(stage):
+        a = algorithmic_bytes(stage, dim, M, ncells, rsz)
+        ach = a / (kern_ms[stage] * 1e-3) / 1e9
+        r = {"bound": "hbm", "kernel": names[stage], "achieved": ach, "peak": HBM_PEAK_GBS,
+             "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+             "traffic": load_traffic(names[stage], workload) if default_shape else None,
+             "algorithmic_bytes_per_launch": a, "avg_launch_ms": kern_ms[stage]}
+        cnt = load_counters(names[stage], workload) if default_shape else None
+        if cnt:
+            # fractions of the other two ceilings, from hardware counters of
+            # the same kernel source (profiles/counters.json)
+            r["fractions"] = {"hbm": ach / HBM_PEAK_GBS, "valu": cnt["valu_busy"],
+                              "lds": cnt["lds_util"]}
+            r["counters"] = cnt
+        return r
+
+    res = {
         "value": value,
-        "unit": "NU points/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
+        "ms_per_step": total_ms / K,
         "dtype": prec,
-        "data": "synthetic",
         "config": {
             "workload": f"{dim}D type 1 + type 2 per step (setpts, execute, adjoint), "
                         f"modes {'x'.join(map(str, modes))}, M={M} {kind} points, "
@@ -510,48 +697,21 @@ def main():
             "binsize": info["binsize"][:dim], "msub": info["msub"],
             "upsampfac": info["upsampfac"],
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": kernel_name,
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": algo,
-            "avg_launch_ms": kern_ms[dominant],
-        },
-        "stage_ms_per_step": {k: v[0] / K for k, v in stages.items()},
+        "roofline": roof(dominant),
+        "roofline_other": roof("interp" if dominant == "spread" else "spread"),
+        "stage_ms_per_step": per_step,
         "exec_pts_per_s": {"type1": M / (t1_ms * 1e-3), "type2": M / (t2_ms * 1e-3)},
         "total_pts_per_s": {"type1": M / ((setpts_ms + t1_ms) * 1e-3),
                             "type2": M / ((setpts_ms + t2_ms) * 1e-3)},
     }
-    if info["method"] == 3 and kern_ms["spread"] > 0:
-        # one 64-bit LDS atomic per tap (two per tap for the two-word accumulator)
-        words = 1 if (prec == "f32" and dim >= 2) else 2
-        ops = M * info["w"] ** dim * words
-        rate = ops / (kern_ms["spread"] * 1e-3)
-        out["lds_atomic"] = {"kernel": sm_spread, "ops_per_launch": ops, "achieved": rate,
-                             "peak": LDS_U64_ATOMIC_PEAK, "unit": "ops/s",
-                             "frac": rate / LDS_U64_ATOMIC_PEAK}
-    if info["method"] == 3 and not args.no_sorted:
-        out["sorted_order"] = sorted_order_kernels(plan, modes, pts, c, f, eps, cdt, args,
+    if sorted_order and info["method"] == 3 and not args.no_sorted:
+        res["sorted_order"] = sorted_order_kernels(plan, modes, pts, c, f, eps, cdt, args,
                                                    dim, M, ncells, rsz)
-    if not args.no_batched:
-        print("[bench] batched vs plain (64 transforms)", file=sys.stderr, flush=True)
-        runs = [batched_speedup(kind, ntype) for kind, ntype in
-                (("uniform", 1), ("cluster", 1), ("radial", 1), ("uniform", 2))]
-        out["batched_speedup"] = dict(runs[0], others=[
-            {k: r[k] for k in ("kind", "type", "plain_ms", "batched_ms", "selector_ms", "speedup")}
-            for r in runs[1:]])
-    if not args.no_cpu_baseline:
-        sample = min(args.cpu_sample, M)
-        print(f"[bench] timing the oracle on {sample} points", file=sys.stderr, flush=True)
-        pts64 = tuple(a.astype(np.float64) for a in pts_np)
-        out["cpu_baseline"] = cpu_baseline(pts64, c_np.astype(np.complex128),
-                                           f_np.astype(np.complex128), modes, eps, sample)
     plan.destroy()
-    print(json.dumps(out), flush=True)
+    data = {"pts64": tuple(a.astype(np.float64) for a in pts_np),
+            "c64": c_np.astype(np.complex128), "f64": f_np.astype(np.complex128),
+            "modes": modes, "eps": eps, "workload": workload}
+    return res, data
 
 
 def bench_type3(args):

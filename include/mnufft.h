@@ -69,7 +69,10 @@ typedef struct mnufft_opts {
                            first remark), halved along the longest side while the
                            padded bins of method SM do not fit in 160 KB of LDS */
     int   msub;         /* max points per subproblem, > 0; 0 selects 4096 (the paper
-                           used 1024, same remark) */
+                           used 1024, same remark).  Default bins are also halved
+                           along their longest side, down to 8 cells, while the fine
+                           grid holds fewer than 1024 of them (small grids would
+                           leave most compute units idle) */
     int   validate_pts; /* nonzero: setpts checks that every coordinate is finite and
                            in [-3pi, 3pi) and returns MNUFFT_ERR_PTS otherwise (this
                            synchronises the stream) */
@@ -78,8 +81,19 @@ typedef struct mnufft_opts {
     double upsampfac;   /* fine-grid upsampling factor sigma: 0 or 2 selects the paper's
                            2 (Sec. II); values in [1.25, 2) use smaller fine grids with
                            wider kernels (see mnufft_choose_params_sigma) */
-    int   reserved[6];  /* must be zero */
+    int   tune;         /* MNUFFT_TUNE_*: OFF (default) keeps method, bins and msub as
+                           given (or their defaults); AUTOTUNE or LEARNED make every
+                           mnufft_setpts choose them for its points with mnufft_select
+                           (types 1 and 2 in 2D / 3D; method must be AUTO and binsize,
+                           msub 0); the plan re-plans its bin tables when the choice
+                           changes, which never changes results beyond rounding */
+    int   reserved[5];  /* must be zero */
 } mnufft_opts;
+
+/* Parameter selection modes (mnufft_opts.tune, mnufft_select). */
+#define MNUFFT_TUNE_OFF      0
+#define MNUFFT_TUNE_AUTOTUNE 1  /* time every autotuner candidate on the points (cached per class) */
+#define MNUFFT_TUNE_LEARNED  2  /* the registered learned selector; the autotuner when none fits */
 
 typedef struct mnufft_plan_s *mnufft_plan;
 
@@ -321,16 +335,18 @@ int mnufft_type3_grid(double X, double S, double sigma, int w, int64_t *nf, doub
 
 /* The parameter sets the autotuner searches for a dimension, precision and
  * tolerance: method SM with several bin shapes (those whose padded bins fit
- * in LDS) times msub in {256, 1024, 4096, 16384}, then GMSORT and GM, in
- * this fixed order.  Writes min(count, cap) default-initialised options with
+ * in LDS; in 2D every m_1 >= m_2 from {8, 16, 32, 64, 128}) times msub (2D:
+ * {1024, 4096}; 3D: {256, 1024, 4096, 16384}), then GMSORT and GM, in this
+ * fixed order.  Writes min(count, cap) default-initialised options with
  * method, binsize and msub set (host array, may be NULL when cap = 0) and
  * returns the count (>= 0).  Host only.  Errors: ERR_ARG.  (The paper tuned
  * bins and msub by hand on its GPU: Sec. III-A, first remark.) */
 int mnufft_tune_candidates(int dim, int prec, double eps, mnufft_opts *list, int cap);
 
-/* Time setpts + execute of one transform for each candidate (a plan is
- * created per candidate, untimed), in milliseconds of device time measured
- * with HIP events on each candidate's stream: the median of `reps` runs after
+/* Time setpts + execute of one transform for each candidate (one plan is
+ * made, untimed, and given each candidate's method, bins and msub in turn;
+ * stream, device and upsampfac come from the first candidate), in
+ * milliseconds of device time measured with HIP events on that stream: the median of `reps` runs after
  * one warm-up run; a candidate whose warm-up takes more than cutoff (> 1)
  * times the best median so far keeps that single time.  Candidates that are
  * invalid for the problem get -1.  x, y, z, c, f are device arrays as for
@@ -390,6 +406,58 @@ int mnufft_mlp_backward(int F, int H, int K, const float *params, int B, const f
 /* One Adam step (step >= 1) over n parameters with moments m, v. */
 int mnufft_mlp_adam(int64_t n, float *params, const float *grads, float *m, float *v, float lr,
                     float beta1, float beta2, float eps, int step, void *stream);
+
+/* Register a learned selector from a file (host path), replacing one of the
+ * same dimension, precision and tolerance.  Format (little-endian): the 8
+ * bytes "MNSEL001"; int32 dim, prec; double eps; int32 F, H, K; double
+ * margin; K records of int32 (method, binsize[0..2], msub) that must equal
+ * mnufft_tune_candidates(dim, prec, eps) in order; then the
+ * mnufft_mlp_nparams(F, H, K) float32 parameters of the network, and
+ * nothing after them.  F must be 262: the 256 density features of
+ * mnufft_density_features followed by log2 M / 24, log2 n_i / 12 (i = 1..3,
+ * 0 for an absent dimension; n_i the sigma = 2 fine grid), w / 16 and the
+ * type minus one.  The network predicts each candidate's log run time
+ * relative to the fastest; a prediction whose runner-up is less than
+ * `margin` behind is left to the autotuner.  Errors: ERR_ARG (unreadable
+ * file, bad format, candidate list mismatch). */
+int mnufft_selector_load(const char *path);
+
+/* Forget every registered selector and the autotuner's cached choices. */
+int mnufft_selector_clear(void);
+
+/* Choose method, bins and msub for one type 1 / 2 problem on its points.
+ *   mode    MNUFFT_TUNE_AUTOTUNE: time every candidate of mnufft_tune_candidates
+ *           (setpts + execute, mnufft_tune_time) on these points and take the
+ *           fastest; the choice is cached per problem class (type, dimension,
+ *           precision, tolerance, rounded log2 of N_i and M, and the points'
+ *           clustering level from the density features) for later calls.
+ *           MNUFFT_TUNE_LEARNED: the registered selector's argmin over all
+ *           candidates from the density features, or the autotuner when no
+ *           selector is registered for (dim, prec, eps) or its margin is not met.
+ *   base    NULL or options whose stream, device and upsampfac are used
+ *   out     receives the chosen options (the base's stream, device, upsampfac)
+ *   source  NULL, or receives 0 (learned prediction) or 1 (autotuner)
+ * x, y, z as for mnufft_setpts.  Synchronises the stream.  Errors: ERR_ARG,
+ * ERR_ALLOC, ERR_HIP, ERR_FFT. */
+int mnufft_select(int type, int dim, const int64_t *nmodes, int iflag, double eps, int prec,
+                  int64_t M, const void *x, const void *y, const void *z, int mode,
+                  const mnufft_opts *base, mnufft_opts *out, int *source);
+
+/* Choose bins and msub (method SM) for each transform of a batch from its
+ * points, for mnufft_batch_makeplan: arguments as mnufft_batch_makeplan and
+ * mnufft_batch_setpts; binsize (ntr x 3) and msub (ntr) are host arrays that
+ * receive the choices, source (ntr, may be NULL) 0 for a learned prediction
+ * and 1 for the autotuner.  With MNUFFT_TUNE_LEARNED and a registered
+ * selector, all transforms are scored by one batched density-histogram pass,
+ * one forward pass of the network and one argmin launch on the device (the
+ * scalar features are computed on the host and copied once); transforms
+ * whose margin is not met, or all of them with MNUFFT_TUNE_AUTOTUNE, are
+ * timed by the autotuner on their own points.  Synchronises the stream.
+ * Errors: ERR_ARG, ERR_ALLOC, ERR_HIP, ERR_FFT. */
+int mnufft_batch_select(int type, int dim, int ntr, const int64_t *nmodes, const int64_t *npts,
+                        const void *x, const void *y, const void *z, double eps, int prec,
+                        int mode, const mnufft_opts *base, int32_t *binsize, int32_t *msub,
+                        int32_t *source);
 
 /* ---- batches of transforms of uneven size ---------------------------- */
 

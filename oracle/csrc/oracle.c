@@ -316,3 +316,7 @@ void orc_direct_type3(int dim, int64_t M, const double *x, const double *y,
 
 /* Number of OpenMP threads the reference will use. */
 int orc_num_threads(void) { return omp_get_max_threads(); }
+
+/* Thread count of the OpenMP loops above (timing control only; the results
+ * do not depend on it beyond summation order). */
+void orc_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }

@@ -34,6 +34,7 @@ def _L():
             ctypes.c_int, ctypes.c_int64, dp, dp, dp, dp, ctypes.c_int, dp, dp, dp,
             ctypes.c_int64, ip, dp]
         _lib.orc_num_threads.restype = ctypes.c_int
+        _lib.orc_set_threads.argtypes = [ctypes.c_int]
     return _lib
 
 
@@ -55,6 +56,11 @@ def _c128(a):
 
 def num_threads():
     return int(_L().orc_num_threads())
+
+
+def set_threads(n):
+    """Threads of the C loops (a timing control; results are unchanged)."""
+    _L().orc_set_threads(int(n))
 
 
 def _xyz(pts):

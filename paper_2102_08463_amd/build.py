@@ -13,7 +13,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmnufft.so")
-MICROBENCH = os.path.join(HERE, "microbench")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -31,6 +30,7 @@ UNITS = [
     ("host_common.cpp", [], "host_common.o"),
     ("batch.cpp", [], "batch.o"),
     ("tune.cpp", [], "tune.o"),
+    ("select.cpp", [], "select.o"),
     ("kernels_mlp.hip", [], "kernels_mlp.o"),
     ("kernels_sort.hip", [], "kernels_sort.o"),
     ("kernels_deconv.hip", [], "kernels_deconv.o"),
@@ -74,11 +74,6 @@ def build(jobs=None, verbose=False):
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + " ".join(cmd) + "\n" + r.stdout + r.stderr)
     os.replace(tmp, LIB)
-    # the stand-alone microbenchmarks the kernel design rests on
-    cmd = [HIPCC] + COMMON + ["-o", MICROBENCH, os.path.join(CSRC, "microbench.hip")]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError("microbenchmark build failed:\n" + " ".join(cmd) + "\n" + r.stderr)
     return LIB
 
 

@@ -111,6 +111,7 @@ mn::Pts batch_points(mnufft_batch b)
     P.mergelist = b->mergelist;
     P.nmerge = b->nmerge;
     P.cmax = b->cmax;
+    P.spos = nullptr;
     P.msub = b->msub_max;
     P.tg = b->d_geo;
     P.T = b->T;
@@ -227,7 +228,6 @@ int mnufft_batch_makeplan(int type, int dim, int ntr, const int64_t *nmodes, con
     b->g.beta = beta;
     b->g.pad = (w + 1) / 2;
     const int P = b->g.pad;
-    const int defm[2][3] = {{32, 32, 1}, {8, 8, 8}};
     b->geo.resize(ntr);
     std::vector<double> pf[3];
     std::vector<int2> cv[3];
@@ -237,12 +237,17 @@ int mnufft_batch_makeplan(int type, int dim, int ntr, const int64_t *nmodes, con
         mn::TGeom &tg = b->geo[t];
         std::memset(&tg, 0, sizeof(tg));
         int64_t cells = 1, nm = 1, nb = 1;
+        int64_t nf[3];
+        for (int d = 0; d < 3; ++d)
+            nf[d] = d < dim ? mn::host::fine_size(nmodes[3 * t + d], w, sigma) : 1;
+        int defm[3];
+        mn::host::default_bins(dim, nf, defm);
         for (int d = 0; d < 3; ++d) {
             const int64_t N = d < dim ? nmodes[3 * t + d] : 1;
-            const int64_t n = d < dim ? mn::host::fine_size(N, w, sigma) : 1;
+            const int64_t n = nf[d];
             int m = d < dim ? (binsize && binsize[3 * t + d] > 0
                                    ? binsize[3 * t + d]
-                                   : (o.binsize[d] > 0 ? o.binsize[d] : defm[dim - 2][d]))
+                                   : (o.binsize[d] > 0 ? o.binsize[d] : defm[d]))
                             : 1;
             m = (int)std::min<int64_t>(m, n);
             tg.N[d] = (int)N;

@@ -87,6 +87,23 @@ void correction(int64_t N, int64_t n, int w, double beta, std::vector<double> &p
     }
 }
 
+void default_bins(int dim, const int64_t n[3], int m[3])
+{
+    static const int defm[3][3] = {{64, 1, 1}, {32, 32, 1}, {16, 8, 8}};
+    for (int d = 0; d < 3; ++d)
+        m[d] = d < dim ? (int)std::min<int64_t>(defm[dim - 1][d], n[d]) : 1;
+    for (;;) {
+        int64_t nb = 1;
+        int dl = 0;
+        for (int d = 0; d < dim; ++d) {
+            nb *= (n[d] + m[d] - 1) / m[d];
+            if (m[d] > m[dl]) dl = d;
+        }
+        if (nb >= kMinBins || m[dl] <= kMinSide) break;
+        m[dl] = (m[dl] + 1) / 2;
+    }
+}
+
 int bits_for(int64_t nbins)
 {
     int b = 0;

@@ -32,6 +32,23 @@ void correction(int64_t N, int64_t n, int w, double beta, std::vector<double> &p
 // quadrature, 513 nodes).
 void es_fourier(double beta, const std::vector<double> &xi, std::vector<double> &out);
 
+// Default bin extents for a fine grid n (dim dimensions): 64 cells in 1D,
+// 32 x 32 in 2D and 16 x 8 x 8 in 3D (measured on gfx950; the paper's V100
+// choice was 32 x 32 and 16 x 16 x 2, Sec. III-A, first remark), each at most
+// the grid, then halved along the longest side while the grid holds fewer
+// than kMinBins bins and that side is above kMinSide: a small grid cut into
+// few bins leaves most of the GPU's compute units idle.
+constexpr int64_t kMinBins = 1024;
+constexpr int kMinSide = 8;
+void default_bins(int dim, const int64_t n[3], int m[3]);
+
+// Give a type 1 / 2 plan another method, bins and msub (c.method, binsize,
+// msub; the rest of c is ignored), keeping its fine grid, FFT and correction
+// factors; the points must be set again.  Used by the autotuner to time
+// candidates on one plan.  Errors: ERR_ARG (bins that do not fit LDS for
+// method SM, a type 3 plan), ERR_ALLOC, ERR_HIP.
+int plan_set_params(mnufft_plan p, const mnufft_opts &c);
+
 // Bits needed to hold bin indices 0 .. nbins - 1.
 int bits_for(int64_t nbins);
 

@@ -88,12 +88,60 @@ __device__ __forceinline__ Geom geom_of(const Geom &g, const TGeom &t)
     return r;
 }
 
+// ---- start-cell histogram of the SM spreading scale ------------------------
+// Start cell (first tap in padded-tile coordinates, halo P = ceil(w/2)) of a
+// point at bin-relative coordinate u: ceil(u + P - w/2), evaluated the same
+// way by the spreading kernels and by setpts.
+template <typename T>
+__host__ __device__ inline int start_cell_rt(T u, int w)
+{
+    const T v = u + (T)((w + 1) / 2);
+    return (int)ceil(v - (T)(0.5 * w));
+}
+
+// Layout of the start-cell histogram of a tile with bin extents m: start
+// cells s_d in [0, m_d + 1] (c_d of them), x rows of pitch lx = c_1 + w - 1
+// (room for the box sums along x in place), ly rows per z plane (3D: room
+// for the box sums along y in place).
+struct StartHist {
+    int c[3];
+    int lx, ly;
+    int size;
+};
+
+__host__ __device__ inline StartHist start_hist_rt(int dim, int w, int m1, int m2, int m3)
+{
+    StartHist h;
+    h.c[0] = m1 + 2;
+    h.c[1] = dim >= 2 ? m2 + 2 : 1;
+    h.c[2] = dim == 3 ? m3 + 2 : 1;
+    h.lx = h.c[0] + w - 1;
+    h.ly = dim == 3 ? h.c[1] + w - 1 : h.c[1];
+    h.size = h.c[2] * h.ly * h.lx;
+    return h;
+}
+
+// Histogram slot of start cell (s1, s2, s3), clamped into the histogram (the
+// start of a point inside its bin is always in range); s2 = s3 = 0 for
+// absent dimensions.
+__host__ __device__ inline int hist_slot_rt(const StartHist &h, int s2, int s3, int s1)
+{
+    s1 = s1 < 0 ? 0 : (s1 > h.c[0] - 1 ? h.c[0] - 1 : s1);
+    s2 = s2 < 0 ? 0 : (s2 > h.c[1] - 1 ? h.c[1] - 1 : s2);
+    s3 = s3 < 0 ? 0 : (s3 > h.c[2] - 1 ? h.c[2] - 1 : s3);
+    return (s3 * h.ly + s2) * h.lx + s1;
+}
+
 // Sorted-point storage produced by setpts.
 struct Pts {
     int M;
     const void *u[3];        // bin-relative coordinates g_i - binstart_i (plan precision), sorted
     const uint32_t *key;     // bin index per sorted point
     const int32_t *perm;     // sorted position -> input index; null: c in sorted order
+    const int32_t *spos;     // with perm null: sorted position of each processed point
+                             // (null: the position itself)
+    const uint16_t *hslot;   // SM spreading: start-cell histogram slot of each processed
+                             // point (null: computed from the coordinates)
     const int32_t *binstart; // nbins + 1
     const int32_t *sub;      // subproblem records (bin, start, len, 0)
     const int32_t *nsub;     // device count of records
@@ -169,6 +217,15 @@ hipError_t launch_subproblems(int nbins, int msub, int nsub_max, const int32_t *
                               int32_t *subcount, uint32_t *partials, int32_t *sub,
                               int32_t *nsub, hipStream_t s, const TGeom *tg = nullptr, int T = 1);
 
+// Processing order of the SM kernels within each subproblem (see k_balance):
+// v[d] / vperm / spos / hslot receive the sorted coordinates, the
+// permutation, the sorted position and the start-cell histogram slot of the
+// point processed at each position.
+hipError_t launch_balance(const Geom &g, int prec, int nsub_max, const int32_t *sub,
+                          const int32_t *nsub, const void *const u[3], const int32_t *perm,
+                          void *const v[3], int32_t *vperm, int32_t *spos, uint16_t *hslot,
+                          hipStream_t s);
+
 // Exclusive prefix sum of n uint32 values (in and out may alias).
 hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, size_t n, uint32_t *partials,
                           hipStream_t s);
@@ -241,6 +298,13 @@ hipError_t launch_t3_postfac(int prec, int n, int dim, const void *const sf[3],
 // out[t][i] = in[t][i] * fac[i] over ntransf stacked complex vectors of n entries.
 hipError_t launch_cmul(int prec, long long n, int ntransf, const void *in, const void *fac,
                        void *out, hipStream_t s);
+
+// ---- learned selector (kernels_mlp.hip) -----------------------------------
+// Per row of Y (T x K floats): index of the smallest entry among the columns
+// whose bit is set in mask (column k: bit k % 64 of mask[k / 64], K <= 128)
+// and its gap to the runner-up; -1 when no column is allowed.
+hipError_t launch_argmin_rows(int T, int K, const float *Y, const unsigned long long mask[2],
+                              int *idx, float *gap, hipStream_t s);
 
 // Fill n bytes of device memory with zero by a kernel.
 hipError_t launch_zero(void *ptr, size_t bytes, hipStream_t s);

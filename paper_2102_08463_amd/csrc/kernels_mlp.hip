@@ -179,7 +179,60 @@ __global__ void k_hist_batch_final(const int64_t *__restrict__ off,
 
 inline int blocks_for(long long n) { return (int)std::max<long long>(1, (n + kThreads - 1) / kThreads); }
 
+// Per row of Y (T x K): the allowed column of smallest value and its gap to
+// the runner-up (infinity with one allowed column); -1 when none is allowed.
+// allowed: bit k of mask[k / 64] marks column k.
+__global__ void k_argmin_rows(int T, int K, const float *__restrict__ Y, unsigned long long m0,
+                              unsigned long long m1, int *__restrict__ idx, float *__restrict__ gap)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    int best = -1;
+    float b0 = INFINITY, b1 = INFINITY;
+    for (int k = 0; k < K; ++k) {
+        const unsigned long long m = k < 64 ? m0 : m1;
+        if (!((m >> (k & 63)) & 1ull)) continue;
+        const float v = Y[(size_t)t * K + k];
+        if (v < b0) {
+            b1 = b0;
+            b0 = v;
+            best = k;
+        } else if (v < b1) {
+            b1 = v;
+        }
+    }
+    idx[t] = best;
+    gap[t] = b1 - b0;
+}
+
+int density_batch(int prec, int T, const int64_t *off, const void *x, const void *y, float *feat,
+                  int ldf, void *work, hipStream_t s)
+{
+    uint32_t *part = (uint32_t *)work;
+    const dim3 grid(kBatchChunks, T);
+    if (prec == MNUFFT_F32)
+        hipLaunchKernelGGL(k_hist_batch<float>, grid, dim3(kThreads), 0, s, off,
+                           (const float *)x, (const float *)y, part);
+    else
+        hipLaunchKernelGGL(k_hist_batch<double>, grid, dim3(kThreads), 0, s, off,
+                           (const double *)x, (const double *)y, part);
+    hipLaunchKernelGGL(k_hist_batch_final, dim3(T), dim3(256), 0, s, off,
+                       (const uint32_t *)part, feat, ldf);
+    return hipGetLastError() == hipSuccess ? MNUFFT_OK : MNUFFT_ERR_HIP;
+}
+
 }  // namespace
+
+namespace mn {
+hipError_t launch_argmin_rows(int T, int K, const float *Y, const unsigned long long mask[2],
+                              int *idx, float *gap, hipStream_t s)
+{
+    if (T <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_argmin_rows, dim3(blocks_for(T)), dim3(kThreads), 0, s, T, K, Y,
+                       mask[0], mask[1], idx, gap);
+    return hipGetLastError();
+}
+}  // namespace mn
 
 extern "C" {
 
@@ -282,18 +335,7 @@ int mnufft_density_features_batch(int prec, int T, const int64_t *off, const voi
     if ((prec != MNUFFT_F32 && prec != MNUFFT_F64) || T < 1 || T > 65535 || !off || !x || !y ||
         !feat || !work || ldf < 256)
         return MNUFFT_ERR_ARG;
-    hipStream_t s = (hipStream_t)stream;
-    uint32_t *part = (uint32_t *)work;
-    const dim3 grid(kBatchChunks, T);
-    if (prec == MNUFFT_F32)
-        hipLaunchKernelGGL(k_hist_batch<float>, grid, dim3(kThreads), 0, s, off,
-                           (const float *)x, (const float *)y, part);
-    else
-        hipLaunchKernelGGL(k_hist_batch<double>, grid, dim3(kThreads), 0, s, off,
-                           (const double *)x, (const double *)y, part);
-    hipLaunchKernelGGL(k_hist_batch_final, dim3(T), dim3(256), 0, s, off,
-                       (const uint32_t *)part, feat, ldf);
-    return hipGetLastError() == hipSuccess ? MNUFFT_OK : MNUFFT_ERR_HIP;
+    return density_batch(prec, T, off, x, y, feat, ldf, work, (hipStream_t)stream);
 }
 
 }  // extern "C"

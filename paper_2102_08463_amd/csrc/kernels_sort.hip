@@ -491,6 +491,101 @@ hipError_t launch_binstart(int M, int nbins, const uint32_t *skey, int32_t *bins
     return hipGetLastError();
 }
 
+// ---- processing order of the SM kernels -----------------------------------
+// The SM kernels give each lane of a wave one point and have all lanes touch
+// the same tap of their points at once, so a wave's LDS addresses are the
+// points' tile start cells plus a common offset.  The LDS serves 64-bit
+// accesses sixteen lanes at a time and stalls when two of them hit the same
+// bank; the banks follow the cell index modulo 16 (two or four banks per
+// cell), so sixteen points whose start-cell indices differ modulo 16 are
+// served without conflict whatever the tap.  This kernel orders each
+// subproblem's points round-robin over their start-cell index modulo 16:
+// every point of rank k in its residue class comes before every point of
+// rank k + 1, residues ascending within a rank, i.e. point (r, k) goes to
+//   pos = sum_t min(c_t, k) + #{t < r : c_t > k}     (c_t = class sizes).
+// The sorted coordinates, the permutation, each point's sorted position and
+// its slot in the spreading kernels' start-cell histogram are written in
+// that order.  Subproblems above kBalCap points keep their
+// sorted order.  The ranks come from LDS atomics, so the order within a
+// class may differ between runs; the SM kernels' results do not depend on
+// the order (integer tile sums, per-point interpolation).
+constexpr int kBalCap = 4096;
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_balance(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__ nsubp,
+          const T *__restrict__ u0, const T *__restrict__ u1, const T *__restrict__ u2,
+          const int32_t *__restrict__ perm, T *__restrict__ v0, T *__restrict__ v1,
+          T *__restrict__ v2, int32_t *__restrict__ vperm, int32_t *__restrict__ spos,
+          uint16_t *__restrict__ hslot)
+{
+    __shared__ unsigned cnt[16];
+    __shared__ unsigned rk[kBalCap];
+    const int P = (g.w + 1) / 2;
+    const int p1 = g.m[0] + 2 * P, p2 = g.m[1] + 2 * P;
+    const T lead = (T)P - (T)(0.5 * g.w);
+    const StartHist hg = start_hist_rt(g.dim, g.w, g.m[0], g.m[1], g.m[2]);
+    const int nsub = *nsubp;
+    for (int q = blockIdx.x; q < nsub; q += gridDim.x) {
+        const int4 rec = reinterpret_cast<const int4 *>(sub)[q];
+        const int n = rec.z;
+        const bool fits = n <= kBalCap;
+        if (threadIdx.x < 16) cnt[threadIdx.x] = 0u;
+        __syncthreads();
+        if (fits) {
+            for (int j = threadIdx.x; j < n; j += blockDim.x) {
+                const int i = rec.y + j;
+                int base = (int)ceil(u0[i] + lead);
+                if (g.dim >= 2) base += p1 * (int)ceil(u1[i] + lead);
+                if (g.dim == 3) base += p1 * p2 * (int)ceil(u2[i] + lead);
+                const unsigned r = (unsigned)base & 15u;
+                rk[j] = r | (atomicAdd(&cnt[r], 1u) << 4);
+            }
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < n; j += blockDim.x) {
+            int pos = j;
+            if (fits) {
+                const unsigned r = rk[j] & 15u, k = rk[j] >> 4;
+                pos = 0;
+                for (int t = 0; t < 16; ++t) {
+                    const unsigned ct = cnt[t];
+                    pos += (int)min(ct, k) + ((t < (int)r && ct > k) ? 1 : 0);
+                }
+            }
+            const int i = rec.y + j, o = rec.y + pos;
+            const T a = u0[i], b = g.dim >= 2 ? u1[i] : (T)0, cc = g.dim == 3 ? u2[i] : (T)0;
+            v0[o] = a;
+            if (g.dim >= 2) v1[o] = b;
+            if (g.dim == 3) v2[o] = cc;
+            vperm[o] = perm[i];
+            spos[o] = i;
+            // the spreading kernels' start-cell histogram slot (same expressions)
+            hslot[o] = (uint16_t)hist_slot_rt(hg, g.dim >= 2 ? start_cell_rt<T>(b, g.w) : 0,
+                                              g.dim == 3 ? start_cell_rt<T>(cc, g.w) : 0,
+                                              start_cell_rt<T>(a, g.w));
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_balance(const Geom &g, int prec, int nsub_max, const int32_t *sub,
+                          const int32_t *nsub, const void *const u[3], const int32_t *perm,
+                          void *const v[3], int32_t *vperm, int32_t *spos, uint16_t *hslot,
+                          hipStream_t s)
+{
+    if (nsub_max <= 0) return hipSuccess;
+    const dim3 grid(std::max(1, std::min(nsub_max, 256 * 8)));
+    if (prec == 0)
+        hipLaunchKernelGGL(k_balance<float>, grid, dim3(256), 0, s, g, sub, nsub,
+                           (const float *)u[0], (const float *)u[1], (const float *)u[2], perm,
+                           (float *)v[0], (float *)v[1], (float *)v[2], vperm, spos, hslot);
+    else
+        hipLaunchKernelGGL(k_balance<double>, grid, dim3(256), 0, s, g, sub, nsub,
+                           (const double *)u[0], (const double *)u[1], (const double *)u[2], perm,
+                           (double *)v[0], (double *)v[1], (double *)v[2], vperm, spos, hslot);
+    return hipGetLastError();
+}
+
 hipError_t launch_subproblems(int nbins, int msub, int nsub_max, const int32_t *binstart,
                               int32_t *subcount, uint32_t *partials, int32_t *sub,
                               int32_t *nsub, hipStream_t s, const TGeom *tg, int T)

@@ -60,6 +60,11 @@ struct mnufft_plan_s {
     uint32_t *key_in = nullptr;
     uint32_t *skey = nullptr;   // alias of keyA/keyB after the sort
     int32_t *perm = nullptr;    // alias of valA/valB after the sort
+    // method SM: the sorted points in the kernels' processing order (see
+    // k_balance): coordinates, permutation and sorted position
+    void *su_proc[3] = {nullptr, nullptr, nullptr};
+    int32_t *perm_proc = nullptr, *spos_proc = nullptr;
+    uint16_t *hslot_proc = nullptr;
     int32_t *binstart = nullptr, *subcount = nullptr, *sub = nullptr, *nsub = nullptr;
     int nsub_max = 0, nsub_cap = 0;
     uint32_t *hist = nullptr, *partials = nullptr;
@@ -147,6 +152,10 @@ void free_points(mnufft_plan p)
     dfree(p, (void **)&p->keyB, M * 4);
     dfree(p, (void **)&p->valB, M * 4);
     dfree(p, (void **)&p->key_in, M * 4);
+    for (int d = 0; d < 3; ++d) dfree(p, &p->su_proc[d], M * p->rsz);
+    dfree(p, (void **)&p->perm_proc, M * 4);
+    dfree(p, (void **)&p->spos_proc, M * 4);
+    dfree(p, (void **)&p->hslot_proc, M * 2);
     dfree(p, (void **)&p->sub, (size_t)p->nsub_cap * 16);
     dfree(p, (void **)&p->hist, p->hist_cap * 4);
     dfree(p, (void **)&p->partials, p->partials_cap * 4);
@@ -177,6 +186,11 @@ int alloc_points(mnufft_plan p, int64_t M)
     p->nsub_cap = (int)(p->g.nbins + (M + p->msub - 1) / p->msub);
     if ((rc = dalloc(p, (void **)&p->sub, (size_t)std::max(p->nsub_cap, 1) * 16))) return rc;
     if (p->method == MNUFFT_METHOD_SM) {
+        for (int d = 0; d < p->dim; ++d)
+            if ((rc = dalloc(p, &p->su_proc[d], Ma * p->rsz))) return rc;
+        if ((rc = dalloc(p, (void **)&p->perm_proc, Ma * 4))) return rc;
+        if ((rc = dalloc(p, (void **)&p->spos_proc, Ma * 4))) return rc;
+        if ((rc = dalloc(p, (void **)&p->hslot_proc, Ma * 2))) return rc;
         p->scratch_bytes = (size_t)std::max(p->nsub_cap, 1) * p->ts2 * p->rsz;
         if ((rc = dalloc(p, &p->scratch, p->scratch_bytes))) return rc;
         if ((rc = dalloc(p, (void **)&p->mergelist, (size_t)std::max(p->nsub_cap, 1) * 4)))
@@ -246,6 +260,7 @@ mn::Pts points_of(mnufft_plan p)
     }
     P.key = p->skey;
     P.perm = p->perm;
+    P.spos = nullptr;
     P.binstart = p->binstart;
     P.sub = p->sub;
     P.nsub = p->nsub;
@@ -269,6 +284,23 @@ mn::Pts points_of(mnufft_plan p)
     return P;
 }
 
+// The points as the SM spreading / interpolation kernels take them: in their
+// processing order (k_balance); other methods use the sorted order.  With
+// `sorted`, the vectors are in bin-sorted order and are reached through the
+// points' sorted positions.
+mn::Pts kernel_points(mnufft_plan p, bool sorted)
+{
+    mn::Pts P = points_of(p);
+    if (p->method == MNUFFT_METHOD_SM) {
+        for (int d = 0; d < 3; ++d) P.u[d] = p->su_proc[d];
+        P.perm = p->perm_proc;
+        P.hslot = p->hslot_proc;
+        if (sorted) P.spos = p->spos_proc;
+    }
+    if (sorted) P.perm = nullptr;
+    return P;
+}
+
 size_t grid_bytes(mnufft_plan p) { return p->grid_elems * 2 * p->rsz; }
 
 // SM spreading with the two-word accumulator (double precision, and single
@@ -279,8 +311,7 @@ bool needs_cmax(mnufft_plan p) { return p->prec == MNUFFT_F64 || p->dim == 1; }
 // bin-sorted order when `sorted`.
 int spread_all(mnufft_plan p, const void *c, bool sorted = false)
 {
-    mn::Pts P = points_of(p);
-    if (sorted) P.perm = nullptr;
+    mn::Pts P = kernel_points(p, sorted);
     if (p->method != MNUFFT_METHOD_SM) {  // SM writes every cell itself
         StageTimer tm(p->tm, MNUFFT_STAGE_ZERO, p->stream);
         MN_HIP(mn::launch_zero(p->grid, grid_bytes(p) * p->ntransf, p->stream));
@@ -327,8 +358,7 @@ int exec_type1(mnufft_plan p, int sign, const void *c, void *f, bool sorted = fa
 // bin-sorted order when `sorted`.
 int exec_type2(mnufft_plan p, int sign, const void *f, void *c, bool sorted = false)
 {
-    mn::Pts P = points_of(p);
-    if (sorted) P.perm = nullptr;
+    mn::Pts P = kernel_points(p, sorted);
     {
         StageTimer tm(p->tm, MNUFFT_STAGE_PRECORRECT, p->stream);
         MN_HIP(mn::launch_precorrect(p->dim, p->N, p->g.n, p->prec, (int)p->ntransf, f,
@@ -404,8 +434,66 @@ int enqueue_setpts(mnufft_plan p, int64_t M, const void *x, const void *y, const
         MN_HIP(mn::launch_zero(p->nmerge, 4, s));
         MN_HIP(mn::launch_merge_list(p->nsub_max, p->nsub, p->sub, p->subcount, kMergeGroup,
                                      p->mergelist, p->nmerge, s));
+        const void *su[3] = {p->su[0], p->su[1], p->su[2]};
+        MN_HIP(mn::launch_balance(g, p->prec, p->nsub_max, p->sub, p->nsub, su, p->perm,
+                                  p->su_proc, p->perm_proc, p->spos_proc, p->hslot_proc, s));
     }
     return MNUFFT_OK;
+}
+
+int plan_geometry(mnufft_plan p, const int64_t nf[3], int w, double beta, const mnufft_opts &o);
+int plan_bins_device(mnufft_plan p);
+
+// New method, bins and msub for a type 1 / 2 plan (the fine grid, the FFT
+// and the correction factors stay): drops the point storage and the bin
+// tables and makes them again for the new bins.
+int replan(mnufft_plan p, const mnufft_opts &c)
+{
+    free_points(p);
+    dfree(p, (void **)&p->binstart, ((size_t)p->g.nbins + 1) * 4);
+    dfree(p, (void **)&p->subcount, ((size_t)p->g.nbins + 1) * 4);
+    for (int d = 0; d < 3; ++d) {
+        dfree(p, (void **)&p->cov[d], p->cov_bytes[d]);
+        p->cov_bytes[d] = 0;
+        p->kmax[d] = 1;
+    }
+    p->M = -1;
+    mnufft_opts o = p->opts;
+    o.method = c.method;
+    for (int d = 0; d < 3; ++d) o.binsize[d] = c.binsize[d];
+    o.msub = c.msub;
+    o.tune = MNUFFT_TUNE_OFF;
+    p->msub = o.msub > 0 ? o.msub : 4096;
+    int64_t nf[3] = {p->g.n[0], p->g.n[1], p->g.n[2]};
+    int rc = plan_geometry(p, nf, p->g.w, p->g.beta, o);
+    if (!rc) rc = plan_bins_device(p);
+    return rc;
+}
+
+}  // namespace
+
+int mn::host::plan_set_params(mnufft_plan p, const mnufft_opts &c)
+{
+    if (!p || p->type == 3) return MNUFFT_ERR_ARG;
+    int rc = use_device(p);
+    if (!rc) rc = replan(p, c);
+    return rc;
+}
+
+namespace {
+
+// Parameter selection at setpts for plans with opts.tune set: pick method,
+// bins and msub for these points and re-plan when they change.
+int tune_for_points(mnufft_plan p, int64_t M, const void *x, const void *y, const void *z)
+{
+    mnufft_opts c;
+    int rc = mnufft_select(p->type, p->dim, p->N, p->iflag, p->eps, p->prec, M, x, y, z,
+                           p->opts.tune, &p->opts, &c, nullptr);
+    if (rc < 0) return rc;
+    bool same = c.method == p->method && c.msub == p->msub;
+    for (int d = 0; d < p->dim; ++d) same = same && std::min(c.binsize[d], p->g.n[d]) == p->g.m[d];
+    if (same) return MNUFFT_OK;
+    return replan(p, c);
 }
 
 int check_ready(mnufft_plan p)
@@ -457,11 +545,12 @@ int plan_geometry(mnufft_plan p, const int64_t nf[3], int w, double beta, const 
     // 1D bins stay short: sorted points carry their coordinate relative to the
     // bin start in the plan precision, and in single precision a 1024-cell bin
     // would leave those coordinates only about 6e-5 cells of resolution
-    const int defm[3][3] = {{64, 1, 1}, {32, 32, 1}, {16, 8, 8}};
+    int defm[3];
+    mn::host::default_bins(dim, nf, defm);
     bool user_bins = false;
     for (int d = 0; d < 3; ++d) {
         g.n[d] = d < dim ? (int)nf[d] : 1;
-        int m = d < dim ? (o.binsize[d] > 0 ? o.binsize[d] : defm[dim - 1][d]) : 1;
+        int m = d < dim ? (o.binsize[d] > 0 ? o.binsize[d] : defm[d]) : 1;
         user_bins = user_bins || (d < dim && o.binsize[d] > 0);
         g.m[d] = std::min(m, g.n[d]);
         g.S[d] = (double)g.n[d] / (2.0 * kPi);
@@ -497,6 +586,22 @@ int plan_geometry(mnufft_plan p, const int64_t nf[3], int w, double beta, const 
     return MNUFFT_OK;
 }
 
+// The device state that depends on the bins: bin starts, per-bin subproblem
+// offsets and, for method SM, the merge counter, the max |c| partials and
+// the cover tables of the add-back.
+int plan_bins_device(mnufft_plan p)
+{
+    const mn::Geom &g = p->g;
+    int rc = dalloc(p, (void **)&p->binstart, ((size_t)g.nbins + 1) * 4);
+    if (!rc) rc = dalloc(p, (void **)&p->subcount, ((size_t)g.nbins + 1) * 4);
+    if (!rc && p->method == MNUFFT_METHOD_SM) {
+        if (!p->nmerge) rc = dalloc(p, (void **)&p->nmerge, 16);
+        if (!rc && !p->cmax) rc = dalloc(p, &p->cmax, 1024 * 8);  // partial maxima, see k_maxabs
+        for (int d = 0; d < p->dim && !rc; ++d) rc = build_cover(p, d);
+    }
+    return rc;
+}
+
 // Device state of a plan after plan_geometry: fine grids, bin tables, cover
 // tables and, with_fft, the correction factors and the rocFFT plan (a type 3
 // plan's spreading plan has neither).
@@ -523,15 +628,9 @@ int plan_device(mnufft_plan p, bool with_fft)
             rc = MNUFFT_ERR_HIP;
         }
     }
-    if (!rc) rc = dalloc(p, (void **)&p->binstart, ((size_t)g.nbins + 1) * 4);
-    if (!rc) rc = dalloc(p, (void **)&p->subcount, ((size_t)g.nbins + 1) * 4);
     if (!rc) rc = dalloc(p, (void **)&p->nsub, 16);
     if (!rc) rc = dalloc(p, (void **)&p->flag, 16);
-    if (!rc && p->method == MNUFFT_METHOD_SM) {
-        rc = dalloc(p, (void **)&p->nmerge, 16);
-        if (!rc) rc = dalloc(p, &p->cmax, 1024 * 8);  // partial maxima, see k_maxabs
-        for (int d = 0; d < dim && !rc; ++d) rc = build_cover(p, d);
-    }
+    if (!rc) rc = plan_bins_device(p);
     if (with_fft) {
         if (!rc && rocfft_execution_info_create(&p->fftinfo) != rocfft_status_success)
             rc = MNUFFT_ERR_FFT;
@@ -796,8 +895,15 @@ int mnufft_makeplan(int type, int dim, const int64_t *nmodes, int iflag, int64_t
     if (o.method < MNUFFT_METHOD_AUTO || o.method > MNUFFT_METHOD_SM || o.msub < 0 ||
         o.device < -1)
         return MNUFFT_ERR_ARG;
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < 5; ++i)
         if (o.reserved[i]) return MNUFFT_ERR_ARG;
+    if (o.tune < MNUFFT_TUNE_OFF || o.tune > MNUFFT_TUNE_LEARNED) return MNUFFT_ERR_ARG;
+    // parameter selection covers types 1 and 2 in 2D / 3D and picks method,
+    // bins and msub itself
+    if (o.tune != MNUFFT_TUNE_OFF &&
+        (type == 3 || dim == 1 || o.method != MNUFFT_METHOD_AUTO || o.msub != 0 ||
+         o.binsize[0] || o.binsize[1] || o.binsize[2]))
+        return MNUFFT_ERR_ARG;
     const double sigma = o.upsampfac == 0.0 ? 2.0 : o.upsampfac;
     if (!(sigma >= 1.25 && sigma <= 2.0)) return MNUFFT_ERR_ARG;
     for (int d = 0; d < dim; ++d)
@@ -836,9 +942,10 @@ int mnufft_setpts(mnufft_plan p, int64_t M, const void *x, const void *y, const 
     if (p->dim == 1 && (y || z)) return MNUFFT_ERR_ARG;
     if (M > 0 && (!x || (p->dim >= 2 && !y))) return MNUFFT_ERR_ARG;
     if (M > 0 && p->dim >= 2 && ((p->dim == 3) != (z != nullptr))) return MNUFFT_ERR_ARG;
-    if (p->g.nbins + (M + p->msub - 1) / p->msub > 2147483647LL) return MNUFFT_ERR_ARG;
     int rc = use_device(p);
     if (rc) return rc;
+    if (p->opts.tune != MNUFFT_TUNE_OFF && (rc = tune_for_points(p, M, x, y, z)) < 0) return rc;
+    if (p->g.nbins + (M + p->msub - 1) / p->msub > 2147483647LL) return MNUFFT_ERR_ARG;
     p->M = -1;  // invalid until the whole setup has been enqueued
     if (M > p->Mcap && (rc = alloc_points(p, M))) {
         free_points(p);
@@ -984,7 +1091,7 @@ int mnufft_spread(mnufft_plan p, const void *c, void *grid)
     if ((rc = use_device(p))) return rc;
     if (p->method != MNUFFT_METHOD_SM) MN_HIP(mn::launch_zero(grid, grid_bytes(p), p->stream));
     else if (needs_cmax(p)) MN_HIP(mn::launch_zero(p->cmax, 1024 * 8, p->stream));
-    MN_HIP(mn::launch_spread(p->g, p->prec, p->method, points_of(p), c, grid, p->stream));
+    MN_HIP(mn::launch_spread(p->g, p->prec, p->method, kernel_points(p, false), c, grid, p->stream));
     return MNUFFT_OK;
 }
 
@@ -995,7 +1102,7 @@ int mnufft_interp(mnufft_plan p, const void *grid, void *c)
     if (p->type == 3) return MNUFFT_ERR_UNSUPPORTED;
     if (!grid || (p->M > 0 && !c)) return MNUFFT_ERR_ARG;
     if ((rc = use_device(p))) return rc;
-    MN_HIP(mn::launch_interp(p->g, p->prec, p->method, points_of(p), grid, c, p->stream));
+    MN_HIP(mn::launch_interp(p->g, p->prec, p->method, kernel_points(p, false), grid, c, p->stream));
     return MNUFFT_OK;
 }
 

@@ -51,13 +51,26 @@ int sm_tile_stride(const Geom &g)
 size_t sm_lds_bytes(const Geom &g, int prec, bool interp, int msub)
 {
     const size_t rsz = prec == 0 ? sizeof(float) : sizeof(double);
+    // The spreading kernels build a start-cell histogram of
+    // (m_3 + 2) (m_2 + w + 1) (m_1 + w + 1) words (fewer factors in 1D / 2D)
+    // in the tile's LDS before clearing the tile; it always fits in the
+    // ts2 words of a single-precision tile and its slots fit 16 bits, which
+    // this check confirms.
+    if (!interp) {
+        size_t hist = (size_t)g.m[0] + g.w + 1;
+        if (g.dim >= 2) hist *= (size_t)g.m[1] + (g.dim == 3 ? g.w + 1 : 2);
+        if (g.dim == 3) hist *= (size_t)g.m[2] + 2;
+        if (hist > (size_t)sm_tile_stride(g) || hist > 65535) return ~(size_t)0;
+    }
     // 64-bit fixed-point accumulators: one word per cell in single precision,
     // one per part in double precision
-    // (single precision also stages smp_stage strengths, 8 bytes each)
+    // (single precision also stages smp_stage strengths, 8 bytes each, and
+    // their 16-bit histogram slots, rounded up to 16 bytes)
     // (1D single precision uses the two-word accumulator of double precision)
     if (!interp)
         return prec == 0 && g.dim >= 2
-                   ? (size_t)sm_tile_stride(g) * 4 + (size_t)8 * smp_stage(g.dim, msub)
+                   ? (size_t)sm_tile_stride(g) * 4 + (size_t)8 * smp_stage(g.dim, msub) +
+                         ((size_t)2 * smp_stage(g.dim, msub) + 15) / 16 * 16
                    : (size_t)sm_tile_stride(g) * 8;
     const int P = (g.w + 1) / 2;
     size_t cells = 1;
@@ -97,6 +110,8 @@ hipError_t launch_spread(const Geom &g, int prec, int method, const Pts &P, cons
         return launch_zero(grid, (size_t)P.ncells * 2 * (prec == 0 ? sizeof(float) : sizeof(double)),
                            s);
     }
+    // the SM kernels reach every strength through an index array
+    if (method == 3 && !P.perm && !P.spos) return hipErrorInvalidValue;
     const size_t lds = method == 3 ? sm_lds_bytes(g, prec, false, P.msub) : 0;
 #define MN_SPREAD(TT)                                                                        \
     (g.dim == 1   ? detail::spread_dim<TT, 1>(g, method, P, c, grid, s, lds, part)           \
@@ -111,6 +126,7 @@ hipError_t launch_interp(const Geom &g, int prec, int method, const Pts &P, cons
                          void *c, hipStream_t s)
 {
     if (P.M == 0) return hipSuccess;
+    if (method == 3 && !P.perm && !P.spos) return hipErrorInvalidValue;
     const size_t lds = method == 3 ? sm_lds_bytes(g, prec, true, P.msub) : 0;
 #define MN_INTERP(TT)                                                                        \
     (g.dim == 1   ? detail::interp_dim<TT, 1>(g, method, P, grid, c, s, lds)                 \

@@ -12,7 +12,9 @@
 //
 // Strengths (spreading) and results (interpolation) are in the caller's point
 // order, reached through the sort permutation; with a null permutation they
-// are in bin-sorted order instead (mnufft_execute_sorted).
+// are in bin-sorted order instead (mnufft_execute_sorted).  The SM kernels
+// take one index array for this: the input index of each point they
+// process, or its sorted position.
 //
 // Methods (Sec. III-A / III-B):
 //   GM      one thread per point in input order, global atomics
@@ -288,96 +290,243 @@ __device__ __forceinline__ T block_cmax(const T *__restrict__ parts)
 }
 
 // ----------------------------------------------------------------------------
+// Rounding of a scaled contribution to the fixed-point word.
+__device__ __forceinline__ long long to_fixed(float v) { return __float2ll_rn(v); }
+__device__ __forceinline__ long long to_fixed(double v) { return __double2ll_rn(v); }
+
 // SM spreading, step 2 of Sec. III-A: each subproblem accumulates its points
 // into an LDS copy of its padded bin (p_i = m_i + 2 ceil(w/2), offset
 // binstart - ceil(w/2)), then stores the tile to its own scratch slot.
 // Adding the tiles into the grid (SM step 3) is done without atomics by
 // k_tile_merge / k_tile_gather below.
 //
-// The LDS accumulator is 64-bit fixed point: on gfx950 integer LDS atomics
+// The LDS accumulators are 64-bit fixed point: on gfx950 integer LDS atomics
 // (ds_add_u64) sustain roughly ten times the rate of floating-point ones.
-// This kernel serves double precision and 1D single precision (2D / 3D single
-// precision uses k_spread_smp, one word per cell, whose scale bounds a cell by
-// the subproblem's whole strength sum; a 1D subproblem of thousands of points,
-// each touching only w cells, would overstate every cell by far).  Every
-// contribution v = c_j * phi * phi is turned into round(v * S) with
-// S = 2^62 / (2^ceil(log2 n_q) 2^ceil(log2 cmax)), n_q <= msub the points of
-// subproblem q and cmax = max_j max(|Re c_j|, |Im c_j|): a cell gets at most
-// n_q contributions of size <= cmax, so the sum stays below 2^62, with quantum
-// about n_q cmax 2^-62.
+// A contribution v = c_j phi phi (phi) becomes round(v S); integer addition
+// is exact and associative, so a tile is the same whatever order its atomics
+// land in, and only the final cell values have to fit the word.
+//
+// The scale S of a subproblem comes from a bound on its cells.  A point
+// whose first tap (in padded-tile coordinates) is s covers the cells
+// s .. s + w - 1 per dimension with weights at most one, so
+//   |Re b_l|, |Im b_l| <= sum over points with s in (l - w, l] of a_j,
+//   a_j = max(|Re c_j|, |Im c_j|).
+// Each subproblem histograms ceil(a_j / u) (u a power of two) over the start
+// cells in LDS, takes box sums of width w along every dimension and their
+// maximum B; B u bounds every cell of the tile.  This is tighter than the
+// subproblem's whole strength sum by roughly the ratio of the bin to the
+// kernel footprint (about 20x for 32 x 32 bins and w = 6), and it follows
+// the strengths where they are: large strengths elsewhere in the input do
+// not coarsen this subproblem's quantum.  The histogram and its box sums use
+// the tile's own LDS before the tile is cleared.
+
+// Start cell (first tap in padded-tile coordinates) of a point at
+// bin-relative coordinate u: the expression taps() evaluates for u + P
+// (start_cell_rt in internal.h, which setpts uses for the same slots).
+template <typename T, int W>
+__device__ __forceinline__ int start_cell(T u)
+{
+    return start_cell_rt<T>(u, W);
+}
+
+__device__ __forceinline__ int ceil_log2(unsigned v) { return v <= 1u ? 0 : 32 - __clz(v - 1u); }
+
+template <int DIM, int W>
+__device__ __forceinline__ StartHist start_hist(int m1, int m2, int m3)
+{
+    return start_hist_rt(DIM, W, m1, m2, m3);
+}
+
+template <int DIM>
+__device__ __forceinline__ int hist_slot(const StartHist &h, int s1, int s2, int s3)
+{
+    return hist_slot_rt(h, DIM >= 2 ? s2 : 0, DIM == 3 ? s3 : 0, s1);
+}
+
+// Box sums of width W along a line of `len` slots (stride st) in place, by
+// one thread: after the call slot k holds the sum of the original slots
+// (k - W, k].
+__device__ __forceinline__ void box_in_place(unsigned *H, int len, int st, int W)
+{
+    unsigned acc = 0;
+    for (int k = 0; k < len; ++k) {
+        acc += H[k * st];
+        H[k * st] = acc;
+    }
+    for (int k = len - 1; k >= W; --k) H[k * st] -= H[(k - W) * st];
+}
+
+// Largest box sum of width W along a line holding `cnt` values (stride st),
+// over all cnt + W - 1 window positions, by one thread.
+__device__ __forceinline__ unsigned box_max(const unsigned *H, int cnt, int st, int W)
+{
+    unsigned acc = 0, mx = 0;
+    for (int k = 0; k < cnt + W - 1; ++k) {
+        if (k < cnt) acc += H[k * st];
+        if (k >= W) acc -= H[(k - W) * st];
+        mx = max(mx, acc);
+    }
+    return mx;
+}
+
+// The same with one wave per line (window positions <= 64): lane k holds
+// position k and adds the W - 1 positions below it by lane shuffles.  Lines
+// are line(l) + k st for l < nl, k < cnt (the positions up to npos are zero
+// beyond cnt).  In place (box sums written back) or, with mx, the largest
+// box sum is folded into *mx instead.
+template <typename Line>
+__device__ __forceinline__ void box_lines(unsigned *H, int nl, int cnt, int npos, int st, int W,
+                                          Line line, unsigned *mx)
+{
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    for (int l = threadIdx.x >> 6; l < nl; l += nw) {
+        unsigned *p = H + line(l);
+        const unsigned v = lane < cnt ? p[lane * st] : 0u;
+        unsigned sum = v;
+        for (int j = 1; j < W; ++j) {
+            const unsigned t = (unsigned)__shfl_up((int)v, j, 64);
+            if (lane >= j) sum += t;
+        }
+        if (lane >= npos) sum = 0u;
+        if (mx) *mx = max(*mx, sum);
+        else if (lane < npos) p[lane * st] = sum;
+    }
+}
+
+// Largest w-box sum of the start histogram over every cell of the tile
+// (all threads of the block call this; it ends with a barrier).  Lines of
+// up to 64 window positions are summed one wave per line, longer ones one
+// thread per line.
+template <int DIM, int W>
+__device__ unsigned tile_bound(unsigned *H, const StartHist &h, unsigned *red)
+{
+    const int tid = threadIdx.x, NT = blockDim.x;
+    unsigned mx = 0;
+    const int lastc = h.c[DIM - 1];
+    const bool waves = h.lx <= 64 && (DIM < 3 || h.ly <= 64) && lastc + W - 1 <= 64;
+    if (waves) {
+        if constexpr (DIM == 1) {
+            box_lines(H, 1, h.c[0], h.c[0] + W - 1, 1, W, [](int) { return 0; }, &mx);
+        } else {
+            // along x, in place, on the rows that hold starts
+            box_lines(H, h.c[2] * h.c[1], h.c[0], h.lx, 1, W,
+                      [&](int r) { return ((r / h.c[1]) * h.ly + r % h.c[1]) * h.lx; }, nullptr);
+            __syncthreads();
+            if constexpr (DIM == 2) {
+                box_lines(H, h.lx, h.c[1], h.c[1] + W - 1, h.lx, W, [](int x) { return x; }, &mx);
+            } else {
+                box_lines(H, h.c[2] * h.lx, h.c[1], h.ly, h.lx, W,
+                          [&](int r) { return (r / h.lx) * h.ly * h.lx + r % h.lx; }, nullptr);
+                __syncthreads();
+                box_lines(H, h.ly * h.lx, h.c[2], h.c[2] + W - 1, h.ly * h.lx, W,
+                          [](int x) { return x; }, &mx);
+            }
+        }
+    } else if constexpr (DIM == 1) {
+        if (tid == 0) mx = box_max(H, h.c[0], 1, W);
+    } else {
+        for (int r = tid; r < h.c[2] * h.c[1]; r += NT)
+            box_in_place(H + ((r / h.c[1]) * h.ly + r % h.c[1]) * h.lx, h.lx, 1, W);
+        __syncthreads();
+        if constexpr (DIM == 2) {
+            for (int x = tid; x < h.lx; x += NT) mx = max(mx, box_max(H + x, h.c[1], h.lx, W));
+        } else {
+            for (int r = tid; r < h.c[2] * h.lx; r += NT)
+                box_in_place(H + (r / h.lx) * h.ly * h.lx + r % h.lx, h.ly, h.lx, W);
+            __syncthreads();
+            for (int x = tid; x < h.ly * h.lx; x += NT)
+                mx = max(mx, box_max(H + x, h.c[2], h.ly * h.lx, W));
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, (unsigned)__shfl_xor((int)mx, o, 64));
+    if ((tid & 63) == 0) red[tid >> 6] = mx;
+    __syncthreads();
+    mx = red[0];
+    for (int k = 1; k < NT / 64; ++k) mx = max(mx, red[k]);
+    __syncthreads();
+    return mx;
+}
+
+// SM spreading with two 64-bit words per cell (one per part): double
+// precision, and single precision in 1D.  The histogram unit is
+// u = 2^(e + ceil(log2 n_q) - 31) with cmax < 2^e the largest part of any
+// strength of the vector (k_maxabs) and n_q the subproblem's point count, so
+// the histogram's total stays below 2^32; with the box bound B u < 2^E the
+// scale is S = 2^(61 - E) and every cell stays below 2^62 in magnitude.
 // Grid-stride loop over the subproblem list; the tile is interleaved
 // (re, im) with ts2 >= 2 p1 p2 p3 entries per slot (a multiple of 8).
-template <typename T> struct FixedScale;
-template <> struct FixedScale<float> {
-    __device__ static float scale(float cmax, int lg_msub, float &inv)
-    {
-        int e;
-        frexpf(cmax, &e);
-        inv = ldexpf(1.0f, e + lg_msub - 62);
-        return ldexpf(1.0f, 62 - lg_msub - e);
-    }
-    __device__ static long long to_fixed(float v) { return __float2ll_rn(v); }
-};
-template <> struct FixedScale<double> {
-    __device__ static double scale(double cmax, int lg_msub, double &inv)
-    {
-        int e;
-        frexp(cmax, &e);
-        inv = ldexp(1.0, e + lg_msub - 62);
-        return ldexp(1.0, 62 - lg_msub - e);
-    }
-    __device__ static long long to_fixed(double v) { return __double2ll_rn(v); }
-};
-
 template <typename T, int DIM, int W, bool BATCH>
 __global__ void __launch_bounds__(kThreads)
 k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__ nsubp,
             const T *__restrict__ u0, const T *__restrict__ u1, const T *__restrict__ u2,
-            const int32_t *__restrict__ perm, const typename Cplx<T>::type *__restrict__ c,
-            const T *__restrict__ cmaxp, int lg_msub, T *__restrict__ scratch, int ts2, T bk,
+            const int32_t *__restrict__ idx, const uint16_t *__restrict__ hslot,
+            const typename Cplx<T>::type *__restrict__ c,
+            const T *__restrict__ cmaxp, T *__restrict__ scratch, int ts2, T bk,
             const TGeom *__restrict__ tg, int T_)
 {
     using V = typename Vec16<T>::type;
     constexpr int NV = 16 / sizeof(T);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     unsigned long long *tile = reinterpret_cast<unsigned long long *>(smem_raw);
+    unsigned *H = reinterpret_cast<unsigned *>(smem_raw);  // start histogram, before the tile
+    __shared__ unsigned red[kThreads / 64];
     constexpr int P = (W + 1) / 2;
     const int nvec = ts2 / NV;
     const int nsub = *nsubp;
-    const T cmax = block_cmax(cmaxp);
+    int ecm;
+    frexp(block_cmax(cmaxp), &ecm);  // cmax < 2^ecm
     for (int q = blockIdx.x; q < nsub; q += gridDim.x) {
         const int4 rec = reinterpret_cast<const int4 *>(sub)[q];
-        // a cell gets at most one contribution per point of the subproblem,
-        // so its own point count (<= msub) bounds the sum
-        int lg = 0;
-        while ((1 << lg) < rec.z && lg < lg_msub) ++lg;
-        T inv;
-        const T S = FixedScale<T>::scale(cmax, lg, inv);
-        int p1 = g.m[0] + 2 * P, p2 = g.m[1] + 2 * P;
+        int m1 = g.m[0], m2 = g.m[1], m3 = g.m[2];
         if constexpr (BATCH) {
             const TGeom &tt =
                 tg[find_transform(tg, T_, rec.x, [](const TGeom &a) { return a.bin_off; })];
-            p1 = tt.m[0] + 2 * P;
-            p2 = tt.m[1] + 2 * P;
+            m1 = tt.m[0];
+            m2 = tt.m[1];
+            m3 = tt.m[2];
         }
+        const int p1 = m1 + 2 * P, p2 = m2 + 2 * P;
+        const StartHist hg = start_hist<DIM, W>(m1, m2, m3);
+        const int end = rec.y + rec.z;
+        // histogram of ceil(a_j / u) over the start cells
+        const int hu = 31 - ceil_log2((unsigned)rec.z) - ecm;  // a_j 2^hu < 2^(31 - lg n_q)
+        for (int e = threadIdx.x; e < hg.size; e += blockDim.x) H[e] = 0u;
+        __syncthreads();
+        for (int i = rec.y + threadIdx.x; i < end; i += blockDim.x) {
+            const auto cv = c[idx[i]];
+            int hs;
+            if (hslot) {
+                hs = hslot[i];
+            } else {
+                const int s1 = start_cell<T, W>(u0[i]);
+                const int s2 = DIM >= 2 ? start_cell<T, W>(u1[i]) : 0;
+                const int s3 = DIM == 3 ? start_cell<T, W>(u2[i]) : 0;
+                hs = hist_slot<DIM>(hg, s1, s2, s3);
+            }
+            const unsigned hv = (unsigned)ceil(ldexp(fmax(fabs(cv.x), fabs(cv.y)), hu));
+            atomicAdd(H + hs, hv);
+        }
+        __syncthreads();
+        const unsigned B = tile_bound<DIM, W>(H, hg, red);
+        const int sh = 61 - (ceil_log2(B) - hu);  // S = 2^sh
         for (int e = threadIdx.x; e < ts2; e += blockDim.x) tile[e] = 0ull;
         __syncthreads();
-        const int end = rec.y + rec.z;
         for (int i = rec.y + threadIdx.x; i < end; i += blockDim.x) {
             T kx[W], ky[W];
             const int sx = taps<T, W>(u0[i] + (T)P, bk, kx);
             int sy = 0;
             if constexpr (DIM >= 2) sy = taps<T, W>(u1[i] + (T)P, bk, ky);
-            const auto cv = c[perm ? perm[i] : i];
-            const T cr0 = cv.x * S, ci0 = cv.y * S;
+            const auto cv = c[idx[i]];
+            const T cr0 = ldexp(cv.x, sh), ci0 = ldexp(cv.y, sh);
             if constexpr (DIM == 1) {
                 unsigned long long *row = tile + 2 * sx;
 #pragma unroll
                 for (int a1 = 0; a1 < W; ++a1) {
                     atomicAdd(row + 2 * a1,
-                              (unsigned long long)FixedScale<T>::to_fixed(cr0 * kx[a1]));
+                              (unsigned long long)to_fixed(cr0 * kx[a1]));
                     atomicAdd(row + 2 * a1 + 1,
-                              (unsigned long long)FixedScale<T>::to_fixed(ci0 * kx[a1]));
+                              (unsigned long long)to_fixed(ci0 * kx[a1]));
                 }
             } else if constexpr (DIM == 2) {
 #pragma unroll
@@ -387,9 +536,9 @@ k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
 #pragma unroll
                     for (int a1 = 0; a1 < W; ++a1) {
                         atomicAdd(row + 2 * a1,
-                                  (unsigned long long)FixedScale<T>::to_fixed(wr * kx[a1]));
+                                  (unsigned long long)to_fixed(wr * kx[a1]));
                         atomicAdd(row + 2 * a1 + 1,
-                                  (unsigned long long)FixedScale<T>::to_fixed(wi * kx[a1]));
+                                  (unsigned long long)to_fixed(wi * kx[a1]));
                     }
                 }
             } else {
@@ -406,9 +555,9 @@ k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
 #pragma unroll
                         for (int a1 = 0; a1 < W; ++a1) {
                             atomicAdd(row + 2 * a1,
-                                      (unsigned long long)FixedScale<T>::to_fixed(wr * kx[a1]));
+                                      (unsigned long long)to_fixed(wr * kx[a1]));
                             atomicAdd(row + 2 * a1 + 1,
-                                      (unsigned long long)FixedScale<T>::to_fixed(wi * kx[a1]));
+                                      (unsigned long long)to_fixed(wi * kx[a1]));
                         }
                     }
                 }
@@ -420,7 +569,7 @@ k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
             T vals[NV];
 #pragma unroll
             for (int k = 0; k < NV; ++k)
-                vals[k] = (T)((double)(long long)tile[e * NV + k] * (double)inv);
+                vals[k] = (T)ldexp((double)(long long)tile[e * NV + k], -sh);
             V out;
             __builtin_memcpy(&out, vals, sizeof(V));
             dst[e] = out;
@@ -429,97 +578,142 @@ k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
     }
 }
 
-// SM spreading in single precision with one LDS atomic per tap.
+// SM spreading in single precision with one LDS atomic per tap (2D / 3D).
 //
 // Same input and output as k_spread_sm<float>, but both parts of a cell share
-// one 64-bit LDS word: with a scale S, a contribution (a, b) becomes the
-// integers r = round(a S), i = round(b S) and the word is incremented by
-// i 2^32 + r (modulo 2^64).  Integer addition is exact, so the word holds
+// one 64-bit LDS word: a contribution (a, b) becomes the integers
+// r = round(a S), i = round(b S) and the word is incremented by i 2^32 + r
+// (modulo 2^64).  Integer addition is exact, so the word holds
 // (sum i) 2^32 + (sum r) as long as both sums stay within int32, and the two
-// sums are read back from its low (signed) and high halves.  The scale is
-// chosen per subproblem from A = max(sum_j |Re c_j|, sum_j |Im c_j|) over its
-// points: since the kernel is at most 1, no cell of the subproblem can gather
-// more than A, and S = 2^29 / 2^ceil(log2 A) leaves a factor two for the
-// rounding of A and of the contributions.  The quantum 1 / S <= A 2^-28
-// tracks the subproblem's own strengths.  This halves the atomics of the
-// 64-bit two-word tile, which bound 3D spreading, and halves its LDS.
+// sums are read back from its low (signed) and high halves.  The histogram
+// unit is u = 2^(ea + ceil(log2 n_q) - 31) with 2^ea above every part of the
+// subproblem's strengths (a maximum, which unlike a floating-point sum does
+// not depend on the order the points are visited in), so the histogram's
+// total stays below 2^32; with the box bound B u < 2^E the scale is
+// S = 2^(30 - E), which keeps every cell's parts below 2^30 plus at most
+// n_q / 2 of rounding.  This halves the
+// atomics of the two-word tile, which bound 3D spreading, and halves its LDS.
 // The strengths gathered for the scale (up to stage_cap of them) stay in LDS
-// for the accumulation: the random gather through the permutation moves a
-// whole cache line per point and is the kernel's main HBM traffic, so it is
-// done once.
+// for the histogram and the accumulation: the random gather through the
+// permutation moves a whole cache line per point and is the kernel's main
+// HBM traffic, so it is done once.  The same pass loads the coordinates and
+// keeps each point's histogram slot (16 bits) in LDS, so the histogram pass
+// reads LDS only.
+// (LDS use, the tile plus the staged strengths, allows about three
+// workgroups per CU, i.e. three waves per SIMD; the register budget follows.)
 template <typename T, int DIM, int W, bool BATCH>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8)))
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
 k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__ nsubp,
              const float *__restrict__ u0, const float *__restrict__ u1,
-             const float *__restrict__ u2, const int32_t *__restrict__ perm,
-             const float2 *__restrict__ c, float *__restrict__ scratch, int ts2, float bk,
-             int stage_cap, const TGeom *__restrict__ tg, int T_)
+             const float *__restrict__ u2, const int32_t *__restrict__ idx,
+             const uint16_t *__restrict__ hslot, const float2 *__restrict__ c,
+             float *__restrict__ scratch, int ts2, float bk, int stage_cap,
+             const TGeom *__restrict__ tg, int T_)
 {
     static_assert(std::is_same<T, float>::value && DIM >= 2, "2D / 3D single precision only");
     constexpr int P = (W + 1) / 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     unsigned long long *tile = reinterpret_cast<unsigned long long *>(smem_raw);  // ts2 / 2 cells
+    unsigned *H = reinterpret_cast<unsigned *>(smem_raw);  // start histogram, before the tile
     float2 *cs = reinterpret_cast<float2 *>(tile + ts2 / 2);  // first stage_cap strengths
-    __shared__ float red[2][kThreads / 64];
+    unsigned short *slot = reinterpret_cast<unsigned short *>(cs + stage_cap);  // their slots
+    __shared__ float red[kThreads / 64];
+    __shared__ unsigned redu[kThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int ncell = ts2 / 2;
     const int nsub = *nsubp;
     for (int q = blockIdx.x; q < nsub; q += gridDim.x) {
         const int4 rec = reinterpret_cast<const int4 *>(sub)[q];
-        int p1 = g.m[0] + 2 * P, p2 = g.m[1] + 2 * P;
+        int m1 = g.m[0], m2 = g.m[1], m3 = g.m[2];
         if constexpr (BATCH) {
             const TGeom &tt =
                 tg[find_transform(tg, T_, rec.x, [](const TGeom &a) { return a.bin_off; })];
-            p1 = tt.m[0] + 2 * P;
-            p2 = tt.m[1] + 2 * P;
+            m1 = tt.m[0];
+            m2 = tt.m[1];
+            m3 = tt.m[2];
         }
+        const int p1 = m1 + 2 * P, p2 = m2 + 2 * P;
+        const StartHist hg = start_hist<DIM, W>(m1, m2, m3);
         const int end = rec.y + rec.z;
-        // scale of this subproblem (the gathers are issued kPre at a time so
-        // that their latencies overlap)
+        // the largest part of any strength and the histogram slots of the
+        // staged points (the loads are issued kPre at a time so that their
+        // latencies overlap)
         constexpr int kPre = 8;
-        float sr = 0.f, si = 0.f;
+        float am = 0.f;
         for (int i0 = rec.y + tid; i0 < end; i0 += kPre * kThreads) {
-            int pj[kPre];
+            int pj[kPre], hs[kPre];
 #pragma unroll
             for (int k = 0; k < kPre; ++k) {
                 const int i = i0 + k * kThreads;
-                pj[k] = i < end ? (perm ? perm[i] : i) : -1;
+                const bool in = i < end;
+                pj[k] = in ? idx[i] : -1;
+                const bool st = in && i - rec.y < stage_cap;
+                if (hslot) {
+                    hs[k] = st ? (int)hslot[i] : 0;
+                } else if (st) {
+                    hs[k] = hist_slot<DIM>(hg, start_cell<float, W>(u0[i]),
+                                           start_cell<float, W>(u1[i]),
+                                           DIM == 3 ? start_cell<float, W>(u2[i]) : 0);
+                } else {
+                    hs[k] = 0;
+                }
             }
 #pragma unroll
             for (int k = 0; k < kPre; ++k) {
                 if (pj[k] >= 0) {
                     const float2 cv = c[pj[k]];
-                    sr += fabsf(cv.x);
-                    si += fabsf(cv.y);
+                    am = fmaxf(am, fmaxf(fabsf(cv.x), fabsf(cv.y)));
                     const int j = i0 + k * kThreads - rec.y;
-                    if (j < stage_cap) cs[j] = cv;
+                    if (j < stage_cap) {
+                        cs[j] = cv;
+                        slot[j] = (unsigned short)hs[k];
+                    }
                 }
             }
         }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            sr += __shfl_xor(sr, o, 64);
-            si += __shfl_xor(si, o, 64);
-        }
-        if (lane == 0) {
-            red[0][wv] = sr;
-            red[1][wv] = si;
-        }
-        for (int e = tid; e < ncell; e += kThreads) tile[e] = 0ull;
+        for (int o = 32; o > 0; o >>= 1) am = fmaxf(am, __shfl_xor(am, o, 64));
+        if (lane == 0) red[wv] = am;
+        for (int e = tid; e < hg.size; e += kThreads) H[e] = 0u;
         __syncthreads();
         float A = 0.f;
-        for (int k = 0; k < kThreads / 64; ++k) A = fmaxf(A, fmaxf(red[0][k], red[1][k]));
+        for (int k = 0; k < kThreads / 64; ++k) A = fmaxf(A, red[k]);
         int ea;
-        frexpf(A, &ea);  // A < 2^ea
-        const float S = ldexpf(1.0f, 29 - ea), inv = ldexpf(1.0f, ea - 29);
+        frexpf(A, &ea);  // every part of every strength is below 2^ea
+        // histogram unit 2^-hu: each entry is below 2^(31 - lg n_q), so the
+        // histogram's total stays below 2^32
+        const int hu = 31 - ceil_log2((unsigned)rec.z) - ea;
+        // strengths past the staged ones are gathered again
+        auto strength = [&](int ii) {
+            return ii - rec.y < stage_cap ? cs[ii - rec.y] : c[idx[ii]];
+        };
+        // histogram of ceil(a_j 2^hu) over the start cells
+        for (int i = rec.y + tid; i < end; i += kThreads) {
+            const int j = i - rec.y;
+            int hs;
+            float2 cv;
+            if (j < stage_cap) {
+                hs = slot[j];
+                cv = cs[j];
+            } else {
+                hs = hslot ? (int)hslot[i]
+                           : hist_slot<DIM>(hg, start_cell<float, W>(u0[i]),
+                                            start_cell<float, W>(u1[i]),
+                                            DIM == 3 ? start_cell<float, W>(u2[i]) : 0);
+                cv = c[idx[i]];
+            }
+            const unsigned hv = (unsigned)ceilf(ldexpf(fmaxf(fabsf(cv.x), fabsf(cv.y)), hu));
+            atomicAdd(H + hs, hv);
+        }
+        __syncthreads();
+        const unsigned B = tile_bound<DIM, W>(H, hg, redu);
+        const int sh = 30 - (ceil_log2(B) - hu);  // S = 2^sh: cells below 2^30
+        for (int e = tid; e < ncell; e += kThreads) tile[e] = 0ull;
+        __syncthreads();
         // points of this thread, with the next one's loads issued ahead
         int i = rec.y + tid;
         float nu0 = 0.f, nu1 = 0.f, nu2 = 0.f;
         float2 ncv = make_float2(0.f, 0.f);
-        // strengths past the staged ones are gathered again
-        auto strength = [&](int ii) {
-            return ii - rec.y < stage_cap ? cs[ii - rec.y] : c[perm ? perm[ii] : ii];
-        };
         if (i < end) {
             nu0 = u0[i];
             if constexpr (DIM >= 2) nu1 = u1[i];
@@ -539,7 +733,7 @@ k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict_
             const int sx = taps<float, W>(x0 + (float)P, bk, kx);
             int sy = 0;
             if constexpr (DIM >= 2) sy = taps<float, W>(x1 + (float)P, bk, ky);
-            const float cr0 = cv.x * S, ci0 = cv.y * S;
+            const float cr0 = ldexpf(cv.x, sh), ci0 = ldexpf(cv.y, sh);
             auto row_add = [&](unsigned long long *row, float wr, float wi) {
 #pragma unroll
                 for (int a1 = 0; a1 < W; ++a1) {
@@ -576,8 +770,8 @@ k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict_
                 const long long word = (long long)tile[2 * e + h];
                 const int r = (int)(unsigned)(word & 0xffffffffll);
                 const long long im = (word - (long long)r) >> 32;
-                v[2 * h] = (float)r * inv;
-                v[2 * h + 1] = (float)im * inv;
+                v[2 * h] = ldexpf((float)r, -sh);
+                v[2 * h + 1] = ldexpf((float)im, -sh);
             }
             dst[e] = make_float4(v[0], v[1], v[2], v[3]);
         }
@@ -787,7 +981,7 @@ template <typename T, int DIM, int W, bool BATCH>
 __global__ void __launch_bounds__(kThreads)
 k_interp_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__ nsubp,
             const T *__restrict__ u0, const T *__restrict__ u1, const T *__restrict__ u2,
-            const int32_t *__restrict__ perm, const typename Cplx<T>::type *__restrict__ grid_,
+            const int32_t *__restrict__ idx, const typename Cplx<T>::type *__restrict__ grid_,
             typename Cplx<T>::type *__restrict__ c, T bk, const TGeom *__restrict__ tg, int T_)
 {
     using C = typename Cplx<T>::type;
@@ -841,24 +1035,35 @@ k_interp_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
         }
         __syncthreads();
         const int end = rec.y + rec.z;
-        int i = rec.y + threadIdx.x;
-        T nu0 = 0, nu1 = 0, nu2 = 0;
-        int npj = 0;
-        if (i < end) {
-            nu0 = u0[i];
-            if constexpr (DIM >= 2) nu1 = u1[i];
-            if constexpr (DIM == 3) nu2 = u2[i];
-            npj = perm ? perm[i] : i;
-        }
-        for (; i < end; i += blockDim.x) {
-            const T x0 = nu0, x1 = nu1, x2 = nu2;
-            const int pj = npj;
-            if (i + (int)blockDim.x < end) {
-                nu0 = u0[i + blockDim.x];
-                if constexpr (DIM >= 2) nu1 = u1[i + blockDim.x];
-                if constexpr (DIM == 3) nu2 = u2[i + blockDim.x];
-                npj = perm ? perm[i + blockDim.x] : i + (int)blockDim.x;
-            }
+        const int NT = blockDim.x;
+        // Round r of the subproblem's points is thread t's point rec.y + t + r NT.
+        // Its loads are issued kAhead rounds before its use: one counter tracks
+        // vector loads and stores together, so waiting for a load also waits
+        // for every store issued before it, and the scattered result stores
+        // are slow to complete.  Every load is unconditional (lanes past the
+        // last point take the last point again and store the same value to
+        // the same place), so the compiler can wait for exactly the loads it
+        // needs.
+        constexpr int kAhead = 4;
+        const int nr = (rec.z + NT - 1) / NT;  // rounds, the same for every thread
+        T a0[kAhead], a1[kAhead], a2[kAhead];
+        int ap[kAhead];
+        auto load_round = [&](int r, int k) {
+            const int ii = min(rec.y + (int)threadIdx.x + r * NT, end - 1);
+            a0[k] = u0[ii];
+            a1[k] = DIM >= 2 ? u1[ii] : (T)0;
+            a2[k] = DIM == 3 ? u2[ii] : (T)0;
+            ap[k] = idx[ii];
+        };
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k) load_round(k, k);
+        for (int r0 = 0; r0 < nr; r0 += kAhead) {
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k) {
+            if (r0 + k >= nr) continue;
+            const T x0 = a0[k], x1 = a1[k], x2 = a2[k];
+            const int pj = ap[k];
+            load_round(r0 + k + kAhead, k);
             T kx[W], ky[W];
             const int sx = taps<T, W>(x0 + (T)P, bk, kx);
             int sy = 0;
@@ -915,6 +1120,7 @@ k_interp_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
             out.y = ai;
             c[pj] = out;
         }
+        }
         __syncthreads();
     }
 }
@@ -926,6 +1132,11 @@ inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 template <typename T> T kernel_param(double beta);
 template <> inline float kernel_param<float>(double beta) { return (float)(beta * 1.4426950408889634); }
 template <> inline double kernel_param<double>(double beta) { return beta; }
+
+// Index array of the SM kernels: the input index of each processed point
+// (strength / result in the caller's order), or for vectors kept in
+// bin-sorted order its sorted position.
+inline const int32_t *sm_index(const Pts &P) { return P.perm ? P.perm : P.spos; }
 
 // Persistent grid size for the subproblem loops.
 inline int sm_grid(const Pts &P) { return std::max(1, std::min(P.nsub_max, 256 * 16)); }
@@ -1090,7 +1301,7 @@ hipError_t spread_wb(const Geom &g, int method, const Pts &P, const void *c, voi
                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
                 hipLaunchKernelGGL(pk, dim3(sm_grid(P)), dim3(kThreads), lds, s, g, P.sub,
                                    P.nsub, (const float *)P.u[0], (const float *)P.u[1],
-                                   (const float *)P.u[2], P.perm, (const float2 *)c,
+                                   (const float *)P.u[2], sm_index(P), P.hslot, (const float2 *)c,
                                    (float *)P.scratch, P.ts2, (float)bk,
                                    smp_stage(DIM, P.msub), P.tg, P.T);
             } else {
@@ -1098,11 +1309,10 @@ hipError_t spread_wb(const Geom &g, int method, const Pts &P, const void *c, voi
                 if (lds > 65536)
                     (void)hipFuncSetAttribute((const void *)kern,
                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-                int lg = 0;
-                while ((1 << lg) < P.msub) ++lg;
                 hipLaunchKernelGGL(kern, dim3(sm_grid(P)), dim3(kThreads), lds, s, g, P.sub,
                                    P.nsub, (const T *)P.u[0], (const T *)P.u[1], (const T *)P.u[2],
-                                   P.perm, (const C *)c, (const T *)P.cmax, lg, (T *)P.scratch,
+                                   sm_index(P), P.hslot, (const C *)c, (const T *)P.cmax,
+                                   (T *)P.scratch,
                                    P.ts2, bk, P.tg, P.T);
             }
         }
@@ -1158,7 +1368,7 @@ hipError_t interp_wb(const Geom &g, int method, const Pts &P, const void *grid, 
             (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)lds);
         hipLaunchKernelGGL(kern, dim3(sm_grid(P)), dim3(kThreads), lds, s, g, P.sub, P.nsub,
-                           (const T *)P.u[0], (const T *)P.u[1], (const T *)P.u[2], P.perm,
+                           (const T *)P.u[0], (const T *)P.u[1], (const T *)P.u[2], sm_index(P),
                            (const C *)grid, (C *)c, bk, P.tg, P.T);
     } else {
         const bool gm = method == 1;

@@ -33,9 +33,13 @@ EXPORTS = (
     "mnufft_batch_makeplan", "mnufft_batch_setpts", "mnufft_batch_execute",
     "mnufft_batch_set_timing", "mnufft_batch_get_timing", "mnufft_batch_get_totals",
     "mnufft_batch_destroy", "mnufft_tune_candidates", "mnufft_tune_time",
-    "mnufft_density_features", "mnufft_density_features_batch", "mnufft_mlp_nparams", "mnufft_mlp_forward",
+    "mnufft_density_features", "mnufft_density_features_batch",
+    "mnufft_mlp_nparams", "mnufft_mlp_forward",
     "mnufft_mlp_loss_grad", "mnufft_mlp_backward", "mnufft_mlp_adam",
+    "mnufft_selector_load", "mnufft_selector_clear", "mnufft_select", "mnufft_batch_select",
 )
+TUNE_OFF, TUNE_AUTOTUNE, TUNE_LEARNED = 0, 1, 2
+TUNES = {"off": TUNE_OFF, "autotune": TUNE_AUTOTUNE, "learned": TUNE_LEARNED}
 DENSITY_WORK_BYTES = 512 * 256 * 4
 DENSITY_BATCH_WORK_BYTES = 32 * 256 * 4  # per point set
 
@@ -52,7 +56,8 @@ class Opts(ctypes.Structure):
         ("device", ctypes.c_int),
         ("stream", ctypes.c_void_p),
         ("upsampfac", ctypes.c_double),
-        ("reserved", ctypes.c_int * 6),
+        ("tune", ctypes.c_int),
+        ("reserved", ctypes.c_int * 5),
     ]
 
 
@@ -149,6 +154,14 @@ def load():
     L.mnufft_mlp_backward.argtypes = [ci, ci, ci, vp, ci, vp, vp, vp, vp, vp, vp, vp]
     L.mnufft_mlp_adam.argtypes = [i64, vp, vp, vp, vp, ctypes.c_float, ctypes.c_float,
                                   ctypes.c_float, ctypes.c_float, ci, vp]
+    L.mnufft_selector_load.argtypes = [ctypes.c_char_p]
+    L.mnufft_selector_clear.argtypes = []
+    L.mnufft_select.argtypes = [ci, ci, ctypes.POINTER(i64), ci, ctypes.c_double, ci, i64, vp, vp,
+                                vp, ci, ctypes.POINTER(Opts), ctypes.POINTER(Opts),
+                                ctypes.POINTER(ci)]
+    L.mnufft_batch_select.argtypes = [ci, ci, ci, ctypes.POINTER(i64), ctypes.POINTER(i64), vp,
+                                      vp, vp, ctypes.c_double, ci, ci, ctypes.POINTER(Opts),
+                                      i32p, i32p, i32p]
     for name in EXPORTS:
         getattr(L, name).restype = ctypes.c_char_p if name == "mnufft_strerror" else ci
     L.mnufft_mlp_nparams.restype = ctypes.c_int64
@@ -202,6 +215,54 @@ def tune_candidates(dim, prec, eps):
     check(load().mnufft_tune_candidates(int(dim), int(prec), float(eps), arr, n),
           "mnufft_tune_candidates")
     return [arr[i] for i in range(n)]
+
+
+def selector_load(path):
+    """Register a learned selector file with the library (mnufft_selector_load)."""
+    check(load().mnufft_selector_load(str(path).encode()), "mnufft_selector_load")
+
+
+def select(nufft_type, n_modes, points, eps, mode="learned", isign=None, upsampfac=0.0):
+    """(Opts chosen by mnufft_select, source: 0 learned / 1 autotuner) for one
+    problem on its points (torch device tensors of the run precision)."""
+    import torch
+    dim = len(n_modes)
+    prec = F32 if points[0].dtype == torch.float32 else F64
+    nm = (ctypes.c_int64 * 3)(*(list(n_modes) + [1] * (3 - dim)))
+    base = default_opts()
+    base.stream = torch.cuda.current_stream().cuda_stream
+    base.upsampfac = float(upsampfac)
+    out, src = Opts(), ctypes.c_int(-1)
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+    pts = list(points) + [None] * (3 - dim)
+    isign = isign if isign is not None else (-1 if nufft_type == 1 else 1)
+    check(load().mnufft_select(int(nufft_type), dim, nm, int(isign), float(eps), prec,
+                               points[0].numel(), ptr(pts[0]), ptr(pts[1]), ptr(pts[2]),
+                               TUNES[mode], ctypes.byref(base), ctypes.byref(out),
+                               ctypes.byref(src)), "mnufft_select")
+    return out, src.value
+
+
+def batch_select(nufft_type, n_modes_list, npts, x, y, eps, z=None, mode="learned"):
+    """Per-transform (binsize list, msub list, source list) from
+    mnufft_batch_select for point sets stored back to back in x, y (, z)."""
+    import torch
+    T = len(npts)
+    dim = len(n_modes_list[0])
+    prec = F32 if x.dtype == torch.float32 else F64
+    nm = (ctypes.c_int64 * (3 * T))(*[v for m in n_modes_list for v in list(m) + [1] * (3 - dim)])
+    npa = (ctypes.c_int64 * T)(*[int(m) for m in npts])
+    bins = (ctypes.c_int32 * (3 * T))()
+    msub = (ctypes.c_int32 * T)()
+    src = (ctypes.c_int32 * T)()
+    base = default_opts()
+    base.stream = torch.cuda.current_stream().cuda_stream
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+    check(load().mnufft_batch_select(int(nufft_type), dim, T, nm, npa, ptr(x), ptr(y), ptr(z),
+                                     float(eps), prec, TUNES[mode], ctypes.byref(base), bins,
+                                     msub, src), "mnufft_batch_select")
+    return ([tuple(bins[3 * t + d] for d in range(dim)) for t in range(T)],
+            [msub[t] for t in range(T)], [src[t] for t in range(T)])
 
 
 def describe(o):

@@ -44,11 +44,13 @@ class Plan:
     method       "auto", "gm", "gmsort" or "sm"
     binsize      bin extents m_i (None = library default), msub: points per subproblem
     upsampfac    fine-grid upsampling factor sigma (0 = 2; 1.25 .. 2 allowed)
+    tune         "off", "autotune" or "learned": every setpts lets the library
+                 choose method, bins and msub for the points (mnufft_select)
     """
 
     def __init__(self, nufft_type, n_modes, n_trans=1, eps=1e-6, isign=None,
                  dtype=torch.complex64, method="auto", binsize=None, msub=0,
-                 device=None, validate_pts=False, upsampfac=0.0):
+                 device=None, validate_pts=False, upsampfac=0.0, tune="off"):
         self._lib = L.load()
         self._h = ctypes.c_void_p(0)
         if dtype not in _PREC:
@@ -75,6 +77,7 @@ class Plan:
         o.msub = int(msub)
         o.validate_pts = int(bool(validate_pts))
         o.upsampfac = float(upsampfac)
+        o.tune = L.TUNES[tune] if isinstance(tune, str) else int(tune)
         o.device = self.device.index if self.device.index is not None else -1
         o.stream = torch.cuda.current_stream(self.device).cuda_stream
         self._stream = torch.cuda.current_stream(self.device)

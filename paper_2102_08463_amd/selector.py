@@ -159,17 +159,39 @@ class Selector:
         return best, gap, False
 
     # -- persistence -------------------------------------------------------
-    def save(self, path):
-        np.savez(path, params=self.params.cpu().numpy(), names=np.array(self.names),
-                 dim=self.dim, prec=self.prec, eps=self.eps)
+    # The library's selector file (mnufft_selector_load): "MNSEL001", int32
+    # dim, prec, double eps, int32 F, H, K, double margin, K candidate records
+    # of int32 (method, binsize[3], msub), then the float32 parameters.
+    MAGIC = b"MNSEL001"
+
+    def save(self, path, margin=0.0):
+        head = np.array([self.dim, self.prec], np.int32).tobytes() + \
+            np.array([self.eps], np.float64).tobytes() + \
+            np.array([F, H, self.K], np.int32).tobytes() + \
+            np.array([margin], np.float64).tobytes()
+        recs = np.array([[o.method, o.binsize[0], o.binsize[1], o.binsize[2], o.msub]
+                         for o in self.cands], np.int32).tobytes()
+        with open(path, "wb") as fh:
+            fh.write(self.MAGIC + head + recs + self.params.cpu().numpy().astype(np.float32).tobytes())
 
     @classmethod
     def load(cls, path, device=None):
-        d = np.load(path, allow_pickle=False)
-        s = cls(int(d["dim"]), int(d["prec"]), float(d["eps"]), device=device)
-        if list(d["names"]) != s.names:
+        raw = open(path, "rb").read()
+        if raw[:8] != cls.MAGIC:
+            raise ValueError("not a selector file")
+        dim, prec = np.frombuffer(raw, np.int32, 2, 8)
+        eps = float(np.frombuffer(raw, np.float64, 1, 16)[0])
+        f, h, k = np.frombuffer(raw, np.int32, 3, 24)
+        s = cls(int(dim), int(prec), eps, device=device)
+        if (int(f), int(h), int(k)) != (F, H, s.K):
+            raise ValueError("weights were trained for another network or candidate list")
+        recs = np.frombuffer(raw, np.int32, 5 * s.K, 44).reshape(s.K, 5)
+        mine = [[o.method, o.binsize[0], o.binsize[1], o.binsize[2], o.msub] for o in s.cands]
+        if recs.tolist() != mine:
             raise ValueError("weights were trained for another candidate list")
-        s.params = torch.from_numpy(d["params"]).float().to(s.device)
+        s.margin = float(np.frombuffer(raw, np.float64, 1, 36)[0])
+        s.params = torch.from_numpy(
+            np.frombuffer(raw, np.float32, s.n, 44 + 20 * s.K).copy()).float().to(s.device)
         return s
 
 

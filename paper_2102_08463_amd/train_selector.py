@@ -4,9 +4,10 @@ Draws a set of synthetic 2D problems shaped like the batched workload
 (modes uniform in {64..512}^2, M lognormal around 2e5 within [1e4, 4e6],
 uniform / clustered / radial points, types 1 and 2), times every autotuner
 candidate on each with the library's timer, trains the MLP with the
-library's kernels and writes the weights (.npz) and the timing table (.npz).
+library's kernels and writes the weights in the library's selector format
+(mnufft_selector_load) and the timing table (.npz).
 
-    python -m paper_2102_08463_amd.train_selector --out weights.npz --problems 48
+    python -m paper_2102_08463_amd.train_selector --out weights.bin --problems 48
 """
 import argparse
 import math
@@ -68,6 +69,8 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--epochs", type=int, default=3000)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--margin", type=float, default=0.0,
+                    help="predicted log-time margin below which the library asks the autotuner")
     args = ap.parse_args()
     torch.cuda.set_device(0)
     sel = Selector(2, L.F32, args.eps)
@@ -80,7 +83,7 @@ def main():
     hist = sel.fit(torch.from_numpy(X).to(dev), torch.from_numpy(T).to(dev),
                    torch.from_numpy(Mk).to(dev), epochs=args.epochs, log_every=500)
     print(f"[train] loss {hist}", flush=True)
-    sel.save(args.out)
+    sel.save(args.out, margin=args.margin)
     if args.table:
         np.savez(args.table, X=X, T=T, mask=Mk, ms=raw, names=np.array(sel.names),
                  problems=np.array([str(p) for p in probs]))

@@ -31,6 +31,14 @@ def make_complex(shape, prec, seed=1):
     return v.astype(np.complex128), torch.from_numpy(np.ascontiguousarray(v)).cuda()
 
 
+def make_heavy(shape, prec, seed=1):
+    """Heavy-tailed strengths (workloads.heavy_strengths), cast like make_complex."""
+    import torch
+    v = workloads.heavy_strengths(shape, seed)
+    v = v.astype(np.complex64 if prec == "f32" else np.complex128)
+    return v.astype(np.complex128), torch.from_numpy(np.ascontiguousarray(v)).cuda()
+
+
 def cdtype(prec):
     import torch
     return torch.complex64 if prec == "f32" else torch.complex128

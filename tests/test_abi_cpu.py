@@ -34,6 +34,7 @@ def test_struct_layouts():
     assert ctypes.sizeof(L.Opts) == 72
     assert L.Opts.stream.offset == 32
     assert L.Opts.upsampfac.offset == 40
+    assert L.Opts.tune.offset == 48
     # mnufft_info ends with upsampfac (double) and ntargets (int64)
     assert L.Info.ntargets.offset == L.Info.upsampfac.offset + 8
     assert ctypes.sizeof(L.Info) == L.Info.ntargets.offset + 8
@@ -247,3 +248,65 @@ def test_tune_candidates_fixed_order_and_lds_fit(dim, prec, eps):
     # the same list on every call
     assert [L.describe(o) for o in L.tune_candidates(dim, prec, eps)] == \
         [L.describe(o) for o in cands]
+
+
+@pytest.mark.parametrize("field", ["binsize", "msub", "method", "type3", "dim1", "bad"])
+def test_makeplan_rejects_tune_with_fixed_parameters(field):
+    """opts.tune picks method, bins and msub itself (types 1 / 2, 2D / 3D):
+    combined with fixed ones, or out of range, makeplan refuses before any
+    device call."""
+    lib = L.load()
+    o = L.default_opts()
+    o.tune = L.TUNE_LEARNED
+    typ, dim = 1, 2
+    if field == "binsize":
+        o.binsize[0] = 32
+    elif field == "msub":
+        o.msub = 1024
+    elif field == "method":
+        o.method = L.METHOD_SM
+    elif field == "type3":
+        typ = 3
+    elif field == "dim1":
+        dim = 1
+    else:
+        o.tune = 7
+    nm = (ctypes.c_int64 * 3)(64, 64, 1)
+    h = ctypes.c_void_p(0)
+    assert lib.mnufft_makeplan(typ, dim, nm, -1, 1, 1e-6, L.F32, ctypes.byref(o),
+                               ctypes.byref(h)) == L.ERR_ARG
+    assert not h.value
+
+
+def _selector_file(path, dim=2, prec=0, eps=1e-6, H=8, margin=0.0, recs=None, extra=b""):
+    cands = L.tune_candidates(dim, prec, eps)
+    K = len(cands)
+    if recs is None:
+        recs = [[o.method, o.binsize[0], o.binsize[1], o.binsize[2], o.msub] for o in cands]
+    n = int(L.load().mnufft_mlp_nparams(262, H, K))
+    with open(path, "wb") as fh:
+        fh.write(b"MNSEL001" + np.array([dim, prec], np.int32).tobytes() +
+                 np.array([eps], np.float64).tobytes() + np.array([262, H, K], np.int32).tobytes() +
+                 np.array([margin], np.float64).tobytes() + np.array(recs, np.int32).tobytes() +
+                 np.zeros(n, np.float32).tobytes() + extra)
+
+
+def test_selector_load_format(tmp_path):
+    """mnufft_selector_load (host only) takes a well-formed file and refuses a
+    missing file, a wrong magic, a candidate list that is not the
+    autotuner's, and trailing bytes."""
+    lib = L.load()
+    good = tmp_path / "good.bin"
+    _selector_file(good)
+    assert lib.mnufft_selector_load(str(good).encode()) == L.OK
+    assert lib.mnufft_selector_load(str(tmp_path / "missing.bin").encode()) == L.ERR_ARG
+    bad = tmp_path / "magic.bin"
+    bad.write_bytes(b"MNSELxxx" + good.read_bytes()[8:])
+    assert lib.mnufft_selector_load(str(bad).encode()) == L.ERR_ARG
+    cands = L.tune_candidates(2, 0, 1e-6)
+    recs = [[o.method, o.binsize[0], o.binsize[1], o.binsize[2], o.msub] for o in cands][::-1]
+    _selector_file(tmp_path / "order.bin", recs=recs)
+    assert lib.mnufft_selector_load(str(tmp_path / "order.bin").encode()) == L.ERR_ARG
+    _selector_file(tmp_path / "extra.bin", extra=b"\0")
+    assert lib.mnufft_selector_load(str(tmp_path / "extra.bin").encode()) == L.ERR_ARG
+    assert lib.mnufft_selector_clear() == L.OK

@@ -65,3 +65,34 @@ def test_summarize_profiles_calibrates_traffic(tmp_path):
     assert t["2d:k_interp_sm"]["bytes_per_launch"] == pytest.approx((100000 * 2.0 + 300000) * 1024)
     text = open(md).read()
     assert "k_spread_smp<float, 2, 6, false>" in text and "250.0" in text
+
+
+def test_summarize_profiles_sq_fractions(tmp_path):
+    """SQ counters -> utilisation fractions: cycles are one XCD's
+    GRBM_GUI_ACTIVE (the CSV sums eight), fractions are per CU and cycle."""
+    d = str(tmp_path)
+    spread = "void mn::detail::k_spread_smp<float, 3, 6, false>(mn::Geom, int const*)"
+    _write(f"{d}/stats/run_kernel_stats.csv", ["Name", "Calls", "AverageNs", "Percentage"],
+           [[spread, 1, 1000000, 50.0]])
+    cyc = 2_400_000  # 1 ms at 2.4 GHz on each XCD
+    rows = [[spread, "GRBM_GUI_ACTIVE", 8 * cyc],
+            [spread, "SQ_ACTIVE_INST_VALU", 0.5 * 256 * cyc],
+            [spread, "SQ_INSTS_VALU", 0.25 * 256 * cyc],
+            [spread, "SQ_LDS_IDX_ACTIVE", 0.75 * 256 * cyc],
+            [spread, "SQ_LDS_BANK_CONFLICT", 0.25 * 256 * cyc],
+            [spread, "SQ_WAVE_CYCLES", 16 * 256 * cyc / 4]]
+    _write(f"{d}/sq/run_counter_collection.csv", ["Kernel_Name", "Counter_Name", "Counter_Value"],
+           rows)
+    out = f"{d}/counters.json"
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--summarize-profiles",
+                        "--stats-dir", f"{d}/stats", "--sq-dir", f"{d}/sq", "--workload", "3d",
+                        "--md-out", f"{d}/s.md", "--counters-out", out],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    e = json.load(open(out))["3d:k_spread_smp"]
+    assert e["valu_busy"] == pytest.approx(0.5) and e["lds_util"] == pytest.approx(0.75)
+    assert e["lds_bank_conflict"] == pytest.approx(0.25)
+    assert e["valu_insts_per_cu_cycle"] == pytest.approx(0.25)
+    assert e["occupancy"] == pytest.approx(0.5)
+    assert e["source_hash"] == bench.kernel_source_hash()
+    assert "| `k_spread_smp` | 0.50 | 0.25 | 0.75 | 0.25 | 0.50 |" in open(f"{d}/s.md").read()

@@ -99,7 +99,7 @@ def test_training_reduces_loss():
 
 
 WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
-                       "paper_2102_08463_amd", "data", "selector_2d_f32_1e-06.npz")
+                       "paper_2102_08463_amd", "data", "selector_2d_f32_1e-06.bin")
 
 
 def test_choose_falls_back_below_margin():
@@ -138,37 +138,45 @@ def test_batched_features_match_single():
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained selector weights in the package")
 def test_trained_selector_gain_over_defaults():
     """On held-out problems (another seed than the training set) the trained
-    selector's pick is timed against the library defaults and against the
-    exhaustive autotuner's best: gain = geomean(t_default / t_selected),
-    regret = geomean(t_selected / t_best).  Results do not depend on the
-    pick (every candidate is checked against the exact sums elsewhere)."""
+    selector's pick is timed against the library defaults (the adaptive
+    bins: 32 x 32, halved while the grid holds fewer than 1024 bins; msub
+    4096) and against the exhaustive autotuner's best:
+    gain = geomean(t_default / t_selected), regret = geomean(t_selected / t_best).
+    Results do not depend on the pick (every candidate is checked against
+    the exact sums elsewhere)."""
     import torch
+    from paper_2102_08463_amd import lib as L
     from paper_2102_08463_amd.selector import Selector
     from paper_2102_08463_amd.train_selector import draw_problems
     from paper_2102_08463_amd.tune import time_candidates
     import workloads
     sel = Selector.load(WEIGHTS)
-    dflt = sel.names.index("sm:32x32:4096")
-    gains, regrets = [], []
+    dflt = L.default_opts()
+    gains, regrets, auto = [], [], []
     for p in draw_problems(24, seed=99, mmax=1_000_000):
         note(f"selector gain {p}")
         pts = [torch.from_numpy(np.asarray(a, np.float32)).cuda()
                for a in workloads.points(p["kind"], p["M"], 2, p["seed"])]
         feat = sel.features(p["type"], p["N"], pts)
         _, _, Y = sel.forward(feat.reshape(1, -1))
-        _, ms = time_candidates(p["type"], p["N"], pts, sel.eps, candidates=sel.cands, reps=5)
-        ms = np.array(ms)
+        _, ms = time_candidates(p["type"], p["N"], pts, sel.eps,
+                                candidates=list(sel.cands) + [dflt], reps=5)
+        t_def = ms[-1]
+        ms = np.array(ms[:-1])
         y = Y[0].cpu().numpy()
         y[ms <= 0] = np.inf
         pick = int(np.argmin(y))
         best = ms[ms > 0].min()
-        gains.append(ms[dflt] / ms[pick])
+        gains.append(t_def / ms[pick])
         regrets.append(ms[pick] / best)
+        auto.append(t_def / best)
     gain = float(np.exp(np.mean(np.log(gains))))
     regret = float(np.exp(np.mean(np.log(regrets))))
-    print(f"[selector] gain over defaults {gain:.3f}x, regret vs autotuner {regret:.3f}x "
+    ceiling = float(np.exp(np.mean(np.log(auto))))
+    print(f"[selector] gain over the adaptive defaults {gain:.3f}x (autotuner's best "
+          f"{ceiling:.3f}x), regret vs autotuner {regret:.3f}x "
           f"(per problem gain {np.round(gains, 2).tolist()})", flush=True)
-    # the defaults are far from the best on these small, uneven problems; the
-    # network must recover a clear part of that, and stay near the autotuner
-    assert gain >= 1.15
-    assert regret <= 1.5
+    # the selector must not lose to the defaults on average and stay near the
+    # autotuner's best
+    assert gain >= 1.0
+    assert regret <= 1.3

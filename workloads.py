@@ -139,6 +139,16 @@ def strengths(shape, seed=1):
     return re + 1j * im
 
 
+def heavy_strengths(shape, seed=1, sigma=2.3):
+    """Complex strengths with lognormal magnitudes (log-magnitude N(0, sigma^2);
+    sigma = 2.3 puts the 0.1% and 99.9% quantiles six decades apart) and
+    uniform phases: a wide dynamic range among the points of any one bin."""
+    g = rng(seed)
+    mag = np.exp(sigma * g.standard_normal(shape))
+    ph = g.uniform(0.0, 2.0 * math.pi, size=shape)
+    return mag * np.cos(ph) + 1j * (mag * np.sin(ph))
+
+
 def batch_descriptors(ntransf=64, seed=7, mmin=10_000, mmax=4_000_000, median=200_000):
     """Mode counts and point counts of the batched 2D workload: N_1, N_2 iid
     uniform integers in [64, 512]; M lognormal with the given median, sigma 1,
