@@ -100,9 +100,11 @@ __host__ __device__ inline int start_cell_rt(T u, int w)
 }
 
 // Layout of the start-cell histogram of a tile with bin extents m: start
-// cells s_d in [0, m_d + 1] (c_d of them), x rows of pitch lx = c_1 + w - 1
-// (room for the box sums along x in place), ly rows per z plane (3D: room
-// for the box sums along y in place).
+// cells s_d in [0, m_d + 1] (c_d of them) in the first two dimensions, x
+// rows of pitch lx = c_1 + w - 1 (room for the box sums along x in place).
+// In 3D the third start coordinate is not kept: summing a cell's column
+// over every z start still bounds it, at a cost of about (m_3 + 2) / w in
+// tightness, and the box sums stay two-dimensional and cheap.
 struct StartHist {
     int c[3];
     int lx, ly;
@@ -111,13 +113,14 @@ struct StartHist {
 
 __host__ __device__ inline StartHist start_hist_rt(int dim, int w, int m1, int m2, int m3)
 {
+    (void)m3;
     StartHist h;
     h.c[0] = m1 + 2;
     h.c[1] = dim >= 2 ? m2 + 2 : 1;
-    h.c[2] = dim == 3 ? m3 + 2 : 1;
+    h.c[2] = 1;
     h.lx = h.c[0] + w - 1;
-    h.ly = dim == 3 ? h.c[1] + w - 1 : h.c[1];
-    h.size = h.c[2] * h.ly * h.lx;
+    h.ly = h.c[1];
+    h.size = h.ly * h.lx;
     return h;
 }
 
@@ -246,6 +249,9 @@ hipError_t launch_interp(const Geom &g, int prec, int method, const Pts &P, cons
 hipError_t launch_interp_grad(const Geom &g, int prec, const Pts &P, int ntransf,
                               const void *grid, const void *wts, void *const out[3],
                               hipStream_t s);
+// Rounds of points per chunk in SM interpolation; each thread keeps one
+// index per round in LDS after the staged tile (kInterpRounds x 256 ints).
+constexpr int kInterpRounds = 2;
 // Dynamic LDS bytes the SM kernels need for these bins and subproblem size.
 size_t sm_lds_bytes(const Geom &g, int prec, bool interp, int msub);
 // Single-precision SM spreading keeps up to this many gathered strengths of

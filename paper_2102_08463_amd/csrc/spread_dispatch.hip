@@ -52,14 +52,13 @@ size_t sm_lds_bytes(const Geom &g, int prec, bool interp, int msub)
 {
     const size_t rsz = prec == 0 ? sizeof(float) : sizeof(double);
     // The spreading kernels build a start-cell histogram of
-    // (m_3 + 2) (m_2 + w + 1) (m_1 + w + 1) words (fewer factors in 1D / 2D)
-    // in the tile's LDS before clearing the tile; it always fits in the
-    // ts2 words of a single-precision tile and its slots fit 16 bits, which
-    // this check confirms.
+    // (m_2 + 2) (m_1 + w + 1) words (m_1 + w + 1 in 1D) in the tile's LDS
+    // before clearing the tile; it always fits in the ts2 words of a
+    // single-precision tile and its slots fit 16 bits, which this check
+    // confirms.
     if (!interp) {
         size_t hist = (size_t)g.m[0] + g.w + 1;
-        if (g.dim >= 2) hist *= (size_t)g.m[1] + (g.dim == 3 ? g.w + 1 : 2);
-        if (g.dim == 3) hist *= (size_t)g.m[2] + 2;
+        if (g.dim >= 2) hist *= (size_t)g.m[1] + 2;
         if (hist > (size_t)sm_tile_stride(g) || hist > 65535) return ~(size_t)0;
     }
     // 64-bit fixed-point accumulators: one word per cell in single precision,
@@ -75,7 +74,8 @@ size_t sm_lds_bytes(const Geom &g, int prec, bool interp, int msub)
     const int P = (g.w + 1) / 2;
     size_t cells = 1;
     for (int d = 0; d < g.dim; ++d) cells *= (size_t)(g.m[d] + 2 * P);
-    return cells * 2 * rsz;
+    // the staged padded bin and each thread's per-round point indices
+    return cells * 2 * rsz + (size_t)kInterpRounds * 256 * 4;
 }
 
 namespace {

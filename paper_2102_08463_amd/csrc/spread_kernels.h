@@ -312,8 +312,9 @@ __device__ __forceinline__ long long to_fixed(double v) { return __double2ll_rn(
 //   |Re b_l|, |Im b_l| <= sum over points with s in (l - w, l] of a_j,
 //   a_j = max(|Re c_j|, |Im c_j|).
 // Each subproblem histograms ceil(a_j / u) (u a power of two) over the start
-// cells in LDS, takes box sums of width w along every dimension and their
-// maximum B; B u bounds every cell of the tile.  This is tighter than the
+// cells in LDS, takes box sums of width w along x and y and their maximum
+// B; B u bounds every cell of the tile.  (In 3D the histogram sums over
+// the z start, which bounds each cell too and keeps the sums 2D.)  This is tighter than the
 // subproblem's whole strength sum by roughly the ratio of the bin to the
 // kernel footprint (about 20x for 32 x 32 bins and w = 6), and it follows
 // the strengths where they are: large strengths elsewhere in the input do
@@ -396,47 +397,28 @@ __device__ __forceinline__ void box_lines(unsigned *H, int nl, int cnt, int npos
 // Largest w-box sum of the start histogram over every cell of the tile
 // (all threads of the block call this; it ends with a barrier).  Lines of
 // up to 64 window positions are summed one wave per line, longer ones one
-// thread per line.
+// thread per line.  (The histogram is two-dimensional in 3D; see StartHist.)
 template <int DIM, int W>
 __device__ unsigned tile_bound(unsigned *H, const StartHist &h, unsigned *red)
 {
     const int tid = threadIdx.x, NT = blockDim.x;
     unsigned mx = 0;
-    const int lastc = h.c[DIM - 1];
-    const bool waves = h.lx <= 64 && (DIM < 3 || h.ly <= 64) && lastc + W - 1 <= 64;
-    if (waves) {
-        if constexpr (DIM == 1) {
+    if constexpr (DIM == 1) {
+        if (h.c[0] + W - 1 <= 64)
             box_lines(H, 1, h.c[0], h.c[0] + W - 1, 1, W, [](int) { return 0; }, &mx);
-        } else {
-            // along x, in place, on the rows that hold starts
-            box_lines(H, h.c[2] * h.c[1], h.c[0], h.lx, 1, W,
-                      [&](int r) { return ((r / h.c[1]) * h.ly + r % h.c[1]) * h.lx; }, nullptr);
-            __syncthreads();
-            if constexpr (DIM == 2) {
-                box_lines(H, h.lx, h.c[1], h.c[1] + W - 1, h.lx, W, [](int x) { return x; }, &mx);
-            } else {
-                box_lines(H, h.c[2] * h.lx, h.c[1], h.ly, h.lx, W,
-                          [&](int r) { return (r / h.lx) * h.ly * h.lx + r % h.lx; }, nullptr);
-                __syncthreads();
-                box_lines(H, h.ly * h.lx, h.c[2], h.c[2] + W - 1, h.ly * h.lx, W,
-                          [](int x) { return x; }, &mx);
-            }
-        }
-    } else if constexpr (DIM == 1) {
-        if (tid == 0) mx = box_max(H, h.c[0], 1, W);
+        else if (tid == 0)
+            mx = box_max(H, h.c[0], 1, W);
     } else {
-        for (int r = tid; r < h.c[2] * h.c[1]; r += NT)
-            box_in_place(H + ((r / h.c[1]) * h.ly + r % h.c[1]) * h.lx, h.lx, 1, W);
+        // along x, in place, then the largest box sum along y
+        if (h.lx <= 64)
+            box_lines(H, h.c[1], h.c[0], h.lx, 1, W, [&](int r) { return r * h.lx; }, nullptr);
+        else
+            for (int r = tid; r < h.c[1]; r += NT) box_in_place(H + r * h.lx, h.lx, 1, W);
         __syncthreads();
-        if constexpr (DIM == 2) {
+        if (h.c[1] + W - 1 <= 64)
+            box_lines(H, h.lx, h.c[1], h.c[1] + W - 1, h.lx, W, [](int x) { return x; }, &mx);
+        else
             for (int x = tid; x < h.lx; x += NT) mx = max(mx, box_max(H + x, h.c[1], h.lx, W));
-        } else {
-            for (int r = tid; r < h.c[2] * h.lx; r += NT)
-                box_in_place(H + (r / h.lx) * h.ly * h.lx + r % h.lx, h.ly, h.lx, W);
-            __syncthreads();
-            for (int x = tid; x < h.ly * h.lx; x += NT)
-                mx = max(mx, box_max(H + x, h.c[2], h.ly * h.lx, W));
-        }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) mx = max(mx, (unsigned)__shfl_xor((int)mx, o, 64));
@@ -734,6 +716,9 @@ k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict_
             int sy = 0;
             if constexpr (DIM >= 2) sy = taps<float, W>(x1 + (float)P, bk, ky);
             const float cr0 = ldexpf(cv.x, sh), ci0 = ldexpf(cv.y, sh);
+            // contributions are rounded to nearest: truncation would save an
+            // instruction per term but biases every term toward zero, which
+            // doubles the quantisation error in dense cells
             auto row_add = [&](unsigned long long *row, float wr, float wi) {
 #pragma unroll
                 for (int a1 = 0; a1 < W; ++a1) {
@@ -1036,34 +1021,23 @@ k_interp_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
         __syncthreads();
         const int end = rec.y + rec.z;
         const int NT = blockDim.x;
-        // Round r of the subproblem's points is thread t's point rec.y + t + r NT.
-        // Its loads are issued kAhead rounds before its use: one counter tracks
-        // vector loads and stores together, so waiting for a load also waits
-        // for every store issued before it, and the scattered result stores
-        // are slow to complete.  Every load is unconditional (lanes past the
-        // last point take the last point again and store the same value to
-        // the same place), so the compiler can wait for exactly the loads it
-        // needs.
-        constexpr int kAhead = 4;
-        const int nr = (rec.z + NT - 1) / NT;  // rounds, the same for every thread
-        T a0[kAhead], a1[kAhead], a2[kAhead];
-        int ap[kAhead];
-        auto load_round = [&](int r, int k) {
-            const int ii = min(rec.y + (int)threadIdx.x + r * NT, end - 1);
-            a0[k] = u0[ii];
-            a1[k] = DIM >= 2 ? u1[ii] : (T)0;
-            a2[k] = DIM == 3 ? u2[ii] : (T)0;
-            ap[k] = idx[ii];
-        };
-#pragma unroll
-        for (int k = 0; k < kAhead; ++k) load_round(k, k);
-        for (int r0 = 0; r0 < nr; r0 += kAhead) {
-#pragma unroll
-        for (int k = 0; k < kAhead; ++k) {
-            if (r0 + k >= nr) continue;
-            const T x0 = a0[k], x1 = a1[k], x2 = a2[k];
-            const int pj = ap[k];
-            load_round(r0 + k + kAhead, k);
+        // Round r of the subproblem's points is thread t's point rec.y + t + r NT;
+        // kRounds rounds make a chunk.  One counter tracks vector loads and
+        // stores together, so waiting for a load also waits for every store
+        // issued before it, and the scattered result stores are slow to
+        // complete.  Each chunk's coordinates and indices are therefore loaded
+        // at the top of an iteration and used at its bottom, with the previous
+        // chunk's stores issued in between: the wait covers only stores two
+        // chunks old, and the count of operations in between is fixed (every
+        // load and those stores are unconditional; lanes past the last point
+        // take the last point again and store the same value to the same
+        // place).  A thread keeps its own results in registers and its own
+        // indices in LDS (sidx), so no barrier is needed.
+        constexpr int kRounds = kInterpRounds;
+        const int nr = (rec.z + NT - 1) / NT;          // rounds holding points
+        const int nch = (nr + kRounds - 1) / kRounds;  // chunks
+        int *sidx = reinterpret_cast<int *>(tile + tsize) + threadIdx.x;
+        auto point = [&](T x0, T x1, T x2) __attribute__((always_inline)) {
             T kx[W], ky[W];
             const int sx = taps<T, W>(x0 + (T)P, bk, kx);
             int sy = 0;
@@ -1118,9 +1092,44 @@ k_interp_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
             C out;
             out.x = ar;
             out.y = ai;
-            c[pj] = out;
+            return out;
+        };
+        C res[kRounds];
+        T x0[kRounds], x1[kRounds], x2[kRounds];
+        int ix[kRounds];
+        auto load_chunk = [&](int k) __attribute__((always_inline)) {
+#pragma unroll
+            for (int r = 0; r < kRounds; ++r) {
+                const int ii = min(rec.y + (int)threadIdx.x + (k * kRounds + r) * NT, end - 1);
+                x0[r] = u0[ii];
+                x1[r] = DIM >= 2 ? u1[ii] : (T)0;
+                x2[r] = DIM == 3 ? u2[ii] : (T)0;
+                ix[r] = idx[ii];
+            }
+        };
+        // (rounds past the last one repeat the last point: cheaper than a
+        // branch, which would let the compiler sink their loads past the
+        // stores)
+        auto compute_chunk = [&]() __attribute__((always_inline)) {
+#pragma unroll
+            for (int r = 0; r < kRounds; ++r) {
+                sidx[r * NT] = ix[r];
+                res[r] = point(x0[r], x1[r], x2[r]);
+            }
+        };
+        load_chunk(0);
+        compute_chunk();
+        for (int k = 1; k < nch; ++k) {
+            load_chunk(k);
+#pragma unroll
+            for (int r = 0; r < kRounds; ++r) c[sidx[r * NT]] = res[r];  // chunk k - 1 (full)
+            // keep those stores ahead of this chunk's arithmetic
+            __builtin_amdgcn_sched_barrier(0);
+            compute_chunk();
         }
-        }
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r)
+            if ((nch - 1) * kRounds + r < nr) c[sidx[r * NT]] = res[r];
         __syncthreads();
     }
 }
