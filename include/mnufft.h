@@ -380,6 +380,22 @@ int mnufft_density_features(int prec, int64_t M, const void *x, const void *y, f
 int mnufft_density_features_batch(int prec, int T, const int64_t *off, const void *x,
                                   const void *y, float *feat, int ldf, void *work, void *stream);
 
+/* mnufft_density_features_batch without a workspace argument, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the partial histograms
+ * go to a workspace of MNUFFT_DENSITY_NOALLOC_MAX_SETS *
+ * MNUFFT_DENSITY_BATCH_WORK_BYTES bytes (2 MiB) that the library holds in
+ * static device memory, one copy per GPU for the life of the process (its
+ * address is looked up on the first call on each device; the call allocates
+ * nothing).  All calls on one GPU share that workspace, so calls that
+ * overlap on one GPU (on different streams or host threads) race and must
+ * be ordered by the caller.  Same arguments and results as
+ * mnufft_density_features_batch otherwise.  Errors: ERR_ARG (also for
+ * T > MNUFFT_DENSITY_NOALLOC_MAX_SETS), ERR_HIP. */
+#define MNUFFT_DENSITY_NOALLOC_MAX_SETS 64
+int mnufft_density_features_batch_noalloc(int prec, int T, const int64_t *off, const void *x,
+                                          const void *y, float *feat, int ldf, void *stream);
+
 /* A multilayer perceptron F -> H -> H -> K with ReLU after the two hidden
  * layers, in single precision, all arrays on the device, all calls ordered on
  * `stream` (a hipStream_t).  Parameters are one flat array laid out as

@@ -9,6 +9,7 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <mutex>
 
 namespace {
 
@@ -205,6 +206,35 @@ __global__ void k_argmin_rows(int T, int K, const float *__restrict__ Y, unsigne
     gap[t] = b1 - b0;
 }
 
+// Workspace of mnufft_density_features_batch_noalloc: the partial histograms
+// of up to kNoAllocSets point sets (2 MiB), one copy per GPU for the life of
+// the process.  In host code `scratch` names a host-side stand-in; the device
+// address of each GPU's copy comes from hipGetSymbolAddress, taken once per
+// device and kept in g_scratch.
+constexpr int kNoAllocSets = 64;
+static __device__ __align__(256) uint32_t scratch[kNoAllocSets * kBatchChunks * 256];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+// Device address of the current device's workspace (looked up on its first use).
+int scratch_of_current_device(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return MNUFFT_ERR_HIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return MNUFFT_ERR_HIP;
+        }
+        g_scratch[dev] = ptr;
+    }
+    *out = g_scratch[dev];
+    return MNUFFT_OK;
+}
+
 int density_batch(int prec, int T, const int64_t *off, const void *x, const void *y, float *feat,
                   int ldf, void *work, hipStream_t s)
 {
@@ -336,6 +366,20 @@ int mnufft_density_features_batch(int prec, int T, const int64_t *off, const voi
         !feat || !work || ldf < 256)
         return MNUFFT_ERR_ARG;
     return density_batch(prec, T, off, x, y, feat, ldf, work, (hipStream_t)stream);
+}
+
+int mnufft_density_features_batch_noalloc(int prec, int T, const int64_t *off, const void *x,
+                                          const void *y, float *feat, int ldf, void *stream)
+{
+    if ((prec != MNUFFT_F32 && prec != MNUFFT_F64) || T < 1 || T > kNoAllocSets || !off || !x ||
+        !y || !feat || ldf < 256)
+        return MNUFFT_ERR_ARG;
+    void *ws = nullptr;
+    const int rc = scratch_of_current_device(&ws);
+    if (rc) return rc;
+    // every partial histogram the final kernel reads is written first, so the
+    // workspace needs no clearing between calls
+    return density_batch(prec, T, off, x, y, feat, ldf, ws, (hipStream_t)stream);
 }
 
 }  // extern "C"

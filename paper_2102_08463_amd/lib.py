@@ -34,7 +34,7 @@ EXPORTS = (
     "mnufft_batch_set_timing", "mnufft_batch_get_timing", "mnufft_batch_get_totals",
     "mnufft_batch_destroy", "mnufft_tune_candidates", "mnufft_tune_time",
     "mnufft_density_features", "mnufft_density_features_batch",
-    "mnufft_mlp_nparams", "mnufft_mlp_forward",
+    "mnufft_density_features_batch_noalloc", "mnufft_mlp_nparams", "mnufft_mlp_forward",
     "mnufft_mlp_loss_grad", "mnufft_mlp_backward", "mnufft_mlp_adam",
     "mnufft_selector_load", "mnufft_selector_clear", "mnufft_select", "mnufft_batch_select",
 )
@@ -42,6 +42,7 @@ TUNE_OFF, TUNE_AUTOTUNE, TUNE_LEARNED = 0, 1, 2
 TUNES = {"off": TUNE_OFF, "autotune": TUNE_AUTOTUNE, "learned": TUNE_LEARNED}
 DENSITY_WORK_BYTES = 512 * 256 * 4
 DENSITY_BATCH_WORK_BYTES = 32 * 256 * 4  # per point set
+DENSITY_NOALLOC_MAX_SETS = 64
 
 
 STAGES = ("setpts", "zero", "spread", "fft", "deconv", "precorrect", "interp", "addback", "scale")
@@ -148,6 +149,7 @@ def load():
     fp = ctypes.POINTER(ctypes.c_float)
     L.mnufft_density_features.argtypes = [ci, i64, vp, vp, vp, vp, vp]
     L.mnufft_density_features_batch.argtypes = [ci, ci, vp, vp, vp, vp, ci, vp, vp]
+    L.mnufft_density_features_batch_noalloc.argtypes = [ci, ci, vp, vp, vp, vp, ci, vp]
     L.mnufft_mlp_nparams.argtypes = [ci, ci, ci]
     L.mnufft_mlp_forward.argtypes = [ci, ci, ci, vp, ci, vp, vp, vp, vp, vp]
     L.mnufft_mlp_loss_grad.argtypes = [ci, ci, vp, vp, vp, vp, vp, vp]
