@@ -373,8 +373,9 @@ int mnufft_density_features(int prec, int64_t M, const void *x, const void *y, f
 /* The same features for T point sets stored back to back: set t is points
  * off[t] .. off[t+1]-1 of x, y (off: device array of T + 1 nondecreasing
  * int64, off[0] = 0); its 256 features go to feat + t * ldf (ldf >= 256).
- * work: device scratch of T * MNUFFT_DENSITY_BATCH_WORK_BYTES bytes.  Two
- * kernel launches whatever T.  Errors: ERR_ARG (T < 1 or above 65535, NULL
+ * work: device scratch of T * MNUFFT_DENSITY_BATCH_WORK_BYTES bytes (cleared
+ * by the call itself).  Three kernel launches whatever T; the points are
+ * split evenly over the GPU whatever the set sizes.  Errors: ERR_ARG (T < 1 or above 65535, NULL
  * pointers, ldf < 256), ERR_HIP. */
 #define MNUFFT_DENSITY_BATCH_WORK_BYTES (32 * 256 * 4)
 int mnufft_density_features_batch(int prec, int T, const int64_t *off, const void *x,
@@ -429,7 +430,7 @@ int mnufft_mlp_adam(int64_t n, float *params, const float *grads, float *m, floa
  * margin; K records of int32 (method, binsize[0..2], msub) that must equal
  * mnufft_tune_candidates(dim, prec, eps) in order; then the
  * mnufft_mlp_nparams(F, H, K) float32 parameters of the network, and
- * nothing after them.  F must be 262: the 256 density features of
+ * nothing after them.  1 <= H <= 256.  F must be 262: the 256 density features of
  * mnufft_density_features followed by log2 M / 24, log2 n_i / 12 (i = 1..3,
  * 0 for an absent dimension; n_i the sigma = 2 fine grid), w / 16 and the
  * type minus one.  The network predicts each candidate's log run time

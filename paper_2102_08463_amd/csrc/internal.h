@@ -249,9 +249,6 @@ hipError_t launch_interp(const Geom &g, int prec, int method, const Pts &P, cons
 hipError_t launch_interp_grad(const Geom &g, int prec, const Pts &P, int ntransf,
                               const void *grid, const void *wts, void *const out[3],
                               hipStream_t s);
-// Rounds of points per chunk in SM interpolation; each thread keeps one
-// index per round in LDS after the staged tile (kInterpRounds x 256 ints).
-constexpr int kInterpRounds = 2;
 // Dynamic LDS bytes the SM kernels need for these bins and subproblem size.
 size_t sm_lds_bytes(const Geom &g, int prec, bool interp, int msub);
 // Single-precision SM spreading keeps up to this many gathered strengths of
@@ -311,6 +308,19 @@ hipError_t launch_cmul(int prec, long long n, int ntransf, const void *in, const
 // and its gap to the runner-up; -1 when no column is allowed.
 hipError_t launch_argmin_rows(int T, int K, const float *Y, const unsigned long long mask[2],
                               int *idx, float *gap, hipStream_t s);
+// mnufft_density_features_batch (work of T * MNUFFT_DENSITY_BATCH_WORK_BYTES)
+// that also copies nscal extra features per set from scal (device, T x
+// nscal) into columns 256 .. 256 + nscal - 1 of each row.
+hipError_t launch_density_batch(int prec, int T, const int64_t *off, const void *x, const void *y,
+                                float *feat, int ldf, void *work, const float *scal, int nscal,
+                                hipStream_t s);
+// The network (F -> H -> H -> K, mnufft_mlp_forward's parameter layout) and
+// the argmin above fused, one block per row of X (T rows of stride ldx):
+// idx / gap as launch_argmin_rows gives them on the network's output.
+// F <= 512, H <= 256, K <= 128, else hipErrorInvalidValue.
+hipError_t launch_mlp_argmin(int F, int H, int K, const float *params, int T, const float *X,
+                             int ldx, const unsigned long long mask[2], int *idx, float *gap,
+                             hipStream_t s);
 
 // Fill n bytes of device memory with zero by a kernel.
 hipError_t launch_zero(void *ptr, size_t bytes, hipStream_t s);

@@ -148,34 +148,156 @@ __global__ void k_hist_final(long long M, int nblk, const uint32_t *__restrict__
     feat[c] = M > 0 ? log1pf(256.0f * (float)((double)s / (double)M)) : 0.0f;
 }
 
-// Batched histograms: block (b, t) counts chunk b of kBatchChunks of set t.
-constexpr int kBatchChunks = 32;  // see MNUFFT_DENSITY_BATCH_WORK_BYTES
-template <typename T>
-__global__ void __launch_bounds__(kThreads)
-k_hist_batch(const int64_t *__restrict__ off, const T *__restrict__ x, const T *__restrict__ y,
-             uint32_t *__restrict__ part)
+// Batched histograms, balanced over points rather than sets (a few large
+// sets would otherwise keep a few blocks busy long after the rest): the
+// concatenated points are cut into chunks of kHistChunk, block b takes
+// chunks b, b + gridDim.x, ..., and for each set a chunk overlaps it counts
+// that set's part in LDS (one histogram per wave) and adds the counts to the
+// set's partial row (chunk index mod kBatchChunks).  The rows must start at
+// zero (k_hist_clear).
+constexpr int kBatchChunks = 32;  // partial rows per set; see MNUFFT_DENSITY_BATCH_WORK_BYTES
+constexpr int kHistChunk = 16384;
+constexpr int kHistBatchBlocks = 1024;
+constexpr int kHistUnroll = 4;
+
+__global__ void k_hist_clear(size_t n, uint32_t *__restrict__ part)
 {
-    __shared__ uint32_t h[256];
-    const int t = blockIdx.y, b = blockIdx.x;
-    h[threadIdx.x] = 0;
-    __syncthreads();
-    const long long a = off[t], n = off[t + 1] - a;
-    const long long lo = a + n * b / kBatchChunks, hi = a + n * (b + 1) / kBatchChunks;
-    for (long long j = lo + threadIdx.x; j < hi; j += kThreads)
-        atomicAdd(&h[cell16((double)x[j]) + 16 * cell16((double)y[j])], 1u);
-    __syncthreads();
-    part[((size_t)t * kBatchChunks + b) * 256 + threadIdx.x] = h[threadIdx.x];
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (size_t)gridDim.x * blockDim.x)
+        part[e] = 0u;
 }
 
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_hist_batch(int nset, const int64_t *__restrict__ off, const T *__restrict__ x,
+             const T *__restrict__ y, uint32_t *__restrict__ part)
+{
+    constexpr int kWaves = kThreads / 64;
+    __shared__ uint32_t h[kWaves][256];
+    __shared__ int first;
+    const long long Mtot = off[nset];
+    const int wave = threadIdx.x >> 6;
+    for (long long a = (long long)blockIdx.x * kHistChunk; a < Mtot;
+         a += (long long)gridDim.x * kHistChunk) {
+        const long long e = min(a + (long long)kHistChunk, Mtot);
+        if (threadIdx.x == 0) {  // the first set whose points reach past a
+            int lo = 0, hi = nset - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (off[mid + 1] > a) hi = mid;
+                else lo = mid + 1;
+            }
+            first = lo;
+        }
+        __syncthreads();
+        const int t0 = first;
+        __syncthreads();
+        const int row = (int)((a / kHistChunk) % kBatchChunks);
+        // the bounds below are the same for every thread, so is the control flow
+        for (int t = t0; t < nset && off[t] < e; ++t) {
+            const long long s0 = max(a, (long long)off[t]), s1 = min(e, (long long)off[t + 1]);
+            if (s0 >= s1) continue;
+            for (int k = threadIdx.x; k < kWaves * 256; k += kThreads) (&h[0][0])[k] = 0u;
+            __syncthreads();
+            for (long long j = s0 + threadIdx.x; j < s1; j += kHistUnroll * kThreads) {
+                T xv[kHistUnroll], yv[kHistUnroll];
+#pragma unroll
+                for (int u = 0; u < kHistUnroll; ++u) {
+                    const long long jj = min(j + (long long)u * kThreads, s1 - 1);
+                    xv[u] = x[jj];
+                    yv[u] = y[jj];
+                }
+#pragma unroll
+                for (int u = 0; u < kHistUnroll; ++u)
+                    if (j + (long long)u * kThreads < s1)
+                        atomicAdd(&h[wave][cell16((double)xv[u]) + 16 * cell16((double)yv[u])], 1u);
+            }
+            __syncthreads();
+            for (int c = threadIdx.x; c < 256; c += kThreads) {
+                uint32_t v = 0;
+#pragma unroll
+                for (int w = 0; w < kWaves; ++w) v += h[w][c];
+                if (v) atomicAdd(&part[((size_t)t * kBatchChunks + row) * 256 + c], v);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Features of set t from its partial rows; with scal, also copies the set's
+// nscal extra features (scal + t * nscal) after the 256 density features.
 __global__ void k_hist_batch_final(const int64_t *__restrict__ off,
                                    const uint32_t *__restrict__ part, float *__restrict__ feat,
-                                   int ldf)
+                                   int ldf, const float *__restrict__ scal, int nscal)
 {
     const int t = blockIdx.x, c = threadIdx.x;
     const long long M = off[t + 1] - off[t];
     unsigned long long s = 0;
     for (int b = 0; b < kBatchChunks; ++b) s += part[((size_t)t * kBatchChunks + b) * 256 + c];
     feat[(size_t)t * ldf + c] = M > 0 ? log1pf(256.0f * (float)((double)s / (double)M)) : 0.0f;
+    if (scal && c < nscal) feat[(size_t)t * ldf + 256 + c] = scal[(size_t)t * nscal + c];
+}
+
+// One layer of the network inside a block: out = act(bias + W^T in), with
+// the In-sum of each output split over the block's 256 / Out thread groups
+// and the group sums added in LDS.  Out <= 256.  Ends with a barrier.
+__device__ void block_dense(int In, int Out, const float *in, const float *__restrict__ W,
+                            const float *__restrict__ bias, float *out, float *red, bool relu)
+{
+    const int G = max(1, (int)blockDim.x / Out);
+    const int o = threadIdx.x % Out, grp = threadIdx.x / Out;
+    if (grp < G) {
+        float acc = 0.0f;
+        for (int i = grp; i < In; i += G) acc = fmaf(in[i], W[(size_t)i * Out + o], acc);
+        red[grp * Out + o] = acc;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < Out) {
+        float v = bias[threadIdx.x];
+        for (int q = 0; q < G; ++q) v += red[q * Out + threadIdx.x];
+        out[threadIdx.x] = relu ? fmaxf(v, 0.0f) : v;
+    }
+    __syncthreads();
+}
+
+// The selector's whole pass for one row per block: the three layers of the
+// network on the row's features, then the allowed output of smallest value
+// and its gap to the runner-up (infinity with one allowed output, index -1
+// with none), as k_argmin_rows computes them.
+constexpr int kFusedMaxF = 512, kFusedMaxH = 256, kFusedMaxK = 128;
+__global__ void __launch_bounds__(256)
+k_mlp_argmin(int F, int H, int K, const float *__restrict__ params, const float *__restrict__ X,
+             int ldx, unsigned long long m0, unsigned long long m1, int *__restrict__ idx,
+             float *__restrict__ gap)
+{
+    __shared__ float xs[kFusedMaxF], h1[kFusedMaxH], h2[kFusedMaxH], ys[kFusedMaxK];
+    __shared__ float red[256];
+    const int b = blockIdx.x;
+    const float *W1 = params, *b1 = W1 + (size_t)F * H, *W2 = b1 + H, *b2 = W2 + (size_t)H * H;
+    const float *W3 = b2 + H, *b3 = W3 + (size_t)H * K;
+    for (int i = threadIdx.x; i < F; i += blockDim.x) xs[i] = X[(size_t)b * ldx + i];
+    __syncthreads();
+    block_dense(F, H, xs, W1, b1, h1, red, true);
+    block_dense(H, H, h1, W2, b2, h2, red, true);
+    block_dense(H, K, h2, W3, b3, ys, red, false);
+    if (threadIdx.x == 0) {
+        int best = -1;
+        float v0 = INFINITY, v1 = INFINITY;
+        for (int k = 0; k < K; ++k) {
+            const unsigned long long m = k < 64 ? m0 : m1;
+            if (!((m >> (k & 63)) & 1ull)) continue;
+            const float v = ys[k];
+            if (v < v0) {
+                v1 = v0;
+                v0 = v;
+                best = k;
+            } else if (v < v1) {
+                v1 = v;
+            }
+        }
+        idx[b] = best;
+        gap[b] = v1 - v0;
+    }
 }
 
 inline int blocks_for(long long n) { return (int)std::max<long long>(1, (n + kThreads - 1) / kThreads); }
@@ -236,18 +358,20 @@ int scratch_of_current_device(void **out)
 }
 
 int density_batch(int prec, int T, const int64_t *off, const void *x, const void *y, float *feat,
-                  int ldf, void *work, hipStream_t s)
+                  int ldf, void *work, hipStream_t s, const float *scal = nullptr, int nscal = 0)
 {
     uint32_t *part = (uint32_t *)work;
-    const dim3 grid(kBatchChunks, T);
+    const size_t nrow = (size_t)T * kBatchChunks * 256;
+    hipLaunchKernelGGL(k_hist_clear, dim3((unsigned)std::min<size_t>(1024, (nrow + 255) / 256)),
+                       dim3(256), 0, s, nrow, part);
     if (prec == MNUFFT_F32)
-        hipLaunchKernelGGL(k_hist_batch<float>, grid, dim3(kThreads), 0, s, off,
-                           (const float *)x, (const float *)y, part);
+        hipLaunchKernelGGL(k_hist_batch<float>, dim3(kHistBatchBlocks), dim3(kThreads), 0, s, T,
+                           off, (const float *)x, (const float *)y, part);
     else
-        hipLaunchKernelGGL(k_hist_batch<double>, grid, dim3(kThreads), 0, s, off,
-                           (const double *)x, (const double *)y, part);
+        hipLaunchKernelGGL(k_hist_batch<double>, dim3(kHistBatchBlocks), dim3(kThreads), 0, s, T,
+                           off, (const double *)x, (const double *)y, part);
     hipLaunchKernelGGL(k_hist_batch_final, dim3(T), dim3(256), 0, s, off,
-                       (const uint32_t *)part, feat, ldf);
+                       (const uint32_t *)part, feat, ldf, scal, nscal);
     return hipGetLastError() == hipSuccess ? MNUFFT_OK : MNUFFT_ERR_HIP;
 }
 
@@ -260,6 +384,29 @@ hipError_t launch_argmin_rows(int T, int K, const float *Y, const unsigned long 
     if (T <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_argmin_rows, dim3(blocks_for(T)), dim3(kThreads), 0, s, T, K, Y,
                        mask[0], mask[1], idx, gap);
+    return hipGetLastError();
+}
+
+hipError_t launch_density_batch(int prec, int T, const int64_t *off, const void *x, const void *y,
+                                float *feat, int ldf, void *work, const float *scal, int nscal,
+                                hipStream_t s)
+{
+    if (nscal < 0 || 256 + nscal > ldf) return hipErrorInvalidValue;
+    return density_batch(prec, T, off, x, y, feat, ldf, work, s, scal, nscal) == MNUFFT_OK
+               ? hipSuccess
+               : hipErrorLaunchFailure;
+}
+
+hipError_t launch_mlp_argmin(int F, int H, int K, const float *params, int T, const float *X,
+                             int ldx, const unsigned long long mask[2], int *idx, float *gap,
+                             hipStream_t s)
+{
+    if (F < 1 || F > kFusedMaxF || H < 1 || H > kFusedMaxH || K < 1 || K > kFusedMaxK ||
+        ldx < F)
+        return hipErrorInvalidValue;
+    if (T <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mlp_argmin, dim3(T), dim3(256), 0, s, F, H, K, params, X, ldx, mask[0],
+                       mask[1], idx, gap);
     return hipGetLastError();
 }
 }  // namespace mn
@@ -377,8 +524,8 @@ int mnufft_density_features_batch_noalloc(int prec, int T, const int64_t *off, c
     void *ws = nullptr;
     const int rc = scratch_of_current_device(&ws);
     if (rc) return rc;
-    // every partial histogram the final kernel reads is written first, so the
-    // workspace needs no clearing between calls
+    // density_batch clears the partial rows it uses (with a kernel) before
+    // counting, so nothing is left over from an earlier call
     return density_batch(prec, T, off, x, y, feat, ldf, ws, (hipStream_t)stream);
 }
 

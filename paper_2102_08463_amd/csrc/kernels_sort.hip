@@ -505,13 +505,18 @@ hipError_t launch_binstart(int M, int nbins, const uint32_t *skey, int32_t *bins
 //   pos = sum_t min(c_t, k) + #{t < r : c_t > k}     (c_t = class sizes).
 // The sorted coordinates, the permutation, each point's sorted position and
 // its slot in the spreading kernels' start-cell histogram are written in
-// that order.  Subproblems above kBalCap points keep their
-// sorted order.  The ranks come from LDS atomics, so the order within a
+// that order.  Subproblems above kBalCap points keep their sorted order.
+// A block loads a subproblem's points once (coalesced, kBalItems per
+// thread), ranks them in their classes with LDS atomics, then writes each
+// output array through an LDS stage so that the global stores are
+// contiguous too.  The ranks come from LDS atomics, so the order within a
 // class may differ between runs; the SM kernels' results do not depend on
 // the order (integer tile sums, per-point interpolation).
 constexpr int kBalCap = 4096;
-template <typename T>
-__global__ void __launch_bounds__(256)
+constexpr int kBalThreads = 256;
+constexpr int kBalItems = kBalCap / kBalThreads;
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBalThreads)
 k_balance(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__ nsubp,
           const T *__restrict__ u0, const T *__restrict__ u1, const T *__restrict__ u2,
           const int32_t *__restrict__ perm, T *__restrict__ v0, T *__restrict__ v1,
@@ -519,52 +524,90 @@ k_balance(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__ n
           uint16_t *__restrict__ hslot)
 {
     __shared__ unsigned cnt[16];
-    __shared__ unsigned rk[kBalCap];
+    __shared__ __align__(16) unsigned char stage_raw[kBalCap * sizeof(T)];
+    T *sT = reinterpret_cast<T *>(stage_raw);
+    int32_t *sI = reinterpret_cast<int32_t *>(stage_raw);
+    uint16_t *sH = reinterpret_cast<uint16_t *>(stage_raw);
+    const int tid = threadIdx.x;
     const int P = (g.w + 1) / 2;
     const int p1 = g.m[0] + 2 * P, p2 = g.m[1] + 2 * P;
     const T lead = (T)P - (T)(0.5 * g.w);
-    const StartHist hg = start_hist_rt(g.dim, g.w, g.m[0], g.m[1], g.m[2]);
+    const StartHist hg = start_hist_rt(DIM, g.w, g.m[0], g.m[1], g.m[2]);
+    // the spreading kernels' start-cell histogram slot (same expressions)
+    const auto slot = [&](T a, T b, T c) {
+        return (uint16_t)hist_slot_rt(hg, DIM >= 2 ? start_cell_rt<T>(b, g.w) : 0,
+                                      DIM == 3 ? start_cell_rt<T>(c, g.w) : 0,
+                                      start_cell_rt<T>(a, g.w));
+    };
     const int nsub = *nsubp;
     for (int q = blockIdx.x; q < nsub; q += gridDim.x) {
         const int4 rec = reinterpret_cast<const int4 *>(sub)[q];
         const int n = rec.z;
-        const bool fits = n <= kBalCap;
-        if (threadIdx.x < 16) cnt[threadIdx.x] = 0u;
-        __syncthreads();
-        if (fits) {
-            for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        if (n > kBalCap) {  // the same for the whole block: keep the sorted order
+            for (int j = tid; j < n; j += kBalThreads) {
                 const int i = rec.y + j;
-                int base = (int)ceil(u0[i] + lead);
-                if (g.dim >= 2) base += p1 * (int)ceil(u1[i] + lead);
-                if (g.dim == 3) base += p1 * p2 * (int)ceil(u2[i] + lead);
+                const T a = u0[i], b = DIM >= 2 ? u1[i] : (T)0, c = DIM == 3 ? u2[i] : (T)0;
+                v0[i] = a;
+                if (DIM >= 2) v1[i] = b;
+                if (DIM == 3) v2[i] = c;
+                vperm[i] = perm[i];
+                spos[i] = i;
+                hslot[i] = slot(a, b, c);
+            }
+            continue;
+        }
+        if (tid < 16) cnt[tid] = 0u;
+        __syncthreads();
+        T a[kBalItems], b[kBalItems], c[kBalItems];
+        int pm[kBalItems], pos[kBalItems];
+#pragma unroll
+        for (int it = 0; it < kBalItems; ++it) {
+            const int j = tid + it * kBalThreads;
+            const int i = rec.y + min(j, n - 1);
+            a[it] = u0[i];
+            b[it] = DIM >= 2 ? u1[i] : (T)0;
+            c[it] = DIM == 3 ? u2[i] : (T)0;
+            pm[it] = perm[i];
+        }
+#pragma unroll
+        for (int it = 0; it < kBalItems; ++it) {
+            const int j = tid + it * kBalThreads;
+            pos[it] = 0;
+            if (j < n) {
+                int base = (int)ceil(a[it] + lead);
+                if (DIM >= 2) base += p1 * (int)ceil(b[it] + lead);
+                if (DIM == 3) base += p1 * p2 * (int)ceil(c[it] + lead);
                 const unsigned r = (unsigned)base & 15u;
-                rk[j] = r | (atomicAdd(&cnt[r], 1u) << 4);
+                pos[it] = (int)(r | (atomicAdd(&cnt[r], 1u) << 4));
             }
         }
         __syncthreads();
-        for (int j = threadIdx.x; j < n; j += blockDim.x) {
-            int pos = j;
-            if (fits) {
-                const unsigned r = rk[j] & 15u, k = rk[j] >> 4;
-                pos = 0;
-                for (int t = 0; t < 16; ++t) {
-                    const unsigned ct = cnt[t];
-                    pos += (int)min(ct, k) + ((t < (int)r && ct > k) ? 1 : 0);
-                }
-            }
-            const int i = rec.y + j, o = rec.y + pos;
-            const T a = u0[i], b = g.dim >= 2 ? u1[i] : (T)0, cc = g.dim == 3 ? u2[i] : (T)0;
-            v0[o] = a;
-            if (g.dim >= 2) v1[o] = b;
-            if (g.dim == 3) v2[o] = cc;
-            vperm[o] = perm[i];
-            spos[o] = i;
-            // the spreading kernels' start-cell histogram slot (same expressions)
-            hslot[o] = (uint16_t)hist_slot_rt(hg, g.dim >= 2 ? start_cell_rt<T>(b, g.w) : 0,
-                                              g.dim == 3 ? start_cell_rt<T>(cc, g.w) : 0,
-                                              start_cell_rt<T>(a, g.w));
+        unsigned cc[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) cc[t] = cnt[t];
+#pragma unroll
+        for (int it = 0; it < kBalItems; ++it) {
+            const unsigned r = (unsigned)pos[it] & 15u, k = (unsigned)pos[it] >> 4;
+            int o = 0;
+#pragma unroll
+            for (int t = 0; t < 16; ++t) o += (int)min(cc[t], k) + ((t < (int)r && cc[t] > k) ? 1 : 0);
+            pos[it] = o;
         }
-        __syncthreads();
+        // each output through the stage: scattered LDS writes, contiguous stores
+        const auto emit = [&](auto *stage, auto *dst, auto value) {
+#pragma unroll
+            for (int it = 0; it < kBalItems; ++it)
+                if (tid + it * kBalThreads < n) stage[pos[it]] = value(it);
+            __syncthreads();
+            for (int j = tid; j < n; j += kBalThreads) dst[rec.y + j] = stage[j];
+            __syncthreads();
+        };
+        emit(sT, v0, [&](int it) { return a[it]; });
+        if constexpr (DIM >= 2) emit(sT, v1, [&](int it) { return b[it]; });
+        if constexpr (DIM == 3) emit(sT, v2, [&](int it) { return c[it]; });
+        emit(sI, vperm, [&](int it) { return pm[it]; });
+        emit(sI, spos, [&](int it) { return rec.y + tid + it * kBalThreads; });
+        emit(sH, hslot, [&](int it) { return slot(a[it], b[it], c[it]); });
     }
 }
 
@@ -575,14 +618,20 @@ hipError_t launch_balance(const Geom &g, int prec, int nsub_max, const int32_t *
 {
     if (nsub_max <= 0) return hipSuccess;
     const dim3 grid(std::max(1, std::min(nsub_max, 256 * 8)));
-    if (prec == 0)
-        hipLaunchKernelGGL(k_balance<float>, grid, dim3(256), 0, s, g, sub, nsub,
-                           (const float *)u[0], (const float *)u[1], (const float *)u[2], perm,
-                           (float *)v[0], (float *)v[1], (float *)v[2], vperm, spos, hslot);
-    else
-        hipLaunchKernelGGL(k_balance<double>, grid, dim3(256), 0, s, g, sub, nsub,
-                           (const double *)u[0], (const double *)u[1], (const double *)u[2], perm,
-                           (double *)v[0], (double *)v[1], (double *)v[2], vperm, spos, hslot);
+#define MN_BAL(TT, DD)                                                                         \
+    hipLaunchKernelGGL((k_balance<TT, DD>), grid, dim3(kBalThreads), 0, s, g, sub, nsub,       \
+                       (const TT *)u[0], (const TT *)u[1], (const TT *)u[2], perm, (TT *)v[0],  \
+                       (TT *)v[1], (TT *)v[2], vperm, spos, hslot)
+    if (prec == 0) {
+        if (g.dim == 1) MN_BAL(float, 1);
+        else if (g.dim == 2) MN_BAL(float, 2);
+        else MN_BAL(float, 3);
+    } else {
+        if (g.dim == 1) MN_BAL(double, 1);
+        else if (g.dim == 2) MN_BAL(double, 2);
+        else MN_BAL(double, 3);
+    }
+#undef MN_BAL
     return hipGetLastError();
 }
 

@@ -38,10 +38,13 @@ struct Selector {
 std::mutex g_mu;                          // guards everything below
 std::vector<Selector> g_sel;
 std::map<std::string, mnufft_opts> g_tuned;  // autotuner choices per problem class
-// per-device workspace of the selection calls (grows, never shrinks)
+// per-device workspace of the selection calls and its pinned host staging
+// buffer (both grow, never shrink)
 struct Work {
     void *ptr = nullptr;
     size_t bytes = 0;
+    void *host = nullptr;
+    size_t hbytes = 0;
 };
 std::map<int, Work> g_work;
 
@@ -76,6 +79,24 @@ void *workspace(size_t bytes)
         w.bytes = bytes;
     }
     return w.ptr;
+}
+
+// Pinned host staging of at least `bytes` for the current device (g_mu held).
+void *host_stage(size_t bytes)
+{
+    Work &w = g_work[current_device()];
+    if (w.hbytes < bytes) {
+        if (w.host) (void)hipHostFree(w.host);
+        w.host = nullptr;
+        w.hbytes = 0;
+        if (hipHostMalloc(&w.host, bytes, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            w.host = nullptr;
+            return nullptr;
+        }
+        w.hbytes = bytes;
+    }
+    return w.host;
 }
 
 float *device_params(Selector &s)
@@ -223,7 +244,7 @@ int mnufft_selector_load(const char *path)
         s.K = hdr[4];
         s.margin = margin;
         ok = (s.dim == 2 || s.dim == 3) && (s.prec == MNUFFT_F32 || s.prec == MNUFFT_F64) &&
-             eps > 0 && eps < 1 && s.F == kF && s.H >= 1 && s.H <= 4096 && s.K >= 1 &&
+             eps > 0 && eps < 1 && s.F == kF && s.H >= 1 && s.H <= 256 && s.K >= 1 &&
              s.K <= kMaxK && margin >= 0;
     }
     if (ok) {
@@ -406,46 +427,42 @@ int mnufft_batch_select(int type, int dim, int ntr, const int64_t *nmodes, const
         if (!sel) {
             for (int t = 0; t < ntr; ++t) need_tune.push_back(t);
         } else {
-            // one batched histogram, one forward pass and one argmin launch for
-            // all transforms; the scalars are computed here and copied once
+            // one upload (set offsets and scalar features), one batched
+            // histogram, one fused network + argmin launch and one download
+            // (picks and gaps) for all transforms, through pinned staging
             const int K = sel->K, H = sel->H;
             const size_t hist = (size_t)ntr * MNUFFT_DENSITY_BATCH_WORK_BYTES;
-            const size_t offb = ((size_t)ntr + 1) * 8;
-            const size_t fl = (size_t)ntr * (kF + 2 * H + K) * 4;
-            const size_t need = hist + offb + fl + (size_t)ntr * 8;
-            char *ws = (char *)workspace(need);
+            const size_t offb = ((size_t)ntr + 1) * 8, scb = (size_t)ntr * kScal * 4;
+            const size_t fl = (size_t)ntr * kF * 4, outb = (size_t)ntr * 8;
+            char *ws = (char *)workspace(hist + offb + scb + fl + outb);
+            char *hs = (char *)host_stage(offb + scb + outb);
             float *params = device_params(*sel);
-            if (!ws || !params) return MNUFFT_ERR_ALLOC;
+            if (!ws || !hs || !params) return MNUFFT_ERR_ALLOC;
             int64_t *off = (int64_t *)(ws + hist);
-            float *feat = (float *)(ws + hist + offb);
-            float *H1 = feat + (size_t)ntr * kF, *H2 = H1 + (size_t)ntr * H, *Y = H2 + (size_t)ntr * H;
-            int *idx = (int *)(Y + (size_t)ntr * K);
+            float *scal = (float *)(ws + hist + offb);
+            float *feat = (float *)(ws + hist + offb + scb);
+            int *idx = (int *)(ws + hist + offb + scb + fl);
             float *gap = (float *)(idx + ntr);
-            std::vector<int64_t> hoff(ntr + 1, 0);
-            std::vector<float> hscal((size_t)ntr * kScal);
+            int64_t *hoff = (int64_t *)hs;
+            float *hscal = (float *)(hs + offb);
+            const int *hidx = (const int *)(hs + offb + scb);
+            const float *hgap = (const float *)(hidx + ntr);
+            hoff[0] = 0;
             for (int t = 0; t < ntr; ++t) {
                 hoff[t + 1] = hoff[t] + npts[t];
                 scalar_features(type, dim, nmodes + 3 * t, npts[t], eps, prec,
-                                hscal.data() + (size_t)t * kScal);
+                                hscal + (size_t)t * kScal);
             }
-            if (hipMemcpyAsync(off, hoff.data(), offb, hipMemcpyHostToDevice, s) != hipSuccess ||
-                hipMemcpy2DAsync(feat + kHist, kF * 4, hscal.data(), kScal * 4, kScal * 4, ntr,
-                                 hipMemcpyHostToDevice, s) != hipSuccess)
+            if (hipMemcpyAsync(off, hoff, offb + scb, hipMemcpyHostToDevice, s) != hipSuccess)
                 return MNUFFT_ERR_HIP;
-            int rc = mnufft_density_features_batch(prec, ntr, off, x, y, feat, kF, ws, s);
-            if (rc < 0) return rc;
-            rc = mnufft_mlp_forward(kF, H, K, params, ntr, feat, H1, H2, Y, s);
-            if (rc < 0) return rc;
+            if (mn::launch_density_batch(prec, ntr, off, x, y, feat, kF, ws, scal, kScal, s) !=
+                hipSuccess)
+                return MNUFFT_ERR_HIP;
             unsigned long long mask[2];
             allowed_mask(*sel, true, mask);
-            if (mn::launch_argmin_rows(ntr, K, Y, mask, idx, gap, s) != hipSuccess)
-                return MNUFFT_ERR_HIP;
-            std::vector<int> hidx(ntr);
-            std::vector<float> hgap(ntr);
-            if (hipMemcpyAsync(hidx.data(), idx, (size_t)ntr * 4, hipMemcpyDeviceToHost, s) !=
+            if (mn::launch_mlp_argmin(kF, H, K, params, ntr, feat, kF, mask, idx, gap, s) !=
                     hipSuccess ||
-                hipMemcpyAsync(hgap.data(), gap, (size_t)ntr * 4, hipMemcpyDeviceToHost, s) !=
-                    hipSuccess ||
+                hipMemcpyAsync((void *)hidx, idx, outb, hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess)
                 return MNUFFT_ERR_HIP;
             for (int t = 0; t < ntr; ++t) {

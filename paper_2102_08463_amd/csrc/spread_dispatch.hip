@@ -74,8 +74,7 @@ size_t sm_lds_bytes(const Geom &g, int prec, bool interp, int msub)
     const int P = (g.w + 1) / 2;
     size_t cells = 1;
     for (int d = 0; d < g.dim; ++d) cells *= (size_t)(g.m[d] + 2 * P);
-    // the staged padded bin and each thread's per-round point indices
-    return cells * 2 * rsz + (size_t)kInterpRounds * 256 * 4;
+    return cells * 2 * rsz;
 }
 
 namespace {

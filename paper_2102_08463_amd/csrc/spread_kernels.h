@@ -321,6 +321,15 @@ __device__ __forceinline__ long long to_fixed(double v) { return __double2ll_rn(
 // not coarsen this subproblem's quantum.  The histogram and its box sums use
 // the tile's own LDS before the tile is cleared.
 
+// Words of a tile with padded extents p1 x p2 (x p3): two per cell,
+// rounded up to a multiple of 8 (the layout sm_tile_stride gives a plan).
+template <int DIM>
+__device__ __forceinline__ int tile_words(int p1, int p2, int p3)
+{
+    const int cells = DIM == 1 ? p1 : (DIM == 2 ? p1 * p2 : p1 * p2 * p3);
+    return (2 * cells + 7) / 8 * 8;
+}
+
 // Start cell (first tap in padded-tile coordinates) of a point at
 // bin-relative coordinate u: the expression taps() evaluates for u + P
 // (start_cell_rt in internal.h, which setpts uses for the same slots).
@@ -454,7 +463,6 @@ k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
     unsigned *H = reinterpret_cast<unsigned *>(smem_raw);  // start histogram, before the tile
     __shared__ unsigned red[kThreads / 64];
     constexpr int P = (W + 1) / 2;
-    const int nvec = ts2 / NV;
     const int nsub = *nsubp;
     int ecm;
     frexp(block_cmax(cmaxp), &ecm);  // cmax < 2^ecm
@@ -469,6 +477,8 @@ k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
             m3 = tt.m[2];
         }
         const int p1 = m1 + 2 * P, p2 = m2 + 2 * P;
+        // this tile's own words (a batch's ts2 fits its largest bins)
+        const int tsz = BATCH ? tile_words<DIM>(p1, p2, m3 + 2 * P) : ts2;
         const StartHist hg = start_hist<DIM, W>(m1, m2, m3);
         const int end = rec.y + rec.z;
         // histogram of ceil(a_j / u) over the start cells
@@ -492,7 +502,7 @@ k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
         __syncthreads();
         const unsigned B = tile_bound<DIM, W>(H, hg, red);
         const int sh = 61 - (ceil_log2(B) - hu);  // S = 2^sh
-        for (int e = threadIdx.x; e < ts2; e += blockDim.x) tile[e] = 0ull;
+        for (int e = threadIdx.x; e < tsz; e += blockDim.x) tile[e] = 0ull;
         __syncthreads();
         for (int i = rec.y + threadIdx.x; i < end; i += blockDim.x) {
             T kx[W], ky[W];
@@ -547,7 +557,7 @@ k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
         }
         __syncthreads();
         V *dst = reinterpret_cast<V *>(scratch + (size_t)q * ts2);
-        for (int e = threadIdx.x; e < nvec; e += blockDim.x) {
+        for (int e = threadIdx.x; e < tsz / NV; e += blockDim.x) {
             T vals[NV];
 #pragma unroll
             for (int k = 0; k < NV; ++k)
@@ -602,7 +612,6 @@ k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict_
     __shared__ float red[kThreads / 64];
     __shared__ unsigned redu[kThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int ncell = ts2 / 2;
     const int nsub = *nsubp;
     for (int q = blockIdx.x; q < nsub; q += gridDim.x) {
         const int4 rec = reinterpret_cast<const int4 *>(sub)[q];
@@ -615,6 +624,8 @@ k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict_
             m3 = tt.m[2];
         }
         const int p1 = m1 + 2 * P, p2 = m2 + 2 * P;
+        // this tile's own words (a batch's ts2 fits its largest bins)
+        const int tsz = BATCH ? tile_words<DIM>(p1, p2, m3 + 2 * P) : ts2;
         const StartHist hg = start_hist<DIM, W>(m1, m2, m3);
         const int end = rec.y + rec.z;
         // the largest part of any strength and the histogram slots of the
@@ -690,7 +701,7 @@ k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict_
         __syncthreads();
         const unsigned B = tile_bound<DIM, W>(H, hg, redu);
         const int sh = 30 - (ceil_log2(B) - hu);  // S = 2^sh: cells below 2^30
-        for (int e = tid; e < ncell; e += kThreads) tile[e] = 0ull;
+        for (int e = tid; e < tsz / 2; e += kThreads) tile[e] = 0ull;
         __syncthreads();
         // points of this thread, with the next one's loads issued ahead
         int i = rec.y + tid;
@@ -748,7 +759,7 @@ k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict_
         }
         __syncthreads();
         float4 *dst = reinterpret_cast<float4 *>(scratch + (size_t)q * ts2);
-        for (int e = tid; e < ts2 / 4; e += kThreads) {
+        for (int e = tid; e < tsz / 4; e += kThreads) {
             float v[4];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
@@ -1021,23 +1032,34 @@ k_interp_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
         __syncthreads();
         const int end = rec.y + rec.z;
         const int NT = blockDim.x;
-        // Round r of the subproblem's points is thread t's point rec.y + t + r NT;
-        // kRounds rounds make a chunk.  One counter tracks vector loads and
-        // stores together, so waiting for a load also waits for every store
-        // issued before it, and the scattered result stores are slow to
-        // complete.  Each chunk's coordinates and indices are therefore loaded
-        // at the top of an iteration and used at its bottom, with the previous
-        // chunk's stores issued in between: the wait covers only stores two
-        // chunks old, and the count of operations in between is fixed (every
-        // load and those stores are unconditional; lanes past the last point
-        // take the last point again and store the same value to the same
-        // place).  A thread keeps its own results in registers and its own
-        // indices in LDS (sidx), so no barrier is needed.
-        constexpr int kRounds = kInterpRounds;
-        const int nr = (rec.z + NT - 1) / NT;          // rounds holding points
-        const int nch = (nr + kRounds - 1) / kRounds;  // chunks
-        int *sidx = reinterpret_cast<int *>(tile + tsize) + threadIdx.x;
-        auto point = [&](T x0, T x1, T x2) __attribute__((always_inline)) {
+        // Round r of the subproblem's points is thread t's point rec.y + t + r NT.
+        // Its loads are issued kAhead rounds before its use: one counter tracks
+        // vector loads and stores together, so waiting for a load also waits
+        // for every store issued before it, and the scattered result stores
+        // are slow to complete.  Every load is unconditional (lanes past the
+        // last point take the last point again and store the same value to
+        // the same place), so the compiler can wait for exactly the loads it
+        // needs.
+        constexpr int kAhead = 4;
+        const int nr = (rec.z + NT - 1) / NT;  // rounds, the same for every thread
+        T a0[kAhead], a1[kAhead], a2[kAhead];
+        int ap[kAhead];
+        auto load_round = [&](int r, int k) {
+            const int ii = min(rec.y + (int)threadIdx.x + r * NT, end - 1);
+            a0[k] = u0[ii];
+            a1[k] = DIM >= 2 ? u1[ii] : (T)0;
+            a2[k] = DIM == 3 ? u2[ii] : (T)0;
+            ap[k] = idx[ii];
+        };
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k) load_round(k, k);
+        for (int r0 = 0; r0 < nr; r0 += kAhead) {
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k) {
+            if (r0 + k >= nr) continue;
+            const T x0 = a0[k], x1 = a1[k], x2 = a2[k];
+            const int pj = ap[k];
+            load_round(r0 + k + kAhead, k);
             T kx[W], ky[W];
             const int sx = taps<T, W>(x0 + (T)P, bk, kx);
             int sy = 0;
@@ -1092,44 +1114,9 @@ k_interp_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
             C out;
             out.x = ar;
             out.y = ai;
-            return out;
-        };
-        C res[kRounds];
-        T x0[kRounds], x1[kRounds], x2[kRounds];
-        int ix[kRounds];
-        auto load_chunk = [&](int k) __attribute__((always_inline)) {
-#pragma unroll
-            for (int r = 0; r < kRounds; ++r) {
-                const int ii = min(rec.y + (int)threadIdx.x + (k * kRounds + r) * NT, end - 1);
-                x0[r] = u0[ii];
-                x1[r] = DIM >= 2 ? u1[ii] : (T)0;
-                x2[r] = DIM == 3 ? u2[ii] : (T)0;
-                ix[r] = idx[ii];
-            }
-        };
-        // (rounds past the last one repeat the last point: cheaper than a
-        // branch, which would let the compiler sink their loads past the
-        // stores)
-        auto compute_chunk = [&]() __attribute__((always_inline)) {
-#pragma unroll
-            for (int r = 0; r < kRounds; ++r) {
-                sidx[r * NT] = ix[r];
-                res[r] = point(x0[r], x1[r], x2[r]);
-            }
-        };
-        load_chunk(0);
-        compute_chunk();
-        for (int k = 1; k < nch; ++k) {
-            load_chunk(k);
-#pragma unroll
-            for (int r = 0; r < kRounds; ++r) c[sidx[r * NT]] = res[r];  // chunk k - 1 (full)
-            // keep those stores ahead of this chunk's arithmetic
-            __builtin_amdgcn_sched_barrier(0);
-            compute_chunk();
+            c[pj] = out;
         }
-#pragma unroll
-        for (int r = 0; r < kRounds; ++r)
-            if ((nch - 1) * kRounds + r < nr) c[sidx[r * NT]] = res[r];
+        }
         __syncthreads();
     }
 }

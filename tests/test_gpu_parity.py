@@ -372,3 +372,34 @@ def test_largest_1d_mode_count():
     ks = np.concatenate([ks, [0, N - 1]])
     ex = direct.type1(pts64, c64, (N,), kk=(ks - N // 2,))
     assert rel_l2(f[ks], ex) <= 1e-4
+
+
+@pytest.mark.parametrize("dim,prec,k", [(2, "f32", -83), (3, "f32", -83), (1, "f32", -83),
+                                        (2, "f32", 83), (2, "f64", -660), (2, "f64", 660)])
+def test_spread_scale_linear(dim, prec, k):
+    """The fixed-point scale of each SM tile follows the tile's own strengths
+    (a power of two applied with ldexp), so spreading neither overflows nor
+    loses bits for strengths near the bottom or the top of the float range:
+    type 1 on 2^k c is 2^k times type 1 on c to rounding (|k| = 83 is about
+    1e25 in single precision, 660 about 1e199 in double), and strengths of
+    about 1e-25 that are not a power-of-two multiple of the first set (so
+    every rounding differs) still meet the tolerance against the exact sums."""
+    import torch
+    note(f"scale 2^{k} {dim}d {prec}")
+    N = {1: (200,), 2: (40, 36), 3: (16, 18, 12)}[dim]
+    M = 20_000
+    pts64, pts = make_points("cluster", M, dim, prec, seed=31)
+    _, c = make_complex(M, prec, seed=32)
+    eps = 1e-6 if prec == "f32" else 1e-12
+    p = _plan(1, N, eps=eps, dtype=cdtype(prec), method="sm")
+    p.setpts(*pts)
+    f1 = p.execute(c).cpu().numpy().astype(np.complex128)
+    f2 = p.execute(c * 2.0 ** k).cpu().numpy().astype(np.complex128)
+    assert np.all(np.isfinite(f2))
+    assert rel_l2(f2 * 2.0 ** -k, f1) <= 1e-12
+    if k < 0 and prec == "f32":
+        c3 = c * 1e-25
+        f3 = p.execute(c3).cpu().numpy()
+        ex = direct.type1(pts64, c3.cpu().numpy().astype(np.complex128), N, iflag=-1)
+        assert rel_l2(f3, ex) <= 10 * eps
+    p.destroy()
