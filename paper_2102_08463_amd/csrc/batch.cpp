@@ -1,10 +1,15 @@
 // Batches of transforms of uneven sizes run as one: all transforms' bins
 // share a global numbering (bin_off per transform), their points, fine grids
 // and modes are concatenated, so the bin-sort is one sort, the subproblem list
-// is one list, and spreading, the add-back, interpolation and the
-// corrections are one persistent launch each, whose work items look up their
-// transform in a device table.  Only the fine-grid FFTs run per transform
-// (rocFFT plans cached by size).  The method is SM for every transform.
+// is one list, and the add-back and the corrections are one persistent launch
+// each, whose work items look up their transform in a device table.
+// Transforms with the same bins and msub form a class, numbered in class
+// order, so each class's subproblems are one range of the list; spreading
+// and interpolation run one launch per class (each with exactly the LDS its
+// tiles need, on parallel streams), so that a few transforms with large
+// bins do not lower the occupancy of all the others.  Only the fine-grid
+// FFTs run per transform (rocFFT plans cached by size).  The method is SM
+// for every transform.
 #include "../../include/mnufft.h"
 #include "host_common.h"
 #include "internal.h"
@@ -36,6 +41,16 @@ struct mnufft_batch_s {
     mn::TGeom *d_geo = nullptr;
     int64_t Mtot = 0, cells = 0, modes = 0;
     int nbins = 0, nsub_max = 0, msub_max = 1, ts2 = 0;
+    // classes of transforms with equal bins and msub: bins [b0, b1) of the
+    // global numbering, at most nsub_max subproblems
+    struct Cls {
+        int m[3];
+        int msub;
+        int b0, b1;
+        int nsub_max;
+    };
+    std::vector<Cls> cls;
+    int32_t *bin_t = nullptr;  // transform of every bin (device)
     void *grid = nullptr;
     void *pfac[3] = {nullptr, nullptr, nullptr};
     int2 *cov[3] = {nullptr, nullptr, nullptr};
@@ -116,7 +131,41 @@ mn::Pts batch_points(mnufft_batch b)
     P.tg = b->d_geo;
     P.T = b->T;
     P.ncells = b->cells;
+    P.bin_t = b->bin_t;
     return P;
+}
+
+// Spreading (interp false) or interpolation of every class: one launch per
+// class with its own bins and msub over its range of the subproblem list,
+// forked over the side streams when there are several classes.
+int sm_classes(mnufft_batch b, const mn::Pts &P, bool interp, const void *in, void *out)
+{
+    const int nc = (int)b->cls.size();
+    const bool fork = nc > 1;
+    if (fork && hipEventRecord(b->fork, b->stream) != hipSuccess) return MNUFFT_ERR_HIP;
+    const int ns = std::min(nc, (int)mnufft_batch_s::kFftStreams);
+    for (int k = 0; fork && k < ns; ++k)
+        if (hipStreamWaitEvent(b->fstream[k], b->fork, 0) != hipSuccess) return MNUFFT_ERR_HIP;
+    for (int c = 0; c < nc; ++c) {
+        const mnufft_batch_s::Cls &k = b->cls[c];
+        mn::Geom g = b->g;
+        for (int d = 0; d < 3; ++d) g.m[d] = k.m[d];
+        mn::Pts Pc = P;
+        Pc.q0 = P.suboff + k.b0;
+        Pc.nsub = P.suboff + k.b1;
+        Pc.nsub_max = std::max(k.nsub_max, 1);
+        Pc.msub = k.msub;
+        hipStream_t st = fork ? b->fstream[c % ns] : b->stream;
+        const hipError_t e =
+            interp ? mn::launch_interp(g, b->prec, MNUFFT_METHOD_SM, Pc, in, out, st)
+                   : mn::launch_spread(g, b->prec, MNUFFT_METHOD_SM, Pc, in, out, st, 1);
+        if (e != hipSuccess) return MNUFFT_ERR_HIP;
+    }
+    for (int k = 0; fork && k < ns; ++k)
+        if (hipEventRecord(b->join[k], b->fstream[k]) != hipSuccess ||
+            hipStreamWaitEvent(b->stream, b->join[k], 0) != hipSuccess)
+            return MNUFFT_ERR_HIP;
+    return MNUFFT_OK;
 }
 
 int run_ffts(mnufft_batch b, int sign)
@@ -273,7 +322,6 @@ int mnufft_batch_makeplan(int type, int dim, int ntr, const int64_t *nmodes, con
             tg.kmax[d] = km;
             cv[d].insert(cv[d].end(), tab.begin(), tab.end());
         }
-        tg.bin_off = (int)bin_off;
         tg.nbins = (int)nb;
         tg.pt_off = (int)pt_off;
         tg.M = (int)npts[t];
@@ -281,7 +329,7 @@ int mnufft_batch_makeplan(int type, int dim, int ntr, const int64_t *nmodes, con
         tg.grid_off = grid_off;
         tg.mode_off = mode_off;
         b->msub_max = std::max(b->msub_max, tg.msub);
-        bin_off += nb;
+        bin_off += nb;  // total so far (the offsets are assigned per class below)
         pt_off += npts[t];
         grid_off += cells;
         mode_off += nm;
@@ -291,6 +339,38 @@ int mnufft_batch_makeplan(int type, int dim, int ntr, const int64_t *nmodes, con
         delete b;
         return MNUFFT_ERR_ARG;
     }
+    // classes of equal bins and msub, in order of first appearance; bins are
+    // numbered class by class (transforms in input order within a class)
+    std::vector<int> cls_of(ntr);
+    for (int t = 0; t < ntr; ++t) {
+        const mn::TGeom &tg = b->geo[t];
+        int c = 0;
+        for (; c < (int)b->cls.size(); ++c) {
+            const mnufft_batch_s::Cls &k = b->cls[c];
+            if (k.m[0] == tg.m[0] && k.m[1] == tg.m[1] && k.m[2] == tg.m[2] && k.msub == tg.msub)
+                break;
+        }
+        if (c == (int)b->cls.size())
+            b->cls.push_back({{tg.m[0], tg.m[1], tg.m[2]}, tg.msub, 0, 0, 0});
+        cls_of[t] = c;
+    }
+    {
+        int64_t next = 0;
+        for (int c = 0; c < (int)b->cls.size(); ++c) {
+            mnufft_batch_s::Cls &k = b->cls[c];
+            k.b0 = (int)next;
+            int64_t ns = 0;
+            for (int t = 0; t < ntr; ++t) {
+                if (cls_of[t] != c) continue;
+                mn::TGeom &tg = b->geo[t];
+                tg.bin_off = (int)next;
+                next += tg.nbins;
+                ns += tg.nbins + (npts[t] + tg.msub - 1) / tg.msub;
+            }
+            k.b1 = (int)next;
+            k.nsub_max = (int)std::min<int64_t>(ns, 2147483647LL);
+        }
+    }
     b->Mtot = Mtot;
     b->cells = grid_off;
     b->modes = mode_off;
@@ -299,10 +379,14 @@ int mnufft_batch_makeplan(int type, int dim, int ntr, const int64_t *nmodes, con
     for (int d = 0; d < 3; ++d) b->g.m[d] = mmax[d];
     b->g.nbins = b->nbins;
     b->ts2 = mn::sm_tile_stride(b->g);
-    if (mn::sm_lds_bytes(b->g, prec, false, b->msub_max) > kLdsMax ||
-        mn::sm_lds_bytes(b->g, prec, true, b->msub_max) > kLdsMax) {
-        delete b;
-        return MNUFFT_ERR_ARG;
+    for (const mnufft_batch_s::Cls &k : b->cls) {
+        mn::Geom g = b->g;
+        for (int d = 0; d < 3; ++d) g.m[d] = k.m[d];
+        if (mn::sm_lds_bytes(g, prec, false, k.msub) > kLdsMax ||
+            mn::sm_lds_bytes(g, prec, true, k.msub) > kLdsMax) {
+            delete b;
+            return MNUFFT_ERR_ARG;
+        }
     }
 
     // ---- device state ----
@@ -311,6 +395,13 @@ int mnufft_batch_makeplan(int type, int dim, int ntr, const int64_t *nmodes, con
     if (!rc && b->device >= 0 && hipSetDevice(b->device) != hipSuccess) rc = MNUFFT_ERR_HIP;
     if (!rc) rc = balloc(b, (void **)&b->d_geo, sizeof(mn::TGeom) * ntr);
     if (!rc) rc = upload(b->d_geo, b->geo.data(), sizeof(mn::TGeom) * ntr);
+    if (!rc) {
+        std::vector<int32_t> bt((size_t)std::max(b->nbins, 1), 0);
+        for (int t = 0; t < ntr; ++t)
+            for (int k = 0; k < b->geo[t].nbins; ++k) bt[(size_t)b->geo[t].bin_off + k] = t;
+        rc = balloc(b, (void **)&b->bin_t, bt.size() * 4);
+        if (!rc) rc = upload(b->bin_t, bt.data(), bt.size() * 4);
+    }
     if (!rc) rc = balloc(b, &b->grid, (size_t)b->cells * 2 * b->rsz);
     for (int d = 0; d < 3 && !rc; ++d) {
         rc = balloc(b, &b->pfac[d], pf[d].size() * b->rsz);
@@ -417,7 +508,7 @@ int mnufft_batch_setpts(mnufft_batch b, const void *x, const void *y, const void
         b->perm = reinterpret_cast<int32_t *>(sv);
         if (mn::launch_binstart(M, b->nbins, b->skey, b->binstart, s)) return MNUFFT_ERR_HIP;
         if (mn::launch_subproblems(b->nbins, b->msub_max, b->nsub_max, b->binstart, b->subcount,
-                                   b->partials, b->sub, b->nsub, s, b->d_geo, b->T))
+                                   b->partials, b->sub, b->nsub, s, b->d_geo, b->T, b->bin_t))
             return MNUFFT_ERR_HIP;
         if (mn::launch_zero(b->nmerge, 4, s)) return MNUFFT_ERR_HIP;
         if (mn::launch_merge_list(b->nsub_max, b->nsub, b->sub, b->subcount, kMergeGroup,
@@ -446,8 +537,8 @@ int mnufft_batch_execute(mnufft_batch b, void *c, void *f)
         }
         {
             StageTimer tm(b->tm, MNUFFT_STAGE_SPREAD, s);
-            if (mn::launch_spread(b->g, b->prec, MNUFFT_METHOD_SM, P, c, b->grid, s, 1))
-                return MNUFFT_ERR_HIP;
+            rc = sm_classes(b, P, false, c, b->grid);
+            if (rc) return rc;
         }
         {
             StageTimer tm(b->tm, MNUFFT_STAGE_ADDBACK, s);
@@ -475,9 +566,7 @@ int mnufft_batch_execute(mnufft_batch b, void *c, void *f)
     }
     if (rc) return rc;
     StageTimer tm(b->tm, MNUFFT_STAGE_INTERP, s);
-    if (mn::launch_interp(b->g, b->prec, MNUFFT_METHOD_SM, P, b->grid, c, s))
-        return MNUFFT_ERR_HIP;
-    return MNUFFT_OK;
+    return sm_classes(b, P, true, b->grid, c);
 }
 
 int mnufft_batch_set_timing(mnufft_batch b, int enable)

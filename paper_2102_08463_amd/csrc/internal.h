@@ -167,6 +167,9 @@ struct Pts {
     const TGeom *tg;
     int T;
     long long ncells;         // fine-grid cells over all transforms
+    const int32_t *bin_t;     // batches: transform of every bin (nbins entries)
+    const int32_t *q0;        // SM kernels: first subproblem to process (device; null: 0),
+                              // with *nsub the end of the range
 };
 
 // ---- bin sort (kernels_sort.hip) ------------------------------------------
@@ -218,7 +221,8 @@ hipError_t launch_binstart(int M, int nbins, const uint32_t *skey, int32_t *bins
 // With a batch table, each bin uses its transform's msub.
 hipError_t launch_subproblems(int nbins, int msub, int nsub_max, const int32_t *binstart,
                               int32_t *subcount, uint32_t *partials, int32_t *sub,
-                              int32_t *nsub, hipStream_t s, const TGeom *tg = nullptr, int T = 1);
+                              int32_t *nsub, hipStream_t s, const TGeom *tg = nullptr, int T = 1,
+                              const int32_t *bin_t = nullptr);
 
 // Processing order of the SM kernels within each subproblem (see k_balance):
 // v[d] / vperm / spos / hslot receive the sorted coordinates, the
@@ -314,6 +318,20 @@ hipError_t launch_argmin_rows(int T, int K, const float *Y, const unsigned long 
 hipError_t launch_density_batch(int prec, int T, const int64_t *off, const void *x, const void *y,
                                 float *feat, int ldf, void *work, const float *scal, int nscal,
                                 hipStream_t s);
+// The parts of launch_density_batch for callers that keep the partial rows
+// (T * MNUFFT_DENSITY_BATCH_WORK_BYTES at part) between calls: clearing
+// them, and counting into them (they must be zero before).
+hipError_t launch_hist_clear(int T, uint32_t *part, hipStream_t s);
+hipError_t launch_hist_count(int prec, int T, const int64_t *off, const void *x, const void *y,
+                             uint32_t *part, hipStream_t s);
+// The selector's pass over T counted sets in one launch: features from the
+// partial rows (returned to zero) and the nscal scalars per set (scal, T x
+// nscal), the network (F = 256 + nscal inputs) and the argmin as
+// launch_mlp_argmin gives it.
+hipError_t launch_select_rows(int T, const int64_t *off, uint32_t *part, const float *scal,
+                              int nscal, int F, int H, int K, const float *params,
+                              const unsigned long long mask[2], int *idx, float *gap,
+                              hipStream_t s);
 // The network (F -> H -> H -> K, mnufft_mlp_forward's parameter layout) and
 // the argmin above fused, one block per row of X (T rows of stride ldx):
 // idx / gap as launch_argmin_rows gives them on the network's output.

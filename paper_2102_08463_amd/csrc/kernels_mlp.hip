@@ -156,9 +156,10 @@ __global__ void k_hist_final(long long M, int nblk, const uint32_t *__restrict__
 // set's partial row (chunk index mod kBatchChunks).  The rows must start at
 // zero (k_hist_clear).
 constexpr int kBatchChunks = 32;  // partial rows per set; see MNUFFT_DENSITY_BATCH_WORK_BYTES
-constexpr int kHistChunk = 16384;
-constexpr int kHistBatchBlocks = 1024;
-constexpr int kHistUnroll = 4;
+constexpr int kHistChunk = 8192;
+constexpr int kHistBatchBlocks = 2048;
+constexpr int kHistUnroll = 8;
+constexpr int kHistOffCache = 1024;  // set offsets kept in LDS (sets below this count)
 
 __global__ void k_hist_clear(size_t n, uint32_t *__restrict__ part)
 {
@@ -174,8 +175,16 @@ k_hist_batch(int nset, const int64_t *__restrict__ off, const T *__restrict__ x,
 {
     constexpr int kWaves = kThreads / 64;
     __shared__ uint32_t h[kWaves][256];
+    __shared__ long long soff[kHistOffCache];
     __shared__ int first;
-    const long long Mtot = off[nset];
+    // the set offsets, from LDS when they fit (the searches below touch them
+    // for every chunk)
+    const bool cached = nset < kHistOffCache;
+    if (cached)
+        for (int k = threadIdx.x; k <= nset; k += kThreads) soff[k] = off[k];
+    __syncthreads();
+    const auto O = [&](int k) { return cached ? soff[k] : (long long)off[k]; };
+    const long long Mtot = O(nset);
     const int wave = threadIdx.x >> 6;
     for (long long a = (long long)blockIdx.x * kHistChunk; a < Mtot;
          a += (long long)gridDim.x * kHistChunk) {
@@ -184,7 +193,7 @@ k_hist_batch(int nset, const int64_t *__restrict__ off, const T *__restrict__ x,
             int lo = 0, hi = nset - 1;
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
-                if (off[mid + 1] > a) hi = mid;
+                if (O(mid + 1) > a) hi = mid;
                 else lo = mid + 1;
             }
             first = lo;
@@ -194,8 +203,8 @@ k_hist_batch(int nset, const int64_t *__restrict__ off, const T *__restrict__ x,
         __syncthreads();
         const int row = (int)((a / kHistChunk) % kBatchChunks);
         // the bounds below are the same for every thread, so is the control flow
-        for (int t = t0; t < nset && off[t] < e; ++t) {
-            const long long s0 = max(a, (long long)off[t]), s1 = min(e, (long long)off[t + 1]);
+        for (int t = t0; t < nset && O(t) < e; ++t) {
+            const long long s0 = max(a, O(t)), s1 = min(e, O(t + 1));
             if (s0 >= s1) continue;
             for (int k = threadIdx.x; k < kWaves * 256; k += kThreads) (&h[0][0])[k] = 0u;
             __syncthreads();
@@ -239,8 +248,9 @@ __global__ void k_hist_batch_final(const int64_t *__restrict__ off,
 }
 
 // One layer of the network inside a block: out = act(bias + W^T in), with
-// the In-sum of each output split over the block's 256 / Out thread groups
-// and the group sums added in LDS.  Out <= 256.  Ends with a barrier.
+// the In-sum of each output split over the block's blockDim / Out thread
+// groups (few terms per thread, so the weight loads are all in flight at
+// once) and the group sums added in LDS.  Out <= 256.  Ends with a barrier.
 __device__ void block_dense(int In, int Out, const float *in, const float *__restrict__ W,
                             const float *__restrict__ bias, float *out, float *red, bool relu)
 {
@@ -248,6 +258,7 @@ __device__ void block_dense(int In, int Out, const float *in, const float *__res
     const int o = threadIdx.x % Out, grp = threadIdx.x / Out;
     if (grp < G) {
         float acc = 0.0f;
+#pragma unroll 8
         for (int i = grp; i < In; i += G) acc = fmaf(in[i], W[(size_t)i * Out + o], acc);
         red[grp * Out + o] = acc;
     }
@@ -264,14 +275,14 @@ __device__ void block_dense(int In, int Out, const float *in, const float *__res
 // network on the row's features, then the allowed output of smallest value
 // and its gap to the runner-up (infinity with one allowed output, index -1
 // with none), as k_argmin_rows computes them.
-constexpr int kFusedMaxF = 512, kFusedMaxH = 256, kFusedMaxK = 128;
-__global__ void __launch_bounds__(256)
+constexpr int kFusedMaxF = 512, kFusedMaxH = 256, kFusedMaxK = 128, kFusedThreads = 1024;
+__global__ void __launch_bounds__(kFusedThreads)
 k_mlp_argmin(int F, int H, int K, const float *__restrict__ params, const float *__restrict__ X,
              int ldx, unsigned long long m0, unsigned long long m1, int *__restrict__ idx,
              float *__restrict__ gap)
 {
     __shared__ float xs[kFusedMaxF], h1[kFusedMaxH], h2[kFusedMaxH], ys[kFusedMaxK];
-    __shared__ float red[256];
+    __shared__ float red[kFusedThreads];
     const int b = blockIdx.x;
     const float *W1 = params, *b1 = W1 + (size_t)F * H, *W2 = b1 + H, *b2 = W2 + (size_t)H * H;
     const float *W3 = b2 + H, *b3 = W3 + (size_t)H * K;
@@ -297,6 +308,67 @@ k_mlp_argmin(int F, int H, int K, const float *__restrict__ params, const float 
         }
         idx[b] = best;
         gap[b] = v1 - v0;
+    }
+}
+
+// The selector's whole pass for set t = blockIdx.x from the partial
+// histogram rows: the set's features (the 256 density features as
+// k_hist_batch_final computes them, then its nscal scalars), which also
+// returns the set's rows to zero for the next count, the network, and the
+// argmin of k_mlp_argmin.
+__global__ void __launch_bounds__(kFusedThreads)
+k_select_rows(const int64_t *__restrict__ off, uint32_t *__restrict__ part,
+              const float *__restrict__ scal, int nscal, int H, int K,
+              const float *__restrict__ params, unsigned long long m0, unsigned long long m1,
+              int *__restrict__ idx, float *__restrict__ gap)
+{
+    __shared__ float xs[kFusedMaxF], h1[kFusedMaxH], h2[kFusedMaxH], ys[kFusedMaxK];
+    __shared__ float red[kFusedThreads];
+    __shared__ unsigned long long cnt[4][256];
+    const int t = blockIdx.x, tid = threadIdx.x;
+    const int F = 256 + nscal;
+    {
+        // four groups of 256 threads sum eight partial rows each
+        const int c = tid & 255, grp = tid >> 8;
+        unsigned long long sum = 0;
+        for (int b = grp; b < kBatchChunks; b += 4) {
+            uint32_t *r = part + ((size_t)t * kBatchChunks + b) * 256 + c;
+            sum += *r;
+            *r = 0u;
+        }
+        cnt[grp][c] = sum;
+    }
+    __syncthreads();
+    if (tid < 256) {
+        const long long M = off[t + 1] - off[t];
+        const unsigned long long sum = cnt[0][tid] + cnt[1][tid] + cnt[2][tid] + cnt[3][tid];
+        xs[tid] = M > 0 ? log1pf(256.0f * (float)((double)sum / (double)M)) : 0.0f;
+    } else if (tid < 256 + nscal) {
+        xs[tid] = scal[(size_t)t * nscal + tid - 256];
+    }
+    __syncthreads();
+    const float *W1 = params, *b1 = W1 + (size_t)F * H, *W2 = b1 + H, *b2 = W2 + (size_t)H * H;
+    const float *W3 = b2 + H, *b3 = W3 + (size_t)H * K;
+    block_dense(F, H, xs, W1, b1, h1, red, true);
+    block_dense(H, H, h1, W2, b2, h2, red, true);
+    block_dense(H, K, h2, W3, b3, ys, red, false);
+    if (tid == 0) {
+        int best = -1;
+        float v0 = INFINITY, v1 = INFINITY;
+        for (int k = 0; k < K; ++k) {
+            const unsigned long long m = k < 64 ? m0 : m1;
+            if (!((m >> (k & 63)) & 1ull)) continue;
+            const float v = ys[k];
+            if (v < v0) {
+                v1 = v0;
+                v0 = v;
+                best = k;
+            } else if (v < v1) {
+                v1 = v;
+            }
+        }
+        idx[t] = best;
+        gap[t] = v1 - v0;
     }
 }
 
@@ -387,6 +459,41 @@ hipError_t launch_argmin_rows(int T, int K, const float *Y, const unsigned long 
     return hipGetLastError();
 }
 
+hipError_t launch_select_rows(int T, const int64_t *off, uint32_t *part, const float *scal,
+                              int nscal, int F, int H, int K, const float *params,
+                              const unsigned long long mask[2], int *idx, float *gap,
+                              hipStream_t s)
+{
+    if (nscal < 0 || F != 256 + nscal || F > kFusedMaxF || H < 1 || H > kFusedMaxH || K < 1 ||
+        K > kFusedMaxK)
+        return hipErrorInvalidValue;
+    if (T <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_select_rows, dim3(T), dim3(kFusedThreads), 0, s, off, part, scal, nscal,
+                       H, K, params, mask[0], mask[1], idx, gap);
+    return hipGetLastError();
+}
+
+hipError_t launch_hist_clear(int T, uint32_t *part, hipStream_t s)
+{
+    const size_t nrow = (size_t)T * kBatchChunks * 256;
+    if (T <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hist_clear, dim3((unsigned)std::min<size_t>(1024, (nrow + 255) / 256)),
+                       dim3(256), 0, s, nrow, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_hist_count(int prec, int T, const int64_t *off, const void *x, const void *y,
+                             uint32_t *part, hipStream_t s)
+{
+    if (prec == MNUFFT_F32)
+        hipLaunchKernelGGL(k_hist_batch<float>, dim3(kHistBatchBlocks), dim3(kThreads), 0, s, T,
+                           off, (const float *)x, (const float *)y, part);
+    else
+        hipLaunchKernelGGL(k_hist_batch<double>, dim3(kHistBatchBlocks), dim3(kThreads), 0, s, T,
+                           off, (const double *)x, (const double *)y, part);
+    return hipGetLastError();
+}
+
 hipError_t launch_density_batch(int prec, int T, const int64_t *off, const void *x, const void *y,
                                 float *feat, int ldf, void *work, const float *scal, int nscal,
                                 hipStream_t s)
@@ -405,8 +512,8 @@ hipError_t launch_mlp_argmin(int F, int H, int K, const float *params, int T, co
         ldx < F)
         return hipErrorInvalidValue;
     if (T <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mlp_argmin, dim3(T), dim3(256), 0, s, F, H, K, params, X, ldx, mask[0],
-                       mask[1], idx, gap);
+    hipLaunchKernelGGL(k_mlp_argmin, dim3(T), dim3(kFusedThreads), 0, s, F, H, K, params, X, ldx,
+                       mask[0], mask[1], idx, gap);
     return hipGetLastError();
 }
 }  // namespace mn

@@ -346,26 +346,27 @@ __global__ void k_binstart(int M, int nbins, const uint32_t *__restrict__ skey,
 }
 
 // msub of bin b: the plan's, or in a batch that of the bin's transform.
-__device__ __forceinline__ int msub_of(int b, int msub, const TGeom *tg, int T)
+__device__ __forceinline__ int msub_of(int b, int msub, const TGeom *tg, const int32_t *bin_t)
 {
-    if (!tg) return msub;
-    return tg[find_transform(tg, T, b, [](const TGeom &a) { return a.bin_off; })].msub;
+    return tg ? tg[bin_t[b]].msub : msub;
 }
 
 __global__ void k_subcount(int nbins, int msub, const int32_t *__restrict__ binstart,
-                           uint32_t *__restrict__ cnt, const TGeom *__restrict__ tg, int T)
+                           uint32_t *__restrict__ cnt, const TGeom *__restrict__ tg,
+                           const int32_t *__restrict__ bin_t)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b > nbins) return;
     if (b == nbins) { cnt[b] = 0; return; }
     const int c = binstart[b + 1] - binstart[b];
-    const int ms = msub_of(b, msub, tg, T);
+    const int ms = msub_of(b, msub, tg, bin_t);
     cnt[b] = (uint32_t)((c + ms - 1) / ms);
 }
 
 __global__ void k_subfill(int nbins, int msub, int nsub_max, const int32_t *__restrict__ binstart,
                           const uint32_t *__restrict__ off, int32_t *__restrict__ sub,
-                          int32_t *__restrict__ nsub, const TGeom *__restrict__ tg, int T)
+                          int32_t *__restrict__ nsub, const TGeom *__restrict__ tg,
+                          const int32_t *__restrict__ bin_t)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     // the count is clamped to the list's capacity so that no consumer can
@@ -379,7 +380,7 @@ __global__ void k_subfill(int nbins, int msub, int nsub_max, const int32_t *__re
         if (off[mid] <= (uint32_t)q) lo = mid; else hi = mid - 1;
     }
     const int b = lo;
-    const int ms = msub_of(b, msub, tg, T);
+    const int ms = msub_of(b, msub, tg, bin_t);
     const int s = q - (int)off[b];
     const int start = binstart[b] + s * ms;
     const int len = std::min(ms, binstart[b + 1] - start);
@@ -637,15 +638,19 @@ hipError_t launch_balance(const Geom &g, int prec, int nsub_max, const int32_t *
 
 hipError_t launch_subproblems(int nbins, int msub, int nsub_max, const int32_t *binstart,
                               int32_t *subcount, uint32_t *partials, int32_t *sub,
-                              int32_t *nsub, hipStream_t s, const TGeom *tg, int T)
+                              int32_t *nsub, hipStream_t s, const TGeom *tg, int T,
+                              const int32_t *bin_t)
 {
+    if (tg && !bin_t) return hipErrorInvalidValue;
+    (void)T;
     uint32_t *cnt = reinterpret_cast<uint32_t *>(subcount);
     hipLaunchKernelGGL(k_subcount, dim3(nblocks(nbins + 1, 256)), dim3(256), 0, s, nbins, msub,
-                       binstart, cnt, tg, T);
+                       binstart, cnt, tg, bin_t);
     hipError_t e = scan_exclusive(cnt, cnt, (size_t)nbins + 1, partials, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_subfill, dim3(nblocks(std::max(nsub_max, 1), 256)), dim3(256), 0, s,
-                       nbins, msub, nsub_max, binstart, (const uint32_t *)cnt, sub, nsub, tg, T);
+                       nbins, msub, nsub_max, binstart, (const uint32_t *)cnt, sub, nsub, tg,
+                       bin_t);
     return hipGetLastError();
 }
 

@@ -45,6 +45,7 @@ struct Work {
     size_t bytes = 0;
     void *host = nullptr;
     size_t hbytes = 0;
+    int clean_sets = 0;  // leading partial-histogram rows (sets) known to be zero
 };
 std::map<int, Work> g_work;
 
@@ -71,6 +72,7 @@ void *workspace(size_t bytes)
         if (w.ptr) (void)hipFree(w.ptr);
         w.ptr = nullptr;
         w.bytes = 0;
+        w.clean_sets = 0;
         if (hipMalloc(&w.ptr, bytes) != hipSuccess) {
             (void)hipGetLastError();
             w.ptr = nullptr;
@@ -427,21 +429,21 @@ int mnufft_batch_select(int type, int dim, int ntr, const int64_t *nmodes, const
         if (!sel) {
             for (int t = 0; t < ntr; ++t) need_tune.push_back(t);
         } else {
-            // one upload (set offsets and scalar features), one batched
-            // histogram, one fused network + argmin launch and one download
-            // (picks and gaps) for all transforms, through pinned staging
+            // one upload (set offsets and scalar features), the batched
+            // histogram counts, one launch for the features, the network and
+            // the argmin of every transform, and one download (picks and
+            // gaps), through pinned staging
             const int K = sel->K, H = sel->H;
             const size_t hist = (size_t)ntr * MNUFFT_DENSITY_BATCH_WORK_BYTES;
             const size_t offb = ((size_t)ntr + 1) * 8, scb = (size_t)ntr * kScal * 4;
-            const size_t fl = (size_t)ntr * kF * 4, outb = (size_t)ntr * 8;
-            char *ws = (char *)workspace(hist + offb + scb + fl + outb);
+            const size_t outb = (size_t)ntr * 8;
+            char *ws = (char *)workspace(hist + offb + scb + outb);
             char *hs = (char *)host_stage(offb + scb + outb);
             float *params = device_params(*sel);
             if (!ws || !hs || !params) return MNUFFT_ERR_ALLOC;
             int64_t *off = (int64_t *)(ws + hist);
             float *scal = (float *)(ws + hist + offb);
-            float *feat = (float *)(ws + hist + offb + scb);
-            int *idx = (int *)(ws + hist + offb + scb + fl);
+            int *idx = (int *)(ws + hist + offb + scb);
             float *gap = (float *)(idx + ntr);
             int64_t *hoff = (int64_t *)hs;
             float *hscal = (float *)(hs + offb);
@@ -453,18 +455,24 @@ int mnufft_batch_select(int type, int dim, int ntr, const int64_t *nmodes, const
                 scalar_features(type, dim, nmodes + 3 * t, npts[t], eps, prec,
                                 hscal + (size_t)t * kScal);
             }
-            if (hipMemcpyAsync(off, hoff, offb + scb, hipMemcpyHostToDevice, s) != hipSuccess)
-                return MNUFFT_ERR_HIP;
-            if (mn::launch_density_batch(prec, ntr, off, x, y, feat, kF, ws, scal, kScal, s) !=
-                hipSuccess)
-                return MNUFFT_ERR_HIP;
+            // The partial rows are cleared only when they may hold something:
+            // the selection kernel returns the rows it reads to zero, and the
+            // rows past this call's sets may be overwritten by its other data.
+            Work &wk = g_work[current_device()];
+            uint32_t *part = (uint32_t *)ws;
+            const bool need_clear = wk.clean_sets < ntr;
+            wk.clean_sets = 0;
             unsigned long long mask[2];
             allowed_mask(*sel, true, mask);
-            if (mn::launch_mlp_argmin(kF, H, K, params, ntr, feat, kF, mask, idx, gap, s) !=
-                    hipSuccess ||
+            if (hipMemcpyAsync(off, hoff, offb + scb, hipMemcpyHostToDevice, s) != hipSuccess ||
+                (need_clear && mn::launch_hist_clear(ntr, part, s) != hipSuccess) ||
+                mn::launch_hist_count(prec, ntr, off, x, y, part, s) != hipSuccess ||
+                mn::launch_select_rows(ntr, off, part, scal, kScal, kF, H, K, params, mask, idx,
+                                       gap, s) != hipSuccess ||
                 hipMemcpyAsync((void *)hidx, idx, outb, hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess)
                 return MNUFFT_ERR_HIP;
+            wk.clean_sets = ntr;
             for (int t = 0; t < ntr; ++t) {
                 if (hidx[t] < 0 || (double)hgap[t] < sel->margin) {
                     need_tune.push_back(t);

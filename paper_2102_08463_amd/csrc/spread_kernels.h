@@ -454,7 +454,8 @@ k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
             const int32_t *__restrict__ idx, const uint16_t *__restrict__ hslot,
             const typename Cplx<T>::type *__restrict__ c,
             const T *__restrict__ cmaxp, T *__restrict__ scratch, int ts2, T bk,
-            const TGeom *__restrict__ tg, int T_)
+            const TGeom *__restrict__ tg, const int32_t *__restrict__ bin_t,
+            const int32_t *__restrict__ q0p)
 {
     using V = typename Vec16<T>::type;
     constexpr int NV = 16 / sizeof(T);
@@ -464,14 +465,15 @@ k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
     __shared__ unsigned red[kThreads / 64];
     constexpr int P = (W + 1) / 2;
     const int nsub = *nsubp;
+    const int q0 = q0p ? *q0p : 0;
     int ecm;
     frexp(block_cmax(cmaxp), &ecm);  // cmax < 2^ecm
-    for (int q = blockIdx.x; q < nsub; q += gridDim.x) {
+    for (int q = q0 + (int)blockIdx.x; q < nsub; q += gridDim.x) {
         const int4 rec = reinterpret_cast<const int4 *>(sub)[q];
         int m1 = g.m[0], m2 = g.m[1], m3 = g.m[2];
         if constexpr (BATCH) {
             const TGeom &tt =
-                tg[find_transform(tg, T_, rec.x, [](const TGeom &a) { return a.bin_off; })];
+                tg[bin_t[rec.x]];
             m1 = tt.m[0];
             m2 = tt.m[1];
             m3 = tt.m[2];
@@ -599,26 +601,30 @@ k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict_
              const float *__restrict__ u0, const float *__restrict__ u1,
              const float *__restrict__ u2, const int32_t *__restrict__ idx,
              const uint16_t *__restrict__ hslot, const float2 *__restrict__ c,
-             float *__restrict__ scratch, int ts2, float bk, int stage_cap,
-             const TGeom *__restrict__ tg, int T_)
+             float *__restrict__ scratch, int ts2, int lts, float bk, int stage_cap,
+             const TGeom *__restrict__ tg, const int32_t *__restrict__ bin_t,
+             const int32_t *__restrict__ q0p)
 {
     static_assert(std::is_same<T, float>::value && DIM >= 2, "2D / 3D single precision only");
     constexpr int P = (W + 1) / 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    unsigned long long *tile = reinterpret_cast<unsigned long long *>(smem_raw);  // ts2 / 2 cells
+    // LDS: the tile (lts / 2 cells, the launch's largest), then the staged
+    // strengths; tiles in scratch are ts2 floats apart
+    unsigned long long *tile = reinterpret_cast<unsigned long long *>(smem_raw);
     unsigned *H = reinterpret_cast<unsigned *>(smem_raw);  // start histogram, before the tile
-    float2 *cs = reinterpret_cast<float2 *>(tile + ts2 / 2);  // first stage_cap strengths
+    float2 *cs = reinterpret_cast<float2 *>(tile + lts / 2);  // first stage_cap strengths
     unsigned short *slot = reinterpret_cast<unsigned short *>(cs + stage_cap);  // their slots
     __shared__ float red[kThreads / 64];
     __shared__ unsigned redu[kThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int nsub = *nsubp;
-    for (int q = blockIdx.x; q < nsub; q += gridDim.x) {
+    const int q0 = q0p ? *q0p : 0;
+    for (int q = q0 + (int)blockIdx.x; q < nsub; q += gridDim.x) {
         const int4 rec = reinterpret_cast<const int4 *>(sub)[q];
         int m1 = g.m[0], m2 = g.m[1], m3 = g.m[2];
         if constexpr (BATCH) {
             const TGeom &tt =
-                tg[find_transform(tg, T_, rec.x, [](const TGeom &a) { return a.bin_off; })];
+                tg[bin_t[rec.x]];
             m1 = tt.m[0];
             m2 = tt.m[1];
             m3 = tt.m[2];
@@ -978,21 +984,23 @@ __global__ void __launch_bounds__(kThreads)
 k_interp_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__ nsubp,
             const T *__restrict__ u0, const T *__restrict__ u1, const T *__restrict__ u2,
             const int32_t *__restrict__ idx, const typename Cplx<T>::type *__restrict__ grid_,
-            typename Cplx<T>::type *__restrict__ c, T bk, const TGeom *__restrict__ tg, int T_)
+            typename Cplx<T>::type *__restrict__ c, T bk, const TGeom *__restrict__ tg,
+            const int32_t *__restrict__ bin_t, const int32_t *__restrict__ q0p)
 {
     using C = typename Cplx<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *tile = reinterpret_cast<C *>(smem_raw);
     constexpr int P = (W + 1) / 2;
     const int nsub = *nsubp;
-    for (int q = blockIdx.x; q < nsub; q += gridDim.x) {
+    const int q0 = q0p ? *q0p : 0;
+    for (int q = q0 + (int)blockIdx.x; q < nsub; q += gridDim.x) {
         const int4 rec = reinterpret_cast<const int4 *>(sub)[q];
         int b = rec.x;
         Geom gg = g;
         const C *grid = grid_;
         if constexpr (BATCH) {
             const TGeom &tt =
-                tg[find_transform(tg, T_, rec.x, [](const TGeom &a) { return a.bin_off; })];
+                tg[bin_t[rec.x]];
             gg = geom_of(g, tt);
             grid = grid_ + tt.grid_off;
             b -= tt.bin_off;
@@ -1298,8 +1306,8 @@ hipError_t spread_wb(const Geom &g, int method, const Pts &P, const void *c, voi
                 hipLaunchKernelGGL(pk, dim3(sm_grid(P)), dim3(kThreads), lds, s, g, P.sub,
                                    P.nsub, (const float *)P.u[0], (const float *)P.u[1],
                                    (const float *)P.u[2], sm_index(P), P.hslot, (const float2 *)c,
-                                   (float *)P.scratch, P.ts2, (float)bk,
-                                   smp_stage(DIM, P.msub), P.tg, P.T);
+                                   (float *)P.scratch, P.ts2, sm_tile_stride(g), (float)bk,
+                                   smp_stage(DIM, P.msub), P.tg, P.bin_t, P.q0);
             } else {
                 auto kern = k_spread_sm<T, DIM, W, BATCH>;
                 if (lds > 65536)
@@ -1309,7 +1317,7 @@ hipError_t spread_wb(const Geom &g, int method, const Pts &P, const void *c, voi
                                    P.nsub, (const T *)P.u[0], (const T *)P.u[1], (const T *)P.u[2],
                                    sm_index(P), P.hslot, (const C *)c, (const T *)P.cmax,
                                    (T *)P.scratch,
-                                   P.ts2, bk, P.tg, P.T);
+                                   P.ts2, bk, P.tg, P.bin_t, P.q0);
             }
         }
         if (!(part & 2)) return hipGetLastError();
@@ -1365,7 +1373,7 @@ hipError_t interp_wb(const Geom &g, int method, const Pts &P, const void *grid, 
                                       (int)lds);
         hipLaunchKernelGGL(kern, dim3(sm_grid(P)), dim3(kThreads), lds, s, g, P.sub, P.nsub,
                            (const T *)P.u[0], (const T *)P.u[1], (const T *)P.u[2], sm_index(P),
-                           (const C *)grid, (C *)c, bk, P.tg, P.T);
+                           (const C *)grid, (C *)c, bk, P.tg, P.bin_t, P.q0);
     } else {
         const bool gm = method == 1;
         hipLaunchKernelGGL((k_interp_gm<T, DIM, W>), dim3(cdiv(P.M, kThreads)), dim3(kThreads),

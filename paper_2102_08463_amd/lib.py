@@ -6,6 +6,7 @@ before the library is loaded so that both share one HIP runtime.  There is
 no CPU fallback: if the library is missing, loading raises.
 """
 import ctypes
+import itertools
 import os
 
 import torch
@@ -161,9 +162,9 @@ def load():
     L.mnufft_select.argtypes = [ci, ci, ctypes.POINTER(i64), ci, ctypes.c_double, ci, i64, vp, vp,
                                 vp, ci, ctypes.POINTER(Opts), ctypes.POINTER(Opts),
                                 ctypes.POINTER(ci)]
-    L.mnufft_batch_select.argtypes = [ci, ci, ci, ctypes.POINTER(i64), ctypes.POINTER(i64), vp,
-                                      vp, vp, ctypes.c_double, ci, ci, ctypes.POINTER(Opts),
-                                      i32p, i32p, i32p]
+    # (raw addresses for the arrays: batch_select passes numpy buffers)
+    L.mnufft_batch_select.argtypes = [ci, ci, ci, vp, vp, vp, vp, vp, ctypes.c_double, ci, ci,
+                                      ctypes.POINTER(Opts), vp, vp, vp]
     for name in EXPORTS:
         getattr(L, name).restype = ctypes.c_char_p if name == "mnufft_strerror" else ci
     L.mnufft_mlp_nparams.restype = ctypes.c_int64
@@ -248,23 +249,41 @@ def select(nufft_type, n_modes, points, eps, mode="learned", isign=None, upsampf
 def batch_select(nufft_type, n_modes_list, npts, x, y, eps, z=None, mode="learned"):
     """Per-transform (binsize list, msub list, source list) from
     mnufft_batch_select for point sets stored back to back in x, y (, z)."""
+    import numpy as np
     import torch
     T = len(npts)
     dim = len(n_modes_list[0])
     prec = F32 if x.dtype == torch.float32 else F64
-    nm = (ctypes.c_int64 * (3 * T))(*[v for m in n_modes_list for v in list(m) + [1] * (3 - dim)])
-    npa = (ctypes.c_int64 * T)(*[int(m) for m in npts])
-    bins = (ctypes.c_int32 * (3 * T))()
-    msub = (ctypes.c_int32 * T)()
-    src = (ctypes.c_int32 * T)()
-    base = default_opts()
+    # (raw addresses: numpy's ctypes.data_as and ctypes.cast cost microseconds
+    # each, and this call sits on the selection's critical path)
+    nm = np.ones((T, 3), np.int64)
+    nm[:, :dim] = np.fromiter(itertools.chain.from_iterable(n_modes_list), np.int64,
+                              T * dim).reshape(T, dim)
+    npa = np.fromiter(npts, np.int64, T)
+    out = np.zeros(5 * T, np.int32)  # binsize (3 T), msub (T), source (T)
+    base = _base_opts()
     base.stream = torch.cuda.current_stream().cuda_stream
-    ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
-    check(load().mnufft_batch_select(int(nufft_type), dim, T, nm, npa, ptr(x), ptr(y), ptr(z),
-                                     float(eps), prec, TUNES[mode], ctypes.byref(base), bins,
-                                     msub, src), "mnufft_batch_select")
-    return ([tuple(bins[3 * t + d] for d in range(dim)) for t in range(T)],
-            [msub[t] for t in range(T)], [src[t] for t in range(T)])
+    o = out.ctypes.data
+    check(load().mnufft_batch_select(int(nufft_type), dim, T, nm.ctypes.data, npa.ctypes.data,
+                                     x.data_ptr(), y.data_ptr(),
+                                     z.data_ptr() if z is not None else None, float(eps), prec,
+                                     TUNES[mode], ctypes.byref(base), o, o + 12 * T, o + 16 * T),
+          "mnufft_batch_select")
+    bins = out[:3 * T].reshape(T, 3)[:, :dim].tolist()
+    return [tuple(b) for b in bins], out[3 * T:4 * T].tolist(), out[4 * T:].tolist()
+
+
+_BASE = None
+
+
+def _base_opts():
+    """A fresh copy of the library's default options (read once)."""
+    global _BASE
+    if _BASE is None:
+        _BASE = default_opts()
+    o = Opts()
+    ctypes.pointer(o)[0] = _BASE
+    return o
 
 
 def describe(o):

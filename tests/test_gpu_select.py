@@ -127,3 +127,41 @@ def test_batch_select_learned():
         off += k
     b.destroy()
     print(f"[select] batch picks {list(zip(bins, msub, src))}", flush=True)
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained selector weights")
+def test_batch_select_matches_network():
+    """The fused selection pass of mnufft_batch_select (histogram counts, then
+    one launch for features, network and argmin) picks what the library's
+    separate feature and network entry points give, for every transform whose
+    two best SM candidates are not within rounding of each other; over calls
+    with more, fewer and again more sets (the partial rows it keeps between
+    calls must not carry counts over)."""
+    import torch
+    from paper_2102_08463_amd import lib as L
+    from paper_2102_08463_amd.selector import Selector
+    note("batch select vs network")
+    L.selector_load(WEIGHTS)
+    sel = Selector.load(WEIGHTS)
+    sm = [k for k, o in enumerate(sel.cands) if o.method == L.METHOD_SM]
+    rng = np.random.default_rng(5)
+    kinds = ["uniform", "cluster", "radial", "gaussian"]
+    for T in (12, 5, 12):
+        modes = [(int(rng.integers(32, 400)), int(rng.integers(32, 400))) for _ in range(T)]
+        npts = [int(rng.integers(0, 80_000)) if t % 5 else 0 for t in range(T)]
+        pts = [workloads.points(kinds[t % 4], m, 2, 70 + t) for t, m in enumerate(npts)]
+        x = torch.from_numpy(np.concatenate([np.asarray(p[0], np.float32) for p in pts])).cuda()
+        y = torch.from_numpy(np.concatenate([np.asarray(p[1], np.float32) for p in pts])).cuda()
+        bins, msub, src = L.batch_select(1, modes, npts, x, y, 1e-6, mode="learned")
+        feat = sel.features_batch(1, modes, x, y, npts)
+        Y = sel.forward(feat)[2].cpu().numpy()[:, sm]
+        checked = 0
+        for t in range(T):
+            order = np.argsort(Y[t])
+            if src[t] != 0 or Y[t][order[1]] - Y[t][order[0]] < 1e-4:
+                continue
+            o = sel.cands[sm[order[0]]]
+            assert bins[t] == tuple(o.binsize[:2]) and msub[t] == o.msub, (T, t)
+            checked += 1
+        assert checked >= T // 2
+        print(f"[select] T={T}: {checked} picks equal the network's", flush=True)
