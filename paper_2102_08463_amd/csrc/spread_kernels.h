@@ -706,7 +706,21 @@ k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict_
         }
         __syncthreads();
         const unsigned B = tile_bound<DIM, W>(H, hg, redu);
-        const int sh = 30 - (ceil_log2(B) - hu);  // S = 2^sh: cells below 2^30
+        // S = 2^sh keeps the cells below 2^30.  A term below 2^22 is rounded
+        // to an integer by adding 1.5 2^23 inside the FMA that forms it (the
+        // sum's float bits are then that integer plus a constant, removed in
+        // the 64-bit word): one instruction instead of a multiply and a
+        // two-instruction conversion.  Every term is below 2^22 when
+        // S <= 2^(22 - ea).  That scale is taken when it is no coarser than
+        // the cells' (dense cells), and for kernels of width 6 or less
+        // (tolerances of 1e-5 and looser) when it is at most 8x coarser: the
+        // quantum stays below 2^-21 of the largest strength, far below the
+        // tolerance.  Otherwise (tight tolerances, or a few strengths far
+        // above the rest) the terms are converted.
+        constexpr int kCoarser = W <= 6 ? 3 : 0;
+        const int sh_cell = 30 - (ceil_log2(B) - hu);
+        const bool magic = 22 - ea >= sh_cell - kCoarser;
+        const int sh = magic ? min(sh_cell, 22 - ea) : sh_cell;
         for (int e = tid; e < tsz / 2; e += kThreads) tile[e] = 0ull;
         __syncthreads();
         // points of this thread, with the next one's loads issued ahead
@@ -733,16 +747,28 @@ k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict_
             int sy = 0;
             if constexpr (DIM >= 2) sy = taps<float, W>(x1 + (float)P, bk, ky);
             const float cr0 = ldexpf(cv.x, sh), ci0 = ldexpf(cv.y, sh);
-            // contributions are rounded to nearest: truncation would save an
-            // instruction per term but biases every term toward zero, which
-            // doubles the quantisation error in dense cells
+            // contributions are rounded to nearest (ties to even): truncation,
+            // or ties away from zero, would bias the terms, and ties are
+            // common (a float between 2^22 and 2^23 is a multiple of 1/2)
             auto row_add = [&](unsigned long long *row, float wr, float wi) {
+                if (magic) {
+                    constexpr float kMagic = 12582912.0f;  // 1.5 2^23
+                    constexpr unsigned long long kMagicPair = 0x4B4000004B400000ull;
 #pragma unroll
-                for (int a1 = 0; a1 < W; ++a1) {
-                    const int r = __float2int_rn(wr * kx[a1]);
-                    const int im = __float2int_rn(wi * kx[a1]);
-                    atomicAdd(row + a1, ((unsigned long long)(unsigned)im << 32) +
-                                            (unsigned long long)(long long)r);
+                    for (int a1 = 0; a1 < W; ++a1) {
+                        const unsigned lo = __float_as_uint(fmaf(wr, kx[a1], kMagic));
+                        const unsigned hi = __float_as_uint(fmaf(wi, kx[a1], kMagic));
+                        atomicAdd(row + a1,
+                                  (((unsigned long long)hi << 32) | lo) - kMagicPair);
+                    }
+                } else {
+#pragma unroll
+                    for (int a1 = 0; a1 < W; ++a1) {
+                        const int r = __float2int_rn(wr * kx[a1]);
+                        const int im = __float2int_rn(wi * kx[a1]);
+                        atomicAdd(row + a1, ((unsigned long long)(unsigned)im << 32) +
+                                                (unsigned long long)(long long)r);
+                    }
                 }
             };
             if constexpr (DIM == 2) {

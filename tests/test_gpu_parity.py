@@ -89,7 +89,7 @@ def test_sort_fold_and_edges():
 # isolated spreading / interpolation against the oracle's plain loops
 @pytest.mark.parametrize("method", ["gm", "gmsort", "sm"])
 @pytest.mark.parametrize("dim,prec,eps", [(2, "f32", 1e-5), (2, "f64", 1e-12), (3, "f32", 1e-5),
-                                          (3, "f64", 1e-9)])
+                                          (3, "f64", 1e-9), (2, "f32", 1e-6), (3, "f32", 1e-6)])
 @pytest.mark.parametrize("kind", ["uniform", "cluster"])
 def test_spread_interp_steps(method, dim, prec, eps, kind):
     import torch
@@ -109,9 +109,15 @@ def test_spread_interp_steps(method, dim, prec, eps, kind):
     # K ~ rho w^d (tens), clustered ones up to M terms on one cell
     # (sqrt(2e4) u ~ 8.5e-6).  SM adds integers exactly in each tile, so its
     # error is the fixed-point quantum of the tile's bound plus the
-    # single-precision evaluation of each term, whatever the clustering.
+    # single-precision evaluation of each term, whatever the clustering.  In
+    # single precision with kernels of width 6 or less (eps >= 1e-5) the
+    # quantum may be up to 2^-21 of the subproblem's largest strength (terms
+    # rounded inside their FMA), a grid error of a few 1e-6 in 3D, which is
+    # held to eps / 3 instead.
     if prec == "f32":
         tol = 2e-5 if (kind == "cluster" and method != "sm") else 2e-6
+        if method == "sm" and w <= 6:
+            tol = max(tol, eps / 3)
     else:
         tol = 1e-12 if (kind == "cluster" and method != "sm") else 1e-13
     assert rel_l2(grid, ref) <= tol
