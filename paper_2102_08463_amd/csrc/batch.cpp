@@ -497,12 +497,11 @@ int mnufft_batch_setpts(mnufft_batch b, const void *x, const void *y, const void
                 pays[q].in[d] = bufs[q][d];
                 pays[q].out[d] = bufs[q + 1][d];
             }
-        void *u0[3] = {bufs[0][0], bufs[0][1], bufs[0][2]};
-        if (mn::launch_binkey(b->g, b->prec, M, x, y, z, b->keyA, u0, b->flag, s, b->d_geo, b->T))
-            return MNUFFT_ERR_HIP;
+        // the sort's first pass computes keys and coordinates from the points
+        const mn::KeySrc ks{b->g, x, y, z, b->flag, b->d_geo, b->T, mn::PtMap{}};
         uint32_t *sk = nullptr, *sv = nullptr;
         if (mn::radix_sort(M, mn::host::bits_for(b->nbins), b->prec, b->dim, b->keyA, b->valA,
-                           b->keyB, b->valB, pays.data(), b->hist, b->partials, &sk, &sv, s))
+                           b->keyB, b->valB, pays.data(), b->hist, b->partials, &sk, &sv, s, &ks))
             return MNUFFT_ERR_HIP;
         b->skey = sk;
         b->perm = reinterpret_cast<int32_t *>(sv);

@@ -202,6 +202,19 @@ hipError_t launch_binkey(const Geom &g, int prec, int M, const void *x, const vo
                          hipStream_t s, const TGeom *tg = nullptr, int T = 1,
                          const PtMap *map = nullptr);
 
+// The caller's points as the source of a bin-sort's keys: with one, the
+// sort's first pass computes every point's bin key and bin-relative
+// coordinates itself (the expressions of k_binkey) instead of reading keys
+// and payload that launch_binkey wrote, and sets *flag like launch_binkey.
+struct KeySrc {
+    Geom g;
+    const void *x, *y, *z;
+    int *flag;
+    const TGeom *tg;  // batches: per-transform table (T entries), else null
+    int T;
+    PtMap map;
+};
+
 // Number of 8-bit passes for keys of `bits` bits (at least one).
 int radix_passes(int bits);
 
@@ -209,9 +222,12 @@ int radix_passes(int bits);
 // dim payload planes of the plan precision; pass p reads pays[p].in and
 // writes pays[p].out.  Returns in *keys_out / *vals_out the buffers (among
 // the two ping-pong pairs) that hold the sorted keys and the permutation.
+// With src, pass 0 takes keys and payload from the points (keysA and
+// pays[0].in are not read).
 hipError_t radix_sort(int M, int bits, int prec, int dim, uint32_t *keysA, uint32_t *valsA,
                       uint32_t *keysB, uint32_t *valsB, const Payload *pays, uint32_t *hist,
-                      uint32_t *partials, uint32_t **keys_out, uint32_t **vals_out, hipStream_t s);
+                      uint32_t *partials, uint32_t **keys_out, uint32_t **vals_out, hipStream_t s,
+                      const KeySrc *src = nullptr);
 
 // binstart[b] = first sorted position with key >= b, b = 0..nbins.
 hipError_t launch_binstart(int M, int nbins, const uint32_t *skey, int32_t *binstart,

@@ -44,6 +44,50 @@ __device__ __forceinline__ double grid_coord(double x, double S, int n, int &bad
     return g;
 }
 
+// Bin key of point j and its bin-relative coordinates u[0..dim-1]; bad is
+// set when a coordinate needed a fallback fold.  For a batch (BATCH), the
+// point's transform is found among the pt_off values (soff: an LDS copy when
+// cached, else the table itself).
+// (xv: the point's coordinates, already loaded; unused dimensions ignored)
+template <typename T, bool BATCH>
+__device__ __forceinline__ uint32_t point_key_of(const Geom &g, const T xc[3], const PtMap &map,
+                                                 const TGeom *tg, int T_, const long long *soff,
+                                                 bool cached, int j, T u[3], int &bad)
+{
+    uint32_t k = 0, stride = 1;
+    Geom gg = g;
+    if constexpr (BATCH) {
+        const auto fld = [](const TGeom &a) { return a.pt_off; };
+        const int t = cached ? find_cached(soff, T_, j) : find_transform(tg, T_, j, fld);
+        gg = geom_of(g, tg[t]);
+        k = (uint32_t)tg[t].bin_off;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        u[d] = (T)0;
+        if (d >= gg.dim) continue;
+        double xv = (double)xc[d];
+        if (map.on) xv = __dmul_rn(__dsub_rn(xv, map.off[d]), map.mul[d]);
+        const double gc = grid_coord(xv, gg.S[d], gg.n[d], bad);
+        const int l = (int)gc;  // gc >= 0, so truncation is floor; l <= n - 1
+        const int b = l / gg.m[d];
+        k += (uint32_t)b * stride;
+        stride *= (uint32_t)gg.B[d];
+        u[d] = (T)(gc - (double)b * (double)gg.m[d]);
+    }
+    return k;
+}
+
+template <typename T, bool BATCH>
+__device__ __forceinline__ uint32_t point_key(const Geom &g, const T *x, const T *y, const T *z,
+                                              const PtMap &map, const TGeom *tg, int T_,
+                                              const long long *soff, bool cached, int j, T u[3],
+                                              int &bad)
+{
+    const T xc[3] = {x[j], g.dim >= 2 ? y[j] : (T)0, g.dim == 3 ? z[j] : (T)0};
+    return point_key_of<T, BATCH>(g, xc, map, tg, T_, soff, cached, j, u, bad);
+}
+
 template <typename T, bool BATCH>
 __global__ void __launch_bounds__(kThreads)
 k_binkey(Geom g, int M, const T *__restrict__ x, const T *__restrict__ y,
@@ -53,34 +97,76 @@ k_binkey(Geom g, int M, const T *__restrict__ x, const T *__restrict__ y,
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     __shared__ long long soff[BATCH ? kTCache : 1];
-    const auto fld = [](const TGeom &a) { return a.pt_off; };
     bool cached = false;
-    if constexpr (BATCH) cached = cache_offsets(soff, tg, T_, fld);
+    if constexpr (BATCH) cached = cache_offsets(soff, tg, T_, [](const TGeom &a) { return a.pt_off; });
     if (j >= M) return;
     int bad = 0;
-    uint32_t k = 0, stride = 1;
-    Geom gg = g;
-    if constexpr (BATCH) {
-        const int t = cached ? find_cached(soff, T_, j) : find_transform(tg, T_, j, fld);
-        gg = geom_of(g, tg[t]);
-        k = (uint32_t)tg[t].bin_off;
-    }
-    const T *xs[3] = {x, y, z};
+    T u[3];
+    const uint32_t k = point_key<T, BATCH>(g, x, y, z, map, tg, T_, soff, cached, j, u, bad);
     T *us[3] = {u0, u1, u2};
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        if (d >= gg.dim) break;
-        double xv = (double)xs[d][j];
-        if (map.on) xv = __dmul_rn(__dsub_rn(xv, map.off[d]), map.mul[d]);
-        const double gc = grid_coord(xv, gg.S[d], gg.n[d], bad);
-        const int l = (int)gc;  // gc >= 0, so truncation is floor; l <= n - 1
-        const int b = l / gg.m[d];
-        k += (uint32_t)b * stride;
-        stride *= (uint32_t)gg.B[d];
-        us[d][j] = (T)(gc - (double)b * (double)gg.m[d]);
-    }
+    for (int d = 0; d < 3; ++d)
+        if (d < g.dim) us[d][j] = u[d];
     key[j] = k;
     if (bad) atomicOr(flag, 1);
+}
+
+// Digit histogram of the first radix pass straight from the points (keys
+// computed as point_key does; the validation flag set as k_binkey sets it).
+// (1024 threads, kTile / 1024 points each: the key arithmetic is long, so
+// more points are in flight per tile than with k_radix_hist's layout)
+constexpr int kSrcThreads = 1024;
+constexpr int kSrcItems = kTile / kSrcThreads;
+template <typename T, bool BATCH>
+__global__ void __launch_bounds__(kSrcThreads)
+k_radix_hist_src(KeySrc src, int M, int shift, uint32_t dmask, int nblk,
+                 uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t h[256];
+    __shared__ long long soff[BATCH ? kTCache : 1];
+    const int tid = threadIdx.x;
+    if (tid < 256) h[tid] = 0;
+    bool cached = false;
+    if constexpr (BATCH)
+        cached = cache_offsets(soff, src.tg, src.T, [](const TGeom &a) { return a.pt_off; });
+    else
+        __syncthreads();
+    const T *x = (const T *)src.x, *y = (const T *)src.y, *z = (const T *)src.z;
+    const int dim = src.g.dim;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    int bad = 0;
+    // every coordinate load first, so that their latencies overlap
+    T xc[kSrcItems][3];
+#pragma unroll
+    for (int r = 0; r < kSrcItems; ++r) {
+        const int64_t jc =
+            std::min<int64_t>(base + (int64_t)r * kSrcThreads + tid, (int64_t)M - 1);
+        xc[r][0] = x[jc];
+        xc[r][1] = dim >= 2 ? y[jc] : (T)0;
+        xc[r][2] = dim == 3 ? z[jc] : (T)0;
+    }
+#pragma unroll
+    for (int r = 0; r < kSrcItems; ++r) {
+        const int64_t idx = base + (int64_t)r * kSrcThreads + tid;
+        const bool valid = idx < M;
+        uint32_t d = 0;
+        if (valid) {
+            T u[3];
+            d = (point_key_of<T, BATCH>(src.g, xc[r], src.map, src.tg, src.T, soff, cached,
+                                        (int)idx, u, bad) >> shift) & dmask;
+        }
+        const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)d);
+        const bool same = !valid || d == d0;
+        if (__all(same)) {
+            const uint64_t vm = __ballot(valid);
+            if ((threadIdx.x & 63) == 0 && vm) atomicAdd(&h[d0], (uint32_t)__popcll(vm));
+        } else if (valid) {
+            atomicAdd(&h[d], 1u);
+        }
+    }
+    if (bad) atomicOr(src.flag, 1);
+    __syncthreads();
+    if (tid < 256) hist[(int64_t)tid * nblk + blockIdx.x] = h[tid];
 }
 
 // Per-tile digit histogram, stored digit-major: hist[d * nblk + blk]; the
@@ -128,11 +214,13 @@ constexpr int scatter_threads()
     return kTile * (8 + ND * (int)sizeof(T)) > 65536 ? 1024 : 512;
 }
 
-template <typename T, int ND, int NT = scatter_threads<T, ND>()>
+// SRC: 0 reads keys and payload; 1 computes them from the points (src, a
+// plain plan); 2 the same for a batch (transform by binary search of pt_off).
+template <typename T, int ND, int SRC = 0, int NT = scatter_threads<T, ND>()>
 __global__ void __launch_bounds__(NT)
 k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, int M,
                 int shift, int dbits, int nblk, const uint32_t *__restrict__ offs,
-                uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, Payload pl)
+                uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, Payload pl, KeySrc src)
 {
     constexpr int kSWaves = NT / 64, kSItems = kTile / NT;
     __shared__ uint32_t cnt[kSWaves][256];   // running per-wave digit counts, then prefixes
@@ -155,11 +243,36 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint32_t dmask = (1u << dbits) - 1u;
     uint32_t kk[kSItems], vv[kSItems], rk[kSItems];
+    T pu[SRC ? kSItems : 1][ND];  // payload computed from the points (SRC)
+    if constexpr (SRC) {
+        // every coordinate load first, so that their latencies overlap
+        const T *cs[3] = {(const T *)src.x, (const T *)src.y, (const T *)src.z};
+#pragma unroll
+        for (int r = 0; r < kSItems; ++r) {
+            const int64_t jc = std::min<int64_t>(base + r * 64 + lane, (int64_t)M - 1);
+#pragma unroll
+            for (int q = 0; q < ND; ++q) pu[r][q] = cs[q][jc];
+        }
+    }
 #pragma unroll
     for (int r = 0; r < kSItems; ++r) {
         const int64_t idx = base + r * 64 + lane;
         const bool valid = idx < M;
-        const uint32_t key = valid ? kin[idx] : 0u;
+        uint32_t key = 0u;
+        if constexpr (SRC) {
+            if (valid) {
+                T xc[3] = {pu[r][0], ND >= 2 ? pu[r][ND >= 2 ? 1 : 0] : (T)0,
+                           ND == 3 ? pu[r][ND == 3 ? 2 : 0] : (T)0};
+                T u[3];
+                int bad = 0;
+                key = point_key_of<T, SRC == 2>(src.g, xc, src.map, src.tg, src.T, nullptr,
+                                                false, (int)idx, u, bad);
+#pragma unroll
+                for (int q = 0; q < ND; ++q) pu[r][q] = u[q];
+            }
+        } else {
+            key = valid ? kin[idx] : 0u;
+        }
         const uint32_t val = valid ? (vin ? vin[idx] : (uint32_t)idx) : 0u;
         const uint32_t d = (key >> shift) & dmask;
         uint64_t mask = __ballot(valid);
@@ -212,8 +325,10 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
             skey[lpos] = kk[r];
             sval[lpos] = vv[r];
 #pragma unroll
-            for (int q = 0; q < ND; ++q)
-                spay[q * kTile + lpos] = static_cast<const T *>(pl.in[q])[idx];
+            for (int q = 0; q < ND; ++q) {
+                if constexpr (SRC) spay[q * kTile + lpos] = pu[r][q];
+                else spay[q * kTile + lpos] = static_cast<const T *>(pl.in[q])[idx];
+            }
         }
     }
     __syncthreads();
@@ -434,7 +549,8 @@ int radix_passes(int bits) { return std::max(1, (bits + 7) / 8); }
 
 hipError_t radix_sort(int M, int bits, int prec, int dim, uint32_t *keysA, uint32_t *valsA,
                       uint32_t *keysB, uint32_t *valsB, const Payload *pays, uint32_t *hist,
-                      uint32_t *partials, uint32_t **keys_out, uint32_t **vals_out, hipStream_t s)
+                      uint32_t *partials, uint32_t **keys_out, uint32_t **vals_out, hipStream_t s,
+                      const KeySrc *src)
 {
     // Keys start in keysA with implicit values 0..M-1; each pass moves the
     // pairs to the other buffer.  Pass p moves the payload as pays[p] says.
@@ -449,22 +565,46 @@ hipError_t radix_sort(int M, int bits, int prec, int dim, uint32_t *keysA, uint3
     for (int p = 0; p < passes; ++p) {
         if (M > 0) {
             const int shift = dbits * p;
-            hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kThreads), 0, s,
-                               (const uint32_t *)kb[cur], M, shift, dmask, nblk, hist);
+            // pass 0 from the points themselves when a source is given
+            const int from = (p == 0 && src) ? (src->tg ? 2 : 1) : 0;
+            const KeySrc ks = src ? *src : KeySrc{};
+            if (from) {
+#define MN_HSRC(TT)                                                                           \
+    do {                                                                                      \
+        if (from == 2)                                                                        \
+            hipLaunchKernelGGL((k_radix_hist_src<TT, true>), dim3(nblk), dim3(kSrcThreads), 0, \
+                               s, ks, M, shift, dmask, nblk, hist);                           \
+        else                                                                                  \
+            hipLaunchKernelGGL((k_radix_hist_src<TT, false>), dim3(nblk), dim3(kSrcThreads),   \
+                               0, s, ks, M, shift, dmask, nblk, hist);                        \
+    } while (0)
+                if (prec == 0) MN_HSRC(float);
+                else MN_HSRC(double);
+#undef MN_HSRC
+            } else {
+                hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kThreads), 0, s,
+                                   (const uint32_t *)kb[cur], M, shift, dmask, nblk, hist);
+            }
             // digits above dmask are empty: only the first dmask + 1 rows are scanned
             hipError_t e = scan_exclusive(hist, hist, (size_t)(dmask + 1) * nblk, partials, s);
             if (e != hipSuccess) return e;
             const uint32_t *vin = p == 0 ? nullptr : (const uint32_t *)vb[cur];
-#define MN_SCATTER(TT, DD)                                                                  \
+#define MN_SCATTER1(TT, DD, SS)                                                             \
     do {                                                                                    \
         const size_t lds = (size_t)kTile * (8 + DD * sizeof(TT));                           \
         if (lds > 65536)                                                                    \
-            (void)hipFuncSetAttribute((const void *)k_radix_scatter<TT, DD>,                \
+            (void)hipFuncSetAttribute((const void *)k_radix_scatter<TT, DD, SS>,            \
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
-        hipLaunchKernelGGL((k_radix_scatter<TT, DD>), dim3(nblk),                           \
+        hipLaunchKernelGGL((k_radix_scatter<TT, DD, SS>), dim3(nblk),                       \
                            dim3(scatter_threads<TT, DD>()), lds, s,                        \
                            (const uint32_t *)kb[cur], vin, M, shift, dbits, nblk,           \
-                           (const uint32_t *)hist, kb[1 - cur], vb[1 - cur], pays[p]);      \
+                           (const uint32_t *)hist, kb[1 - cur], vb[1 - cur], pays[p], ks); \
+    } while (0)
+#define MN_SCATTER(TT, DD)                                                                  \
+    do {                                                                                    \
+        if (from == 2) MN_SCATTER1(TT, DD, 2);                                              \
+        else if (from == 1) MN_SCATTER1(TT, DD, 1);                                         \
+        else MN_SCATTER1(TT, DD, 0);                                                        \
     } while (0)
             if (prec == 0) {
                 if (dim == 1) MN_SCATTER(float, 1);
@@ -476,6 +616,7 @@ hipError_t radix_sort(int M, int bits, int prec, int dim, uint32_t *keysA, uint3
                 else MN_SCATTER(double, 3);
             }
 #undef MN_SCATTER
+#undef MN_SCATTER1
         }
         cur = 1 - cur;
     }

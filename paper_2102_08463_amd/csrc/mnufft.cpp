@@ -417,14 +417,21 @@ int enqueue_setpts(mnufft_plan p, int64_t M, const void *x, const void *y, const
             pays[q].in[d] = bufs[q][d];
             pays[q].out[d] = bufs[q + 1][d];
         }
-    void *u0[3] = {bufs[0][0], bufs[0][1], bufs[0][2]};
-    MN_HIP(mn::launch_binkey(g, p->prec, (int)M, x, y, z, p->keyA, u0, p->flag, s, nullptr, 1,
-                             p->ptmap.on ? &p->ptmap : nullptr));
-    if (p->method == MNUFFT_METHOD_GM && M > 0)
-        MN_HIP(hipMemcpyAsync(p->key_in, p->keyA, (size_t)M * 4, hipMemcpyDeviceToDevice, s));
+    // GM keeps input-order copies of the keys and coordinates (k_binkey);
+    // otherwise the sort's first pass computes them from the points itself
+    const bool gm = p->method == MNUFFT_METHOD_GM;
+    if (gm) {
+        void *u0[3] = {bufs[0][0], bufs[0][1], bufs[0][2]};
+        MN_HIP(mn::launch_binkey(g, p->prec, (int)M, x, y, z, p->keyA, u0, p->flag, s, nullptr,
+                                 1, p->ptmap.on ? &p->ptmap : nullptr));
+        if (M > 0)
+            MN_HIP(hipMemcpyAsync(p->key_in, p->keyA, (size_t)M * 4, hipMemcpyDeviceToDevice, s));
+    }
+    const mn::KeySrc ks{g, x, y, z, p->flag, nullptr, 1, p->ptmap};
     uint32_t *sk = nullptr, *sv = nullptr;
     MN_HIP(mn::radix_sort((int)M, bits_for(g.nbins), p->prec, p->dim, p->keyA, p->valA, p->keyB,
-                          p->valB, pays.data(), p->hist, p->partials, &sk, &sv, s));
+                          p->valB, pays.data(), p->hist, p->partials, &sk, &sv, s,
+                          gm ? nullptr : &ks));
     p->skey = sk;
     p->perm = reinterpret_cast<int32_t *>(sv);
     MN_HIP(mn::launch_binstart((int)M, g.nbins, p->skey, p->binstart, s));
