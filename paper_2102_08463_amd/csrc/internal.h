@@ -244,6 +244,8 @@ hipError_t launch_subproblems(int nbins, int msub, int nsub_max, const int32_t *
 // v[d] / vperm / spos / hslot receive the sorted coordinates, the
 // permutation, the sorted position and the start-cell histogram slot of the
 // point processed at each position.
+// out[i] = i for i < n.
+hipError_t launch_iota(int32_t *out, int n, hipStream_t s);
 hipError_t launch_balance(const Geom &g, int prec, int nsub_max, const int32_t *sub,
                           const int32_t *nsub, const void *const u[3], const int32_t *perm,
                           void *const v[3], int32_t *vperm, int32_t *spos, uint16_t *hslot,
@@ -275,6 +277,14 @@ size_t sm_lds_bytes(const Geom &g, int prec, bool interp, int msub);
 // a subproblem in LDS, so the strengths are read from HBM once (fewer in 3D,
 // where bins hold fewer points and LDS occupancy matters more).
 inline int smp_stage(int dim, int msub) { return msub < (dim <= 2 ? 4096 : 1024) ? msub : (dim <= 2 ? 4096 : 1024); }
+// Strengths the two-word SM spreading kernel stages in LDS per subproblem
+// for its second pass over them (1D double precision only: single precision
+// makes one pass, and in 2D / 3D double precision the tiles leave no room).
+inline int sm2_stage(int dim, int prec, int msub)
+{
+    const int cap = dim == 1 && prec != 0 ? 2048 : 0;
+    return msub < cap ? msub : cap;
+}
 // Reals per scratch tile slot of SM spreading.
 int sm_tile_stride(const Geom &g);
 // Leaders of tile groups to merge: subproblems q with (q - suboff[bin]) % G == 0

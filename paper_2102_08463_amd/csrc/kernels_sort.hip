@@ -753,6 +753,21 @@ k_balance(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__ n
     }
 }
 
+namespace {
+__global__ void k_iota(int n, int32_t *__restrict__ out)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        out[i] = i;
+}
+}  // namespace
+
+hipError_t launch_iota(int32_t *out, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_iota, dim3(std::min(nblocks(n, 256), 4096)), dim3(256), 0, s, n, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_balance(const Geom &g, int prec, int nsub_max, const int32_t *sub,
                           const int32_t *nsub, const void *const u[3], const int32_t *perm,
                           void *const v[3], int32_t *vperm, int32_t *spos, uint16_t *hslot,

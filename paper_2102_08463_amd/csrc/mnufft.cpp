@@ -168,6 +168,11 @@ void free_points(mnufft_plan p)
     p->partials_cap = 0;
 }
 
+// SM plans in 2D and 3D process each subproblem's points in the bank-
+// balanced order of k_balance (kept in the *_proc arrays); 1D tiles are a
+// single row, where the sorted order does as well.
+bool balanced(const mnufft_plan_s *p) { return p->method == MNUFFT_METHOD_SM && p->dim >= 2; }
+
 int alloc_points(mnufft_plan p, int64_t M)
 {
     free_points(p);
@@ -186,11 +191,15 @@ int alloc_points(mnufft_plan p, int64_t M)
     p->nsub_cap = (int)(p->g.nbins + (M + p->msub - 1) / p->msub);
     if ((rc = dalloc(p, (void **)&p->sub, (size_t)std::max(p->nsub_cap, 1) * 16))) return rc;
     if (p->method == MNUFFT_METHOD_SM) {
-        for (int d = 0; d < p->dim; ++d)
-            if ((rc = dalloc(p, &p->su_proc[d], Ma * p->rsz))) return rc;
-        if ((rc = dalloc(p, (void **)&p->perm_proc, Ma * 4))) return rc;
+        // (spos_proc: each processed point's sorted position, the identity
+        // without balancing, for execute_sorted)
         if ((rc = dalloc(p, (void **)&p->spos_proc, Ma * 4))) return rc;
-        if ((rc = dalloc(p, (void **)&p->hslot_proc, Ma * 2))) return rc;
+        if (balanced(p)) {
+            for (int d = 0; d < p->dim; ++d)
+                if ((rc = dalloc(p, &p->su_proc[d], Ma * p->rsz))) return rc;
+            if ((rc = dalloc(p, (void **)&p->perm_proc, Ma * 4))) return rc;
+            if ((rc = dalloc(p, (void **)&p->hslot_proc, Ma * 2))) return rc;
+        }
         p->scratch_bytes = (size_t)std::max(p->nsub_cap, 1) * p->ts2 * p->rsz;
         if ((rc = dalloc(p, &p->scratch, p->scratch_bytes))) return rc;
         if ((rc = dalloc(p, (void **)&p->mergelist, (size_t)std::max(p->nsub_cap, 1) * 4)))
@@ -291,12 +300,12 @@ mn::Pts points_of(mnufft_plan p)
 mn::Pts kernel_points(mnufft_plan p, bool sorted)
 {
     mn::Pts P = points_of(p);
-    if (p->method == MNUFFT_METHOD_SM) {
+    if (balanced(p)) {
         for (int d = 0; d < 3; ++d) P.u[d] = p->su_proc[d];
         P.perm = p->perm_proc;
         P.hslot = p->hslot_proc;
-        if (sorted) P.spos = p->spos_proc;
     }
+    if (sorted && p->method == MNUFFT_METHOD_SM) P.spos = p->spos_proc;
     if (sorted) P.perm = nullptr;
     return P;
 }
@@ -441,6 +450,10 @@ int enqueue_setpts(mnufft_plan p, int64_t M, const void *x, const void *y, const
         MN_HIP(mn::launch_zero(p->nmerge, 4, s));
         MN_HIP(mn::launch_merge_list(p->nsub_max, p->nsub, p->sub, p->subcount, kMergeGroup,
                                      p->mergelist, p->nmerge, s));
+    }
+    if (p->method == MNUFFT_METHOD_SM && !balanced(p))
+        MN_HIP(mn::launch_iota(p->spos_proc, (int)M, s));
+    if (balanced(p)) {
         const void *su[3] = {p->su[0], p->su[1], p->su[2]};
         MN_HIP(mn::launch_balance(g, p->prec, p->nsub_max, p->sub, p->nsub, su, p->perm,
                                   p->su_proc, p->perm_proc, p->spos_proc, p->hslot_proc, s));

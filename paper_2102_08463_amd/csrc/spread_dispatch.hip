@@ -66,11 +66,12 @@ size_t sm_lds_bytes(const Geom &g, int prec, bool interp, int msub)
     // (single precision also stages smp_stage strengths, 8 bytes each, and
     // their 16-bit histogram slots, rounded up to 16 bytes)
     // (1D single precision uses the two-word accumulator of double precision)
+    // (the two-word kernel stages sm2_stage strengths of 2 rsz bytes each)
     if (!interp)
         return prec == 0 && g.dim >= 2
                    ? (size_t)sm_tile_stride(g) * 4 + (size_t)8 * smp_stage(g.dim, msub) +
                          ((size_t)2 * smp_stage(g.dim, msub) + 15) / 16 * 16
-                   : (size_t)sm_tile_stride(g) * 8;
+                   : (size_t)sm_tile_stride(g) * 8 + (size_t)sm2_stage(g.dim, prec, msub) * 2 * rsz;
     const int P = (g.w + 1) / 2;
     size_t cells = 1;
     for (int d = 0; d < g.dim; ++d) cells *= (size_t)(g.m[d] + 2 * P);

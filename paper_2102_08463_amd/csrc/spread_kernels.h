@@ -453,15 +453,20 @@ k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
             const T *__restrict__ u0, const T *__restrict__ u1, const T *__restrict__ u2,
             const int32_t *__restrict__ idx, const uint16_t *__restrict__ hslot,
             const typename Cplx<T>::type *__restrict__ c,
-            const T *__restrict__ cmaxp, T *__restrict__ scratch, int ts2, T bk,
-            const TGeom *__restrict__ tg, const int32_t *__restrict__ bin_t,
+            const T *__restrict__ cmaxp, T *__restrict__ scratch, int ts2, int lts, T bk,
+            int stage_cap, const TGeom *__restrict__ tg, const int32_t *__restrict__ bin_t,
             const int32_t *__restrict__ q0p)
 {
     using V = typename Vec16<T>::type;
+    using C = typename Cplx<T>::type;
     constexpr int NV = 16 / sizeof(T);
+    // LDS: the tile (lts words, the launch's largest), then the first
+    // stage_cap strengths of the subproblem, gathered once by the histogram
+    // pass and read again by the accumulation pass
     extern __shared__ __align__(16) unsigned char smem_raw[];
     unsigned long long *tile = reinterpret_cast<unsigned long long *>(smem_raw);
     unsigned *H = reinterpret_cast<unsigned *>(smem_raw);  // start histogram, before the tile
+    C *cs = reinterpret_cast<C *>(tile + lts);
     __shared__ unsigned red[kThreads / 64];
     constexpr int P = (W + 1) / 2;
     const int nsub = *nsubp;
@@ -483,12 +488,20 @@ k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
         const int tsz = BATCH ? tile_words<DIM>(p1, p2, m3 + 2 * P) : ts2;
         const StartHist hg = start_hist<DIM, W>(m1, m2, m3);
         const int end = rec.y + rec.z;
+        int sh;  // S = 2^sh
+        if constexpr (std::is_same<T, float>::value) {
+            // single precision (1D): the subproblem's count times the largest
+            // part bounds every cell, and 2^-61 of that is far below a float's
+            // own rounding, so no box bound (nor its pass over the points)
+            sh = 61 - ceil_log2((unsigned)rec.z) - ecm;
+        } else {
         // histogram of ceil(a_j / u) over the start cells
         const int hu = 31 - ceil_log2((unsigned)rec.z) - ecm;  // a_j 2^hu < 2^(31 - lg n_q)
         for (int e = threadIdx.x; e < hg.size; e += blockDim.x) H[e] = 0u;
         __syncthreads();
         for (int i = rec.y + threadIdx.x; i < end; i += blockDim.x) {
-            const auto cv = c[idx[i]];
+            const C cv = c[idx[i]];
+            if (i - rec.y < stage_cap) cs[i - rec.y] = cv;
             int hs;
             if (hslot) {
                 hs = hslot[i];
@@ -503,7 +516,8 @@ k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
         }
         __syncthreads();
         const unsigned B = tile_bound<DIM, W>(H, hg, red);
-        const int sh = 61 - (ceil_log2(B) - hu);  // S = 2^sh
+        sh = 61 - (ceil_log2(B) - hu);
+        }
         for (int e = threadIdx.x; e < tsz; e += blockDim.x) tile[e] = 0ull;
         __syncthreads();
         for (int i = rec.y + threadIdx.x; i < end; i += blockDim.x) {
@@ -511,7 +525,7 @@ k_spread_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
             const int sx = taps<T, W>(u0[i] + (T)P, bk, kx);
             int sy = 0;
             if constexpr (DIM >= 2) sy = taps<T, W>(u1[i] + (T)P, bk, ky);
-            const auto cv = c[idx[i]];
+            const C cv = i - rec.y < stage_cap ? cs[i - rec.y] : c[idx[i]];
             const T cr0 = ldexp(cv.x, sh), ci0 = ldexp(cv.y, sh);
             if constexpr (DIM == 1) {
                 unsigned long long *row = tile + 2 * sx;
@@ -1342,8 +1356,9 @@ hipError_t spread_wb(const Geom &g, int method, const Pts &P, const void *c, voi
                 hipLaunchKernelGGL(kern, dim3(sm_grid(P)), dim3(kThreads), lds, s, g, P.sub,
                                    P.nsub, (const T *)P.u[0], (const T *)P.u[1], (const T *)P.u[2],
                                    sm_index(P), P.hslot, (const C *)c, (const T *)P.cmax,
-                                   (T *)P.scratch,
-                                   P.ts2, bk, P.tg, P.bin_t, P.q0);
+                                   (T *)P.scratch, P.ts2, sm_tile_stride(g), bk,
+                                   sm2_stage(DIM, sizeof(T) == 4 ? 0 : 1, P.msub), P.tg,
+                                   P.bin_t, P.q0);
             }
         }
         if (!(part & 2)) return hipGetLastError();
