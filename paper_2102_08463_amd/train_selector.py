@@ -1,13 +1,16 @@
 """Train the parameter selector on the GPU from autotuner timings.
 
-Draws a set of synthetic 2D problems shaped like the batched workload
+Draws a set of synthetic problems -- 2D: shaped like the batched workload
 (modes uniform in {64..512}^2, M lognormal around 2e5 within [1e4, 4e6],
-uniform / clustered / radial points, types 1 and 2), times every autotuner
-candidate on each with the library's timer, trains the MLP with the
-library's kernels and writes the weights in the library's selector format
-(mnufft_selector_load) and the timing table (.npz).
+uniform / clustered / radial points); 3D: modes uniform in {32..160}^3, M
+lognormal around 1e6 within [3e4, 8e6], uniform / clustered / Gaussian
+points -- types 1 and 2, times every autotuner candidate on each with the
+library's timer, trains the MLP with the library's kernels and writes the
+weights in the library's selector format (mnufft_selector_load) and the
+timing table (.npz).
 
     python -m paper_2102_08463_amd.train_selector --out weights.bin --problems 48
+    python -m paper_2102_08463_amd.train_selector --dim 3 --eps 1e-5 --out w3.bin
 """
 import argparse
 import math
@@ -27,16 +30,21 @@ from paper_2102_08463_amd import lib as L  # noqa: E402
 from paper_2102_08463_amd.selector import Selector, targets_from_times  # noqa: E402
 from paper_2102_08463_amd.tune import time_candidates  # noqa: E402
 
-KINDS = ("uniform", "cluster", "radial")
+KINDS = {2: ("uniform", "cluster", "radial"), 3: ("uniform", "cluster", "gaussian")}
 
 
-def draw_problems(count, seed, mmax=4_000_000):
+def draw_problems(count, seed, mmax=4_000_000, dim=2):
     rng = np.random.default_rng(seed)
     out = []
     for i in range(count):
-        N = (int(rng.integers(64, 513)), int(rng.integers(64, 513)))
-        M = int(np.clip(round(math.exp(math.log(2e5) + rng.standard_normal())), 10_000, mmax))
-        out.append({"type": 1 + (i % 2), "N": N, "M": M, "kind": KINDS[(i // 2) % 3],
+        if dim == 2:
+            N = (int(rng.integers(64, 513)), int(rng.integers(64, 513)))
+            M = int(np.clip(round(math.exp(math.log(2e5) + rng.standard_normal())), 10_000, mmax))
+        else:
+            N = tuple(int(rng.integers(32, 161)) for _ in range(3))
+            M = int(np.clip(round(math.exp(math.log(1e6) + rng.standard_normal())), 30_000,
+                            2 * mmax))
+        out.append({"type": 1 + (i % 2), "N": N, "M": M, "kind": KINDS[dim][(i // 2) % 3],
                     "seed": int(seed * 1000 + i)})
     return out
 
@@ -45,7 +53,7 @@ def collect(sel, problems, eps, reps=3, log=print):
     X, T, Mk, raw = [], [], [], []
     for k, p in enumerate(problems):
         pts = [torch.from_numpy(np.asarray(a, dtype=np.float32)).cuda()
-               for a in workloads.points(p["kind"], p["M"], 2, p["seed"])]
+               for a in workloads.points(p["kind"], p["M"], len(p["N"]), p["seed"])]
         feat = sel.features(p["type"], p["N"], pts)
         _, ms = time_candidates(p["type"], p["N"], pts, eps, dtype=torch.complex64,
                                 candidates=sel.cands, reps=reps)
@@ -71,11 +79,12 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--margin", type=float, default=0.0,
                     help="predicted log-time margin below which the library asks the autotuner")
+    ap.add_argument("--dim", type=int, default=2, choices=(2, 3))
     args = ap.parse_args()
     torch.cuda.set_device(0)
-    sel = Selector(2, L.F32, args.eps)
+    sel = Selector(args.dim, L.F32, args.eps)
     t0 = time.time()
-    probs = draw_problems(args.problems, args.seed)
+    probs = draw_problems(args.problems, args.seed, dim=args.dim)
     X, T, Mk, raw = collect(sel, probs, args.eps)
     print(f"[train] collected {len(probs)} problems x {sel.K} candidates in {time.time() - t0:.1f} s",
           flush=True)

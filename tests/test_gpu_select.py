@@ -17,6 +17,7 @@ pytestmark = pytest.mark.gpu
 
 WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                        "paper_2102_08463_amd", "data", "selector_2d_f32_1e-06.bin")
+WEIGHTS3 = os.path.join(os.path.dirname(WEIGHTS), "selector_3d_f32_1e-05.bin")
 
 
 def _check_type1(p, pts64, pts, N, eps, seed=3):
@@ -165,3 +166,30 @@ def test_batch_select_matches_network():
             checked += 1
         assert checked >= T // 2
         print(f"[select] T={T}: {checked} picks equal the network's", flush=True)
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS3), reason="no trained 3D selector weights")
+def test_plan_learned_3d_through_abi():
+    """tune = LEARNED in 3D with the 3D selector: the plan's parameters are
+    the network's pick (mnufft_select) and the type 1 result stays within
+    10 eps of the exact sums at sampled modes."""
+    import torch
+    from paper_2102_08463_amd import Plan, lib as L
+    note("tune learned plan 3d")
+    L.selector_load(WEIGHTS3)
+    N, eps, M = (48, 40, 56), 1e-5, 300_000
+    pts64, pts = make_points("gaussian", M, 3, "f32", seed=12)
+    o, src = L.select(1, N, pts, eps, mode="learned")
+    p = Plan(1, N, eps=eps, dtype=torch.complex64, tune="learned")
+    c64, c = make_complex(M, "f32", seed=13)
+    p.setpts(*pts)
+    inf = p.info()
+    assert inf["method"] == o.method and inf["msub"] == o.msub
+    f = p.execute(c).cpu().numpy()
+    rng = np.random.default_rng(3)
+    kk = tuple(np.sort(rng.choice(np.arange(-(n // 2), n - n // 2), 6, replace=False)) for n in N)
+    ref = direct.type1(pts64, c64, N, iflag=-1, kk=kk)
+    got = f[np.ix_(*[k + n // 2 for k, n in zip(kk, N)][::-1])]
+    assert rel_l2(got, ref) <= 10 * eps
+    print(f"[select] 3D learned pick {L.describe(o)} from source {src}", flush=True)
+    p.destroy()

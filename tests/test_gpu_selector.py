@@ -98,8 +98,10 @@ def test_training_reduces_loss():
     assert hist[-1] < 0.2 * hist[0]
 
 
-WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
-                       "paper_2102_08463_amd", "data", "selector_2d_f32_1e-06.bin")
+DATA = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                    "paper_2102_08463_amd", "data")
+WEIGHTS = os.path.join(DATA, "selector_2d_f32_1e-06.bin")
+WEIGHTS3 = os.path.join(DATA, "selector_3d_f32_1e-05.bin")
 
 
 def test_choose_falls_back_below_margin():
@@ -135,8 +137,9 @@ def test_batched_features_match_single():
     assert torch.equal(both.cpu(), single.cpu())
 
 
-@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained selector weights in the package")
-def test_trained_selector_gain_over_defaults():
+@pytest.mark.parametrize("dim,path,count,mmax", [(2, WEIGHTS, 24, 1_000_000),
+                                                  (3, WEIGHTS3, 10, 1_000_000)])
+def test_trained_selector_gain_over_defaults(dim, path, count, mmax):
     """On held-out problems (another seed than the training set) the trained
     selector's pick is timed against the library defaults (the adaptive
     bins: 32 x 32, halved while the grid holds fewer than 1024 bins; msub
@@ -150,13 +153,15 @@ def test_trained_selector_gain_over_defaults():
     from paper_2102_08463_amd.train_selector import draw_problems
     from paper_2102_08463_amd.tune import time_candidates
     import workloads
-    sel = Selector.load(WEIGHTS)
+    if not os.path.exists(path):
+        pytest.skip("no trained selector weights in the package")
+    sel = Selector.load(path)
     dflt = L.default_opts()
     gains, regrets, auto = [], [], []
-    for p in draw_problems(24, seed=99, mmax=1_000_000):
+    for p in draw_problems(count, seed=99, mmax=mmax, dim=dim):
         note(f"selector gain {p}")
         pts = [torch.from_numpy(np.asarray(a, np.float32)).cuda()
-               for a in workloads.points(p["kind"], p["M"], 2, p["seed"])]
+               for a in workloads.points(p["kind"], p["M"], dim, p["seed"])]
         feat = sel.features(p["type"], p["N"], pts)
         _, _, Y = sel.forward(feat.reshape(1, -1))
         _, ms = time_candidates(p["type"], p["N"], pts, sel.eps,
@@ -173,7 +178,7 @@ def test_trained_selector_gain_over_defaults():
     gain = float(np.exp(np.mean(np.log(gains))))
     regret = float(np.exp(np.mean(np.log(regrets))))
     ceiling = float(np.exp(np.mean(np.log(auto))))
-    print(f"[selector] gain over the adaptive defaults {gain:.3f}x (autotuner's best "
+    print(f"[selector] {dim}D gain over the adaptive defaults {gain:.3f}x (autotuner's best "
           f"{ceiling:.3f}x), regret vs autotuner {regret:.3f}x "
           f"(per problem gain {np.round(gains, 2).tolist()})", flush=True)
     # the selector must not lose to the defaults on average and stay near the
