@@ -656,8 +656,10 @@ hipError_t launch_binstart(int M, int nbins, const uint32_t *skey, int32_t *bins
 // the order (integer tile sums, per-point interpolation).
 constexpr int kBalCap = 4096;
 constexpr int kBalThreads = 256;
-constexpr int kBalItems = kBalCap / kBalThreads;
-template <typename T, int DIM>
+// Two instantiations share the subproblems: ITEMS = 8 takes those of up to
+// 2048 points (3D bins, typically), ITEMS = 16 the rest, so small
+// subproblems neither load unused rounds nor hold the larger one's registers.
+template <typename T, int DIM, int ITEMS>
 __global__ void __launch_bounds__(kBalThreads)
 k_balance(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__ nsubp,
           const T *__restrict__ u0, const T *__restrict__ u1, const T *__restrict__ u2,
@@ -665,8 +667,11 @@ k_balance(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__ n
           T *__restrict__ v2, int32_t *__restrict__ vperm, int32_t *__restrict__ spos,
           uint16_t *__restrict__ hslot)
 {
+    constexpr int kBalItems = ITEMS;
+    constexpr int kLo = ITEMS == 8 ? 0 : 8 * kBalThreads;         // sizes n with kLo < n
+    constexpr int kHi = ITEMS == 8 ? 8 * kBalThreads : 1 << 30;   // and n <= kHi
     __shared__ unsigned cnt[16];
-    __shared__ __align__(16) unsigned char stage_raw[kBalCap * sizeof(T)];
+    __shared__ __align__(16) unsigned char stage_raw[kBalItems * kBalThreads * sizeof(T)];
     T *sT = reinterpret_cast<T *>(stage_raw);
     int32_t *sI = reinterpret_cast<int32_t *>(stage_raw);
     uint16_t *sH = reinterpret_cast<uint16_t *>(stage_raw);
@@ -685,6 +690,7 @@ k_balance(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__ n
     for (int q = blockIdx.x; q < nsub; q += gridDim.x) {
         const int4 rec = reinterpret_cast<const int4 *>(sub)[q];
         const int n = rec.z;
+        if (n <= kLo || n > kHi) continue;  // the other instantiation's subproblem
         if (n > kBalCap) {  // the same for the whole block: keep the sorted order
             for (int j = tid; j < n; j += kBalThreads) {
                 const int i = rec.y + j;
@@ -775,10 +781,15 @@ hipError_t launch_balance(const Geom &g, int prec, int nsub_max, const int32_t *
 {
     if (nsub_max <= 0) return hipSuccess;
     const dim3 grid(std::max(1, std::min(nsub_max, 256 * 8)));
-#define MN_BAL(TT, DD)                                                                         \
-    hipLaunchKernelGGL((k_balance<TT, DD>), grid, dim3(kBalThreads), 0, s, g, sub, nsub,       \
+#define MN_BAL1(TT, DD, II)                                                                    \
+    hipLaunchKernelGGL((k_balance<TT, DD, II>), grid, dim3(kBalThreads), 0, s, g, sub, nsub,   \
                        (const TT *)u[0], (const TT *)u[1], (const TT *)u[2], perm, (TT *)v[0],  \
                        (TT *)v[1], (TT *)v[2], vperm, spos, hslot)
+#define MN_BAL(TT, DD)                                                                         \
+    do {                                                                                       \
+        MN_BAL1(TT, DD, 8);                                                                    \
+        MN_BAL1(TT, DD, 16);                                                                   \
+    } while (0)
     if (prec == 0) {
         if (g.dim == 1) MN_BAL(float, 1);
         else if (g.dim == 2) MN_BAL(float, 2);
@@ -789,6 +800,7 @@ hipError_t launch_balance(const Geom &g, int prec, int nsub_max, const int32_t *
         else MN_BAL(double, 3);
     }
 #undef MN_BAL
+#undef MN_BAL1
     return hipGetLastError();
 }
 
