@@ -1087,8 +1087,12 @@ k_interp_sm(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict__
         // are slow to complete.  Every load is unconditional (lanes past the
         // last point take the last point again and store the same value to
         // the same place), so the compiler can wait for exactly the loads it
-        // needs.
-        constexpr int kAhead = 4;
+        // needs.  The deeper the ring, the older the stores a wait covers:
+        // 16 rounds in 2D single precision (2D default workload 0.234 ->
+        // 0.173 ms against 4), 4 elsewhere: 3D's 216-tap reads need the
+        // registers (6 rounds: 0.76 -> 0.80 ms), and 1D got slower with 16
+        // (0.231 -> 0.256 ms).
+        constexpr int kAhead = (DIM == 2 && sizeof(T) == 4) ? 16 : 4;
         const int nr = (rec.z + NT - 1) / NT;  // rounds, the same for every thread
         T a0[kAhead], a1[kAhead], a2[kAhead];
         int ap[kAhead];
