@@ -341,20 +341,10 @@ hipError_t launch_cmul(int prec, long long n, int ntransf, const void *in, const
                        void *out, hipStream_t s);
 
 // ---- learned selector (kernels_mlp.hip) -----------------------------------
-// Per row of Y (T x K floats): index of the smallest entry among the columns
-// whose bit is set in mask (column k: bit k % 64 of mask[k / 64], K <= 128)
-// and its gap to the runner-up; -1 when no column is allowed.
-hipError_t launch_argmin_rows(int T, int K, const float *Y, const unsigned long long mask[2],
-                              int *idx, float *gap, hipStream_t s);
-// mnufft_density_features_batch (work of T * MNUFFT_DENSITY_BATCH_WORK_BYTES)
-// that also copies nscal extra features per set from scal (device, T x
-// nscal) into columns 256 .. 256 + nscal - 1 of each row.
-hipError_t launch_density_batch(int prec, int T, const int64_t *off, const void *x, const void *y,
-                                float *feat, int ldf, void *work, const float *scal, int nscal,
-                                hipStream_t s);
-// The parts of launch_density_batch for callers that keep the partial rows
-// (T * MNUFFT_DENSITY_BATCH_WORK_BYTES at part) between calls: clearing
-// them, and counting into them (they must be zero before).
+// The batched density histograms (mnufft_density_features_batch) in parts,
+// for callers that keep the partial rows (T * MNUFFT_DENSITY_BATCH_WORK_BYTES
+// at part) between calls: clearing them, and counting into them (they must
+// be zero before).
 hipError_t launch_hist_clear(int T, uint32_t *part, hipStream_t s);
 hipError_t launch_hist_count(int prec, int T, const int64_t *off, const void *x, const void *y,
                              uint32_t *part, hipStream_t s);
@@ -367,8 +357,10 @@ hipError_t launch_select_rows(int T, const int64_t *off, uint32_t *part, const f
                               const unsigned long long mask[2], int *idx, float *gap,
                               hipStream_t s);
 // The network (F -> H -> H -> K, mnufft_mlp_forward's parameter layout) and
-// the argmin above fused, one block per row of X (T rows of stride ldx):
-// idx / gap as launch_argmin_rows gives them on the network's output.
+// an argmin fused, one block per row of X (T rows of stride ldx): idx[t] is
+// the column of smallest output among those whose bit is set in mask
+// (column k: bit k % 64 of mask[k / 64], K <= 128), -1 when none is allowed,
+// and gap[t] its distance to the runner-up (infinity with one allowed).
 // F <= 512, H <= 256, K <= 128, else hipErrorInvalidValue.
 hipError_t launch_mlp_argmin(int F, int H, int K, const float *params, int T, const float *X,
                              int ldx, const unsigned long long mask[2], int *idx, float *gap,

@@ -274,7 +274,7 @@ __device__ void block_dense(int In, int Out, const float *in, const float *__res
 // The selector's whole pass for one row per block: the three layers of the
 // network on the row's features, then the allowed output of smallest value
 // and its gap to the runner-up (infinity with one allowed output, index -1
-// with none), as k_argmin_rows computes them.
+// with none).
 constexpr int kFusedMaxF = 512, kFusedMaxH = 256, kFusedMaxK = 128, kFusedThreads = 1024;
 __global__ void __launch_bounds__(kFusedThreads)
 k_mlp_argmin(int F, int H, int K, const float *__restrict__ params, const float *__restrict__ X,
@@ -374,31 +374,6 @@ k_select_rows(const int64_t *__restrict__ off, uint32_t *__restrict__ part,
 
 inline int blocks_for(long long n) { return (int)std::max<long long>(1, (n + kThreads - 1) / kThreads); }
 
-// Per row of Y (T x K): the allowed column of smallest value and its gap to
-// the runner-up (infinity with one allowed column); -1 when none is allowed.
-// allowed: bit k of mask[k / 64] marks column k.
-__global__ void k_argmin_rows(int T, int K, const float *__restrict__ Y, unsigned long long m0,
-                              unsigned long long m1, int *__restrict__ idx, float *__restrict__ gap)
-{
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= T) return;
-    int best = -1;
-    float b0 = INFINITY, b1 = INFINITY;
-    for (int k = 0; k < K; ++k) {
-        const unsigned long long m = k < 64 ? m0 : m1;
-        if (!((m >> (k & 63)) & 1ull)) continue;
-        const float v = Y[(size_t)t * K + k];
-        if (v < b0) {
-            b1 = b0;
-            b0 = v;
-            best = k;
-        } else if (v < b1) {
-            b1 = v;
-        }
-    }
-    idx[t] = best;
-    gap[t] = b1 - b0;
-}
 
 // Workspace of mnufft_density_features_batch_noalloc: the partial histograms
 // of up to kNoAllocSets point sets (2 MiB), one copy per GPU for the life of
@@ -450,14 +425,6 @@ int density_batch(int prec, int T, const int64_t *off, const void *x, const void
 }  // namespace
 
 namespace mn {
-hipError_t launch_argmin_rows(int T, int K, const float *Y, const unsigned long long mask[2],
-                              int *idx, float *gap, hipStream_t s)
-{
-    if (T <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_argmin_rows, dim3(blocks_for(T)), dim3(kThreads), 0, s, T, K, Y,
-                       mask[0], mask[1], idx, gap);
-    return hipGetLastError();
-}
 
 hipError_t launch_select_rows(int T, const int64_t *off, uint32_t *part, const float *scal,
                               int nscal, int F, int H, int K, const float *params,
@@ -494,15 +461,6 @@ hipError_t launch_hist_count(int prec, int T, const int64_t *off, const void *x,
     return hipGetLastError();
 }
 
-hipError_t launch_density_batch(int prec, int T, const int64_t *off, const void *x, const void *y,
-                                float *feat, int ldf, void *work, const float *scal, int nscal,
-                                hipStream_t s)
-{
-    if (nscal < 0 || 256 + nscal > ldf) return hipErrorInvalidValue;
-    return density_batch(prec, T, off, x, y, feat, ldf, work, s, scal, nscal) == MNUFFT_OK
-               ? hipSuccess
-               : hipErrorLaunchFailure;
-}
 
 hipError_t launch_mlp_argmin(int F, int H, int K, const float *params, int T, const float *X,
                              int ldx, const unsigned long long mask[2], int *idx, float *gap,

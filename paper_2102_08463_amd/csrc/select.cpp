@@ -316,14 +316,13 @@ int mnufft_select(int type, int dim, const int64_t *nmodes, int iflag, double ep
     // density features (and the learned prediction) under the lock: the
     // workspace is shared by all selection calls on a device
     float host_feat[kF];
-    std::vector<float> y_host;
     std::string key;
     int pick = -1;
     {
         std::lock_guard<std::mutex> lk(g_mu);
         Selector *sel = mode == MNUFFT_TUNE_LEARNED ? find_selector(dim, prec, eps) : nullptr;
         const int K = sel ? sel->K : 0, H = sel ? sel->H : 0;
-        const size_t need = (size_t)MNUFFT_DENSITY_WORK_BYTES + 4 * ((size_t)kF + 2 * H + K);
+        const size_t need = (size_t)MNUFFT_DENSITY_WORK_BYTES + 4 * ((size_t)kF + 2);
         char *ws = (char *)workspace(need);
         if (!ws) return MNUFFT_ERR_ALLOC;
         float *feat = (float *)(ws + MNUFFT_DENSITY_WORK_BYTES);
@@ -335,32 +334,28 @@ int mnufft_select(int type, int dim, const int64_t *nmodes, int iflag, double ep
             return MNUFFT_ERR_HIP;
         float *params = sel ? device_params(*sel) : nullptr;
         if (sel && !params) return MNUFFT_ERR_ALLOC;
+        // the network and the argmin over all candidates in one launch; the
+        // pick is trusted when the runner-up is at least the selector's
+        // margin behind (in predicted log time)
+        int *idx = (int *)(feat + kF);
+        float *gap = (float *)(idx + 1);
+        int hidx = -1;
+        float hgap = 0.f;
         if (sel) {
-            float *H1 = feat + kF, *H2 = H1 + H, *Y = H2 + H;
-            rc = mnufft_mlp_forward(sel->F, H, K, params, 1, feat, H1, H2, Y, s);
-            if (rc < 0) return rc;
-            y_host.resize(K);
-            if (hipMemcpyAsync(y_host.data(), Y, K * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+            unsigned long long mask[2];
+            allowed_mask(*sel, false, mask);
+            if (mn::launch_mlp_argmin(kF, H, K, params, 1, feat, kF, mask, idx, gap, s) !=
+                    hipSuccess ||
+                hipMemcpyAsync(&hidx, idx, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipMemcpyAsync(&hgap, gap, 4, hipMemcpyDeviceToHost, s) != hipSuccess)
                 return MNUFFT_ERR_HIP;
         }
         if (hipMemcpyAsync(host_feat, feat, kHist * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return MNUFFT_ERR_HIP;
         if (sel) {
-            // argmin over the candidates; trust it when the runner-up is at
-            // least the selector's margin behind (in predicted log time)
-            int best = -1;
-            float b0 = INFINITY, b1 = INFINITY;
-            for (int k = 0; k < K; ++k) {
-                if (y_host[k] < b0) {
-                    b1 = b0;
-                    b0 = y_host[k];
-                    best = k;
-                } else if (y_host[k] < b1) {
-                    b1 = y_host[k];
-                }
-            }
-            if (best >= 0 && (double)(b1 - b0) >= sel->margin) pick = best;
+            const int best = hidx;
+            if (best >= 0 && (double)hgap >= sel->margin) pick = best;
             if (pick >= 0) {
                 *out = sel->cands[pick];
                 out->stream = b.stream;
