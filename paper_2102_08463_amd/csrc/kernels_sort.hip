@@ -345,7 +345,7 @@ k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ v
     }
 }
 
-// ---- generic exclusive scan (reduce, scan partials, down-sweep) ----------
+// ---- generic exclusive scan (chunk totals; down-sweep adds earlier ones) ----
 constexpr int kScanChunk = kThreads * kItems;
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane)
@@ -390,31 +390,6 @@ k_scan_reduce(const uint32_t *__restrict__ in, size_t n, uint32_t *__restrict__ 
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
-__global__ void __launch_bounds__(1024) k_scan_partials(uint32_t *__restrict__ partials, int np)
-{
-    // One block: thread t scans a contiguous run of the partials serially.
-    __shared__ uint32_t sums[1024];
-    const int t = threadIdx.x;
-    const int per = (np + 1023) / 1024;
-    const int lo = std::min(np, t * per), hi = std::min(np, lo + per);
-    uint32_t s = 0;
-    for (int i = lo; i < hi; ++i) s += partials[i];
-    sums[t] = s;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const uint32_t v = (t >= o) ? sums[t - o] : 0u;
-        __syncthreads();
-        sums[t] += v;
-        __syncthreads();
-    }
-    uint32_t run = sums[t] - s;
-    for (int i = lo; i < hi; ++i) {
-        const uint32_t v = partials[i];
-        partials[i] = run;
-        run += v;
-    }
-}
-
 __global__ void __launch_bounds__(kThreads)
 k_scan_down(const uint32_t *__restrict__ in, uint32_t *__restrict__ out, size_t n,
             const uint32_t *__restrict__ partials)
@@ -428,11 +403,16 @@ k_scan_down(const uint32_t *__restrict__ in, uint32_t *__restrict__ out, size_t 
         buf[sk(e)] = (i < n) ? in[i] : 0u;
     }
     __syncthreads();
+    // this chunk's offset: the sum of the earlier chunks' totals
+    uint32_t before = 0;
+    for (int k = threadIdx.x; k < (int)blockIdx.x; k += kThreads) before += partials[k];
+    uint32_t ex0;
+    before = block_excl_scan(before, ex0);
     uint32_t s = 0;
     for (int q = 0; q < kItems; ++q) s += buf[sk(threadIdx.x * kItems + q)];
     uint32_t ex;
     block_excl_scan(s, ex);
-    uint32_t run = ex + partials[blockIdx.x];
+    uint32_t run = ex + before;
     for (int q = 0; q < kItems; ++q) {
         const int e = threadIdx.x * kItems + q;
         const uint32_t v = buf[sk(e)];
@@ -517,8 +497,10 @@ hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, size_t n, uint32_t 
 {
     if (n == 0) return hipSuccess;
     const int np = (int)((n + kScanChunk - 1) / kScanChunk);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(np), dim3(kThreads), 0, s, in, n, partials);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, np);
+    // chunk totals, then each chunk adds the totals before it (one chunk:
+    // nothing before it, so the first kernel is skipped)
+    if (np > 1)
+        hipLaunchKernelGGL(k_scan_reduce, dim3(np), dim3(kThreads), 0, s, in, n, partials);
     hipLaunchKernelGGL(k_scan_down, dim3(np), dim3(kThreads), 0, s, in, out, n,
                        (const uint32_t *)partials);
     return hipGetLastError();
