@@ -550,8 +550,8 @@ def main():
         print(json.dumps({"copy_bytes": src.numel() * 4, "launches": 3}))
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the "
-              f"multi-GPU path is a design, not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library "
+              f"has no multi-GPU path (sharding over GPUs is a design only).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

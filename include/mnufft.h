@@ -42,7 +42,7 @@ extern "C" {
 #define MNUFFT_ERR_FFT          (-4)  /* rocFFT plan creation or execution failed */
 #define MNUFFT_ERR_STATE        (-5)  /* call out of order (e.g. execute before setpts) */
 #define MNUFFT_ERR_PTS          (-6)  /* a point is non-finite or outside [-3pi, 3pi) (validate_pts) */
-#define MNUFFT_ERR_UNSUPPORTED  (-7)  /* valid request this build does not provide */
+#define MNUFFT_ERR_UNSUPPORTED  (-7)  /* valid request the library does not provide */
 
 /* ---- precisions and methods ------------------------------------------ */
 #define MNUFFT_F32 0
