@@ -104,3 +104,49 @@ def test_batch_64_fullsize(kind):
         got = c[offs[t]:offs[t + 1]][idx]
         assert rel_l2(got, ref) <= 1e-5, t
     b2.destroy()
+
+
+@pytest.mark.parametrize("prec,eps", [("f32", 1e-5), ("f64", 1e-8)])
+@pytest.mark.parametrize("ntype", [1, 2])
+def test_small_mixed_batch_3d(prec, eps, ntype):
+    """3D transforms of different sizes, bins and msub in one batch (four
+    classes of equal bins and msub, one transform without points): each
+    within 10 eps of its exact sums."""
+    import torch
+    from paper_2102_08463_amd import Batch
+    note(f"batch small 3d {prec} {eps} type{ntype}")
+    n_modes = [(12, 10, 14), (20, 16, 8), (9, 9, 9), (16, 16, 16), (6, 20, 10)]
+    n_points = [3000, 2500, 0, 4000, 1200]
+    kinds = ["uniform", "cluster", "uniform", "gaussian", "uniform"]
+    pts, tens, cdt = _batch_inputs(n_modes, n_points, kinds, prec, seed=21)
+    rng = np.random.default_rng(6)
+    b = Batch(ntype, n_modes, n_points, eps=eps,
+              dtype=torch.complex64 if prec == "f32" else torch.complex128,
+              binsize=[(8, 8, 8), (16, 8, 4), (8, 8, 8), (16, 8, 8), (16, 8, 4)],
+              msub=[256, 1024, 256, 512, 1024])
+    b.setpts(*tens)
+    if ntype == 1:
+        cs = [(rng.standard_normal(M) + 1j * rng.standard_normal(M)).astype(cdt) for M in n_points]
+        fs = b.split_modes(b.execute(torch.from_numpy(np.concatenate(cs)).cuda()))
+        for t in range(len(n_modes)):
+            got = fs[t].cpu().numpy()
+            if n_points[t] == 0:
+                assert np.count_nonzero(got) == 0
+                continue
+            ref = direct.type1(tuple(a.astype(np.float64) for a in pts[t]),
+                               cs[t].astype(np.complex128), n_modes[t], iflag=-1)
+            assert rel_l2(got, ref) <= 10 * eps, t
+    else:
+        fm = [(rng.standard_normal(nm[::-1]) + 1j * rng.standard_normal(nm[::-1])).astype(cdt)
+              for nm in n_modes]
+        c = b.execute(torch.from_numpy(np.concatenate([f.ravel() for f in fm])).cuda()).cpu().numpy()
+        off = 0
+        for t in range(len(n_modes)):
+            got = c[off:off + n_points[t]]
+            off += n_points[t]
+            if n_points[t] == 0:
+                continue
+            ref = direct.type2(tuple(a.astype(np.float64) for a in pts[t]),
+                               fm[t].astype(np.complex128), iflag=+1)
+            assert rel_l2(got, ref) <= 10 * eps, t
+    b.destroy()
