@@ -1017,6 +1017,130 @@ k_tile_gather2(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__
     }
 }
 
+// Bin-oriented add-back, for a grid its bins tile exactly (n_i a multiple of
+// m_i) with bins at least two halos wide (m_i >= 2P): a workgroup writes the
+// cells of one bin.  Per dimension a cell at bin-relative r is covered by its
+// own bin's tile (at r + P) and, within P of an edge, by the neighbour's
+// (periodically: at r + m + P in the previous bin if r < P, at r - m + P in
+// the next if r >= m - P), so with the tile lists of the 3^d neighbouring
+// bins read once per workgroup every tile value is one independent load; CPT
+// cells per thread are loaded before any is summed.  A cell's tiles are
+// summed own tile first in each dimension (x fastest), then in list order.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kThreads)
+k_tile_sum(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__ scratch, int ts2,
+           int G, int P, typename Cplx<T>::type *__restrict__ grid)
+{
+    using C = typename Cplx<T>::type;
+    constexpr int NB = DIM == 3 ? 27 : 9;
+    constexpr int NC = DIM == 3 ? 8 : 4;   // tile combinations per cell, at most
+    constexpr int CPT = sizeof(T) == 4 ? 2 : 1;
+    __shared__ int sfirst[NB], scnt[NB];
+    const int m1 = g.m[0], m2 = g.m[1], m3 = DIM == 3 ? g.m[2] : 1;
+    const int p1 = m1 + 2 * P, p2 = m2 + 2 * P;
+    const int ncb = m1 * m2 * m3;
+    for (int b = blockIdx.x; b < g.nbins; b += gridDim.x) {
+        const int b1 = b % g.B[0], b23 = b / g.B[0];
+        const int b2 = b23 % g.B[1], b3 = DIM == 3 ? b23 / g.B[1] : 0;
+        __syncthreads();  // the previous bin's lists are no longer read
+        if (threadIdx.x < NB) {
+            const int j1 = threadIdx.x % 3, j2 = (threadIdx.x / 3) % 3, j3 = threadIdx.x / 9;
+            const int n1 = (b1 + j1 - 1 + g.B[0]) % g.B[0];
+            const int n2 = (b2 + j2 - 1 + g.B[1]) % g.B[1];
+            const int n3 = DIM == 3 ? (b3 + j3 - 1 + g.B[2]) % g.B[2] : 0;
+            const int nb = n1 + g.B[0] * (n2 + g.B[1] * n3);
+            const int f = suboff[nb];
+            sfirst[threadIdx.x] = f;
+            scnt[threadIdx.x] = suboff[nb + 1] - f;
+        }
+        __syncthreads();
+        for (int c0 = threadIdx.x; c0 < ncb; c0 += CPT * kThreads) {
+            int lst[CPT][NC];      // neighbour list of each combination (-1: none)
+            int off[CPT][NC];      // offset of the cell in that neighbour's tiles (reals)
+            T vr[CPT][NC], vi[CPT][NC];
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) {
+                const int c = c0 + k * kThreads;
+                const int r1 = c % m1, r12 = c / m1;
+                const int r2 = r12 % m2, r3 = DIM == 3 ? r12 / m2 : 0;
+                // per dimension: [0] own tile, [1] the neighbour's (j = -1 when none)
+                int j[3][2], s[3][2];
+                const int rr[3] = {r1, r2, r3}, mm[3] = {m1, m2, m3};
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    j[d][0] = 1;
+                    s[d][0] = rr[d] + P;
+                    j[d][1] = -1;
+                    s[d][1] = 0;
+                    if (d < DIM) {
+                        if (rr[d] < P) {
+                            j[d][1] = 0;
+                            s[d][1] = rr[d] + mm[d] + P;
+                        } else if (rr[d] >= mm[d] - P) {
+                            j[d][1] = 2;
+                            s[d][1] = rr[d] - mm[d] + P;
+                        }
+                    } else {
+                        j[d][0] = 0;
+                        s[d][0] = 0;
+                    }
+                }
+#pragma unroll
+                for (int v = 0; v < NC; ++v) {
+                    const int a1 = v & 1, a2 = (v >> 1) & 1, a3 = DIM == 3 ? (v >> 2) & 1 : 0;
+                    const bool ok = c < ncb && j[0][a1] >= 0 && j[1][a2] >= 0 && j[2][a3] >= 0;
+                    lst[k][v] = ok ? (j[2][a3] * 3 + j[1][a2]) * 3 + j[0][a1] : -1;
+                    off[k][v] = 2 * (s[0][a1] + p1 * (s[1][a2] + p2 * s[2][a3]));
+                }
+            }
+            // first tile of every combination, all loads in flight together
+#pragma unroll
+            for (int k = 0; k < CPT; ++k)
+#pragma unroll
+                for (int v = 0; v < NC; ++v) {
+                    vr[k][v] = 0;
+                    vi[k][v] = 0;
+                    const int l = lst[k][v];
+                    if (l >= 0 && scnt[l] > 0) {
+                        const C t = *reinterpret_cast<const C *>(
+                            scratch + (size_t)sfirst[l] * ts2 + off[k][v]);
+                        vr[k][v] = t.x;
+                        vi[k][v] = t.y;
+                    }
+                }
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) {
+                const int c = c0 + k * kThreads;
+                if (c >= ncb) break;
+                T ar = 0, ai = 0;
+#pragma unroll
+                for (int v = 0; v < NC; ++v) {
+                    const int l = lst[k][v];
+                    if (l < 0) continue;
+                    ar += vr[k][v];
+                    ai += vi[k][v];
+                    const int first = sfirst[l], cnt = scnt[l];
+                    const int step = cnt > G ? G : 1;
+                    for (int q = first + step; q < first + cnt; q += step) {
+                        const C t = *reinterpret_cast<const C *>(scratch + (size_t)q * ts2 + off[k][v]);
+                        ar += t.x;
+                        ai += t.y;
+                    }
+                }
+                const int r1 = c % m1, r12 = c / m1;
+                const int r2 = r12 % m2, r3 = DIM == 3 ? r12 / m2 : 0;
+                const size_t e = (size_t)(b1 * m1 + r1) +
+                                 (size_t)g.n[0] * ((size_t)(b2 * m2 + r2) +
+                                                   (size_t)g.n[1] * (size_t)(b3 * m3 + r3));
+                C o;
+                o.x = ar;
+                o.y = ai;
+                grid[e] = o;
+            }
+        }
+    }
+}
+
 // SM interpolation: stage the padded bin in LDS, then every point of the
 // subproblem reads its w^d values there.
 template <typename T, int DIM, int W, bool BATCH>
@@ -1371,6 +1495,17 @@ hipError_t spread_wb(const Geom &g, int method, const Pts &P, const void *c, voi
         const int mgrid = std::max(1, std::min(P.nsub_max / std::max(P.G, 1) * nchunk + nchunk, 8192));
         hipLaunchKernelGGL(k_tile_merge<T>, dim3(mgrid), dim3(kThreads), 0, s, P.nmerge,
                            P.mergelist, P.sub, P.suboff, (T *)P.scratch, P.ts2, P.G);
+        if constexpr (!BATCH && DIM >= 2) {
+            bool exact = true;
+            for (int d = 0; d < DIM; ++d)
+                exact = exact && g.n[d] % g.m[d] == 0 && g.m[d] >= 2 * ((W + 1) / 2);
+            if (exact) {
+                hipLaunchKernelGGL((k_tile_sum<T, DIM>), dim3(std::min(g.nbins, 1 << 20)),
+                                   dim3(kThreads), 0, s, g, P.suboff, (const T *)P.scratch,
+                                   P.ts2, P.G, (W + 1) / 2, (C *)grid);
+                return hipGetLastError();
+            }
+        }
         const long long ncell = P.ncells;
         const int ggrid = (int)std::min<long long>((ncell + kThreads - 1) / kThreads, 16384);
         // (for a batch, P.kmax holds the largest table width over its transforms)

@@ -217,6 +217,60 @@ def test_methods_and_signs(method, dim):
         assert _type2_check(pts64, pts, N, "f32", 1e-5, iflag=iflag, method=method) <= 1e-4
 
 
+# Grids that their bins tile exactly, bins at least two halos wide: the
+# add-back runs bin by bin (own tile plus the neighbours' halos, periodic),
+# including dimensions of one and two bins and clustered points whose heavy
+# bins hold many subproblems (tiles merged in groups first).
+TILED_CASES = [
+    # (dim, N, binsize, prec, eps, kind)
+    (2, (64, 48), (32, 32), "f32", 1e-5, "uniform"),
+    (2, (64, 48), (32, 32), "f32", 1e-5, "cluster"),
+    (2, (16, 32), (32, 32), "f64", 1e-12, "uniform"),     # one bin in x, two in y
+    (2, (40, 24), (16, 16), "f64", 1e-9, "cluster"),
+    (3, (16, 16, 16), (16, 8, 8), "f32", 1e-5, "uniform"),
+    (3, (16, 16, 16), (16, 8, 8), "f32", 1e-5, "cluster"),
+    (3, (8, 8, 8), (16, 8, 8), "f64", 1e-6, "uniform"),    # one bin in x, two in y and z
+    (3, (12, 16, 8), (8, 8, 8), "f64", 1e-6, "cluster"),
+]
+
+
+@pytest.mark.parametrize("case", TILED_CASES,
+                         ids=lambda c: f"{c[0]}d-{c[1]}-{c[2]}-{c[3]}-{c[5]}")
+def test_spread_exactly_tiled_grids(case):
+    dim, N, bs, prec, eps, kind = case
+    note(f"spread exact tiling {case}")
+    M = 20_000 if dim == 2 else 8_000
+    pts64, pts = make_points(kind, M, dim, prec, seed=14)
+    c64, c = make_complex(M, prec, seed=15)
+    p = _plan(1, N, eps=eps, dtype=cdtype(prec), method="sm", binsize=bs, msub=300)
+    p.setpts(*pts)
+    inf = p.info()
+    ns, w, beta = inf["nfine"][:dim], inf["w"], inf["beta"]
+    assert list(inf["binsize"][:dim]) == list(bs)
+    P = (w + 1) // 2
+    assert all(n % m == 0 and m >= 2 * P for n, m in zip(ns, bs))
+    grid = p.spread(c).cpu().numpy()
+    ref = direct.spread(pts64, c64, ns, w, beta)
+    # SM tolerance of test_spread_interp_steps; in single precision the
+    # tiles' fixed-point quantum follows the heaviest cell of each tile, so
+    # a 3D cluster on a grid this small reaches about 4e-6 (held to eps / 2)
+    if prec == "f32":
+        tol = max(2e-6, eps / (2 if (dim == 3 and kind == "cluster") else 3)) if w <= 6 else 2e-6
+    else:
+        tol = 1e-13
+    assert rel_l2(grid, ref) <= tol
+    f_plan = p.execute(c).cpu().numpy()
+    p.destroy()
+    # A one-transform batch builds the same subproblems and the same tiles and
+    # sums them with the cell-oriented gather: the two type 1 results may
+    # differ only by the order of the final additions.
+    from paper_2102_08463_amd import Batch
+    with Batch(1, [N], [M], eps=eps, dtype=cdtype(prec), binsize=[bs], msub=[300]) as b:
+        b.setpts(*pts)
+        f_batch = b.split_modes(b.execute(c))[0].cpu().numpy()
+    assert rel_l2(f_plan, f_batch) <= (1e-6 if prec == "f32" else 1e-14)
+
+
 def test_many_transforms():
     note("ntransf 3")
     pts64, pts = make_points("uniform", 9_999, 2, "f32", seed=8)
