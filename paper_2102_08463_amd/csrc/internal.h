@@ -74,6 +74,18 @@ __device__ __forceinline__ int find_cached(const long long *s, int T, long long 
     return lo;
 }
 
+// Workgroups of a launch are dispatched to the eight XCDs in turn (block b to
+// XCD b mod 8), and each XCD has its own L2.  Kernels whose neighbouring
+// blocks read neighbouring data renumber their blocks with this map, so that
+// each XCD takes one contiguous range of the logical block indices and the
+// shared cache lines meet in one L2.
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    constexpr int kXcd = 8;
+    const int q = nb / kXcd, r = nb % kXcd, x = b % kXcd;
+    return x * q + min(x, r) + b / kXcd;
+}
+
 // Geometry of transform t as a Geom (shared fields from g).
 __device__ __forceinline__ Geom geom_of(const Geom &g, const TGeom &t)
 {

@@ -1026,6 +1026,8 @@ k_tile_gather2(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__
 // bins read once per workgroup every tile value is one independent load; CPT
 // cells per thread are loaded before any is summed.  A cell's tiles are
 // summed own tile first in each dimension (x fastest), then in list order.
+// Neighbouring bins read pieces of the same tile rows, so each XCD takes a
+// contiguous range of bins (3D: 0.244 -> 0.222 ms at n = 256^3).
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kThreads)
 k_tile_sum(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__ scratch, int ts2,
@@ -1039,7 +1041,7 @@ k_tile_sum(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__ scr
     const int m1 = g.m[0], m2 = g.m[1], m3 = DIM == 3 ? g.m[2] : 1;
     const int p1 = m1 + 2 * P, p2 = m2 + 2 * P;
     const int ncb = m1 * m2 * m3;
-    for (int b = blockIdx.x; b < g.nbins; b += gridDim.x) {
+    for (int b = xcd_block(blockIdx.x, gridDim.x); b < g.nbins; b += gridDim.x) {
         const int b1 = b % g.B[0], b23 = b / g.B[0];
         const int b2 = b23 % g.B[1], b3 = DIM == 3 ? b23 / g.B[1] : 0;
         __syncthreads();  // the previous bin's lists are no longer read
