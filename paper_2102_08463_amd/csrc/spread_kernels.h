@@ -1017,15 +1017,16 @@ k_tile_gather2(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__
     }
 }
 
-// Bin-oriented add-back, for a grid its bins tile exactly (n_i a multiple of
-// m_i) with bins at least two halos wide (m_i >= 2P): a workgroup writes the
-// cells of one bin.  Per dimension a cell at bin-relative r is covered by its
-// own bin's tile (at r + P) and, within P of an edge, by the neighbour's
-// (periodically: at r + m + P in the previous bin if r < P, at r - m + P in
-// the next if r >= m - P), so with the tile lists of the 3^d neighbouring
-// bins read once per workgroup every tile value is one independent load; CPT
-// cells per thread are loaded before any is summed.  A cell's tiles are
-// summed own tile first in each dimension (x fastest), then in list order.
+// Bin-oriented add-back, for grids whose bins (the last one of a dimension
+// possibly narrower, n_i - (B_i - 1) m_i) are all at least two halos wide:
+// a workgroup writes the cells of one bin.  Per dimension a cell at
+// bin-relative r of a bin of width mb is covered by its own bin's tile (at
+// r + P) and, within P of an edge, by one neighbour's, periodically: at
+// r + mp + P in the previous bin (width mp) if r < P, at r - mb + P in the
+// next if r >= mb - P.  With the tile lists of the 3^d neighbouring bins read
+// once per workgroup every tile value is one independent load; CPT cells per
+// thread are loaded before any is summed.  A cell's tiles are summed own
+// tile first in each dimension (x fastest), then in list order.
 // Neighbouring bins read pieces of the same tile rows, so each XCD takes a
 // contiguous range of bins (3D: 0.244 -> 0.222 ms at n = 256^3).
 template <typename T, int DIM>
@@ -1038,12 +1039,21 @@ k_tile_sum(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__ scr
     constexpr int NC = DIM == 3 ? 8 : 4;   // tile combinations per cell, at most
     constexpr int CPT = sizeof(T) == 4 ? 2 : 1;
     __shared__ int sfirst[NB], scnt[NB];
-    const int m1 = g.m[0], m2 = g.m[1], m3 = DIM == 3 ? g.m[2] : 1;
-    const int p1 = m1 + 2 * P, p2 = m2 + 2 * P;
-    const int ncb = m1 * m2 * m3;
+    const int p1 = g.m[0] + 2 * P, p2 = g.m[1] + 2 * P;
     for (int b = xcd_block(blockIdx.x, gridDim.x); b < g.nbins; b += gridDim.x) {
         const int b1 = b % g.B[0], b23 = b / g.B[0];
         const int b2 = b23 % g.B[1], b3 = DIM == 3 ? b23 / g.B[1] : 0;
+        const int bb[3] = {b1, b2, b3};
+        int mb[3], mp[3];  // width of this bin and of the previous one, per dimension
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int last = d < DIM ? g.n[d] - (g.B[d] - 1) * g.m[d] : 1;
+            const int m = d < DIM ? g.m[d] : 1;
+            mb[d] = bb[d] == g.B[d] - 1 ? last : m;
+            mp[d] = bb[d] == 0 ? last : m;
+        }
+        const int m1 = mb[0], m2 = mb[1], m3 = mb[2];
+        const int ncb = m1 * m2 * m3;
         __syncthreads();  // the previous bin's lists are no longer read
         if (threadIdx.x < NB) {
             const int j1 = threadIdx.x % 3, j2 = (threadIdx.x / 3) % 3, j3 = threadIdx.x / 9;
@@ -1067,7 +1077,7 @@ k_tile_sum(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__ scr
                 const int r2 = r12 % m2, r3 = DIM == 3 ? r12 / m2 : 0;
                 // per dimension: [0] own tile, [1] the neighbour's (j = -1 when none)
                 int j[3][2], s[3][2];
-                const int rr[3] = {r1, r2, r3}, mm[3] = {m1, m2, m3};
+                const int rr[3] = {r1, r2, r3};
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
                     j[d][0] = 1;
@@ -1077,10 +1087,10 @@ k_tile_sum(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__ scr
                     if (d < DIM) {
                         if (rr[d] < P) {
                             j[d][1] = 0;
-                            s[d][1] = rr[d] + mm[d] + P;
-                        } else if (rr[d] >= mm[d] - P) {
+                            s[d][1] = rr[d] + mp[d] + P;
+                        } else if (rr[d] >= mb[d] - P) {
                             j[d][1] = 2;
-                            s[d][1] = rr[d] - mm[d] + P;
+                            s[d][1] = rr[d] - mb[d] + P;
                         }
                     } else {
                         j[d][0] = 0;
@@ -1131,9 +1141,9 @@ k_tile_sum(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__ scr
                 }
                 const int r1 = c % m1, r12 = c / m1;
                 const int r2 = r12 % m2, r3 = DIM == 3 ? r12 / m2 : 0;
-                const size_t e = (size_t)(b1 * m1 + r1) +
-                                 (size_t)g.n[0] * ((size_t)(b2 * m2 + r2) +
-                                                   (size_t)g.n[1] * (size_t)(b3 * m3 + r3));
+                const size_t e = (size_t)(b1 * g.m[0] + r1) +
+                                 (size_t)g.n[0] * ((size_t)(b2 * g.m[1] + r2) +
+                                                   (size_t)g.n[1] * (size_t)(b3 * g.m[2] + r3));
                 C o;
                 o.x = ar;
                 o.y = ai;
@@ -1498,10 +1508,12 @@ hipError_t spread_wb(const Geom &g, int method, const Pts &P, const void *c, voi
         hipLaunchKernelGGL(k_tile_merge<T>, dim3(mgrid), dim3(kThreads), 0, s, P.nmerge,
                            P.mergelist, P.sub, P.suboff, (T *)P.scratch, P.ts2, P.G);
         if constexpr (!BATCH && DIM >= 2) {
-            bool exact = true;
-            for (int d = 0; d < DIM; ++d)
-                exact = exact && g.n[d] % g.m[d] == 0 && g.m[d] >= 2 * ((W + 1) / 2);
-            if (exact) {
+            bool wide = true;  // every bin, the last one included, two halos wide
+            for (int d = 0; d < DIM; ++d) {
+                const int last = g.n[d] - (g.B[d] - 1) * g.m[d];
+                wide = wide && std::min(g.m[d], last) >= 2 * ((W + 1) / 2);
+            }
+            if (wide) {
                 hipLaunchKernelGGL((k_tile_sum<T, DIM>), dim3(std::min(g.nbins, 1 << 20)),
                                    dim3(kThreads), 0, s, g, P.suboff, (const T *)P.scratch,
                                    P.ts2, P.G, (W + 1) / 2, (C *)grid);

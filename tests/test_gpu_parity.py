@@ -217,28 +217,33 @@ def test_methods_and_signs(method, dim):
         assert _type2_check(pts64, pts, N, "f32", 1e-5, iflag=iflag, method=method) <= 1e-4
 
 
-# Grids that their bins tile exactly, bins at least two halos wide: the
-# add-back runs bin by bin (own tile plus the neighbours' halos, periodic),
-# including dimensions of one and two bins and clustered points whose heavy
-# bins hold many subproblems (tiles merged in groups first).
+# Grids whose bins, the last one of each dimension included, are at least
+# two halos wide: the add-back runs bin by bin (own tile plus a neighbour's
+# halo per dimension, periodic), including dimensions of one and two bins,
+# narrower last bins (odd n too) and clustered points whose heavy bins hold
+# many subproblems (tiles merged in groups first).
 TILED_CASES = [
     # (dim, N, binsize, prec, eps, kind)
     (2, (64, 48), (32, 32), "f32", 1e-5, "uniform"),
     (2, (64, 48), (32, 32), "f32", 1e-5, "cluster"),
     (2, (16, 32), (32, 32), "f64", 1e-12, "uniform"),     # one bin in x, two in y
     (2, (40, 24), (16, 16), "f64", 1e-9, "cluster"),
+    (2, (60, 40), (32, 32), "f32", 1e-5, "cluster"),      # last bins 24 and 16 wide
+    (2, (60, 40), (32, 32), "f64", 1e-12, "uniform"),
     (3, (16, 16, 16), (16, 8, 8), "f32", 1e-5, "uniform"),
     (3, (16, 16, 16), (16, 8, 8), "f32", 1e-5, "cluster"),
     (3, (8, 8, 8), (16, 8, 8), "f64", 1e-6, "uniform"),    # one bin in x, two in y and z
     (3, (12, 16, 8), (8, 8, 8), "f64", 1e-6, "cluster"),
+    (3, (20, 12, 14), (16, 8, 8), "f32", 1e-5, "uniform"),  # last z bin exactly two halos
+    (3, (22, 12, 14), (16, 8, 8), "f64", 1e-5, "cluster"),  # n = (45, 24, 30)
 ]
 
 
 @pytest.mark.parametrize("case", TILED_CASES,
                          ids=lambda c: f"{c[0]}d-{c[1]}-{c[2]}-{c[3]}-{c[5]}")
-def test_spread_exactly_tiled_grids(case):
+def test_spread_binwise_addback(case):
     dim, N, bs, prec, eps, kind = case
-    note(f"spread exact tiling {case}")
+    note(f"spread bin-wise add-back {case}")
     M = 20_000 if dim == 2 else 8_000
     pts64, pts = make_points(kind, M, dim, prec, seed=14)
     c64, c = make_complex(M, prec, seed=15)
@@ -248,7 +253,9 @@ def test_spread_exactly_tiled_grids(case):
     ns, w, beta = inf["nfine"][:dim], inf["w"], inf["beta"]
     assert list(inf["binsize"][:dim]) == list(bs)
     P = (w + 1) // 2
-    assert all(n % m == 0 and m >= 2 * P for n, m in zip(ns, bs))
+    for n, m in zip(ns, bs):
+        last = n - (-(-n // m) - 1) * m
+        assert min(m, last) >= 2 * P
     grid = p.spread(c).cpu().numpy()
     ref = direct.spread(pts64, c64, ns, w, beta)
     # SM tolerance of test_spread_interp_steps; in single precision the
