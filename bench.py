@@ -447,7 +447,8 @@ def sq_summary(args, raw, stats):
              "stall | occupancy |", "|---|---|---|---|---|---|"]
     path = args.counters_out or os.path.join(ROOT, "profiles", "counters.json")
     table = json.load(open(path)) if os.path.exists(path) else {}
-    for k in args.kernels.split(",") + ["k_tile_gather2", "k_radix_scatter", "k_binkey"]:
+    extra = ["k_tile_sum", "k_tile_gather2", "k_radix_scatter", "k_binkey"]
+    for k in dict.fromkeys(args.kernels.split(",") + extra):
         if k not in raw or "GRBM_GUI_ACTIVE" not in raw[k]:
             continue
         fr = sq_fractions(raw[k])

@@ -125,6 +125,7 @@ mn::Pts batch_points(mnufft_batch b)
     P.G = kMergeGroup;
     P.mergelist = b->mergelist;
     P.nmerge = b->nmerge;
+    P.heavy = nullptr;  // the batched add-back gathers per cell
     P.cmax = b->cmax;
     P.spos = nullptr;
     P.msub = b->msub_max;

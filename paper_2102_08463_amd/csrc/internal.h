@@ -170,7 +170,9 @@ struct Pts {
     int ts2;                  // reals per slot (>= 2 * padded-bin cells, multiple of 8)
     int G;                    // tiles merged per leader in heavily loaded bins
     const int32_t *mergelist; // leaders (subproblem indices)
-    const int32_t *nmerge;    // device count of leaders
+    int32_t *nmerge;          // device: [0] count of leaders, [1] count of listed bins
+    int32_t *heavy;           // bin-wise add-back: bins whose neighbourhood holds a bin of
+                              // several tiles (nbins entries; null: the add-back gathers)
     const int2 *cov[3];       // per-dimension cover tables (see k_tile_gather)
     int kmax[3];
     void *cmax;               // 1024 partial maxima of |Re c|, |Im c| of the vector being spread

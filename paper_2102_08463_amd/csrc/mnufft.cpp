@@ -281,6 +281,8 @@ mn::Pts points_of(mnufft_plan p)
     P.G = kMergeGroup;
     P.mergelist = p->mergelist;
     P.nmerge = p->nmerge;
+    // the heavy-bin list of the add-back follows the nbins + 1 subproblem offsets
+    P.heavy = p->method == MNUFFT_METHOD_SM ? p->subcount + p->g.nbins + 1 : nullptr;
     P.cmax = p->cmax;
     P.msub = p->msub;
     P.tg = nullptr;
@@ -471,7 +473,7 @@ int replan(mnufft_plan p, const mnufft_opts &c)
 {
     free_points(p);
     dfree(p, (void **)&p->binstart, ((size_t)p->g.nbins + 1) * 4);
-    dfree(p, (void **)&p->subcount, ((size_t)p->g.nbins + 1) * 4);
+    dfree(p, (void **)&p->subcount, (2 * (size_t)p->g.nbins + 1) * 4);
     for (int d = 0; d < 3; ++d) {
         dfree(p, (void **)&p->cov[d], p->cov_bytes[d]);
         p->cov_bytes[d] = 0;
@@ -613,7 +615,8 @@ int plan_bins_device(mnufft_plan p)
 {
     const mn::Geom &g = p->g;
     int rc = dalloc(p, (void **)&p->binstart, ((size_t)g.nbins + 1) * 4);
-    if (!rc) rc = dalloc(p, (void **)&p->subcount, ((size_t)g.nbins + 1) * 4);
+    // subproblem offsets (nbins + 1), then the add-back's list of bins (nbins)
+    if (!rc) rc = dalloc(p, (void **)&p->subcount, (2 * (size_t)g.nbins + 1) * 4);
     if (!rc && p->method == MNUFFT_METHOD_SM) {
         if (!p->nmerge) rc = dalloc(p, (void **)&p->nmerge, 16);
         if (!rc && !p->cmax) rc = dalloc(p, &p->cmax, 1024 * 8);  // partial maxima, see k_maxabs

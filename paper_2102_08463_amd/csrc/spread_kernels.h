@@ -826,10 +826,12 @@ k_spread_smp(Geom g, const int32_t *__restrict__ sub, const int32_t *__restrict_
 // summed into tile q.  Work items are (leader, chunk of 256 vectors).
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_tile_merge(const int32_t *__restrict__ nmergep, const int32_t *__restrict__ mergelist,
+k_tile_merge(int32_t *__restrict__ nmergep, const int32_t *__restrict__ mergelist,
              const int32_t *__restrict__ sub, const int32_t *__restrict__ suboff,
              T *__restrict__ scratch, int ts2, int G)
 {
+    // (nmergep[1] counts the bins the bin-wise add-back lists after this launch)
+    if (blockIdx.x == 0 && threadIdx.x == 0) nmergep[1] = 0;
     using V = typename Vec16<T>::type;
     constexpr int NV = 16 / sizeof(T);
     const int nvec = ts2 / NV;
@@ -1024,23 +1026,37 @@ k_tile_gather2(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__
 // r + P) and, within P of an edge, by one neighbour's, periodically: at
 // r + mp + P in the previous bin (width mp) if r < P, at r - mb + P in the
 // next if r >= mb - P.  With the tile lists of the 3^d neighbouring bins read
-// once per workgroup every tile value is one independent load; CPT cells per
-// thread are loaded before any is summed.  A cell's tiles are summed own
-// tile first in each dimension (x fastest), then in list order.
-// Neighbouring bins read pieces of the same tile rows, so each XCD takes a
-// contiguous range of bins (3D: 0.244 -> 0.222 ms at n = 256^3).
-template <typename T, int DIM>
+// once per workgroup every tile value is one independent load.  A cell's
+// tiles are summed own tile first in each dimension (x fastest), then in
+// list order, each bin's tiles in subproblem order.
+//
+// Two passes.  HEAVY = false takes every bin whose neighbourhood holds at
+// most one tile per bin (CPT cells per thread loaded before any is summed;
+// neighbouring bins read pieces of the same tile rows, so each XCD takes a
+// contiguous range of bins: 3D 0.244 -> 0.222 ms at n = 256^3) and appends
+// the other bins to `heavy` (count in cnt[1], cleared by k_tile_merge).
+// HEAVY = true splits each listed bin over kSlices workgroups, one cell per
+// thread, the further tiles of a bin loaded kBurst at a time: a bin of
+// clustered points may hold dozens of tiles, and one workgroup summing them
+// alone would hold up the whole launch.
+constexpr int kSlices = 4;
+template <typename T, int DIM, bool HEAVY>
 __global__ void __launch_bounds__(kThreads)
 k_tile_sum(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__ scratch, int ts2,
-           int G, int P, typename Cplx<T>::type *__restrict__ grid)
+           int G, int P, typename Cplx<T>::type *__restrict__ grid, int32_t *__restrict__ heavy,
+           int32_t *__restrict__ cnt)
 {
     using C = typename Cplx<T>::type;
     constexpr int NB = DIM == 3 ? 27 : 9;
     constexpr int NC = DIM == 3 ? 8 : 4;   // tile combinations per cell, at most
-    constexpr int CPT = sizeof(T) == 4 ? 2 : 1;
+    constexpr int CPT = HEAVY ? 1 : (sizeof(T) == 4 ? 2 : 1);
+    constexpr int kBurst = 8;
     __shared__ int sfirst[NB], scnt[NB];
     const int p1 = g.m[0] + 2 * P, p2 = g.m[1] + 2 * P;
-    for (int b = xcd_block(blockIdx.x, gridDim.x); b < g.nbins; b += gridDim.x) {
+    const int nwork = HEAVY ? cnt[1] * kSlices : g.nbins;
+    for (int w = xcd_block(blockIdx.x, gridDim.x); w < nwork; w += gridDim.x) {
+        const int b = HEAVY ? heavy[w / kSlices] : w;
+        const int slice = HEAVY ? w % kSlices : 0;
         const int b1 = b % g.B[0], b23 = b / g.B[0];
         const int b2 = b23 % g.B[1], b3 = DIM == 3 ? b23 / g.B[1] : 0;
         const int bb[3] = {b1, b2, b3};
@@ -1066,7 +1082,17 @@ k_tile_sum(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__ scr
             scnt[threadIdx.x] = suboff[nb + 1] - f;
         }
         __syncthreads();
-        for (int c0 = threadIdx.x; c0 < ncb; c0 += CPT * kThreads) {
+        if constexpr (!HEAVY) {
+            bool several = false;
+#pragma unroll
+            for (int l = 0; l < NB; ++l) several = several || scnt[l] > 1;
+            if (several) {  // the same for the whole workgroup
+                if (threadIdx.x == 0) heavy[atomicAdd(&cnt[1], 1)] = b;
+                continue;
+            }
+        }
+        const int cstep = (HEAVY ? kSlices : CPT) * kThreads;
+        for (int c0 = slice * kThreads + threadIdx.x; c0 < ncb; c0 += cstep) {
             int lst[CPT][NC];      // neighbour list of each combination (-1: none)
             int off[CPT][NC];      // offset of the cell in that neighbour's tiles (reals)
             T vr[CPT][NC], vi[CPT][NC];
@@ -1131,12 +1157,28 @@ k_tile_sum(Geom g, const int32_t *__restrict__ suboff, const T *__restrict__ scr
                     if (l < 0) continue;
                     ar += vr[k][v];
                     ai += vi[k][v];
-                    const int first = sfirst[l], cnt = scnt[l];
-                    const int step = cnt > G ? G : 1;
-                    for (int q = first + step; q < first + cnt; q += step) {
-                        const C t = *reinterpret_cast<const C *>(scratch + (size_t)q * ts2 + off[k][v]);
-                        ar += t.x;
-                        ai += t.y;
+                    if constexpr (HEAVY) {
+                        const int first = sfirst[l], end = first + scnt[l];
+                        const int step = scnt[l] > G ? G : 1;
+                        for (int q = first + step; q < end; q += kBurst * step) {
+                            T tr[kBurst], ti[kBurst];
+#pragma unroll
+                            for (int u = 0; u < kBurst; ++u) {
+                                tr[u] = 0;
+                                ti[u] = 0;
+                                if (q + u * step < end) {
+                                    const C t = *reinterpret_cast<const C *>(
+                                        scratch + (size_t)(q + u * step) * ts2 + off[k][v]);
+                                    tr[u] = t.x;
+                                    ti[u] = t.y;
+                                }
+                            }
+#pragma unroll
+                            for (int u = 0; u < kBurst; ++u) {
+                                ar += tr[u];
+                                ai += ti[u];
+                            }
+                        }
                     }
                 }
                 const int r1 = c % m1, r12 = c / m1;
@@ -1513,10 +1555,15 @@ hipError_t spread_wb(const Geom &g, int method, const Pts &P, const void *c, voi
                 const int last = g.n[d] - (g.B[d] - 1) * g.m[d];
                 wide = wide && std::min(g.m[d], last) >= 2 * ((W + 1) / 2);
             }
-            if (wide) {
-                hipLaunchKernelGGL((k_tile_sum<T, DIM>), dim3(std::min(g.nbins, 1 << 20)),
+            if (wide && P.heavy) {
+                // bins of one tile per neighbourhood, then the listed others
+                hipLaunchKernelGGL((k_tile_sum<T, DIM, false>), dim3(std::min(g.nbins, 1 << 20)),
                                    dim3(kThreads), 0, s, g, P.suboff, (const T *)P.scratch,
-                                   P.ts2, P.G, (W + 1) / 2, (C *)grid);
+                                   P.ts2, P.G, (W + 1) / 2, (C *)grid, P.heavy, P.nmerge);
+                hipLaunchKernelGGL((k_tile_sum<T, DIM, true>),
+                                   dim3(std::min(g.nbins * kSlices, 2048)), dim3(kThreads), 0, s,
+                                   g, P.suboff, (const T *)P.scratch, P.ts2, P.G, (W + 1) / 2,
+                                   (C *)grid, P.heavy, P.nmerge);
                 return hipGetLastError();
             }
         }

@@ -223,35 +223,39 @@ def test_methods_and_signs(method, dim):
 # narrower last bins (odd n too) and clustered points whose heavy bins hold
 # many subproblems (tiles merged in groups first).
 TILED_CASES = [
-    # (dim, N, binsize, prec, eps, kind)
-    (2, (64, 48), (32, 32), "f32", 1e-5, "uniform"),
-    (2, (64, 48), (32, 32), "f32", 1e-5, "cluster"),
-    (2, (16, 32), (32, 32), "f64", 1e-12, "uniform"),     # one bin in x, two in y
-    (2, (40, 24), (16, 16), "f64", 1e-9, "cluster"),
-    (2, (60, 40), (32, 32), "f32", 1e-5, "cluster"),      # last bins 24 and 16 wide
-    (2, (60, 40), (32, 32), "f64", 1e-12, "uniform"),
-    (3, (16, 16, 16), (16, 8, 8), "f32", 1e-5, "uniform"),
-    (3, (16, 16, 16), (16, 8, 8), "f32", 1e-5, "cluster"),
-    (3, (8, 8, 8), (16, 8, 8), "f64", 1e-6, "uniform"),    # one bin in x, two in y and z
-    (3, (12, 16, 8), (8, 8, 8), "f64", 1e-6, "cluster"),
-    (3, (20, 12, 14), (16, 8, 8), "f32", 1e-5, "uniform"),  # last z bin exactly two halos
-    (3, (22, 12, 14), (16, 8, 8), "f64", 1e-5, "cluster"),  # n = (45, 24, 30)
+    # (dim, N, binsize, prec, eps, kind, msub)
+    (2, (64, 48), (32, 32), "f32", 1e-5, "uniform", 300),
+    (2, (64, 48), (32, 32), "f32", 1e-5, "cluster", 300),
+    (2, (64, 48), (32, 32), "f32", 1e-5, "cluster", 40),    # bins of > 32 tiles: merged
+    (2, (16, 32), (32, 32), "f64", 1e-12, "uniform", 300),  # one bin in x, two in y
+    (2, (40, 24), (16, 16), "f64", 1e-9, "cluster", 300),
+    (2, (60, 40), (32, 32), "f32", 1e-5, "cluster", 300),   # last bins 24 and 16 wide
+    (2, (60, 40), (32, 32), "f64", 1e-12, "uniform", 300),
+    (3, (16, 16, 16), (16, 8, 8), "f32", 1e-5, "uniform", 300),
+    (3, (16, 16, 16), (16, 8, 8), "f32", 1e-5, "cluster", 300),
+    (3, (16, 16, 16), (16, 8, 8), "f64", 1e-5, "cluster", 20),
+    (3, (8, 8, 8), (16, 8, 8), "f64", 1e-6, "uniform", 300),    # one bin in x, two in y and z
+    (3, (12, 16, 8), (8, 8, 8), "f64", 1e-6, "cluster", 300),
+    (3, (20, 12, 14), (16, 8, 8), "f32", 1e-5, "uniform", 300),  # last z bin exactly two halos
+    (3, (22, 12, 14), (16, 8, 8), "f64", 1e-5, "cluster", 300),  # n = (45, 24, 30)
 ]
 
 
 @pytest.mark.parametrize("case", TILED_CASES,
-                         ids=lambda c: f"{c[0]}d-{c[1]}-{c[2]}-{c[3]}-{c[5]}")
+                         ids=lambda c: f"{c[0]}d-{c[1]}-{c[2]}-{c[3]}-{c[5]}-msub{c[6]}")
 def test_spread_binwise_addback(case):
-    dim, N, bs, prec, eps, kind = case
+    dim, N, bs, prec, eps, kind, msub = case
     note(f"spread bin-wise add-back {case}")
     M = 20_000 if dim == 2 else 8_000
     pts64, pts = make_points(kind, M, dim, prec, seed=14)
     c64, c = make_complex(M, prec, seed=15)
-    p = _plan(1, N, eps=eps, dtype=cdtype(prec), method="sm", binsize=bs, msub=300)
+    p = _plan(1, N, eps=eps, dtype=cdtype(prec), method="sm", binsize=bs, msub=msub)
     p.setpts(*pts)
     inf = p.info()
     ns, w, beta = inf["nfine"][:dim], inf["w"], inf["beta"]
     assert list(inf["binsize"][:dim]) == list(bs)
+    if msub < 100:  # some bin holds more than 32 subproblems (tiles merged in groups)
+        assert np.bincount(binsort.bin_keys(pts64, ns, bs)).max() > 32 * msub
     P = (w + 1) // 2
     for n, m in zip(ns, bs):
         last = n - (-(-n // m) - 1) * m
@@ -272,7 +276,7 @@ def test_spread_binwise_addback(case):
     # sums them with the cell-oriented gather: the two type 1 results may
     # differ only by the order of the final additions.
     from paper_2102_08463_amd import Batch
-    with Batch(1, [N], [M], eps=eps, dtype=cdtype(prec), binsize=[bs], msub=[300]) as b:
+    with Batch(1, [N], [M], eps=eps, dtype=cdtype(prec), binsize=[bs], msub=[msub]) as b:
         b.setpts(*pts)
         f_batch = b.split_modes(b.execute(c))[0].cpu().numpy()
     assert rel_l2(f_plan, f_batch) <= (1e-6 if prec == "f32" else 1e-14)
