@@ -316,10 +316,11 @@ def summarize_profiles(args):
         return sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
 
     def counters(d):
+        # keyed by the kernel name with its template arguments (one row per instantiation)
         per = {}
         for f in csvs(d, "counter_collection.csv"):
             for row in csv.DictReader(open(f)):
-                per.setdefault(_base_kernel(row["Kernel_Name"]), []).append(float(row["Counter_Value"]))
+                per.setdefault(_short_kernel(row["Kernel_Name"]), []).append(float(row["Counter_Value"]))
         return per
 
     stats = []
@@ -355,8 +356,10 @@ def summarize_profiles(args):
         print(f"wrote {args.md_out}")
         return
     fetch, write = counters(args.fetch_dir), counters(args.write_dir)
-    cal_f = max(counters(args.cal_fetch_dir)["__amd_rocclr_copyBuffer"])
-    cal_w = max(counters(args.cal_write_dir)["__amd_rocclr_copyBuffer"])
+    def copy_kernel(d):
+        return max(v for k, vals in counters(d).items() if _base_kernel(k) == "__amd_rocclr_copyBuffer"
+                   for v in vals)
+    cal_f, cal_w = copy_kernel(args.cal_fetch_dir), copy_kernel(args.cal_write_dir)
     kib = args.cal_mib * 1024.0
     ff, fw = kib / cal_f, kib / cal_w
     rsz = 4 if prec == "f32" else 8
@@ -369,22 +372,20 @@ def summarize_profiles(args):
               f"{fw:.3f} (write).", "",
               "| kernel | avg us | FETCH_SIZE KiB | WRITE_SIZE KiB | traffic MB | algorithmic MB |",
               "|---|---|---|---|---|---|"]
-    avg_us = {}
-    for name, calls, avg, pct in stats:
-        avg_us.setdefault(name.split("<")[0], avg)
+    avg_us = {name: avg for name, calls, avg, pct in stats}
     path = args.traffic_out or os.path.join(ROOT, "profiles", "traffic.json")
     table = json.load(open(path)) if os.path.exists(path) else {}
     for k in args.kernels.split(","):
-        if k not in fetch or k not in write:
-            continue
-        fk = sum(fetch[k]) / len(fetch[k])
-        wk = sum(write[k]) / len(write[k])
-        traffic = (fk * ff + wk * fw) * 1024.0
-        stage = "spread" if "spread" in k else ("interp" if "interp" in k else None)
-        algo = algorithmic_bytes(stage, dim, M, ncells, rsz) if stage else None
-        lines.append(f"| `{k}` | {avg_us.get(k, float('nan')):.1f} | {fk:.0f} | {wk:.0f} | "
-                     f"{traffic / 1e6:.1f} | {'%.1f' % (algo / 1e6) if algo else '-'} |")
-        if stage:
+        for full in sorted(n for n in fetch if _base_kernel(n) == k and n in write):
+            fk = sum(fetch[full]) / len(fetch[full])
+            wk = sum(write[full]) / len(write[full])
+            traffic = (fk * ff + wk * fw) * 1024.0
+            stage = "spread" if "spread" in k else ("interp" if "interp" in k else None)
+            algo = algorithmic_bytes(stage, dim, M, ncells, rsz) if stage else None
+            lines.append(f"| `{full}` | {avg_us.get(full, float('nan')):.1f} | {fk:.0f} | {wk:.0f} | "
+                         f"{traffic / 1e6:.1f} | {'%.1f' % (algo / 1e6) if algo else '-'} |")
+            if not stage:
+                continue
             table[f"{args.workload}:{k}"] = {"source_hash": kernel_source_hash(),
                                             "bytes_per_launch": traffic, "fetch_kib": fk,
                                             "write_kib": wk, "cal_fetch": ff, "cal_write": fw}
@@ -404,13 +405,14 @@ CUS = 256
 
 
 def counters_raw(d):
-    """{kernel: {counter: [values per dispatch]}} from a --pmc run's CSV."""
+    """{kernel (with template arguments): {counter: [values per dispatch]}} from a
+    --pmc run's CSV."""
     import csv
     import glob
     per = {}
     for f in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
         for row in csv.DictReader(open(f)):
-            per.setdefault(_base_kernel(row["Kernel_Name"]), {}).setdefault(
+            per.setdefault(_short_kernel(row["Kernel_Name"]), {}).setdefault(
                 row["Counter_Name"], []).append(float(row["Counter_Value"]))
     return per
 
@@ -449,14 +451,24 @@ def sq_summary(args, raw, stats):
     table = json.load(open(path)) if os.path.exists(path) else {}
     extra = ["k_tile_sum", "k_tile_gather2", "k_radix_scatter", "k_binkey"]
     for k in dict.fromkeys(args.kernels.split(",") + extra):
-        if k not in raw or "GRBM_GUI_ACTIVE" not in raw[k]:
+        fulls = sorted(n for n in raw if _base_kernel(n) == k and "GRBM_GUI_ACTIVE" in raw[n])
+        if not fulls:
             continue
-        fr = sq_fractions(raw[k])
-        lines.append(f"| `{k}` | {fr['valu_busy']:.2f} | {fr['valu_insts_per_cu_cycle']:.2f} | "
-                     f"{fr['lds_util']:.2f} | {fr['lds_bank_conflict']:.2f} | "
-                     f"{fr.get('occupancy', float('nan')):.2f} |")
-        if "spread" in k or "interp" in k:
-            table[f"{args.workload}:{k}"] = dict(fr, source_hash=kernel_source_hash())
+        if k == "k_radix_scatter":  # one row over its passes
+            merged = {}
+            for n in fulls:
+                for cn, vals in raw[n].items():
+                    merged.setdefault(cn, []).extend(vals)
+            rows = [(k, merged)]
+        else:
+            rows = [(n if len(fulls) > 1 else k, raw[n]) for n in fulls]
+        for label, c in rows:
+            fr = sq_fractions(c)
+            lines.append(f"| `{label}` | {fr['valu_busy']:.2f} | {fr['valu_insts_per_cu_cycle']:.2f} | "
+                         f"{fr['lds_util']:.2f} | {fr['lds_bank_conflict']:.2f} | "
+                         f"{fr.get('occupancy', float('nan')):.2f} |")
+            if ("spread" in k or "interp" in k) and len(fulls) == 1:
+                table[f"{args.workload}:{k}"] = dict(fr, source_hash=kernel_source_hash())
     with open(path, "w") as fh:
         json.dump(table, fh, indent=1, sort_keys=True)
     return lines
