@@ -50,18 +50,11 @@ k_deconv(int N1, int N2, int N3, int n1, int n2, int n3, int chunks,
 // Type 2: grid[t][l] = p1 p2 p3 f[t][k] where l = k mod n for k in I_N, else 0.
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-k_precorrect(int N1, int N2, int N3, int n1, int n2, int n3, int chunks,
+k_precorrect(int N1, int N2, int N3, int n1, int n2, int n3, int chunks, int64_t nwork,
              const typename Cplx<T>::type *__restrict__ f, const T *__restrict__ p1,
              const T *__restrict__ p2, const T *__restrict__ p3,
              typename Cplx<T>::type *__restrict__ grid)
 {
-    const int64_t row = blockIdx.x / chunks;
-    const int l1 = (int)(blockIdx.x % chunks) * kThreads + threadIdx.x;
-    if (l1 >= n1) return;
-    const int l2 = (int)(row % n2);
-    const int64_t r3 = row / n2;
-    const int l3 = (int)(r3 % n3);
-    const int64_t t = r3 / n3;
     // frequency held by index l: k = l for l <= kmax, k = l - n for l >= n + kmin
     auto idx = [](int l, int N, int n) -> int {
         const int kmin = -(N / 2), kmax = N - 1 - N / 2;
@@ -69,17 +62,28 @@ k_precorrect(int N1, int N2, int N3, int n1, int n2, int n3, int chunks,
         if (l >= n + kmin) return l - n - kmin;
         return -1;
     };
-    const int i1 = idx(l1, N1, n1), i2 = idx(l2, N2, n2), i3 = idx(l3, N3, n3);
-    typename Cplx<T>::type v;
-    v.x = 0;
-    v.y = 0;
-    if (i1 >= 0 && i2 >= 0 && i3 >= 0) {
-        const T s = p1[i1] * p2[i2] * p3[i3];
-        v = f[(((size_t)t * N3 + i3) * N2 + i2) * N1 + i1];
-        v.x *= s;
-        v.y *= s;
+    // work item = (row, chunk of kThreads cells); a persistent grid, so that
+    // each wave writes several rows, not one 512 B piece
+    for (int64_t w = blockIdx.x; w < nwork; w += gridDim.x) {
+        const int64_t row = w / chunks;
+        const int l1 = (int)(w % chunks) * kThreads + threadIdx.x;
+        if (l1 >= n1) continue;
+        const int l2 = (int)(row % n2);
+        const int64_t r3 = row / n2;
+        const int l3 = (int)(r3 % n3);
+        const int64_t t = r3 / n3;
+        const int i1 = idx(l1, N1, n1), i2 = idx(l2, N2, n2), i3 = idx(l3, N3, n3);
+        typename Cplx<T>::type v;
+        v.x = 0;
+        v.y = 0;
+        if (i1 >= 0 && i2 >= 0 && i3 >= 0) {
+            const T s = p1[i1] * p2[i2] * p3[i3];
+            v = f[(((size_t)t * N3 + i3) * N2 + i2) * N1 + i1];
+            v.x *= s;
+            v.y *= s;
+        }
+        grid[(((size_t)t * n3 + l3) * n2 + l2) * n1 + l1] = v;
     }
-    grid[(((size_t)t * n3 + l3) * n2 + l2) * n1 + l1] = v;
 }
 
 // Batched forms: one launch over the concatenated modes (deconvolution) or
@@ -193,14 +197,15 @@ hipError_t launch_precorrect(int dim, const int64_t N[3], const int n[3], int pr
     const int n3 = dim == 3 ? n[2] : 1;
     const int chunks = (n[0] + kThreads - 1) / kThreads;
     const int64_t rows = (int64_t)n[1] * n3 * ntransf;
-    const dim3 grd((unsigned)(rows * chunks)), blk(kThreads);
+    const int64_t nwork = rows * chunks;
+    const dim3 grd((unsigned)std::min<int64_t>(nwork, 8192)), blk(kThreads);
     if (prec == 0)
         hipLaunchKernelGGL(k_precorrect<float>, grd, blk, 0, s, N1, N2, N3, n[0], n[1], n3,
-                           chunks, (const float2 *)f, (const float *)p[0], (const float *)p[1],
-                           (const float *)p[2], (float2 *)grid);
+                           chunks, nwork, (const float2 *)f, (const float *)p[0],
+                           (const float *)p[1], (const float *)p[2], (float2 *)grid);
     else
         hipLaunchKernelGGL(k_precorrect<double>, grd, blk, 0, s, N1, N2, N3, n[0], n[1], n3,
-                           chunks, (const double2 *)f, (const double *)p[0],
+                           chunks, nwork, (const double2 *)f, (const double *)p[0],
                            (const double *)p[1], (const double *)p[2], (double2 *)grid);
     return hipGetLastError();
 }

@@ -180,10 +180,18 @@ k_radix_hist(const uint32_t *__restrict__ keys, int M, int shift, uint32_t dmask
     h[tid] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kTile;
+    // every key load first, so that their latencies overlap
+    uint32_t kv[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const int64_t idx = base + (int64_t)r * kThreads + tid;
+        kv[r] = idx < M ? keys[idx] : 0u;
+    }
+#pragma unroll
     for (int r = 0; r < kItems; ++r) {
         const int64_t idx = base + (int64_t)r * kThreads + tid;
         const bool valid = idx < M;
-        const uint32_t d = valid ? (keys[idx] >> shift) & dmask : 0u;
+        const uint32_t d = valid ? (kv[r] >> shift) & dmask : 0u;
         // Lanes are contiguous in idx, so lane 0 is valid whenever any lane is.
         const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)d);
         const bool same = !valid || d == d0;
