@@ -96,3 +96,51 @@ def test_summarize_profiles_sq_fractions(tmp_path):
     assert e["occupancy"] == pytest.approx(0.5)
     assert e["source_hash"] == bench.kernel_source_hash()
     assert "| `k_spread_smp` | 0.50 | 0.25 | 0.75 | 0.25 | 0.50 |" in open(f"{d}/s.md").read()
+
+
+def test_summarize_profiles_rows_per_instantiation(tmp_path):
+    """Two instantiations of one kernel (the add-back's two passes) get a row
+    each, with their own counters, not one row averaging both."""
+    d = str(tmp_path)
+    light = "void mn::detail::k_tile_sum<float, 3, false>(mn::Geom, int const*)"
+    heavy = "void mn::detail::k_tile_sum<float, 3, true>(mn::Geom, int const*)"
+    spread = "void mn::detail::k_spread_smp<float, 3, 6, false>(mn::Geom, int const*)"
+    _write(f"{d}/stats/run_kernel_stats.csv", ["Name", "Calls", "AverageNs", "Percentage"],
+           [[spread, 1, 1000000, 80.0], [light, 1, 180000, 15.0], [heavy, 1, 4000, 1.0]])
+    cc = ["Kernel_Name", "Counter_Value"]
+    _write(f"{d}/fetch/run_counter_collection.csv", cc,
+           [[spread, 500000], [light, 280000], [heavy, 20]])
+    _write(f"{d}/write/run_counter_collection.csv", cc,
+           [[spread, 550000], [light, 131072], [heavy, 0]])
+    _write(f"{d}/cf/run_counter_collection.csv", cc, [["__amd_rocclr_copyBuffer", 131072]])
+    _write(f"{d}/cw/run_counter_collection.csv", cc, [["__amd_rocclr_copyBuffer", 262144]])
+    cyc = 1_000_000
+    sq = []
+    for name, busy in ((spread, 0.5), (light, 0.75), (heavy, 0.0)):
+        sq += [[name, "GRBM_GUI_ACTIVE", 8 * cyc], [name, "SQ_ACTIVE_INST_VALU", busy * 256 * cyc],
+               [name, "SQ_INSTS_VALU", busy * 256 * cyc], [name, "SQ_LDS_IDX_ACTIVE", 0],
+               [name, "SQ_LDS_BANK_CONFLICT", 0]]
+    _write(f"{d}/sq/run_counter_collection.csv", ["Kernel_Name", "Counter_Name", "Counter_Value"],
+           sq)
+    md = f"{d}/s.md"
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--summarize-profiles",
+                        "--stats-dir", f"{d}/stats", "--fetch-dir", f"{d}/fetch",
+                        "--write-dir", f"{d}/write", "--cal-fetch-dir", f"{d}/cf",
+                        "--cal-write-dir", f"{d}/cw", "--sq-dir", f"{d}/sq", "--workload", "3d",
+                        "--kernels", "k_spread_smp,k_tile_sum", "--md-out", md,
+                        "--traffic-out", f"{d}/traffic.json", "--counters-out", f"{d}/c.json"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    text = open(md).read()
+    # traffic: 280000 KiB x 2 + 131072 KiB for the first pass alone
+    assert "| `k_tile_sum<float, 3, false>` | 180.0 | 280000 | 131072 | %.1f | - |" % (
+        (280000 * 2.0 + 131072) * 1024 / 1e6) in text
+    assert "| `k_tile_sum<float, 3, true>` | 4.0 | 20 | 0 |" in text
+    # utilisation: one row per pass, and a single spreading kernel under its plain name
+    assert "| `k_tile_sum<float, 3, false>` | 0.75 |" in text
+    assert "| `k_tile_sum<float, 3, true>` | 0.00 |" in text
+    assert "| `k_spread_smp` | 0.50 |" in text
+    c = json.load(open(f"{d}/c.json"))
+    assert set(c) == {"3d:k_spread_smp"}
+    t = json.load(open(f"{d}/traffic.json"))
+    assert set(t) == {"3d:k_spread_smp"}
