@@ -340,7 +340,7 @@ def summarize_profiles(args):
                 f"{eps:g}, {prec}; one bench step = setpts + type 1 + type 2 (adjoint) with the "
                 f"library defaults.")
     lines = [f"# {args.title}", "", f"Workload `{args.workload}`: {desc}", "",
-             "## Commands (repository root, GPU box)", "",
+             "## Commands (repository root, on the MI355X)", "",
              "```"] + args.command + ["```", "",
              "## Kernel statistics (rocprofv3 --kernel-trace --stats)", "",
              "| kernel | calls | avg us | share % |", "|---|---|---|---|"]
